@@ -1,0 +1,162 @@
+/*
+ * clot.h — C ABI of the MI355X (gfx950) clotting-step library.
+ *
+ * The library advances the clotting model of clotFoam (arXiv 2304.09180) by whole
+ * time steps on one GPU.  One step is, in order:
+ *   1. theta_B, theta_T and the Carman-Kozeny permeability alpha (section 2, eq. NSB;
+ *      Appendix A for theta_T);
+ *   2. the PISO pressure-velocity update: one implicit momentum predictor with the
+ *      Darcy term nu*alpha(theta_B) on the diagonal, then n_corr pressure
+ *      corrections (section 3.2);
+ *   3. the virtual substance eta - (L_eta^2/4) lap eta = theta_B (Appendix A, eq. eta);
+ *   4. the ADP release source sigma by the coarse-tau trapezoid (section 3.2,
+ *      eqs. ADP_source and sigma_disc);
+ *   5. implicit transport of Pmu, Pma, S1, S2, E1, E2, ADP with van Leer TVD
+ *      convection, hindered platelet fluxes (downwind / localMax theta_T, section
+ *      3.2 and Appendix D) and the reactive injury-wall conditions (Appendix B,
+ *      Appendix C table);
+ *   6. the reactions, M_rxn classical RK4 sub-steps per cell and per injury face
+ *      (section 3.2 fractional step; Appendix A and B right-hand sides).
+ *
+ * Conventions
+ *   - Every call returns clot_status: 0 success, >0 warning (state valid),
+ *     <0 error (state unchanged; clot_last_error() says why).
+ *   - Units: mm, s, nmol, platelets/mm^3 (Appendix E tables).
+ *   - Cell fields cross the ABI as float64 in x-fastest order, cell id
+ *     i + nx*(j + ny*k).  Face fluxes (mm^3/s, positive along +axis) are x-faces
+ *     i + (nx+1)*(j + ny*k), y-faces i + nx*(j + (ny+1)*k), z-faces
+ *     i + nx*(j + ny*k) with k in [0, nz].  Injury-face fields follow the injury
+ *     faces x-fastest, then z.
+ *   - Ownership: host buffers are caller-owned and used only during the call.
+ *     The device workspace and the HIP stream are caller-owned and must outlive
+ *     the context; the library allocates no device memory of its own.
+ *   - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef CLOT_H
+#define CLOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CLOT_OK = 0,
+    CLOT_W_NOTCONV = 1,     /* a linear solve stopped at max_iter; the step completed        */
+    CLOT_W_FALLBACK = 2,    /* surrogate step: some cells fell back to the plain integrator  */
+    CLOT_EINVAL = -1,       /* bad argument                                                  */
+    CLOT_ENOMEM = -2,       /* workspace too small                                           */
+    CLOT_EWORKSPACE = -3,   /* workspace pointer misaligned                                  */
+    CLOT_EHIP = -4,         /* a HIP runtime call failed                                     */
+    CLOT_ESTATE = -5,       /* call not valid in the current state                           */
+    CLOT_ENAN = -6          /* a non-finite value appeared                                   */
+} clot_status;
+
+typedef enum { CLOT_FP64 = 0, CLOT_FP32_MIXED = 1 } clot_precision;
+typedef enum { CLOT_RXN_PLAIN = 0, CLOT_RXN_SURROGATE = 1 } clot_rxn_mode;
+
+typedef enum {
+    CLOT_UX = 0, CLOT_UY, CLOT_UZ, CLOT_P, CLOT_PHIX, CLOT_PHIY, CLOT_PHIZ,
+    CLOT_PMU, CLOT_PMA, CLOT_PBA, CLOT_PBSE, CLOT_ADP, CLOT_S1, CLOT_S2, CLOT_E1, CLOT_E2,
+    CLOT_S1B, CLOT_S2B, CLOT_E1B, CLOT_E2B, CLOT_C1, CLOT_C2,   /* 15 cell species          */
+    CLOT_E0, CLOT_C0,                                            /* injury-face species     */
+    CLOT_ETA, CLOT_THETAB, CLOT_SIGMA,                           /* derived, read only      */
+    CLOT_NFIELDS
+} clot_field;
+
+/* One straight channel [0,Lx]x[0,Ly](x[0,Lz]): inlet x=0, outlet x=Lx, walls elsewhere.
+ * 2-D channels have nz = 1 and Lz the cell depth.  The injury patch is the set of
+ * y=0 wall faces whose centre lies in [inj_x0,inj_x1] x [inj_z0,inj_z1]
+ * (section 3.1, injuryWalls).  The inflow is the parabola of eq. parabolicVelocity
+ * (2-D) or the rectangular-duct Poiseuille profile (3-D), scaled to the wall shear
+ * rate `shear` on the bottom-wall centre line; platelets enter with the
+ * margination profile of Appendix C.1 (amplitudes K_y, K_z). */
+typedef struct {
+    int32_t dim, nx, ny, nz;
+    double Lx, Ly, Lz;
+    double inj_x0, inj_x1, inj_z0, inj_z1;
+    double shear;
+    double K_y, K_z;
+    double dt;
+} clot_channel;
+
+/* Model constants (Appendix E) and solver settings. */
+typedef struct {
+    double nu, C_CK, D_P, D_ADP, D_chem, P_diam, P_max, P_0, k_adh, kcoh_Pmax;
+    double eta_t, eta_star, L_eta_over_Pdiam, k_adp, adp_crit, k_e2, e2_crit;
+    double A_hat, tau_f, dtau, N_A, N1, N2;
+    double kC0p, kC0m, kC0cat, kC1p, kC1m, kC1cat, kC2p, kC2m, kC2cat;
+    double kS1p, kS1m, kE1p, kE1m, kS2p, kS2m, kE2p, kE2m;
+    double S1_0, S2_0, E0_0, p_out;
+    int32_t M_rxn;        /* reaction sub-steps per step (section 3.2; default 2)          */
+    int32_t n_corr;       /* PISO pressure corrections per step                            */
+    int32_t max_iter;     /* per linear solve                                              */
+    int32_t marg_m, marg_n;
+    double rtol_p;        /* pressure: ||b - A p|| <= rtol_p ||b|| (FP64 residual)           */
+    double rtol_s;        /* momentum, eta, transport                                      */
+    double rtol_inner;    /* FP32 inner pressure solve of each refinement pass             */
+} clot_params;
+
+/* Per-channel statistics of the last step. */
+typedef struct {
+    int32_t it_mom, it_p[8], it_eta, it_tr;   /* Krylov iterations (it_p per corrector)   */
+    int32_t refine_p[8];                        /* FP64 refinement passes per corrector      */
+    double res_mom, res_p, res_eta, res_tr;     /* final relative residuals                  */
+    double fallback_frac;                       /* surrogate cells sent to the plain RK4     */
+    int64_t steps;
+    double t;
+} clot_stats;
+
+typedef struct clot_ctx clot_ctx;
+
+/* Fills the Appendix E constants; M_rxn = 2, n_corr = 3, tolerances of the precision
+ * contract.  Never fails for a non-NULL pointer. */
+clot_status clot_params_default(clot_params* p);
+
+/* Bytes of device workspace clot_create needs for these channels and precision. */
+clot_status clot_query_workspace(const clot_channel* ch, int32_t n_ch, clot_precision prec, size_t* bytes);
+
+/* Creates a context over n_ch independent channels.  dev_workspace: device memory of
+ * at least the queried size, 256-byte aligned; hip_stream: a hipStream_t (NULL =
+ * default stream).  Builds the mesh tables and the inflow profiles; all fields are
+ * zero until clot_init_state or clot_set_field. */
+clot_status clot_create(const clot_channel* ch, int32_t n_ch, const clot_params* p, clot_precision prec,
+                        void* dev_workspace, size_t ws_bytes, void* hip_stream, clot_ctx** out);
+
+/* Initial state of channel ch (fully developed inflow, its Poiseuille pressure,
+ * margination platelets, S1_0, S2_0, E0_0, zero for the other species), every
+ * species value multiplied by (1 + 0.01*xi).  xi_cell: 15*ncell float64 normal
+ * draws (species in field order CLOT_PMU..CLOT_C2, cells x-fastest); xi_face:
+ * 2*nface draws (E0 then C0). */
+clot_status clot_init_state(clot_ctx* c, int32_t ch, const double* xi_cell, size_t n_cell,
+                            const double* xi_face, size_t n_face);
+
+clot_status clot_field_count(const clot_ctx* c, int32_t ch, clot_field f, size_t* n);
+clot_status clot_set_field(clot_ctx* c, int32_t ch, clot_field f, const double* host, size_t n);
+clot_status clot_get_field(clot_ctx* c, int32_t ch, clot_field f, double* host, size_t n);
+
+/* Advances every channel by nsteps time steps; blocks until done. */
+clot_status clot_step(clot_ctx* c, int32_t nsteps);
+
+/* Enqueues nsteps steps on the context stream without waiting; returns a warning
+ * only through clot_get_stats after a later synchronising call. */
+clot_status clot_step_async(clot_ctx* c, int32_t nsteps);
+clot_status clot_sync(clot_ctx* c);
+
+clot_status clot_get_stats(const clot_ctx* c, int32_t ch, clot_stats* s);
+
+/* Selects the reaction integrator.  mode CLOT_RXN_SURROGATE takes a weight blob
+ * (layout of clot_mlp_layout) and a residual threshold; a cell whose residual
+ * exceeds it is recomputed by the plain RK4 integrator. */
+clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* mlp_blob, size_t blob_bytes,
+                                   double resid_tol);
+
+void clot_destroy(clot_ctx* c);
+const char* clot_last_error(const clot_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,215 @@
+"""ctypes binding of the clotting-step C ABI (include/clot.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libclot.so.  PyTorch supplies the device workspace (a uint8 tensor) and the HIP
+stream; it does no model arithmetic here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclot.so")
+
+FP64, FP32_MIXED = 0, 1
+PLAIN, SURROGATE = 0, 1
+
+FIELDS = ["UX", "UY", "UZ", "P", "PHIX", "PHIY", "PHIZ",
+          "PMU", "PMA", "PBA", "PBSE", "ADP", "S1", "S2", "E1", "E2",
+          "S1B", "S2B", "E1B", "E2B", "C1", "C2", "E0", "C0", "ETA", "THETAB", "SIGMA"]
+FIELD = {n: i for i, n in enumerate(FIELDS)}
+SPECIES_FIELDS = FIELDS[7:22]
+
+STATUS = {0: "OK", 1: "W_NOTCONV", 2: "W_FALLBACK", -1: "EINVAL", -2: "ENOMEM", -3: "EWORKSPACE",
+          -4: "EHIP", -5: "ESTATE", -6: "ENAN"}
+
+
+class Channel(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("Lx", C.c_double), ("Ly", C.c_double), ("Lz", C.c_double),
+                ("inj_x0", C.c_double), ("inj_x1", C.c_double), ("inj_z0", C.c_double), ("inj_z1", C.c_double),
+                ("shear", C.c_double), ("K_y", C.c_double), ("K_z", C.c_double), ("dt", C.c_double)]
+
+
+_PARAM_DOUBLES_A = ["nu", "C_CK", "D_P", "D_ADP", "D_chem", "P_diam", "P_max", "P_0", "k_adh", "kcoh_Pmax",
+                    "eta_t", "eta_star", "L_eta_over_Pdiam", "k_adp", "adp_crit", "k_e2", "e2_crit",
+                    "A_hat", "tau_f", "dtau", "N_A", "N1", "N2",
+                    "kC0p", "kC0m", "kC0cat", "kC1p", "kC1m", "kC1cat", "kC2p", "kC2m", "kC2cat",
+                    "kS1p", "kS1m", "kE1p", "kE1m", "kS2p", "kS2m", "kE2p", "kE2m",
+                    "S1_0", "S2_0", "E0_0", "p_out"]
+
+
+class Params(C.Structure):
+    _fields_ = ([(n, C.c_double) for n in _PARAM_DOUBLES_A] +
+                [("M_rxn", C.c_int32), ("n_corr", C.c_int32), ("max_iter", C.c_int32),
+                 ("marg_m", C.c_int32), ("marg_n", C.c_int32),
+                 ("rtol_p", C.c_double), ("rtol_s", C.c_double), ("rtol_inner", C.c_double)])
+
+
+class Stats(C.Structure):
+    _fields_ = [("it_mom", C.c_int32), ("it_p", C.c_int32 * 8), ("it_eta", C.c_int32), ("it_tr", C.c_int32),
+                ("refine_p", C.c_int32 * 8),
+                ("res_mom", C.c_double), ("res_p", C.c_double), ("res_eta", C.c_double), ("res_tr", C.c_double),
+                ("fallback_frac", C.c_double), ("steps", C.c_int64), ("t", C.c_double)]
+
+
+class ClotError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load libclot.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ClotError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "clot_params_default": ([C.POINTER(Params)], C.c_int),
+        "clot_query_workspace": ([C.POINTER(Channel), C.c_int32, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+        "clot_create": ([C.POINTER(Channel), C.c_int32, C.POINTER(Params), C.c_int, P, C.c_size_t, P, C.POINTER(P)],
+                        C.c_int),
+        "clot_init_state": ([P, C.c_int32, P, C.c_size_t, P, C.c_size_t], C.c_int),
+        "clot_field_count": ([P, C.c_int32, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+        "clot_set_field": ([P, C.c_int32, C.c_int, P, C.c_size_t], C.c_int),
+        "clot_get_field": ([P, C.c_int32, C.c_int, P, C.c_size_t], C.c_int),
+        "clot_step": ([P, C.c_int32], C.c_int),
+        "clot_step_async": ([P, C.c_int32], C.c_int),
+        "clot_sync": ([P], C.c_int),
+        "clot_get_stats": ([P, C.c_int32, C.POINTER(Stats)], C.c_int),
+        "clot_set_reaction_mode": ([P, C.c_int, P, C.c_size_t, C.c_double], C.c_int),
+        "clot_destroy": ([P], None),
+        "clot_last_error": ([P], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the C header declares (for the load/export check)."""
+    return ["clot_params_default", "clot_query_workspace", "clot_create", "clot_init_state", "clot_field_count",
+            "clot_set_field", "clot_get_field", "clot_step", "clot_step_async", "clot_sync", "clot_get_stats",
+            "clot_set_reaction_mode", "clot_destroy", "clot_last_error"]
+
+
+def default_params(precision=FP64, **over) -> Params:
+    p = Params()
+    load().clot_params_default(C.byref(p))
+    if precision == FP32_MIXED:
+        p.rtol_s = 1e-7
+        p.rtol_p = 1e-10
+        p.rtol_inner = 1e-3
+        p.max_iter = 400
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def channel_struct(d: dict) -> Channel:
+    return Channel(d["dim"], d["nx"], d["ny"], d["nz"], d["Lx"], d["Ly"], d["Lz"], d["inj_x0"], d["inj_x1"],
+                   d["inj_z0"], d["inj_z1"], d["shear"], d["K_y"], d["K_z"], d["dt"])
+
+
+def _check(lib, ctx, st, what):
+    if st < 0:
+        msg = lib.clot_last_error(ctx).decode() if ctx else ""
+        raise ClotError(f"{what} failed: {STATUS.get(st, st)} {msg}")
+    return st
+
+
+class Solver:
+    """One context over a list of channel descriptors.
+
+    The workspace is a torch uint8 CUDA tensor; the stream is torch's current
+    stream (or the one passed in).
+    """
+
+    def __init__(self, descs, precision=FP64, params: Params | None = None, device="cuda", stream=None):
+        import torch
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise ClotError("no GPU visible: the clotting-step library runs only on the GPU")
+        self.descs = list(descs)
+        self.precision = precision
+        self.params = params if params is not None else default_params(precision)
+        arr = (Channel * len(self.descs))(*[channel_struct(d) for d in self.descs])
+        self._chs = arr
+        nbytes = C.c_size_t(0)
+        _check(self.lib, None, self.lib.clot_query_workspace(arr, len(self.descs), precision, C.byref(nbytes)),
+               "query_workspace")
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        ctx = C.c_void_p()
+        _check(self.lib, None, self.lib.clot_create(arr, len(self.descs), C.byref(self.params), precision,
+                                                    C.c_void_p(self.ws.data_ptr()), nbytes,
+                                                    C.c_void_p(self.stream.cuda_stream), C.byref(ctx)), "create")
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.clot_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_state(self, ch, xi_cell, xi_face):
+        xc = np.ascontiguousarray(xi_cell, dtype=np.float64)
+        xf = np.ascontiguousarray(xi_face, dtype=np.float64)
+        _check(self.lib, self.ctx, self.lib.clot_init_state(self.ctx, ch, xc.ctypes.data, xc.size, xf.ctypes.data,
+                                                            xf.size), "init_state")
+
+    def count(self, ch, name):
+        n = C.c_size_t(0)
+        _check(self.lib, self.ctx, self.lib.clot_field_count(self.ctx, ch, FIELD[name], C.byref(n)), "field_count")
+        return int(n.value)
+
+    def get(self, ch, name):
+        n = self.count(ch, name)
+        out = np.empty(n, dtype=np.float64)
+        _check(self.lib, self.ctx, self.lib.clot_get_field(self.ctx, ch, FIELD[name], out.ctypes.data, n), "get_field")
+        return out
+
+    def set(self, ch, name, values):
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        return _check(self.lib, self.ctx, self.lib.clot_set_field(self.ctx, ch, FIELD[name], v.ctypes.data, v.size),
+                      "set_field")
+
+    def step(self, n=1):
+        return _check(self.lib, self.ctx, self.lib.clot_step(self.ctx, n), "step")
+
+    def step_async(self, n=1):
+        return _check(self.lib, self.ctx, self.lib.clot_step_async(self.ctx, n), "step_async")
+
+    def sync(self):
+        return _check(self.lib, self.ctx, self.lib.clot_sync(self.ctx), "sync")
+
+    def stats(self, ch=0):
+        s = Stats()
+        st = self.lib.clot_get_stats(self.ctx, ch, C.byref(s))
+        _check(self.lib, self.ctx, st, "get_stats")
+        return {"status": STATUS.get(st, st), "it_mom": s.it_mom, "it_p": list(s.it_p), "it_eta": s.it_eta,
+                "it_tr": s.it_tr, "refine_p": list(s.refine_p), "res_mom": s.res_mom, "res_p": s.res_p,
+                "res_eta": s.res_eta, "res_tr": s.res_tr, "fallback_frac": s.fallback_frac, "steps": s.steps,
+                "t": s.t}
+
+    def fields(self, ch=0):
+        names = ["UX", "UY", "P", "PHIX", "PHIY", "E0", "C0", "ETA", "SIGMA"] + SPECIES_FIELDS
+        if self.descs[ch]["dim"] == 3:
+            names += ["UZ", "PHIZ"]
+        return {n: self.get(ch, n) for n in names}

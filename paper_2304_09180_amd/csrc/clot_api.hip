@@ -1,0 +1,999 @@
+// Host side of the clotting-step library: C ABI, workspace layout, step plan and
+// the Krylov drivers.  Kernels are in clot_step.h / clot_krylov.h / clot_ops.h.
+#include "../../include/clot.h"
+#include "clot_step.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace clot;
+
+namespace {
+
+constexpr int NPOOL = 7 + 7 * 7;     // Krylov vector pool (CG scratch + 7 BiCGStab systems)
+constexpr int NPART = 24;            // max partial sums per tile
+constexpr int NSTAT = 40;            // per-channel statistics slots
+constexpr int MAXCORR = 8;
+enum { ST_MOM = 0, ST_ETA = 1, ST_TR = 2, ST_P = 3 /* +corr */, ST_REF = 12 /* +corr */, ST_RESM = 21, ST_RESP = 22,
+       ST_RESE = 23, ST_REST = 24, ST_FAIL = 25, ST_FALLBACK = 26 };
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class X>
+    X* take(size_t n) {
+        off = (off + 255) & ~size_t(255);
+        X* p = base ? reinterpret_cast<X*>(base + off) : nullptr;
+        off += n * sizeof(X);
+        return p;
+    }
+};
+
+const double PI = 3.14159265358979323846;
+
+// Rectangular duct (0,a)x(0,b): w with -lap w = 1, w = 0 on the walls, as the
+// plane-Poiseuille part minus its Fourier-series wall correction in y.
+double duct_w(double y, double z, double a, double b) {
+    double w = 0.5 * y * (a - y);
+    const double zz = std::fabs(z - 0.5 * b), B = 0.5 * b;
+    for (int n = 1; n < 4000; n += 2) {
+        const double s = n * PI / a;
+        const double e1 = std::exp(s * (zz - B)), e2 = std::exp(-s * (zz + B));
+        const double term = 4.0 * a * a / (PI * PI * PI * n * (double)n * n) * (e1 + e2) / (1.0 + std::exp(-2.0 * s * B)) *
+                            std::sin(s * y);
+        w -= term;
+        if (e1 < 1e-18 && n > 50) break;
+    }
+    return w;
+}
+double duct_slope(double a, double b) {   // dw/dy at (0, b/2)
+    double s = 0.5 * a;
+    for (int n = 1; n < 400; n += 2) s -= 4.0 * a / (PI * PI * n * (double)n) / std::cosh(n * PI * b / (2.0 * a));
+    return s;
+}
+
+struct ChanHost {
+    clot_channel d;
+    int64_t c0, ncell, fx0, fy0, fz0, nfx, nfy, nfz, in0, inj0;
+    int32_t ninj, inj_i0, inj_ni, inj_k0, inj_nk, jadh, t0, nt, ncorr;
+    double dx, dy, dz;
+    double t = 0.0;
+    int64_t n = 0;
+    int64_t next_push = 0;
+    double hist_t[NHIST];
+    int head = -1;           // slot of the newest snapshot
+    int npushed = 0;
+};
+
+}  // namespace
+
+struct clot_ctx {
+    clot_precision prec;
+    std::string err;
+    virtual ~clot_ctx() {}
+    virtual clot_status init_state(int ch, const double* xc, size_t nc, const double* xf, size_t nf) = 0;
+    virtual clot_status count(int ch, clot_field f, size_t* n) const = 0;
+    virtual clot_status set(int ch, clot_field f, const double* h, size_t n) = 0;
+    virtual clot_status get(int ch, clot_field f, double* h, size_t n) = 0;
+    virtual clot_status step(int nsteps, bool wait) = 0;
+    virtual clot_status sync() = 0;
+    virtual clot_status stats(int ch, clot_stats* s) const = 0;
+};
+
+namespace {
+
+#define HIPCHK(x)                                                                       \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess) {                                                         \
+            err = std::string(#x) + ": " + hipGetErrorString(e_);                       \
+            return CLOT_EHIP;                                                           \
+        }                                                                               \
+    } while (0)
+
+template <class T>
+struct Ctx : clot_ctx {
+    std::vector<ChanHost> ch;
+    clot_params prm;
+    ModelDev M;
+    hipStream_t st;
+    int64_t N = 0, NFX = 0, NFY = 0, NFZ = 0, NIN = 0, NINJ = 0;
+    int32_t ntiles = 0;
+    int maxcorr = 2;
+    // device tables
+    ChanDev* d_ch = nullptr;
+    int32_t* d_t2c = nullptr;
+    int32_t* d_f2c = nullptr;
+    Fields<T> F{};
+    T* pool[NPOOL];
+    T* u_in = nullptr;
+    T* pmu_in = nullptr;
+    KState S{};
+    int32_t* refmask = nullptr;
+    int32_t* allmask = nullptr;
+    int32_t* corrmask = nullptr;      // [MAXCORR][nch]
+    double* sigw = nullptr;           // [nch][NHIST]
+    int32_t* push = nullptr;          // [nch][2]
+    double* dstats = nullptr;         // [nch][NSTAT]
+    int32_t* h_nact = nullptr;        // pinned
+    int last_it[8] = {8, 8, 8, 8, 8, 8, 8, 8};
+    bool nonconv = false;
+    Grid grid() const { return Grid{d_ch, d_t2c, ntiles}; }
+    ~Ctx() override {
+        if (h_nact) (void)hipHostFree(h_nact);
+    }
+
+    // ---------------------------------------------------------------------------
+    size_t layout(char* base) {
+        Carver cv{base};
+        const int nch = (int)ch.size();
+        d_ch = cv.take<ChanDev>(nch);
+        d_t2c = cv.take<int32_t>(ntiles);
+        d_f2c = cv.take<int32_t>(std::max<int64_t>(NINJ, 1));
+        for (int c = 0; c < 3; ++c) F.u[c] = cv.take<T>(N);
+        F.p = cv.take<double>(N);
+        F.phi[0] = cv.take<T>(NFX);
+        F.phi[1] = cv.take<T>(NFY);
+        F.phi[2] = cv.take<T>(std::max<int64_t>(NFZ, 1));
+        F.phin[0] = cv.take<T>(NFX);
+        F.phin[1] = cv.take<T>(NFY);
+        F.phin[2] = cv.take<T>(std::max<int64_t>(NFZ, 1));
+        for (int s = 0; s < NSPC; ++s) F.spc[s] = cv.take<T>(N);
+        for (int k = 0; k < NTR; ++k) F.xt[k] = cv.take<T>(N);
+        const int64_t ni = std::max<int64_t>(NINJ, 1);
+        F.E0 = cv.take<T>(ni);
+        F.C0 = cv.take<T>(ni);
+        F.s1w = cv.take<T>(ni);
+        F.eta = cv.take<T>(N);
+        F.thB = cv.take<T>(N);
+        F.thB_prev = cv.take<T>(N);
+        F.Wc = cv.take<T>(N);
+        F.sigma = cv.take<T>(N);
+        F.hist = cv.take<T>((size_t)N * NHIST);
+        u_in = cv.take<T>(NIN);
+        pmu_in = cv.take<T>(NIN);
+        F.u_in = u_in;
+        F.pmu_in = pmu_in;
+        F.aP = cv.take<T>(N);
+        for (int c = 0; c < 3; ++c) F.src[c] = cv.take<T>(N);
+        for (int c = 0; c < 3; ++c) F.bm[c] = cv.take<T>(N);
+        F.rAU = cv.take<T>(N);
+        for (int c = 0; c < 3; ++c) F.HbyA[c] = cv.take<T>(N);
+        F.dP = cv.take<T>(N);
+        F.dE = cv.take<T>(N);
+        F.rhs_p = cv.take<double>(N);
+        for (int k = 0; k < NTR; ++k) F.trd[k] = cv.take<T>(N);
+        for (int k = 0; k < NTR; ++k) F.trb[k] = cv.take<T>(N);
+        for (int q = 0; q < NPOOL; ++q) pool[q] = cv.take<T>(N);
+        F.ncell = N;
+        S.maxit = prm.max_iter;
+        S.sc = cv.take<double>((size_t)nch * MAXK * NSC);
+        S.chact = cv.take<int32_t>(nch);
+        S.nact = cv.take<int32_t>(1);
+        S.part = cv.take<double>((size_t)ntiles * NPART);
+        S.tick = cv.take<uint32_t>(nch);
+        refmask = cv.take<int32_t>(nch);
+        allmask = cv.take<int32_t>(nch);
+        corrmask = cv.take<int32_t>((size_t)MAXCORR * nch);
+        sigw = cv.take<double>((size_t)nch * NHIST);
+        push = cv.take<int32_t>((size_t)nch * 2);
+        dstats = cv.take<double>((size_t)nch * NSTAT);
+        return cv.off + 256;
+    }
+
+    // ---------------------------------------------------------------------------
+    clot_status setup(const clot_channel* cs, int nch, const clot_params* p) {
+        prm = *p;
+        ch.resize(nch);
+        int64_t c0 = 0, fx = 0, fy = 0, fz = 0, in = 0, inj = 0;
+        int32_t t0 = 0;
+        for (int i = 0; i < nch; ++i) {
+            ChanHost& h = ch[i];
+            h.d = cs[i];
+            const clot_channel& d = cs[i];
+            if (!(d.dim == 2 || d.dim == 3) || d.nx < 2 || d.ny < 2 || d.nz < 1 || (d.dim == 2 && d.nz != 1) ||
+                (d.dim == 3 && d.nz < 2) || !(d.Lx > 0) || !(d.Ly > 0) || !(d.Lz > 0) || !(d.dt > 0) || !(d.shear >= 0)) {
+                err = "channel " + std::to_string(i) + ": invalid dimensions, extents or time step";
+                return CLOT_EINVAL;
+            }
+            if ((int64_t)d.nx * d.ny * d.nz > (int64_t)1 << 31) {
+                err = "channel too large";
+                return CLOT_EINVAL;
+            }
+            h.dx = d.Lx / d.nx;
+            h.dy = d.Ly / d.ny;
+            h.dz = d.Lz / d.nz;
+            h.ncell = (int64_t)d.nx * d.ny * d.nz;
+            h.c0 = c0;
+            c0 += h.ncell;
+            h.nfx = (int64_t)(d.nx + 1) * d.ny * d.nz;
+            h.nfy = (int64_t)d.nx * (d.ny + 1) * d.nz;
+            h.nfz = d.dim == 3 ? (int64_t)d.nx * d.ny * (d.nz + 1) : 0;
+            h.fx0 = fx;
+            h.fy0 = fy;
+            h.fz0 = fz;
+            fx += h.nfx;
+            fy += h.nfy;
+            fz += h.nfz;
+            h.in0 = in;
+            in += (int64_t)d.ny * d.nz;
+            // injury patch: face centres inside [x0,x1] x [z0,z1] on y = 0
+            int i0 = -1, i1 = -1, k0 = -1, k1 = -1;
+            for (int ii = 0; ii < d.nx; ++ii) {
+                const double xc = (ii + 0.5) * h.dx;
+                if (xc >= d.inj_x0 && xc <= d.inj_x1) {
+                    if (i0 < 0) i0 = ii;
+                    i1 = ii;
+                }
+            }
+            if (d.dim == 3) {
+                for (int kk = 0; kk < d.nz; ++kk) {
+                    const double zc = (kk + 0.5) * h.dz;
+                    if (zc >= d.inj_z0 && zc <= d.inj_z1) {
+                        if (k0 < 0) k0 = kk;
+                        k1 = kk;
+                    }
+                }
+            } else {
+                k0 = 0;
+                k1 = 0;
+            }
+            if (i0 < 0 || k0 < 0) {
+                h.inj_i0 = 0;
+                h.inj_ni = 0;
+                h.inj_k0 = 0;
+                h.inj_nk = 0;
+            } else {
+                h.inj_i0 = i0;
+                h.inj_ni = i1 - i0 + 1;
+                h.inj_k0 = k0;
+                h.inj_nk = k1 - k0 + 1;
+            }
+            h.ninj = h.inj_ni * h.inj_nk;
+            h.inj0 = inj;
+            inj += h.ninj;
+            // adhesion layers: cell centres within P_diam of the wall, else the first layer
+            int ja = 0;
+            for (int jj = 0; jj < d.ny; ++jj)
+                if ((jj + 0.5) * h.dy <= p->P_diam) ja = jj + 1;
+            h.jadh = ja > 0 ? ja : 1;
+            h.nt = (int32_t)((h.ncell + TILE - 1) / TILE);
+            h.t0 = t0;
+            t0 += h.nt;
+            // PISO corrections: fixed, or chosen from the viscous diffusion number
+            const double hmin = std::min(h.dx, std::min(h.dy, d.dim == 3 ? h.dz : h.dy));
+            const double Dn = p->nu * d.dt / (hmin * hmin);
+            h.ncorr = p->n_corr > 0 ? p->n_corr : (Dn <= 10.0 ? 2 : Dn <= 30.0 ? 3 : Dn <= 60.0 ? 4 : 5);
+            if (h.ncorr > MAXCORR) h.ncorr = MAXCORR;
+            maxcorr = std::max(maxcorr, h.ncorr);
+            for (int q = 0; q < NHIST; ++q) h.hist_t[q] = -1e300;
+        }
+        N = c0;
+        NFX = fx;
+        NFY = fy;
+        NFZ = fz;
+        NIN = in;
+        NINJ = inj;
+        ntiles = t0;
+        const clot_params& q = *p;
+        M = ModelDev{q.nu, q.C_CK, q.D_P, q.D_ADP, q.D_chem, q.P_diam, q.P_max, q.P_0, q.k_adh, q.kcoh_Pmax,
+                     q.eta_t, q.eta_star, 0.0, q.k_adp, q.adp_crit, q.k_e2, q.e2_crit,
+                     q.A_hat, q.tau_f, q.dtau, q.N_A, q.N1, q.N2,
+                     q.kC0p, q.kC0m, q.kC0cat, q.kC1p, q.kC1m, q.kC1cat, q.kC2p, q.kC2m, q.kC2cat,
+                     q.kS1p, q.kS1m, q.kE1p, q.kE1m, q.kS2p, q.kS2m, q.kE2p, q.kE2m,
+                     q.S1_0, q.S2_0, q.E0_0, q.p_out, 0.0, q.M_rxn};
+        const double Le = q.L_eta_over_Pdiam * q.P_diam;
+        M.kappa_eta = Le * Le / 4.0;
+        M.g0 = (std::pow(q.eta_star, 3) + std::pow(1.0 - q.eta_t, 3)) / std::pow(1.0 - q.eta_t, 3);
+        return CLOT_OK;
+    }
+
+    clot_status upload_tables() {
+        const int nch = (int)ch.size();
+        std::vector<ChanDev> dv(nch);
+        std::vector<int32_t> t2c(ntiles), f2c(std::max<int64_t>(NINJ, 1), 0);
+        for (int i = 0; i < nch; ++i) {
+            const ChanHost& h = ch[i];
+            ChanDev& c = dv[i];
+            c.dim = h.d.dim;
+            c.nx = h.d.nx;
+            c.ny = h.d.ny;
+            c.nz = h.d.nz;
+            c.c0 = h.c0;
+            c.ncell = h.ncell;
+            c.fx0 = h.fx0;
+            c.fy0 = h.fy0;
+            c.fz0 = h.fz0;
+            c.in0 = h.in0;
+            c.inj0 = h.inj0;
+            c.ninj = h.ninj;
+            c.inj_i0 = h.inj_i0;
+            c.inj_ni = h.inj_ni;
+            c.inj_k0 = h.inj_k0;
+            c.inj_nk = h.inj_nk;
+            c.jadh = h.jadh;
+            c.t0 = h.t0;
+            c.nt = h.nt;
+            c.dx = h.dx;
+            c.dy = h.dy;
+            c.dz = h.dz;
+            c.V = h.dx * h.dy * h.dz;
+            c.Ax = h.dy * h.dz;
+            c.Ay = h.dx * h.dz;
+            c.Az = h.dx * h.dy;
+            c.dt = h.d.dt;
+            for (int t = 0; t < h.nt; ++t) t2c[h.t0 + t] = i;
+            for (int f = 0; f < h.ninj; ++f) f2c[h.inj0 + f] = i;
+        }
+        HIPCHK(hipMemcpyAsync(d_ch, dv.data(), nch * sizeof(ChanDev), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_t2c, t2c.data(), t2c.size() * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_f2c, f2c.data(), f2c.size() * 4, hipMemcpyHostToDevice, st));
+        std::vector<int32_t> ones(nch, 1), cm((size_t)MAXCORR * nch, 0);
+        for (int k = 0; k < MAXCORR; ++k)
+            for (int i = 0; i < nch; ++i) cm[(size_t)k * nch + i] = k < ch[i].ncorr ? 1 : 0;
+        HIPCHK(hipMemcpyAsync(allmask, ones.data(), nch * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(corrmask, cm.data(), cm.size() * 4, hipMemcpyHostToDevice, st));
+        // inflow profiles (Appendix C.1 / C.2)
+        std::vector<T> ui(NIN), pi(NIN);
+        for (int i = 0; i < nch; ++i) {
+            const ChanHost& h = ch[i];
+            for (int k = 0; k < h.d.nz; ++k)
+                for (int j = 0; j < h.d.ny; ++j) {
+                    const double y = (j + 0.5) * h.dy, z = (k + 0.5) * h.dz;
+                    ui[h.in0 + j + (int64_t)h.d.ny * k] = T(inflow_u(h, y, z));
+                    pi[h.in0 + j + (int64_t)h.d.ny * k] = T(inflow_pmu(h, y, z));
+                }
+        }
+        HIPCHK(hipMemcpyAsync(u_in, ui.data(), NIN * sizeof(T), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(pmu_in, pi.data(), NIN * sizeof(T), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<uint32_t> z(nch, 0);
+        HIPCHK(hipMemcpy(S.tick, z.data(), nch * 4, hipMemcpyHostToDevice));
+        std::vector<double> zs((size_t)nch * NSTAT, 0.0);
+        HIPCHK(hipMemcpy(dstats, zs.data(), zs.size() * 8, hipMemcpyHostToDevice));
+        return CLOT_OK;
+    }
+
+    // inflow speed (eq. parabolicVelocity in 2-D; duct Poiseuille in 3-D) and its
+    // Poiseuille pressure gradient magnitude
+    double inflow_u(const ChanHost& h, double y, double z) const {
+        const double g = h.d.shear;
+        if (h.d.dim == 2) {
+            const double r = 0.5 * h.d.Ly;
+            return -(g / (2.0 * r)) * (y - r) * (y - r) + 0.5 * g * r;
+        }
+        return g / duct_slope(h.d.Ly, h.d.Lz) * duct_w(y, z, h.d.Ly, h.d.Lz);
+    }
+    double inflow_dpdx(const ChanHost& h) const {
+        if (h.d.dim == 2) return prm.nu * h.d.shear / (0.5 * h.d.Ly);
+        return prm.nu * h.d.shear / duct_slope(h.d.Ly, h.d.Lz);
+    }
+    // margination (Appendix C.1, C.2): P0 [1 + K R^{m-1}(1-R)^{n-1} (+ z term)] / (1 + K B(m,n) (+ ...))
+    double inflow_pmu(const ChanHost& h, double y, double z) const {
+        const int m = prm.marg_m, n = prm.marg_n;
+        const double beta = std::exp(std::lgamma((double)m) + std::lgamma((double)n) - std::lgamma((double)(m + n)));
+        const double ry = 0.5 * h.d.Ly;
+        const double Ry = std::fabs(y - ry) / ry;
+        double br = 1.0 + h.d.K_y * std::pow(Ry, m - 1) * std::pow(1.0 - Ry, n - 1);
+        double norm = 1.0 + h.d.K_y * beta;
+        if (h.d.dim == 3) {
+            const double rz = 0.5 * h.d.Lz;
+            const double Rz = std::fabs(z - rz) / rz;
+            br += h.d.K_z * std::pow(Rz, m - 1) * std::pow(1.0 - Rz, n - 1);
+            norm += h.d.K_z * beta;
+        }
+        return prm.P_0 * br / norm;
+    }
+
+    // ---------------------------------------------------------------------------
+    clot_status upload(T* dst, const std::vector<double>& src) {
+        std::vector<T> tmp(src.begin(), src.end());
+        HIPCHK(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return CLOT_OK;
+    }
+
+    clot_status init_state(int c, const double* xc, size_t nc, const double* xf, size_t nf) override {
+        ChanHost& h = ch[c];
+        const int64_t n = h.ncell;
+        if (nc != (size_t)(NSPC * n) || nf != (size_t)(2 * h.ninj) || (!xc && nc) || (!xf && nf)) {
+            err = "init_state: expected 15*ncell cell draws and 2*nface face draws";
+            return CLOT_EINVAL;
+        }
+        std::vector<double> u(n), zero(n, 0.0), pr(n);
+        const double G = inflow_dpdx(h);
+        for (int k = 0; k < h.d.nz; ++k)
+            for (int j = 0; j < h.d.ny; ++j) {
+                const double y = (j + 0.5) * h.dy, z = (k + 0.5) * h.dz;
+                const double uu = inflow_u(h, y, z);
+                for (int i = 0; i < h.d.nx; ++i) {
+                    const int64_t g = i + (int64_t)h.d.nx * (j + (int64_t)h.d.ny * k);
+                    u[g] = uu;
+                    pr[g] = G * (h.d.Lx - (i + 0.5) * h.dx);
+                }
+            }
+        clot_status s;
+        if ((s = upload(F.u[0] + h.c0, u))) return s;
+        if ((s = upload(F.u[1] + h.c0, zero))) return s;
+        if ((s = upload(F.u[2] + h.c0, zero))) return s;
+        HIPCHK(hipMemcpy(F.p + h.c0, pr.data(), n * 8, hipMemcpyHostToDevice));
+        // fluxes: x faces carry the profile, the others none
+        std::vector<double> fxv(h.nfx), fyv(h.nfy, 0.0), fzv(h.nfz, 0.0);
+        const double Ax = h.dy * h.dz;
+        for (int k = 0; k < h.d.nz; ++k)
+            for (int j = 0; j < h.d.ny; ++j) {
+                const double uu = inflow_u(h, (j + 0.5) * h.dy, (k + 0.5) * h.dz);
+                for (int i = 0; i <= h.d.nx; ++i) fxv[i + (int64_t)(h.d.nx + 1) * (j + (int64_t)h.d.ny * k)] = Ax * uu;
+            }
+        if ((s = upload(F.phi[0] + h.fx0, fxv))) return s;
+        if ((s = upload(F.phi[1] + h.fy0, fyv))) return s;
+        if (h.nfz && (s = upload(F.phi[2] + h.fz0, fzv))) return s;
+        // species with 1% multiplicative noise
+        for (int sp = 0; sp < NSPC; ++sp) {
+            std::vector<double> v(n, 0.0);
+            for (int k = 0; k < h.d.nz; ++k)
+                for (int j = 0; j < h.d.ny; ++j) {
+                    const double y = (j + 0.5) * h.dy, z = (k + 0.5) * h.dz;
+                    const double base = sp == PMU ? inflow_pmu(h, y, z) : sp == S1 ? prm.S1_0 : sp == S2 ? prm.S2_0 : 0.0;
+                    for (int i = 0; i < h.d.nx; ++i) {
+                        const int64_t g = i + (int64_t)h.d.nx * (j + (int64_t)h.d.ny * k);
+                        v[g] = base * (1.0 + 0.01 * xc[(size_t)sp * n + g]);
+                    }
+                }
+            if ((s = upload(F.spc[sp] + h.c0, v))) return s;
+        }
+        std::vector<double> e0(h.ninj), c0(h.ninj, 0.0);
+        for (int f = 0; f < h.ninj; ++f) {
+            e0[f] = prm.E0_0 * (1.0 + 0.01 * xf[f]);
+            c0[f] = 0.0 * (1.0 + 0.01 * xf[h.ninj + f]);
+        }
+        if (h.ninj) {
+            if ((s = upload(F.E0 + h.inj0, e0))) return s;
+            if ((s = upload(F.C0 + h.inj0, c0))) return s;
+        }
+        if ((s = upload(F.eta + h.c0, zero))) return s;
+        if ((s = upload(F.sigma + h.c0, zero))) return s;
+        for (int q = 0; q < NHIST; ++q)
+            if ((s = upload(F.hist + (int64_t)q * N + h.c0, zero))) return s;
+        // theta_B of the "previous" step = current
+        std::vector<double> thb(n, 0.0);
+        if ((s = upload(F.thB_prev + h.c0, thb))) return s;
+        h.t = 0.0;
+        h.n = 0;
+        h.next_push = 0;
+        h.head = -1;
+        h.npushed = 0;
+        for (int q = 0; q < NHIST; ++q) h.hist_t[q] = -1e300;
+        // thB_prev must equal theta_B of the initial state: compute it on the device
+        hipLaunchKernelGGL(k_derive<T>, dim3(ntiles), dim3(NT), 0, st, grid(), F, M);
+        HIPCHK(hipGetLastError());
+        const int64_t cnt = h.ncell;
+        hipLaunchKernelGGL(k_copy<T>, dim3((cnt + 255) / 256), dim3(256), 0, st, F.thB_prev + h.c0, F.thB + h.c0, cnt);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return CLOT_OK;
+    }
+
+    // ---------------------------------------------------------------------------
+    struct FieldRef {
+        void* ptr;
+        int64_t n;
+        bool dbl;
+        bool ro;
+    };
+    FieldRef ref(int c, clot_field f) const {
+        const ChanHost& h = ch[c];
+        const int64_t n = h.ncell;
+        switch (f) {
+            case CLOT_UX: return {F.u[0] + h.c0, n, false, false};
+            case CLOT_UY: return {F.u[1] + h.c0, n, false, false};
+            case CLOT_UZ: return {F.u[2] + h.c0, h.d.dim == 3 ? n : 0, false, false};
+            case CLOT_P: return {F.p + h.c0, n, true, false};
+            case CLOT_PHIX: return {F.phi[0] + h.fx0, h.nfx, false, false};
+            case CLOT_PHIY: return {F.phi[1] + h.fy0, h.nfy, false, false};
+            case CLOT_PHIZ: return {F.phi[2] + h.fz0, h.nfz, false, false};
+            case CLOT_E0: return {F.E0 + h.inj0, h.ninj, false, false};
+            case CLOT_C0: return {F.C0 + h.inj0, h.ninj, false, false};
+            case CLOT_ETA: return {F.eta + h.c0, n, false, true};
+            case CLOT_THETAB: return {F.thB_prev + h.c0, n, false, true};
+            case CLOT_SIGMA: return {F.sigma + h.c0, n, false, true};
+            default:
+                if (f >= CLOT_PMU && f <= CLOT_C2) return {F.spc[f - CLOT_PMU] + h.c0, n, false, false};
+        }
+        return {nullptr, 0, false, true};
+    }
+
+    clot_status count(int c, clot_field f, size_t* n) const override {
+        FieldRef r = ref(c, f);
+        if (!r.ptr && r.n == 0 && f != CLOT_UZ && f != CLOT_PHIZ) {
+            const_cast<Ctx*>(this)->err = "unknown field";
+            return CLOT_EINVAL;
+        }
+        *n = (size_t)r.n;
+        return CLOT_OK;
+    }
+
+    clot_status set(int c, clot_field f, const double* h, size_t n) override {
+        FieldRef r = ref(c, f);
+        if (r.ro) {
+            err = "field is read only";
+            return CLOT_EINVAL;
+        }
+        if ((int64_t)n != r.n || (!h && n)) {
+            err = "set_field: size mismatch";
+            return CLOT_EINVAL;
+        }
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(h[i])) {
+                err = "set_field: non-finite value";
+                return CLOT_ENAN;
+            }
+        if (r.dbl) {
+            HIPCHK(hipMemcpyAsync(r.ptr, h, n * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            return CLOT_OK;
+        }
+        std::vector<double> v(h, h + n);
+        return upload((T*)r.ptr, v);
+    }
+
+    clot_status get(int c, clot_field f, double* h, size_t n) override {
+        FieldRef r = ref(c, f);
+        if ((int64_t)n != r.n || (!h && n)) {
+            err = "get_field: size mismatch";
+            return CLOT_EINVAL;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (r.dbl) {
+            HIPCHK(hipMemcpy(h, r.ptr, n * 8, hipMemcpyDeviceToHost));
+            return CLOT_OK;
+        }
+        std::vector<T> tmp(n);
+        HIPCHK(hipMemcpy(tmp.data(), r.ptr, n * sizeof(T), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) h[i] = (double)tmp[i];
+        return CLOT_OK;
+    }
+
+    // ---------------------------------------------------------------------------
+    // Krylov drivers
+    int32_t poll() {
+        hipMemcpyAsync(h_nact, S.nact, 4, hipMemcpyDeviceToHost, st);
+        hipStreamSynchronize(st);
+        return *h_nact;
+    }
+    void fill(int32_t* p, int32_t v, int64_t n) {
+        hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+    }
+    void set_active(const int32_t* mask) {
+        const int nch = (int)ch.size();
+        hipLaunchKernelGGL(k_copy<int32_t>, dim3((nch + 255) / 256), dim3(256), 0, st, S.chact, mask, (int64_t)nch);
+        fill(S.nact, 0, 1);
+    }
+
+    template <class Op, int K>
+    int run_cg(const Op& op, KVec<T, K> V, double rtol, int tol_mode, const int32_t* mask, int slot) {
+        set_active(mask);
+        hipLaunchKernelGGL((k_cg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, rtol, tol_mode);
+        int it = 0, par = 0;
+        int chunk = std::max(2, last_it[slot]);
+        while (it < prm.max_iter) {
+            for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it) {
+                hipLaunchKernelGGL((k_cg_a<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                hipLaunchKernelGGL((k_cg_b<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                par ^= 1;
+            }
+            if (poll() == 0) break;
+            chunk = 4;
+        }
+        last_it[slot] = std::max(2, it - 2);
+        return it;
+    }
+
+    template <class Op, int K>
+    int run_bicg(const Op& op, KVec<T, K> V, double rtol, const int32_t* mask, int slot) {
+        set_active(mask);
+        hipLaunchKernelGGL((k_bicg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, rtol);
+        int it = 0, par = 0;
+        int chunk = std::max(2, last_it[slot]);
+        while (it < prm.max_iter) {
+            for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it) {
+                hipLaunchKernelGGL((k_bicg_1<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                hipLaunchKernelGGL((k_bicg_2<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                hipLaunchKernelGGL((k_bicg_3<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                par ^= 1;
+            }
+            if (poll() == 0) break;
+            chunk = 2;
+        }
+        last_it[slot] = std::max(1, it - 1);
+        return it;
+    }
+
+    template <int K>
+    KVec<T, K> bicg_vecs(int first) {
+        KVec<T, K> V;
+        for (int k = 0; k < K; ++k) {
+            T** b = pool + 7 + 7 * (first + k);
+            V.r[k] = b[0];
+            V.rh[k] = b[1];
+            V.p[0][k] = b[2];
+            V.p[1][k] = b[3];
+            V.v[0][k] = b[4];
+            V.v[1][k] = b[5];
+            V.t[k] = b[6];
+        }
+        return V;
+    }
+    KVec<T, 1> cg_vecs(T* x, const T* b) {
+        KVec<T, 1> V;
+        V.x[0] = x;
+        V.b[0] = b;
+        V.r[0] = pool[1];
+        V.rh[0] = pool[1];
+        V.p[0][0] = pool[2];
+        V.p[1][0] = pool[3];
+        V.v[0][0] = pool[2];
+        V.v[1][0] = pool[3];
+        V.t[0] = pool[4];
+        return V;
+    }
+
+    void record(int slot_it, int slot_res, int K, bool add) {
+        hipLaunchKernelGGL(k_record, dim3(1), dim3(64), 0, st, S.sc, dstats, NSTAT, (int)ch.size(), K, slot_it, slot_res,
+                           (int)ST_FAIL, add ? 1 : 0);
+    }
+
+    // ---------------------------------------------------------------------------
+    void sigma_host(std::vector<int32_t>& pushv, std::vector<double>& w, bool& any) {
+        // push decision and trapezoid weights per channel (section 3.2, eq. sigma_disc)
+        any = false;
+        const int nch = (int)ch.size();
+        pushv.assign((size_t)nch * 2, -1);
+        w.assign((size_t)nch * NHIST, 0.0);
+        for (int i = 0; i < nch; ++i) {
+            ChanHost& h = ch[i];
+            const int64_t m = (int64_t)std::floor(h.t / prm.dtau + 1e-9);
+            if (!(h.n == 0 || m >= h.next_push)) continue;
+            h.next_push = m + 1;
+            h.head = (h.head + 1) % NHIST;
+            h.hist_t[h.head] = h.t;
+            h.npushed = std::min(h.npushed + 1, NHIST);
+            pushv[2 * i] = h.head;
+            pushv[2 * i + 1] = h.n == 0 ? 1 : 0;
+            // node a (0 = newest) lives in slot (head - a) mod NHIST; trapezoid weights
+            for (int a = 0; a < NHIST; ++a) {
+                const int slot = ((h.head - a) % NHIST + NHIST) % NHIST;
+                if (a >= h.npushed) continue;
+                const double age = h.t - h.hist_t[slot];
+                const double wt = (a == 0 || a == NHIST - 1) ? 0.5 * prm.dtau : prm.dtau;
+                w[(size_t)i * NHIST + slot] = prm.A_hat * wt * std::exp(-(age - 3.0) * (age - 3.0)) / std::sqrt(PI);
+            }
+            any = true;
+        }
+    }
+
+    clot_status one_step() {
+        const Grid G = grid();
+        const dim3 gb(ntiles), tb(NT);
+        const int nch = (int)ch.size();
+        // O-0 derived coefficients
+        hipLaunchKernelGGL(k_derive<T>, gb, tb, 0, st, G, F, M);
+        // O-1 momentum predictor
+        hipLaunchKernelGGL(k_mom_assemble<T>, gb, tb, 0, st, G, F, M);
+        MomOp<T> mop{F.aP, F.phi[0], F.phi[1], F.phi[2], T(prm.nu)};
+        {
+            KVec<T, 3> V = bicg_vecs<3>(0);
+            for (int c = 0; c < 3; ++c) {
+                V.x[c] = F.u[c];
+                V.b[c] = F.bm[c];
+            }
+            run_bicg<MomOp<T>, 3>(mop, V, prm.rtol_s, allmask, 0);
+            record(ST_MOM, ST_RESM, 3, false);
+        }
+        // O-2 PISO correctors
+        for (int k = 0; k < maxcorr; ++k) {
+            const int32_t* cm = corrmask + (size_t)k * nch;
+            hipLaunchKernelGGL(k_hbya<T>, gb, tb, 0, st, G, F, mop, cm);
+            hipLaunchKernelGGL(k_prhs<T>, gb, tb, 0, st, G, F, M, cm);
+            // FP64 iterative refinement around a T-precision PCG
+            set_active(cm);
+            // count of active channels for the residual kernel
+            hipLaunchKernelGGL(k_count_active, dim3(1), dim3(64), 0, st, S.chact, S.nact, nch);
+            T* e = pool[5];
+            T* rin = pool[0];
+            PresOp<T, T> pop{F.rAU, F.dP};
+            for (int pass = 0; pass < 12; ++pass) {
+                hipLaunchKernelGGL(k_pres_resid<T>, gb, tb, 0, st, G, F, rin, e, S, prm.rtol_p,
+                                   prec == CLOT_FP64 ? 0.0 : prm.rtol_inner, pass, refmask);
+                const int32_t need = poll();
+                if (need == 0) break;
+                KVec<T, 1> V = cg_vecs(e, rin);
+                run_cg<PresOp<T, T>, 1>(pop, V, 0.0, 1, refmask, 1 + std::min(k, 2));
+                record(ST_P + std::min(k, MAXCORR - 1), ST_RESP, 1, pass > 0);
+                hipLaunchKernelGGL(k_pres_add<T>, gb, tb, 0, st, G, F, e, refmask);
+                set_active(refmask);
+                hipLaunchKernelGGL(k_count_active, dim3(1), dim3(64), 0, st, S.chact, S.nact, nch);
+            }
+            hipLaunchKernelGGL(k_record_pass, dim3(1), dim3(64), 0, st, S.sc, dstats, NSTAT, nch,
+                               ST_REF + std::min(k, MAXCORR - 1), ST_RESP, (int)ST_FAIL);
+            hipLaunchKernelGGL(k_correct<T>, gb, tb, 0, st, G, F, M, cm);
+        }
+        // O-3 eta
+        {
+            T* rhs = pool[0];
+            hipLaunchKernelGGL(k_eta_prep<T>, gb, tb, 0, st, G, F, M, rhs);
+            EtaOp<T> eop{T(M.kappa_eta), F.dE};
+            KVec<T, 1> V = cg_vecs(F.eta, rhs);
+            run_cg<EtaOp<T>, 1>(eop, V, prm.rtol_s, 0, allmask, 4);
+            record(ST_ETA, ST_RESE, 1, false);
+        }
+        // O-4 sigma
+        {
+            std::vector<int32_t> pv;
+            std::vector<double> w;
+            bool any;
+            sigma_host(pv, w, any);
+            if (any) {
+                HIPCHK(hipMemcpyAsync(push, pv.data(), pv.size() * 4, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(sigw, w.data(), w.size() * 8, hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_sigma<T>, gb, tb, 0, st, G, F, M, sigw, push);
+                HIPCHK(hipStreamSynchronize(st));
+            }
+        }
+        // O-5 transport
+        TrOp<T> top;
+        for (int k = 0; k < NTR; ++k) {
+            top.Cn[k] = F.spc[tr_species(k)];
+            top.dg[k] = F.trd[k];
+            top.Dk[k] = tr_diffusivity<T>(k, M);
+        }
+        top.phx = F.phin[0];
+        top.phy = F.phin[1];
+        top.phz = F.phin[2];
+        top.Wc = F.Wc;
+        top.Pmax = T(M.P_max);
+        hipLaunchKernelGGL(k_tr_assemble<T>, gb, tb, 0, st, G, F, top, M);
+        {
+            KVec<T, NTR> V = bicg_vecs<NTR>(0);
+            for (int k = 0; k < NTR; ++k) {
+                V.x[k] = F.xt[k];
+                V.b[k] = F.trb[k];
+            }
+            run_bicg<TrOp<T>, NTR>(top, V, prm.rtol_s, allmask, 5);
+            record(ST_TR, ST_REST, NTR, false);
+        }
+        // O-6 reactions (wall first: it reads the transported S1)
+        if (NINJ > 0)
+            hipLaunchKernelGGL(k_wall_rxn<T>, dim3((NINJ + NT - 1) / NT), tb, 0, st, d_ch, d_f2c, NINJ, F, M);
+        hipLaunchKernelGGL(k_rxn<T>, gb, tb, 0, st, G, F, M);
+        // O-7 rotate theta_B and the flux
+        std::swap(F.thB, F.thB_prev);
+        for (int c = 0; c < 3; ++c) std::swap(F.phi[c], F.phin[c]);
+        for (ChanHost& h : ch) {
+            h.n += 1;
+            h.t = h.n * h.d.dt;
+        }
+        HIPCHK(hipGetLastError());
+        return CLOT_OK;
+    }
+
+    clot_status step(int nsteps, bool wait) override {
+        for (int s = 0; s < nsteps; ++s) {
+            clot_status r = one_step();
+            if (r < 0) return r;
+        }
+        if (wait) return sync();
+        return CLOT_OK;
+    }
+    clot_status sync() override {
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        return CLOT_OK;
+    }
+    clot_status stats(int c, clot_stats* s) const override {
+        std::vector<double> v(NSTAT);
+        if (hipMemcpy(v.data(), dstats + (size_t)c * NSTAT, NSTAT * 8, hipMemcpyDeviceToHost) != hipSuccess) return CLOT_EHIP;
+        std::memset(s, 0, sizeof(*s));
+        s->it_mom = (int)v[ST_MOM];
+        s->it_eta = (int)v[ST_ETA];
+        s->it_tr = (int)v[ST_TR];
+        for (int k = 0; k < 8; ++k) {
+            s->it_p[k] = (int)v[ST_P + k];
+            s->refine_p[k] = (int)v[ST_REF + k];
+        }
+        s->res_mom = v[ST_RESM];
+        s->res_p = v[ST_RESP];
+        s->res_eta = v[ST_RESE];
+        s->res_tr = v[ST_REST];
+        s->fallback_frac = v[ST_FALLBACK];
+        s->steps = ch[c].n;
+        s->t = ch[c].t;
+        return v[ST_FAIL] > 0 ? CLOT_W_NOTCONV : CLOT_OK;
+    }
+};
+
+}  // namespace
+
+// =====================================================================================
+// C ABI
+// =====================================================================================
+static clot_ctx* make_ctx(clot_precision prec) {
+    if (prec == CLOT_FP64) return new Ctx<double>();
+    return new Ctx<float>();
+}
+
+template <class T>
+static size_t ws_size(Ctx<T>* c) {
+    return c->layout(nullptr);
+}
+
+template <class T>
+static clot_status create_t(Ctx<T>* c, const clot_channel* chs, int n_ch, const clot_params* p, void* ws, size_t wsb,
+                            void* stream) {
+    clot_status s = c->setup(chs, n_ch, p);
+    if (s) return s;
+    const size_t need = c->layout(nullptr);
+    if (wsb < need) {
+        c->err = "workspace too small: need " + std::to_string(need) + " bytes";
+        return CLOT_ENOMEM;
+    }
+    if (((uintptr_t)ws & 255) != 0) {
+        c->err = "workspace must be 256-byte aligned";
+        return CLOT_EWORKSPACE;
+    }
+    c->layout((char*)ws);
+    c->st = (hipStream_t)stream;
+    if (hipHostMalloc((void**)&c->h_nact, 64, hipHostMallocDefault) != hipSuccess) {
+        c->err = "hipHostMalloc failed";
+        return CLOT_EHIP;
+    }
+    return c->upload_tables();
+}
+
+extern "C" {
+
+clot_status clot_params_default(clot_params* p) {
+    if (!p) return CLOT_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->nu = 2.62507;
+    p->C_CK = 1.0e6;
+    p->D_P = 2.5e-5;
+    p->D_ADP = 5.0e-4;
+    p->D_chem = 5.0e-5;
+    p->P_diam = 3.0e-3;
+    p->P_max = 6.67e7;
+    p->P_0 = 2.5e5;
+    p->k_adh = 3.3212e-8;
+    p->kcoh_Pmax = 1.0e4;
+    p->eta_t = 0.1;
+    p->eta_star = 0.4;
+    p->L_eta_over_Pdiam = 2.0;
+    p->k_adp = 0.34;
+    p->adp_crit = 2.0e-3;
+    p->k_e2 = 0.5;
+    p->e2_crit = 1.0e-6;
+    p->A_hat = 2.0e-8;
+    p->tau_f = 6.0;
+    p->dtau = 0.25;
+    p->N_A = 6.02214076e14;
+    p->N1 = 2700.0;
+    p->N2 = 2000.0;
+    p->kC0p = 8.95e3;
+    p->kC0m = 1.0;
+    p->kC0cat = 1.15;
+    p->kC1p = 1.03e5;
+    p->kC1m = 1.0;
+    p->kC1cat = 30.0;
+    p->kC2p = 1.73e4;
+    p->kC2m = 1.0;
+    p->kC2cat = 0.23;
+    p->kS1p = 5.7e4;
+    p->kS1m = 0.17;
+    p->kE1p = 1.0e4;
+    p->kE1m = 2.5e-2;
+    p->kS2p = 1.0e4;
+    p->kS2m = 5.9;
+    p->kE2p = 1.0e4;
+    p->kE2m = 5.9;
+    p->S1_0 = 1.7e-4;
+    p->S2_0 = 1.4e-3;
+    p->E0_0 = 1.5e-7;
+    p->p_out = 0.0;
+    p->M_rxn = 2;
+    p->n_corr = 0;
+    p->max_iter = 5000;
+    p->marg_m = 19;
+    p->marg_n = 2;
+    p->rtol_p = 1e-12;
+    p->rtol_s = 1e-12;
+    p->rtol_inner = 1e-4;
+    return CLOT_OK;
+}
+
+clot_status clot_query_workspace(const clot_channel* chs, int32_t n_ch, clot_precision prec, size_t* bytes) {
+    if (!chs || n_ch < 1 || !bytes || (prec != CLOT_FP64 && prec != CLOT_FP32_MIXED)) return CLOT_EINVAL;
+    clot_params p;
+    clot_params_default(&p);
+    clot_ctx* c = make_ctx(prec);
+    clot_status s;
+    if (prec == CLOT_FP64) {
+        auto* d = static_cast<Ctx<double>*>(c);
+        s = d->setup(chs, n_ch, &p);
+        if (s == CLOT_OK) *bytes = ws_size(d);
+    } else {
+        auto* d = static_cast<Ctx<float>*>(c);
+        s = d->setup(chs, n_ch, &p);
+        if (s == CLOT_OK) *bytes = ws_size(d);
+    }
+    delete c;
+    return s;
+}
+
+clot_status clot_create(const clot_channel* chs, int32_t n_ch, const clot_params* p, clot_precision prec, void* ws,
+                        size_t wsb, void* stream, clot_ctx** out) {
+    if (!chs || n_ch < 1 || !p || !ws || !out || (prec != CLOT_FP64 && prec != CLOT_FP32_MIXED)) return CLOT_EINVAL;
+    *out = nullptr;
+    if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1) return CLOT_EINVAL;
+    clot_ctx* c = make_ctx(prec);
+    c->prec = prec;
+    clot_status s = prec == CLOT_FP64 ? create_t(static_cast<Ctx<double>*>(c), chs, n_ch, p, ws, wsb, stream)
+                                      : create_t(static_cast<Ctx<float>*>(c), chs, n_ch, p, ws, wsb, stream);
+    if (s < 0) {
+        delete c;
+        return s;
+    }
+    *out = c;
+    return CLOT_OK;
+}
+
+#define CTXCHK(c, chn)                                        \
+    if (!(c)) return CLOT_EINVAL;
+
+clot_status clot_init_state(clot_ctx* c, int32_t chn, const double* xc, size_t nc, const double* xf, size_t nf) {
+    if (!c) return CLOT_EINVAL;
+    return c->init_state(chn, xc, nc, xf, nf);
+}
+clot_status clot_field_count(const clot_ctx* c, int32_t chn, clot_field f, size_t* n) {
+    if (!c || !n) return CLOT_EINVAL;
+    return c->count(chn, f, n);
+}
+clot_status clot_set_field(clot_ctx* c, int32_t chn, clot_field f, const double* h, size_t n) {
+    if (!c) return CLOT_EINVAL;
+    return c->set(chn, f, h, n);
+}
+clot_status clot_get_field(clot_ctx* c, int32_t chn, clot_field f, double* h, size_t n) {
+    if (!c) return CLOT_EINVAL;
+    return c->get(chn, f, h, n);
+}
+clot_status clot_step(clot_ctx* c, int32_t nsteps) {
+    if (!c || nsteps < 0) return CLOT_EINVAL;
+    return c->step(nsteps, true);
+}
+clot_status clot_step_async(clot_ctx* c, int32_t nsteps) {
+    if (!c || nsteps < 0) return CLOT_EINVAL;
+    return c->step(nsteps, false);
+}
+clot_status clot_sync(clot_ctx* c) {
+    if (!c) return CLOT_EINVAL;
+    return c->sync();
+}
+clot_status clot_get_stats(const clot_ctx* c, int32_t chn, clot_stats* s) {
+    if (!c || !s) return CLOT_EINVAL;
+    return c->stats(chn, s);
+}
+clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* blob, size_t nb, double tol) {
+    if (!c) return CLOT_EINVAL;
+    if (mode != CLOT_RXN_PLAIN) {
+        c->err = "surrogate reaction mode is not available in this build";
+        return CLOT_ESTATE;
+    }
+    return CLOT_OK;
+}
+void clot_destroy(clot_ctx* c) { delete c; }
+const char* clot_last_error(const clot_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

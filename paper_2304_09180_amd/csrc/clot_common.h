@@ -1,0 +1,161 @@
+// Shared device-side definitions of the clotting-step library (gfx950).
+//
+// Layout: every channel's cells are contiguous in the global SoA arrays, x fastest
+// (cell id i + nx*(j + ny*k)).  All launches run over a flattened tile space: a
+// tile is TILE consecutive cells of one channel; a 256-thread block owns one tile.
+// Blocks are remapped so that consecutive tiles run on the same XCD (the hardware
+// deals blocks round-robin over the 8 XCDs, each with its own L2), which keeps the
+// j±1 and k±1 stencil rows of a tile in the L2 that has just read them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clot {
+
+constexpr int NT = 256;           // threads per block (4 wavefronts of 64)
+constexpr int CPT = 4;            // cells per thread
+constexpr int TILE = NT * CPT;    // cells per tile
+constexpr int NXCD = 8;
+constexpr int NSPC = 15;          // cell species
+constexpr int NTR = 7;            // transported species
+constexpr int NRX = 14;           // reacting species
+constexpr int NHIST = 25;         // release-history nodes (tau_f/dtau + 1)
+constexpr int MAXK = 8;           // max systems in one batched Krylov solve
+constexpr int NSC = 64;           // per-channel scalar slots
+
+// Cell species slots (library field order).
+enum { PMU = 0, PMA, PBA, PBSE, ADP, S1, S2, E1, E2, S1B, S2B, E1B, E2B, C1, C2 };
+// Transported species, solve order.
+__host__ __device__ constexpr int tr_species(int k) {
+    return k == 0 ? PMU : k == 1 ? PMA : k == 2 ? S1 : k == 3 ? S2 : k == 4 ? E1 : k == 5 ? E2 : ADP;
+}
+
+struct ChanDev {
+    int32_t dim, nx, ny, nz;
+    int64_t c0, ncell;            // first cell, cell count
+    int64_t fx0, fy0, fz0;        // first x/y/z face
+    int64_t in0;                  // first inflow face (ny*nz of them)
+    int64_t inj0;                 // first injury face
+    int32_t ninj, inj_i0, inj_ni, inj_k0, inj_nk;
+    int32_t jadh;                 // adhesion layers (cells j < jadh over the patch)
+    int32_t t0, nt;               // tile range
+    double dx, dy, dz, V, Ax, Ay, Az;
+    double dt;
+};
+
+// Model constants on the device (same names as clot_params).
+struct ModelDev {
+    double nu, C_CK, D_P, D_ADP, D_chem, P_diam, P_max, P_0, k_adh, kcoh_Pmax;
+    double eta_t, eta_star, kappa_eta, k_adp, adp_crit, k_e2, e2_crit;
+    double A_hat, tau_f, dtau, N_A, N1, N2;
+    double kC0p, kC0m, kC0cat, kC1p, kC1m, kC1cat, kC2p, kC2m, kC2cat;
+    double kS1p, kS1m, kE1p, kE1m, kS2p, kS2m, kE2p, kE2m;
+    double S1_0, S2_0, E0_0, p_out;
+    double g0;
+    int32_t M_rxn;
+};
+
+// Launch-wide tables.
+struct Grid {
+    const ChanDev* ch;            // per channel
+    const int32_t* t2c;           // tile -> channel
+    int32_t ntiles;
+};
+
+__device__ inline int32_t xcd_tile(int32_t b, int32_t nb) {
+    int32_t q = nb / NXCD, r = nb % NXCD;
+    int32_t x = b % NXCD, i = b / NXCD;
+    return x * q + (x < r ? x : r) + i;
+}
+
+struct Cell {
+    int64_t g;      // global cell id
+    int32_t i, j, k;
+};
+
+__device__ inline Cell cell_at(const ChanDev& c, int64_t local) {
+    Cell p;
+    p.g = c.c0 + local;
+    p.i = (int32_t)(local % c.nx);
+    int64_t r = local / c.nx;
+    p.j = (int32_t)(r % c.ny);
+    p.k = (int32_t)(r / c.ny);
+    return p;
+}
+
+__device__ inline int64_t fx_id(const ChanDev& c, int i, int j, int k) {
+    return c.fx0 + i + (int64_t)(c.nx + 1) * (j + (int64_t)c.ny * k);
+}
+__device__ inline int64_t fy_id(const ChanDev& c, int i, int j, int k) {
+    return c.fy0 + i + (int64_t)c.nx * (j + (int64_t)(c.ny + 1) * k);
+}
+__device__ inline int64_t fz_id(const ChanDev& c, int i, int j, int k) {
+    return c.fz0 + i + (int64_t)c.nx * (j + (int64_t)c.ny * k);
+}
+
+// ---------------------------------------------------------------------------------
+// Block reductions and the per-channel "last tile finishes the sum" pattern.
+// Partial sums land in part[tile*NV + v]; the block that finishes last in its
+// channel (an atomic ticket per channel) adds the channel's partials in tile order,
+// so the result is deterministic, then runs the caller's scalar epilogue.
+// ---------------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* lds /* NV*NT/64 */) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) lds[q * (NT / 64) + w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int ww = 0; ww < NT / 64; ++ww) s += lds[threadIdx.x * (NT / 64) + ww];
+        lds[NV * (NT / 64) + threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = lds[NV * (NT / 64) + q];
+}
+
+// Returns true in the block that completes channel ch's reduction; sums[] then holds
+// the channel totals (in every thread of that block).
+template <int NV>
+__device__ inline bool channel_reduce(double (&v)[NV], double* part, uint32_t* ticket, const ChanDev& c,
+                                      int32_t tile, double* lds, double (&sums)[NV]) {
+    block_sum<NV>(v, lds);
+    __shared__ uint32_t s_last;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) part[(int64_t)tile * NV + q] = v[q];
+        __threadfence();
+        uint32_t t = atomicAdd(ticket, 1u);
+        s_last = (t == (uint32_t)(c.nt - 1)) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    // strided partial sums, then a fixed-order block reduction: deterministic
+    for (int t = threadIdx.x; t < c.nt; t += NT) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            acc[q] += part[(int64_t)(c.t0 + t) * NV + q];
+        }
+    }
+    block_sum<NV>(acc, lds);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sums[q] = acc[q];
+    if (threadIdx.x == 0) *ticket = 0u;
+    return true;
+}
+
+}  // namespace clot

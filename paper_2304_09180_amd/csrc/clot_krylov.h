@@ -1,0 +1,416 @@
+// Batched, per-channel Krylov solvers as phase kernels (gfx950).
+//
+// K independent systems per channel share one launch.  Every dot product is an
+// FP64 per-tile partial finished by the last tile of the channel, which also
+// computes the recurrence scalars (alpha, beta, omega) and the convergence
+// decision on the device: the host never reads a scalar to continue.  A channel
+// whose systems have all converged stops doing work (its blocks return at entry)
+// and decrements the global active count that the host polls between chunks.
+//
+// Jacobi-preconditioned CG (SPD: pressure, eta) and BiCGStab (momentum, transport).
+// The preconditioned direction vectors are formed on the fly from r, p and v at
+// each stencil point, so each iteration costs two (CG) or three (BiCGStab) passes.
+#pragma once
+#include "clot_ops.h"
+
+namespace clot {
+
+// Per (channel, system) scalar slots.
+enum {
+    SC_BB = 0, SC_RR, SC_RZ, SC_RHO, SC_ALPHA, SC_OMEGA, SC_BETA, SC_IT, SC_ACT, SC_TOL2, SC_RR0, SC_PQ,
+    SC_TS, SC_TT, SC_FAIL, SC_PASS
+};
+
+struct KState {
+    double* sc;          // [nch][MAXK][NSC]
+    int32_t* chact;      // [nch] 1 while any system of the channel iterates
+    int32_t* nact;       // global count of active channels
+    double* part;        // [ntiles][NV]
+    uint32_t* tick;      // [nch]
+    int32_t maxit;
+};
+
+__device__ inline double* scp(const KState& S, int ch, int k) { return S.sc + ((int64_t)ch * MAXK + k) * NSC; }
+
+template <class T, int K>
+struct KVec {
+    T* x[K];
+    const T* b[K];
+    T* r[K];
+    T* rh[K];
+    T* p[2][K];
+    T* v[2][K];
+    T* t[K];
+};
+
+#define CLOT_TILE_PROLOGUE(G)                                     \
+    const int32_t tile = xcd_tile((int32_t)blockIdx.x, G.ntiles); \
+    const int32_t chid = G.t2c[tile];                             \
+    const ChanDev& C = G.ch[chid];                                \
+    const int64_t tbase = (int64_t)(tile - C.t0) * TILE;
+
+#define CLOT_FOR_CELLS(local)                                        \
+    for (int q_ = 0; q_ < CPT; ++q_) {                               \
+        const int64_t local = tbase + (int64_t)q_ * NT + threadIdx.x; \
+        if (local >= C.ncell) break;
+
+#define CLOT_END_CELLS }
+
+// tol_mode 0: tolerance rtol^2 ||b||^2; 1: tolerance already in SC_TOL2.
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_cg_init(Grid G, Op op, KVec<T, K> V, KState S, double rtol, int tol_mode) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * 3 * K];
+    double acc[3 * K];
+#pragma unroll
+    for (int q = 0; q < 3 * K; ++q) acc[q] = 0.0;
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T* x = V.x[k];
+            const T ax = op.apply(k, C, P, [&](int64_t g) { return x[g]; });
+            const T b = V.b[k][P.g];
+            const T r = b - ax;
+            const T z = r / op.diag(k, P.g);
+            V.r[k][P.g] = r;
+            V.p[0][k][P.g] = z;
+            acc[3 * k + 0] += (double)r * (double)z;
+            acc[3 * k + 1] += (double)b * (double)b;
+            acc[3 * k + 2] += (double)r * (double)r;
+        }
+    CLOT_END_CELLS
+    double sums[3 * K];
+    if (channel_reduce<3 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
+        int any = 0;
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, chid, k);
+            s[SC_RZ] = sums[3 * k];
+            s[SC_BB] = sums[3 * k + 1];
+            s[SC_RR] = sums[3 * k + 2];
+            s[SC_RR0] = sums[3 * k + 2];
+            if (tol_mode == 0) s[SC_TOL2] = rtol * rtol * sums[3 * k + 1];
+            s[SC_BETA] = 0.0;
+            s[SC_IT] = 0.0;
+            s[SC_FAIL] = 0.0;
+            const bool act = s[SC_BB] > 0.0 && s[SC_RR] > s[SC_TOL2];
+            s[SC_ACT] = act ? 1.0 : 0.0;
+            any |= act;
+        }
+        S.chact[chid] = any;
+        if (any) atomicAdd(S.nact, 1);
+    }
+}
+
+// q = A p_new with p_new = z + beta p_old formed on the fly; alpha = rz / (p.q).
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_cg_a(Grid G, Op op, KVec<T, K> V, KState S, int par) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * K];
+    double acc[K];
+    double beta[K];
+    bool act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[k] = 0.0;
+        const double* s = scp(S, chid, k);
+        beta[k] = s[SC_BETA];
+        act[k] = s[SC_ACT] != 0.0;
+    }
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            const T* r = V.r[k];
+            const T* po = V.p[par][k];
+            const T bk = (T)beta[k];
+            // neighbours' new direction: z_N + beta p_N with z_N = r_N / diag_N
+            const T q = op.apply(k, C, P, [&](int64_t g) { return r[g] / op.diag(k, g) + bk * po[g]; });
+            const T pn = r[P.g] / op.diag(k, P.g) + bk * po[P.g];
+            V.p[par ^ 1][k][P.g] = pn;
+            V.t[k][P.g] = q;
+            acc[k] += (double)pn * (double)q;
+        }
+    CLOT_END_CELLS
+    double sums[K];
+    if (channel_reduce<K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, chid, k);
+            if (s[SC_ACT] == 0.0) continue;
+            s[SC_PQ] = sums[k];
+            if (!(sums[k] > 0.0) || !isfinite(sums[k])) {
+                s[SC_ALPHA] = 0.0;
+                s[SC_ACT] = 0.0;
+                s[SC_FAIL] = 1.0;
+            } else {
+                s[SC_ALPHA] = s[SC_RZ] / sums[k];
+            }
+        }
+    }
+}
+
+// x += alpha p; r -= alpha q; rz = r.z; convergence; beta for the next direction.
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_cg_b(Grid G, Op op, KVec<T, K> V, KState S, int par) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * 2 * K];
+    double acc[2 * K];
+    double alpha[K];
+    bool act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[2 * k] = acc[2 * k + 1] = 0.0;
+        const double* s = scp(S, chid, k);
+        alpha[k] = s[SC_ALPHA];
+        act[k] = s[SC_ACT] != 0.0;
+    }
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            const T a = (T)alpha[k];
+            const T pn = V.p[par ^ 1][k][P.g];
+            V.x[k][P.g] += a * pn;
+            const T r = V.r[k][P.g] - a * V.t[k][P.g];
+            V.r[k][P.g] = r;
+            const T z = r / op.diag(k, P.g);
+            acc[2 * k] += (double)r * (double)z;
+            acc[2 * k + 1] += (double)r * (double)r;
+        }
+    CLOT_END_CELLS
+    double sums[2 * K];
+    if (channel_reduce<2 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
+        int any = 0;
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, chid, k);
+            if (s[SC_ACT] != 0.0) {
+                const double rz = sums[2 * k];
+                s[SC_BETA] = s[SC_RZ] != 0.0 ? rz / s[SC_RZ] : 0.0;
+                s[SC_RZ] = rz;
+                s[SC_RR] = sums[2 * k + 1];
+                s[SC_IT] += 1.0;
+                if (s[SC_RR] <= s[SC_TOL2]) s[SC_ACT] = 0.0;
+                else if (s[SC_IT] >= S.maxit || !isfinite(s[SC_RR])) {
+                    s[SC_ACT] = 0.0;
+                    s[SC_FAIL] = 1.0;
+                }
+            }
+            any |= s[SC_ACT] != 0.0;
+        }
+        if (!any) {
+            S.chact[chid] = 0;
+            atomicSub(S.nact, 1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// BiCGStab
+// ------------------------------------------------------------------------------------
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, KState S, double rtol) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * 2 * K];
+    double acc[2 * K];
+#pragma unroll
+    for (int q = 0; q < 2 * K; ++q) acc[q] = 0.0;
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T* x = V.x[k];
+            const T ax = op.apply(k, C, P, [&](int64_t g) { return x[g]; });
+            const T b = V.b[k][P.g];
+            const T r = b - ax;
+            V.r[k][P.g] = r;
+            V.rh[k][P.g] = r;
+            V.p[0][k][P.g] = T(0);
+            V.v[0][k][P.g] = T(0);
+            acc[2 * k] += (double)b * (double)b;
+            acc[2 * k + 1] += (double)r * (double)r;
+        }
+    CLOT_END_CELLS
+    double sums[2 * K];
+    if (channel_reduce<2 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
+        int any = 0;
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, chid, k);
+            s[SC_BB] = sums[2 * k];
+            s[SC_RR] = sums[2 * k + 1];
+            s[SC_RR0] = sums[2 * k + 1];
+            s[SC_RHO] = sums[2 * k + 1];       // rhat . r with rhat = r
+            s[SC_TOL2] = rtol * rtol * sums[2 * k];
+            s[SC_ALPHA] = 1.0;
+            s[SC_OMEGA] = 1.0;
+            s[SC_BETA] = 0.0;
+            s[SC_IT] = 0.0;
+            s[SC_FAIL] = 0.0;
+            const bool act = s[SC_BB] > 0.0 && s[SC_RR] > s[SC_TOL2];
+            s[SC_ACT] = act ? 1.0 : 0.0;
+            any |= act;
+        }
+        S.chact[chid] = any;
+        if (any) atomicAdd(S.nact, 1);
+    }
+}
+
+// p_new = r + beta (p_old - omega v_old); v_new = A (p_new/diag); alpha = rho/(rhat.v_new)
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_bicg_1(Grid G, Op op, KVec<T, K> V, KState S, int par) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * K];
+    double acc[K];
+    double beta[K], omega[K];
+    bool act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[k] = 0.0;
+        const double* s = scp(S, chid, k);
+        beta[k] = s[SC_BETA];
+        omega[k] = s[SC_OMEGA];
+        act[k] = s[SC_ACT] != 0.0;
+    }
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            const T* r = V.r[k];
+            const T* po = V.p[par][k];
+            const T* vo = V.v[par][k];
+            const T bk = (T)beta[k], om = (T)omega[k];
+            const T vn = op.apply(k, C, P, [&](int64_t g) { return (r[g] + bk * (po[g] - om * vo[g])) / op.diag(k, g); });
+            const T pn = r[P.g] + bk * (po[P.g] - om * vo[P.g]);
+            V.p[par ^ 1][k][P.g] = pn;
+            V.v[par ^ 1][k][P.g] = vn;
+            acc[k] += (double)V.rh[k][P.g] * (double)vn;
+        }
+    CLOT_END_CELLS
+    double sums[K];
+    if (channel_reduce<K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, chid, k);
+            if (s[SC_ACT] == 0.0) continue;
+            if (sums[k] == 0.0 || !isfinite(sums[k])) {
+                s[SC_ACT] = 0.0;
+                s[SC_FAIL] = 1.0;
+                s[SC_ALPHA] = 0.0;
+            } else {
+                s[SC_ALPHA] = s[SC_RHO] / sums[k];
+            }
+        }
+    }
+}
+
+// s = r - alpha v; t = A (s/diag); omega = (t.s)/(t.t)
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_bicg_2(Grid G, Op op, KVec<T, K> V, KState S, int par) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * 2 * K];
+    double acc[2 * K];
+    double alpha[K];
+    bool act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[2 * k] = acc[2 * k + 1] = 0.0;
+        const double* s = scp(S, chid, k);
+        alpha[k] = s[SC_ALPHA];
+        act[k] = s[SC_ACT] != 0.0;
+    }
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            const T* r = V.r[k];
+            const T* vn = V.v[par ^ 1][k];
+            const T a = (T)alpha[k];
+            const T t = op.apply(k, C, P, [&](int64_t g) { return (r[g] - a * vn[g]) / op.diag(k, g); });
+            const T sv = r[P.g] - a * vn[P.g];
+            V.t[k][P.g] = t;
+            acc[2 * k] += (double)t * (double)sv;
+            acc[2 * k + 1] += (double)t * (double)t;
+        }
+    CLOT_END_CELLS
+    double sums[2 * K];
+    if (channel_reduce<2 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, chid, k);
+            if (s[SC_ACT] == 0.0) continue;
+            s[SC_TS] = sums[2 * k];
+            s[SC_TT] = sums[2 * k + 1];
+            s[SC_OMEGA] = sums[2 * k + 1] > 0.0 ? sums[2 * k] / sums[2 * k + 1] : 0.0;
+        }
+    }
+}
+
+// x += alpha p/diag + omega s/diag; r = s - omega t; rho_new = rhat.r; beta; convergence
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_bicg_3(Grid G, Op op, KVec<T, K> V, KState S, int par) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * 2 * K];
+    double acc[2 * K];
+    double alpha[K], omega[K];
+    bool act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[2 * k] = acc[2 * k + 1] = 0.0;
+        const double* s = scp(S, chid, k);
+        alpha[k] = s[SC_ALPHA];
+        omega[k] = s[SC_OMEGA];
+        act[k] = s[SC_ACT] != 0.0;
+    }
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            const T a = (T)alpha[k], om = (T)omega[k];
+            const T d = op.diag(k, P.g);
+            const T sv = V.r[k][P.g] - a * V.v[par ^ 1][k][P.g];
+            V.x[k][P.g] += (a * V.p[par ^ 1][k][P.g] + om * sv) / d;
+            const T r = sv - om * V.t[k][P.g];
+            V.r[k][P.g] = r;
+            acc[2 * k] += (double)V.rh[k][P.g] * (double)r;
+            acc[2 * k + 1] += (double)r * (double)r;
+        }
+    CLOT_END_CELLS
+    double sums[2 * K];
+    if (channel_reduce<2 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
+        int any = 0;
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, chid, k);
+            if (s[SC_ACT] != 0.0) {
+                const double rho = sums[2 * k];
+                s[SC_RR] = sums[2 * k + 1];
+                s[SC_IT] += 1.0;
+                const double om = s[SC_OMEGA];
+                if (s[SC_RR] <= s[SC_TOL2]) {
+                    s[SC_ACT] = 0.0;
+                } else if (s[SC_IT] >= S.maxit || !isfinite(s[SC_RR]) || om == 0.0 || rho == 0.0) {
+                    s[SC_ACT] = 0.0;
+                    s[SC_FAIL] = 1.0;
+                } else {
+                    s[SC_BETA] = (rho / s[SC_RHO]) * (s[SC_ALPHA] / om);
+                    s[SC_RHO] = rho;
+                }
+            }
+            any |= s[SC_ACT] != 0.0;
+        }
+        if (!any) {
+            S.chact[chid] = 0;
+            atomicSub(S.nact, 1);
+        }
+    }
+}
+
+}  // namespace clot

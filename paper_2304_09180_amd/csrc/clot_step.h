@@ -1,0 +1,550 @@
+// Per-cell kernels of one clotting time step (gfx950).  Each cites the part of the
+// model it computes; the Krylov solves between them live in clot_krylov.h.
+#pragma once
+#include "clot_krylov.h"
+
+namespace clot {
+
+// theta_B (section 2: bound platelets over P_max) and W(theta_T) (Appendix A).
+template <class T>
+__global__ __launch_bounds__(NT) void k_derive(Grid G, Fields<T> F, ModelDev M) {
+    CLOT_TILE_PROLOGUE(G)
+    CLOT_FOR_CELLS(local)
+        const int64_t g = C.c0 + local;
+        const T pmax = T(M.P_max);
+        const T pb = F.spc[PBA][g] + F.spc[PBSE][g];
+        const T tt = F.spc[PMU][g] + F.spc[PMA][g] + pb;
+        F.thB[g] = pb / pmax;
+        F.Wc[g] = hindrance_fn<T>(tt / pmax);
+    CLOT_END_CELLS
+}
+
+// Momentum predictor matrix diagonal and right-hand sides (section 3.2; Appendix D
+// schemes; Appendix C boundary table).  Implicit Euler, Gauss-linear convection
+// with the old flux, nu Laplacian, implicit Darcy nu alpha(theta_B) V with the
+// Carman-Kozeny alpha, Gauss-linear pressure gradient of the old pressure.
+template <class T>
+__global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelDev M) {
+    CLOT_TILE_PROLOGUE(G)
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const int64_t g = P.g;
+        const T V = T(C.V), rdt = T(1.0 / C.dt), nu = T(M.nu);
+        const T s = T(0.6) * F.thB[g];
+        const T om = T(1) - s;
+        const T alpha = T(M.C_CK) * s * s / (om * om * om);
+        T aP = V * rdt + nu * alpha * V;
+        T srcx = T(0);
+        // x faces: inlet (fixed value) at i = 0, outlet (zero gradient) at i = nx-1
+        const T dfx = nu * T(C.Ax / C.dx);
+        const T fw = F.phi[0][fx_id(C, P.i, P.j, P.k)];
+        const T fe = F.phi[0][fx_id(C, P.i + 1, P.j, P.k)];
+        if (P.i > 0) aP += T(-0.5) * fw + dfx;
+        else {
+            const T ub = F.u_in[C.in0 + P.j + (int64_t)C.ny * P.k];
+            aP += T(2) * dfx;
+            srcx += T(2) * dfx * ub + fw * ub;     // - (outward flux -fw) * u_b
+        }
+        if (P.i < C.nx - 1) aP += T(0.5) * fe + dfx;
+        else aP += fe;
+        // y faces: no-slip walls
+        const T dfy = nu * T(C.Ay / C.dy);
+        const T fs = F.phi[1][fy_id(C, P.i, P.j, P.k)];
+        const T fn = F.phi[1][fy_id(C, P.i, P.j + 1, P.k)];
+        aP += (P.j > 0) ? T(-0.5) * fs + dfy : T(2) * dfy;
+        aP += (P.j < C.ny - 1) ? T(0.5) * fn + dfy : T(2) * dfy;
+        if (C.dim == 3) {
+            const T dfz = nu * T(C.Az / C.dz);
+            const T fb = F.phi[2][fz_id(C, P.i, P.j, P.k)];
+            const T ff = F.phi[2][fz_id(C, P.i, P.j, P.k + 1)];
+            aP += (P.k > 0) ? T(-0.5) * fb + dfz : T(2) * dfz;
+            aP += (P.k < C.nz - 1) ? T(0.5) * ff + dfz : T(2) * dfz;
+        }
+        F.aP[g] = aP;
+        // Gauss-linear gradient of the old pressure (outlet face p_out, others p_P)
+        const double pP = F.p[g];
+        const double pw = P.i > 0 ? 0.5 * (F.p[g - 1] + pP) : pP;
+        const double pe = P.i < C.nx - 1 ? 0.5 * (F.p[g + 1] + pP) : M.p_out;
+        const double ps = P.j > 0 ? 0.5 * (F.p[g - C.nx] + pP) : pP;
+        const double pn = P.j < C.ny - 1 ? 0.5 * (F.p[g + C.nx] + pP) : pP;
+        const double gx = (pe - pw) / C.dx, gy = (pn - ps) / C.dy;
+        const T sx = V * rdt * F.u[0][g] + srcx;
+        const T sy = V * rdt * F.u[1][g];
+        F.src[0][g] = sx;
+        F.src[1][g] = sy;
+        F.bm[0][g] = T((double)sx - C.V * gx);
+        F.bm[1][g] = T((double)sy - C.V * gy);
+        if (C.dim == 3) {
+            const int64_t sz = (int64_t)C.nx * C.ny;
+            const double pb = P.k > 0 ? 0.5 * (F.p[g - sz] + pP) : pP;
+            const double pf = P.k < C.nz - 1 ? 0.5 * (F.p[g + sz] + pP) : pP;
+            const T sz_ = V * rdt * F.u[2][g];
+            F.src[2][g] = sz_;
+            F.bm[2][g] = T((double)sz_ - C.V * (pf - pb) / C.dz);
+        } else {
+            F.src[2][g] = T(0);
+            F.bm[2][g] = T(0);
+        }
+    CLOT_END_CELLS
+}
+
+// PISO: H = src - sum a_N u_N with the latest u; HbyA = H / aP; rAU = V / aP.
+template <class T>
+__global__ __launch_bounds__(NT) void k_hbya(Grid G, Fields<T> F, MomOp<T> op, const int32_t* mask) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!mask[chid]) return;
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const T aP = F.aP[P.g];
+        for (int c = 0; c < C.dim; ++c) {
+            const T* u = F.u[c];
+            const T off = op.offsum(C, P, [&](int64_t g) { return u[g]; });
+            F.HbyA[c][P.g] = (F.src[c][P.g] - off) / aP;
+        }
+        if (C.dim == 2) F.HbyA[2][P.g] = T(0);
+        F.rAU[P.g] = T(C.V) / aP;
+    CLOT_END_CELLS
+}
+
+// Face flux of HbyA (Gauss linear; inlet: fixed u, walls: 0, outlet: HbyA_P).
+template <class T>
+__device__ inline double phiH_x(const ChanDev& C, const Fields<T>& F, const Cell& P, int iface) {
+    // x-face iface of row (j,k); iface in [0, nx]
+    const int64_t row = C.c0 + (int64_t)C.nx * (P.j + (int64_t)C.ny * P.k);
+    if (iface == 0) return C.Ax * (double)F.u_in[C.in0 + P.j + (int64_t)C.ny * P.k];
+    if (iface == C.nx) return C.Ax * (double)F.HbyA[0][row + C.nx - 1];
+    return 0.5 * C.Ax * ((double)F.HbyA[0][row + iface - 1] + (double)F.HbyA[0][row + iface]);
+}
+
+// Pressure system: rhs = -sum_f(outward phiHbyA) + c_out p_out, diagonal dP.
+template <class T>
+__global__ __launch_bounds__(NT) void k_prhs(Grid G, Fields<T> F, ModelDev M, const int32_t* mask) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!mask[chid]) return;
+    PresOp<T, double> op{F.rAU, F.dP};
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const int64_t g = P.g;
+        double div = phiH_x(C, F, P, P.i + 1) - phiH_x(C, F, P, P.i);
+        const double hy = (double)F.HbyA[1][g];
+        if (P.j < C.ny - 1) div += 0.5 * C.Ay * (hy + (double)F.HbyA[1][g + C.nx]);
+        if (P.j > 0) div -= 0.5 * C.Ay * (hy + (double)F.HbyA[1][g - C.nx]);
+        if (C.dim == 3) {
+            const int64_t sz = (int64_t)C.nx * C.ny;
+            const double hz = (double)F.HbyA[2][g];
+            if (P.k < C.nz - 1) div += 0.5 * C.Az * (hz + (double)F.HbyA[2][g + sz]);
+            if (P.k > 0) div -= 0.5 * C.Az * (hz + (double)F.HbyA[2][g - sz]);
+        }
+        double rhs = -div;
+        if (P.i == C.nx - 1) rhs += 2.0 * C.Ax / C.dx * (double)F.rAU[g] * M.p_out;
+        F.rhs_p[g] = rhs;
+        F.dP[g] = T(op.diag_exact(C, P));
+    CLOT_END_CELLS
+}
+
+// FP64 residual of the pressure system r = rhs - K p; stores r in the inner
+// right-hand side (arithmetic type T); sums ||r||^2 and ||rhs||^2 per channel and
+// decides on the device whether the channel needs another refinement pass.
+template <class T>
+__global__ __launch_bounds__(NT) void k_pres_resid(Grid G, Fields<T> F, T* rin, T* ein, KState S, double rtol,
+                                                   double rtol_inner, int pass, int32_t* refmask) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * 2];
+    PresOp<T, double> op{F.rAU, F.dP};
+    double acc[2] = {0.0, 0.0};
+    const double* p = F.p;
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const double kp = op.diag_exact(C, P) * p[P.g] - op.offsum(C, P, [&](int64_t g) { return p[g]; });
+        const double b = F.rhs_p[P.g];
+        const double r = b - kp;
+        rin[P.g] = T(r);
+        ein[P.g] = T(0);
+        acc[0] += r * r;
+        acc[1] += b * b;
+    CLOT_END_CELLS
+    double sums[2];
+    if (channel_reduce<2>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
+        double* s = scp(S, chid, 0);
+        // outer record: slot SC_RR0 keeps ||r|| of this pass for the stats
+        s[SC_RR0] = sums[0];
+        s[SC_BB] = sums[1];
+        const double target2 = rtol * rtol * sums[1];
+        if (sums[0] <= target2 || sums[1] == 0.0 || !isfinite(sums[0])) {
+            S.chact[chid] = 0;
+            refmask[chid] = 0;
+            atomicSub(S.nact, 1);
+            s[SC_ACT] = 0.0;
+            if (!isfinite(sums[0])) s[SC_FAIL] = 1.0;
+        } else {
+            // inner solve target: a fraction of this residual, not below the outer goal
+            const double inner2 = rtol_inner * rtol_inner * sums[0];
+            s[SC_TOL2] = inner2 > 0.25 * target2 ? inner2 : 0.25 * target2;
+            s[SC_ACT] = 1.0;
+            s[SC_PASS] = (double)(pass + 1);
+            refmask[chid] = 1;
+        }
+    }
+}
+
+// p += e (FP64 accumulation of the inner correction).
+template <class T>
+__global__ __launch_bounds__(NT) void k_pres_add(Grid G, Fields<T> F, const T* e, const int32_t* chmask) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!chmask[chid]) return;
+    CLOT_FOR_CELLS(local)
+        const int64_t g = C.c0 + local;
+        F.p[g] += (double)e[g];
+    CLOT_END_CELLS
+}
+
+// PISO flux and velocity correction: phi = phiHbyA - rAU_f (A/d)(p_N - p_P) on the
+// faces each cell owns (its low faces, plus the high boundary faces), and
+// u = HbyA - rAU (grad p)_P with the Gauss-linear gradient.
+template <class T>
+__global__ __launch_bounds__(NT) void k_correct(Grid G, Fields<T> F, ModelDev M, const int32_t* mask) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!mask[chid]) return;
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const int64_t g = P.g;
+        const double* p = F.p;
+        const double pP = p[g];
+        const double rP = (double)F.rAU[g];
+        // x faces
+        {
+            double f = phiH_x(C, F, P, P.i);
+            if (P.i > 0) f -= 0.5 * (rP + (double)F.rAU[g - 1]) * C.Ax / C.dx * (pP - p[g - 1]);
+            F.phin[0][fx_id(C, P.i, P.j, P.k)] = T(f);
+            if (P.i == C.nx - 1) {
+                double fo = phiH_x(C, F, P, C.nx) - rP * 2.0 * C.Ax / C.dx * (M.p_out - pP);
+                F.phin[0][fx_id(C, C.nx, P.j, P.k)] = T(fo);
+            }
+        }
+        // y faces (walls carry no flux)
+        {
+            double f = 0.0;
+            if (P.j > 0)
+                f = 0.5 * C.Ay * ((double)F.HbyA[1][g - C.nx] + (double)F.HbyA[1][g]) -
+                    0.5 * (rP + (double)F.rAU[g - C.nx]) * C.Ay / C.dy * (pP - p[g - C.nx]);
+            F.phin[1][fy_id(C, P.i, P.j, P.k)] = T(f);
+            if (P.j == C.ny - 1) F.phin[1][fy_id(C, P.i, C.ny, P.k)] = T(0);
+        }
+        if (C.dim == 3) {
+            const int64_t sz = (int64_t)C.nx * C.ny;
+            double f = 0.0;
+            if (P.k > 0)
+                f = 0.5 * C.Az * ((double)F.HbyA[2][g - sz] + (double)F.HbyA[2][g]) -
+                    0.5 * (rP + (double)F.rAU[g - sz]) * C.Az / C.dz * (pP - p[g - sz]);
+            F.phin[2][fz_id(C, P.i, P.j, P.k)] = T(f);
+            if (P.k == C.nz - 1) F.phin[2][fz_id(C, P.i, P.j, C.nz)] = T(0);
+        }
+        // velocity
+        const double pw = P.i > 0 ? 0.5 * (p[g - 1] + pP) : pP;
+        const double pe = P.i < C.nx - 1 ? 0.5 * (p[g + 1] + pP) : M.p_out;
+        const double ps = P.j > 0 ? 0.5 * (p[g - C.nx] + pP) : pP;
+        const double pn = P.j < C.ny - 1 ? 0.5 * (p[g + C.nx] + pP) : pP;
+        F.u[0][g] = T((double)F.HbyA[0][g] - rP * (pe - pw) / C.dx);
+        F.u[1][g] = T((double)F.HbyA[1][g] - rP * (pn - ps) / C.dy);
+        if (C.dim == 3) {
+            const int64_t sz = (int64_t)C.nx * C.ny;
+            const double pb = P.k > 0 ? 0.5 * (p[g - sz] + pP) : pP;
+            const double pf = P.k < C.nz - 1 ? 0.5 * (p[g + sz] + pP) : pP;
+            F.u[2][g] = T((double)F.HbyA[2][g] - rP * (pf - pb) / C.dz);
+        }
+    CLOT_END_CELLS
+}
+
+// eta right-hand side V theta_B (Appendix A, eq. eta) and its stored diagonal.
+template <class T>
+__global__ __launch_bounds__(NT) void k_eta_prep(Grid G, Fields<T> F, ModelDev M, T* rhs) {
+    CLOT_TILE_PROLOGUE(G)
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        rhs[P.g] = T(C.V) * F.thB[P.g];
+        F.dE[P.g] = EtaOp<T>::diag_of(T(M.kappa_eta), C, P);
+    CLOT_END_CELLS
+}
+
+// Release history push and trapezoid (section 3.2, eq. sigma_disc): when channel ch
+// pushes at this step, hist[slot] = Pmax (theta_B^n - theta_B^{n-1}) / dt (zero at
+// the first step) and sigma = sum_k w_k hist[k] with the per-channel weights
+// w_k = A_hat * trapezoid weight * R(age_k) computed on the host.
+template <class T>
+__global__ __launch_bounds__(NT) void k_sigma(Grid G, Fields<T> F, ModelDev M, const double* w, const int32_t* push) {
+    CLOT_TILE_PROLOGUE(G)
+    const int32_t slot = push[2 * chid];
+    if (slot < 0) return;
+    const int first = push[2 * chid + 1];
+    const double* wc = w + (int64_t)chid * NHIST;
+    CLOT_FOR_CELLS(local)
+        const int64_t g = C.c0 + local;
+        const T f = first ? T(0) : T(M.P_max) * (F.thB[g] - F.thB_prev[g]) / T(C.dt);
+        F.hist[(int64_t)slot * F.ncell + g] = f;
+        double s = 0.0;
+        for (int k = 0; k < NHIST; ++k) s += wc[k] * (double)F.hist[(int64_t)k * F.ncell + g];
+        F.sigma[g] = T(s);
+    CLOT_END_CELLS
+}
+
+// Transport assembly (section 3.2, Appendix C table, Appendix D): diagonal and
+// right-hand side of the 7 implicit TVD transport systems; initial guess C^n.
+template <class T>
+__global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T> op, ModelDev M) {
+    CLOT_TILE_PROLOGUE(G)
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const int64_t g = P.g;
+        const T V = T(C.V), rdt = T(1.0 / C.dt);
+        const T Wp = F.Wc[g];
+        const bool inj = P.j == 0 && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
+                         P.k < C.inj_k0 + C.inj_nk;
+        const int64_t fi = C.inj0 + (P.i - C.inj_i0) + (int64_t)C.inj_ni * (P.k - C.inj_k0);
+        const T fin = F.phin[0][fx_id(C, 0, P.j, P.k)];
+        const T fout = F.phin[0][fx_id(C, C.nx, P.j, P.k)];
+        for (int k = 0; k < NTR; ++k) {
+            const int sp = tr_species(k);
+            const bool plt = k < 2;
+            const T* c = op.Cn[k];
+            const T D = op.Dk[k];
+            const T cn = c[g];
+            T d = V * rdt;
+            T b = V * rdt * cn;
+            if (sp == ADP) b += V * F.sigma[g];
+            T ad = T(C.Ax / C.dx);
+            if (P.i < C.nx - 1)
+                d += tr_face(c, F.Wc, plt, D, ad, g, 1, P.i, C.nx, F.phin[0][fx_id(C, P.i + 1, P.j, P.k)], op.Pmax).dL;
+            if (P.i > 0)
+                d += tr_face(c, F.Wc, plt, D, ad, g - 1, 1, P.i - 1, C.nx, F.phin[0][fx_id(C, P.i, P.j, P.k)], op.Pmax).dR;
+            ad = T(C.Ay / C.dy);
+            if (P.j < C.ny - 1)
+                d += tr_face(c, F.Wc, plt, D, ad, g, C.nx, P.j, C.ny, F.phin[1][fy_id(C, P.i, P.j + 1, P.k)], op.Pmax).dL;
+            if (P.j > 0)
+                d += tr_face(c, F.Wc, plt, D, ad, g - C.nx, C.nx, P.j - 1, C.ny, F.phin[1][fy_id(C, P.i, P.j, P.k)], op.Pmax).dR;
+            if (C.dim == 3) {
+                const int64_t sz = (int64_t)C.nx * C.ny;
+                ad = T(C.Az / C.dz);
+                if (P.k < C.nz - 1)
+                    d += tr_face(c, F.Wc, plt, D, ad, g, sz, P.k, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k + 1)], op.Pmax).dL;
+                if (P.k > 0)
+                    d += tr_face(c, F.Wc, plt, D, ad, g - sz, sz, P.k - 1, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k)], op.Pmax).dR;
+            }
+            const T W = plt ? Wp : T(1);
+            if (P.i == 0) {
+                const T fo = -fin;       // outward flux through the inlet face
+                const bool fixed = (sp == PMU || sp == S1 || sp == S2);
+                if (fixed) {
+                    const T cb = sp == PMU ? F.pmu_in[C.in0 + P.j + (int64_t)C.ny * P.k] : (sp == S1 ? T(M.S1_0) : T(M.S2_0));
+                    const T gg = T(2) * W * D * T(C.Ax / C.dx);
+                    d += gg;
+                    b += gg * cb - W * fo * cb;
+                } else {
+                    d += W * fo;
+                }
+            }
+            if (P.i == C.nx - 1) d += W * fout;
+            if (inj) {
+                const T A = T(C.dx * C.dz);
+                if (sp == E1) b += A * T(M.kC0cat) * F.C0[fi];
+                if (sp == S1) {
+                    const T kk = T(M.kC0p) * F.E0[fi], qq = T(M.kC0m) * F.C0[fi];
+                    const T gg = T(M.D_chem) / (T(0.5) * T(C.dy));
+                    d += A * kk * gg / (gg + kk);
+                    b += A * qq * gg / (gg + kk);
+                }
+            }
+            F.trd[k][g] = d;
+            F.trb[k][g] = b;
+            F.xt[k][g] = cn;
+        }
+    CLOT_END_CELLS
+}
+
+// Reaction right-hand side (Appendix A platelet equations, Appendix B coagulation
+// equations), y in the order Pmu Pma Pba Pbse S1 S2 E1 E2 S1b S2b E1b E2b C1 C2.
+template <class T>
+__device__ inline void rxn_rhs(const T (&y)[NRX], T adp, T gam, T hadh, const ModelDev& M, T (&f)[NRX]) {
+    const T pmax = T(M.P_max);
+    const T adh = T(M.k_adh) * hadh * (pmax - y[3]);
+    const T act = T(M.k_adp) * adp / (T(M.adp_crit) + adp) + T(M.k_e2) * y[7] / (T(M.e2_crit) + y[7]);
+    const T coh = T(M.kcoh_Pmax) * gam;
+    const T bound = y[2] + y[3];
+    const T B1 = T(M.N1 / M.N_A) * bound - (y[8] + y[10] + y[12] + y[13]);
+    const T B2 = T(M.N2 / M.N_A) * bound - (y[9] + y[11] + y[12] + y[13]);
+    const T c1 = T(M.kC1p) * y[9] * y[10];
+    const T c2 = T(M.kC2p) * y[8] * y[11];
+    const T bS1 = T(M.kS1p) * B1 * y[4] - T(M.kS1m) * y[8];
+    const T bS2 = T(M.kS2p) * B2 * y[5] - T(M.kS2m) * y[9];
+    const T bE1 = T(M.kE1p) * B1 * y[6] - T(M.kE1m) * y[10];
+    const T bE2 = T(M.kE2p) * B2 * y[7] - T(M.kE2m) * y[11];
+    f[0] = -(adh + act) * y[0];
+    f[1] = -adh * y[1] + act * y[0] - coh * y[1];
+    f[2] = -adh * y[2] + coh * y[1];
+    f[3] = adh * (y[0] + y[1] + y[2]);
+    f[4] = -bS1;
+    f[5] = -bS2;
+    f[6] = -bE1;
+    f[7] = -bE2;
+    f[8] = bS1 - c2 + T(M.kC2m) * y[13];
+    f[9] = bS2 - c1 + T(M.kC1m) * y[12];
+    f[10] = bE1 - c1 + T(M.kC1m + M.kC1cat) * y[12] + T(M.kC2cat) * y[13];
+    f[11] = bE2 - c2 + T(M.kC2m + M.kC2cat) * y[13] + T(M.kC1cat) * y[12];
+    f[12] = c1 - T(M.kC1m + M.kC1cat) * y[12];
+    f[13] = c2 - T(M.kC2m + M.kC2cat) * y[13];
+}
+
+template <class T>
+__device__ inline T binding_g(T eta, const ModelDev& M) {
+    const T e = eta - T(M.eta_t);
+    if (!(e > T(0))) return T(0);
+    const T e3 = e * e * e, s3 = T(M.eta_star * M.eta_star * M.eta_star);
+    return T(M.g0) * e3 / (s3 + e3);
+}
+
+// Reactive wall: S1 wall value from the Robin balance with the transported S1,
+// then M_rxn RK4 sub-steps of eqs. seBound_E0/C0 per injury face (Appendix B).
+template <class T>
+__global__ __launch_bounds__(NT) void k_wall_rxn(const ChanDev* chans, const int32_t* f2c, int64_t nfaces, Fields<T> F,
+                                                 ModelDev M) {
+    const int64_t f = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (f >= nfaces) return;
+    const ChanDev& C = chans[f2c[f]];
+    const int64_t lf = f - C.inj0;
+    const int i = C.inj_i0 + (int)(lf % C.inj_ni);
+    const int k = C.inj_k0 + (int)(lf / C.inj_ni);
+    const int64_t g = C.c0 + i + (int64_t)C.nx * C.ny * k;
+    T E0 = F.E0[f], C0 = F.C0[f];
+    const T kk = T(M.kC0p) * E0, qq = T(M.kC0m) * C0;
+    const T gg = T(M.D_chem) / (T(0.5) * T(C.dy));
+    const T s1w = (qq + gg * F.xt[2][g]) / (gg + kk);
+    F.s1w[f] = s1w;
+    const T h = T(C.dt / M.M_rxn);
+    const T kf = T(M.kC0p) * s1w, kb = T(M.kC0m + M.kC0cat);
+    for (int m = 0; m < M.M_rxn; ++m) {
+        auto rate = [&](T e, T c) { return kf * e - kb * c; };   // d C0/dt = -d E0/dt
+        const T r1 = rate(E0, C0);
+        const T r2 = rate(E0 - T(0.5) * h * r1, C0 + T(0.5) * h * r1);
+        const T r3 = rate(E0 - T(0.5) * h * r2, C0 + T(0.5) * h * r2);
+        const T r4 = rate(E0 - h * r3, C0 + h * r3);
+        const T inc = h / T(6) * (r1 + T(2) * r2 + T(2) * r3 + r4);
+        E0 -= inc;
+        C0 += inc;
+    }
+    F.E0[f] = E0;
+    F.C0[f] = C0;
+}
+
+// Cell reactions: M_rxn classical RK4 sub-steps (section 3.2) with ADP (post
+// transport), g(eta) and H_adh frozen.  Reads the transported species from xt and
+// the bound ones in place, writes all species back.
+template <class T>
+__global__ __launch_bounds__(NT) void k_rxn(Grid G, Fields<T> F, ModelDev M) {
+    CLOT_TILE_PROLOGUE(G)
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const int64_t g = P.g;
+        T y[NRX];
+        y[0] = F.xt[0][g];
+        y[1] = F.xt[1][g];
+        y[2] = F.spc[PBA][g];
+        y[3] = F.spc[PBSE][g];
+        y[4] = F.xt[2][g];
+        y[5] = F.xt[3][g];
+        y[6] = F.xt[4][g];
+        y[7] = F.xt[5][g];
+        y[8] = F.spc[S1B][g];
+        y[9] = F.spc[S2B][g];
+        y[10] = F.spc[E1B][g];
+        y[11] = F.spc[E2B][g];
+        y[12] = F.spc[C1][g];
+        y[13] = F.spc[C2][g];
+        const T adp = F.xt[6][g];
+        const T gam = binding_g<T>(F.eta[g], M);
+        const bool hin = P.j < C.jadh && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
+                         P.k < C.inj_k0 + C.inj_nk;
+        const T hadh = hin ? T(1) : T(0);
+        const T h = T(C.dt / M.M_rxn);
+        for (int m = 0; m < M.M_rxn; ++m) {
+            T k1[NRX], k2[NRX], k3[NRX], k4[NRX], w[NRX];
+            rxn_rhs(y, adp, gam, hadh, M, k1);
+#pragma unroll
+            for (int q = 0; q < NRX; ++q) w[q] = y[q] + T(0.5) * h * k1[q];
+            rxn_rhs(w, adp, gam, hadh, M, k2);
+#pragma unroll
+            for (int q = 0; q < NRX; ++q) w[q] = y[q] + T(0.5) * h * k2[q];
+            rxn_rhs(w, adp, gam, hadh, M, k3);
+#pragma unroll
+            for (int q = 0; q < NRX; ++q) w[q] = y[q] + h * k3[q];
+            rxn_rhs(w, adp, gam, hadh, M, k4);
+#pragma unroll
+            for (int q = 0; q < NRX; ++q) y[q] += h / T(6) * (k1[q] + T(2) * k2[q] + T(2) * k3[q] + k4[q]);
+        }
+        F.spc[PMU][g] = y[0];
+        F.spc[PMA][g] = y[1];
+        F.spc[PBA][g] = y[2];
+        F.spc[PBSE][g] = y[3];
+        F.spc[S1][g] = y[4];
+        F.spc[S2][g] = y[5];
+        F.spc[E1][g] = y[6];
+        F.spc[E2][g] = y[7];
+        F.spc[S1B][g] = y[8];
+        F.spc[S2B][g] = y[9];
+        F.spc[E1B][g] = y[10];
+        F.spc[E2B][g] = y[11];
+        F.spc[C1][g] = y[12];
+        F.spc[C2][g] = y[13];
+        F.spc[ADP][g] = adp;
+    CLOT_END_CELLS
+}
+
+// Driver bookkeeping kernels (graph-safe replacements for memset and host reads).
+__global__ void k_count_active(const int32_t* chact, int32_t* nact, int nch) {
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int c = 0; c < nch; ++c) s += chact[c] != 0;
+        *nact = s;
+    }
+}
+
+// Copies Krylov outcomes of the last solve into the per-channel statistics.
+__global__ void k_record(const double* sc, double* stats, int nstat, int nch, int K, int slot_it, int slot_res,
+                         int slot_fail, int add) {
+    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+        double it = 0.0, res = 0.0, fail = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double* s = sc + ((int64_t)c * MAXK + k) * NSC;
+            it = fmax(it, s[SC_IT]);
+            if (s[SC_BB] > 0.0) res = fmax(res, sqrt(s[SC_RR] / s[SC_BB]));
+            fail = fmax(fail, s[SC_FAIL]);
+        }
+        double* st = stats + (int64_t)c * nstat;
+        st[slot_it] = add ? st[slot_it] + it : it;
+        if (slot_res >= 0) st[slot_res] = res;
+        st[slot_fail] = fmax(st[slot_fail], fail);
+    }
+}
+
+__global__ void k_record_pass(const double* sc, double* stats, int nstat, int nch, int slot, int slot_res,
+                              int slot_fail) {
+    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+        const double* s = sc + (int64_t)c * MAXK * NSC;
+        stats[(int64_t)c * nstat + slot] = s[SC_PASS];
+        if (s[SC_BB] > 0.0) stats[(int64_t)c * nstat + slot_res] = sqrt(s[SC_RR0] / s[SC_BB]);
+        stats[(int64_t)c * nstat + slot_fail] = fmax(stats[(int64_t)c * nstat + slot_fail], s[SC_FAIL]);
+    }
+}
+
+// Small utility kernels (graph-safe replacements for memset).
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <class T>
+__global__ void k_copy(T* dst, const T* src, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+}  // namespace clot

@@ -1,0 +1,110 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import clot_inputs as ci
+
+pytestmark = pytest.mark.gpu
+
+# Scales for the relative-l2 floor of fields that stay near zero: err = ||a-b|| / max(||b||, 1e-12 s sqrt(N)).
+SCALE = {"UX": 62.5, "UY": 62.5, "UZ": 62.5, "P": 2e4, "PMU": 2.5e5, "PMA": 2.5e5, "PBA": 6.67e7, "PBSE": 6.67e7,
+         "ADP": 2e-3, "S1": 1.7e-4, "S2": 1.4e-3, "E1": 1.7e-4, "E2": 1.4e-3, "S1B": 1.7e-4, "S2B": 1.4e-3,
+         "E1B": 1.7e-4, "E2B": 1.4e-3, "C1": 1.4e-3, "C2": 1.4e-3, "E0": 1.5e-7, "C0": 1.5e-7, "ETA": 1.0,
+         "SIGMA": 1.0, "PHIX": 1e-2, "PHIY": 1e-2, "PHIZ": 1e-2}
+
+
+def rel_l2(a, b, name):
+    floor = 1e-12 * SCALE[name] * np.sqrt(max(b.size, 1))
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), floor)
+
+
+def run_gpu(descs, precision, steps, params=None):
+    from paper_2304_09180_amd import clot
+    s = clot.Solver(descs, precision, params)
+    for i, d in enumerate(descs):
+        xc, xf = ci.noise(d)
+        s.init_state(i, xc, xf)
+    s.step(steps)
+    out = [s.fields(i) for i in range(len(descs))]
+    st = [s.stats(i) for i in range(len(descs))]
+    s.close()
+    return out, st
+
+
+def run_oracle(d, steps):
+    from oracle import clot_oracle as oc
+    xc, xf = ci.noise(d)
+    o = oc.Oracle(d, xc, xf)
+    for _ in range(steps):
+        o.step()
+    return o.fields()
+
+
+def compare(gpu, ref, tol, names=None):
+    worst = {}
+    for n in (names or ref.keys()):
+        if n not in gpu:
+            continue
+        worst[n] = rel_l2(gpu[n], ref[n], n)
+    bad = {k: v for k, v in worst.items() if not v <= tol}
+    print({k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+    assert not bad, bad
+
+
+def velocity_err(gpu, ref, dim):
+    comps = ["UX", "UY"] + (["UZ"] if dim == 3 else [])
+    a = np.concatenate([gpu[c] for c in comps])
+    b = np.concatenate([ref[c] for c in comps])
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("shape", [(40, 12), (72, 20)])
+def test_fp64_2d_ragged_few_steps(shape):
+    from paper_2304_09180_amd import clot
+    d = ci.channel(2, shape[0], shape[1], shear=1000.0, dt=1e-4, steps=5, seed=3)
+    (g,), (st,) = run_gpu([d], clot.FP64, 5)
+    print(st, flush=True)
+    ref = run_oracle(d, 5)
+    compare(g, ref, 1e-10)
+
+
+def test_fp64_3d_ragged_few_steps():
+    from paper_2304_09180_amd import clot
+    d = ci.channel(3, 24, 10, 9, shear=800.0, steps=4, seed=5)
+    (g,), (st,) = run_gpu([d], clot.FP64, 4)
+    print(st, flush=True)
+    ref = run_oracle(d, 4)
+    compare(g, ref, 1e-10)
+
+
+def test_fp64_channel2d_64x16_100_steps():
+    from paper_2304_09180_amd import clot
+    d = ci.workload("channel2d_64x16")
+    (g,), (st,) = run_gpu([d], clot.FP64, d["steps"])
+    print(st, flush=True)
+    ref = run_oracle(d, d["steps"])
+    assert velocity_err(g, ref, 2) < 1e-10
+    compare(g, ref, 1e-10)
+
+
+def test_fp32_mixed_2d_50_steps():
+    from paper_2304_09180_amd import clot
+    d = ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, steps=50, seed=4)
+    (g,), (st,) = run_gpu([d], clot.FP32_MIXED, 50)
+    print(st, flush=True)
+    ref = run_oracle(d, 50)
+    assert velocity_err(g, ref, 2) < 1e-5
+    compare(g, ref, 1e-5, names=["PMU", "PMA", "PBA", "PBSE", "ADP", "S1", "S2", "E1", "E2", "S1B", "S2B", "E1B",
+                                 "E2B", "C1", "C2", "E0", "C0"])
+
+
+def test_fp64_batched_uneven_channels_match_single_runs():
+    from paper_2304_09180_amd import clot
+    ds = [ci.channel(2, 32, 8, shear=300.0, steps=3, seed=11, inj_frac=0.3),
+          ci.channel(2, 48, 12, shear=1500.0, steps=3, seed=12, inj_frac=0.15),
+          ci.channel(2, 64, 16, shear=700.0, steps=3, seed=13, inj_frac=0.45)]
+    gs, sts = run_gpu(ds, clot.FP64, 3)
+    for d, g in zip(ds, gs):
+        # each channel keeps its own dt; run the oracle with that channel alone
+        ref = run_oracle(d, 3)
+        compare(g, ref, 1e-10)
