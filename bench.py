@@ -1,0 +1,146 @@
+"""Throughput benchmark of the clotting step on one MI355X.
+
+Prints ONE JSON line: cell-timesteps/s of whole steps of the workload (inputs
+resident in HBM), the roofline of the dominant kernel measured live with HIP
+events on the library's stream, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision fp32|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+
+# Algorithmic bytes per cell for each timed phase (compulsory reads + writes of one
+# launch, stencil neighbours counted once), FP32 storage (x2 for FP64).
+#   p_cg_a : r, p_old, diag, rAU read; p_new, q written            -> 6 arrays
+#   p_cg_b : x, p_new, r, q, diag read; x, r written                -> 7 arrays
+#   tr_b1  : per system r, p_old, v_old, diag, rhat, C^n read; p, v written (8)
+#            plus the shared face fluxes (dim arrays) and W(theta_T)
+#   tr_b2  : per system r, v, diag, C^n read; t written (5) + fluxes + W
+#   tr_b3  : per system x, r, rhat, p, v, t, diag read; x, r written (9)
+#   rxn    : 14 species + ADP + eta read; 15 species written (31)
+ARRAYS = {"p_cg_a": lambda dim: 6, "p_cg_b": lambda dim: 7,
+          "tr_b1": lambda dim: 7 * 8 + dim + 1, "tr_b2": lambda dim: 7 * 5 + dim + 1,
+          "tr_b3": lambda dim: 7 * 9, "rxn": lambda dim: 31,
+          "mom_b1": lambda dim: dim * 7 + 1 + dim, "mom_b2": lambda dim: dim * 4 + 1 + dim,
+          "mom_b3": lambda dim: dim * 9 + 1}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="channel3d_256x64x64")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--probe", default="p_cg_a", help="kernel phase timed for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(desc):
+    """FP64 oracle on a bounded sample: the same channel geometry, shear and seed on a
+    grid 4x coarser per axis, 2 steps; reported as cell-timesteps/s."""
+    import numpy as np
+    import clot_inputs as ci
+    from oracle import clot_oracle as oc
+    d = dict(desc)
+    fac = 4
+    d["nx"] = max(8, desc["nx"] // fac)
+    d["ny"] = max(4, desc["ny"] // fac)
+    if desc["dim"] == 3:
+        d["nz"] = max(4, desc["nz"] // fac)
+    d["dt"] = desc["dt"]
+    xc, xf = ci.noise(d)
+    o = oc.Oracle(d, xc, xf)
+    o.step()                        # first step outside the timing (imports, caches)
+    n = 2
+    t0 = time.perf_counter()
+    for _ in range(n):
+        o.step()
+    el = time.perf_counter() - t0
+    cells = d["nx"] * d["ny"] * d["nz"]
+    return {"value": cells * n / el, "unit": "cell-timesteps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} steps of the same channel at {d['nx']}x{d['ny']}x{d['nz']} cells "
+                      f"(4x coarser per axis), FP64 scipy sparse direct solves, single thread",
+            "seconds": el}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
+                                   "this build (see the design notes on slab decomposition)"}))
+        sys.exit(2)
+    import torch
+    import clot_inputs as ci
+    from paper_2304_09180_amd import clot
+
+    desc = ci.workload(args.workload)
+    prec = clot.FP32_MIXED if args.precision == "fp32" else clot.FP64
+    s = clot.Solver([desc], prec)
+    xc, xf = ci.noise(desc)
+    s.init_state(0, xc, xf)
+    ncell = desc["nx"] * desc["ny"] * desc["nz"]
+    print(f"# workload {args.workload}: {ncell} cells, dt {desc['dt']:.3e}, shear {desc['shear']:.1f}", file=sys.stderr,
+          flush=True)
+    for w in range(args.warmup):
+        s.step(1)
+        print(f"# warmup step {w + 1}/{args.warmup} {s.stats(0)}", file=sys.stderr, flush=True)
+
+    stream = s.stream
+    s.probe(args.probe)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step_async(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    probe_ms, probe_n = s.probe_read()
+    s.probe(None)
+    st = s.stats(0)
+    print(f"# timed {args.steps} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms) {st}", file=sys.stderr, flush=True)
+
+    el = max(ms / 1e3, wall)
+    value = ncell * args.steps / el
+    bpe = 4 if prec == clot.FP32_MIXED else 8
+    nbytes = ARRAYS[args.probe](desc["dim"]) * bpe * ncell
+    roof = None
+    if probe_n:
+        avg_s = probe_ms / 1e3 / probe_n
+        achieved = nbytes / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": args.probe, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 3), "launches": probe_n}
+    out = {"metric": "cell-timesteps/s", "value": value, "unit": "cell-timesteps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if prec == clot.FP32_MIXED else "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "cells": ncell, "dim": desc["dim"],
+                      "grid": [desc["nx"], desc["ny"], desc["nz"]], "dt": desc["dt"], "shear": desc["shear"],
+                      "precision": "fp32 fields, fp64 reductions and pressure" if prec == clot.FP32_MIXED else "fp64",
+                      "reaction": "plain RK4"},
+           "solver": {k: st[k] for k in ("it_mom", "it_p", "it_eta", "it_tr", "refine_p")},
+           "roofline": roof}
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(desc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

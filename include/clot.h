@@ -153,6 +153,35 @@ clot_status clot_get_stats(const clot_ctx* c, int32_t ch, clot_stats* s);
 clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* mlp_blob, size_t blob_bytes,
                                    double resid_tol);
 
+/* Kernel-phase timing probe.  While a phase is selected, every launch of it is
+ * bracketed by HIP events on the context stream; clot_probe_read synchronises,
+ * returns the summed event time (ms) and the launch count since the selection,
+ * and keeps counting.  Selecting CLOT_PROBE_OFF stops it. */
+typedef enum {
+    CLOT_PROBE_OFF = 0,
+    CLOT_PROBE_P_CG_A = 1,      /* pressure MG-PCG: direction update + stencil product   */
+    CLOT_PROBE_P_CG_B = 2,      /* pressure MG-PCG: solution/residual update              */
+    CLOT_PROBE_TR_B1 = 3,       /* transport BiCGStab phase 1 (p, v = A M^-1 p)           */
+    CLOT_PROBE_TR_B2 = 4,       /* transport BiCGStab phase 2 (t = A M^-1 s)              */
+    CLOT_PROBE_TR_B3 = 5,       /* transport BiCGStab phase 3 (x, r update)               */
+    CLOT_PROBE_MOM_B1 = 6,
+    CLOT_PROBE_MOM_B2 = 7,
+    CLOT_PROBE_MOM_B3 = 8,
+    CLOT_PROBE_RXN = 9,         /* cell reactions (RK4)                                   */
+    CLOT_PROBE_TR_ASM = 10,     /* transport assembly                                     */
+    CLOT_PROBE_ETA_CG_A = 11,
+    CLOT_PROBE_ETA_CG_B = 12,
+    CLOT_PROBE_P_RESID = 13,    /* FP64 pressure residual                                 */
+    CLOT_PROBE_CORRECT = 14,    /* PISO flux and velocity correction                      */
+    CLOT_PROBE_HBYA = 15,
+    CLOT_PROBE_PRHS = 16,
+    CLOT_PROBE_MOM_ASM = 17,
+    CLOT_PROBE_P_MG_POST = 18,  /* pressure multigrid: finest-level smoothing sweep + r.z  */
+    CLOT_PROBE_NKERNELS
+} clot_probe_kernel;
+clot_status clot_probe(clot_ctx* c, int32_t kernel);
+clot_status clot_probe_read(clot_ctx* c, double* total_ms, int64_t* launches);
+
 void clot_destroy(clot_ctx* c);
 const char* clot_last_error(const clot_ctx* c);
 

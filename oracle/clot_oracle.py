@@ -537,7 +537,7 @@ class Oracle:
         m = self.m
         h = min(m.dx, m.dy, m.dz if m.dim == 3 else m.dy)
         Dn = self.p.nu * self.dt / (h * h)
-        return 2 if Dn <= 10.0 else 3 if Dn <= 30.0 else 4 if Dn <= 60.0 else 5
+        return 2 if Dn <= 10.0 else 3 if Dn <= 30.0 else 4 if Dn <= 50.0 else 5 if Dn <= 80.0 else 6 if Dn <= 120.0 else 8
 
     def flow_step(self, alpha):
         """Momentum predictor + n_corr PISO correctors (section 3.2); updates u, p, phi."""

@@ -86,6 +86,8 @@ def load():
         "clot_sync": ([P], C.c_int),
         "clot_get_stats": ([P, C.c_int32, C.POINTER(Stats)], C.c_int),
         "clot_set_reaction_mode": ([P, C.c_int, P, C.c_size_t, C.c_double], C.c_int),
+        "clot_probe": ([P, C.c_int32], C.c_int),
+        "clot_probe_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
         "clot_destroy": ([P], None),
         "clot_last_error": ([P], C.c_char_p),
     }
@@ -101,7 +103,12 @@ def exported_symbols():
     """Names the C header declares (for the load/export check)."""
     return ["clot_params_default", "clot_query_workspace", "clot_create", "clot_init_state", "clot_field_count",
             "clot_set_field", "clot_get_field", "clot_step", "clot_step_async", "clot_sync", "clot_get_stats",
-            "clot_set_reaction_mode", "clot_destroy", "clot_last_error"]
+            "clot_set_reaction_mode", "clot_probe", "clot_probe_read", "clot_destroy", "clot_last_error"]
+
+
+PROBES = {"p_cg_a": 1, "p_cg_b": 2, "tr_b1": 3, "tr_b2": 4, "tr_b3": 5, "mom_b1": 6, "mom_b2": 7, "mom_b3": 8,
+          "rxn": 9, "tr_asm": 10, "eta_cg_a": 11, "eta_cg_b": 12, "p_resid": 13, "correct": 14, "hbya": 15,
+          "prhs": 16, "mom_asm": 17, "p_mg_post": 18}
 
 
 def default_params(precision=FP64, **over) -> Params:
@@ -207,6 +214,17 @@ class Solver:
                 "it_tr": s.it_tr, "refine_p": list(s.refine_p), "res_mom": s.res_mom, "res_p": s.res_p,
                 "res_eta": s.res_eta, "res_tr": s.res_tr, "fallback_frac": s.fallback_frac, "steps": s.steps,
                 "t": s.t}
+
+    def probe(self, name):
+        """Start timing every launch of one kernel phase (name in PROBES, or None to stop)."""
+        kid = 0 if name is None else PROBES[name]
+        return _check(self.lib, self.ctx, self.lib.clot_probe(self.ctx, kid), "probe")
+
+    def probe_read(self):
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        _check(self.lib, self.ctx, self.lib.clot_probe_read(self.ctx, C.byref(ms), C.byref(n)), "probe_read")
+        return ms.value, n.value
 
     def fields(self, ch=0):
         names = ["UX", "UY", "P", "PHIX", "PHIY", "E0", "C0", "ETA", "SIGMA"] + SPECIES_FIELDS

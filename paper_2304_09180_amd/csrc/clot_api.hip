@@ -2,8 +2,10 @@
 // the Krylov drivers.  Kernels are in clot_step.h / clot_krylov.h / clot_ops.h.
 #include "../../include/clot.h"
 #include "clot_step.h"
+#include "clot_mg.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -82,9 +84,23 @@ struct clot_ctx {
     virtual clot_status step(int nsteps, bool wait) = 0;
     virtual clot_status sync() = 0;
     virtual clot_status stats(int ch, clot_stats* s) const = 0;
+    virtual clot_status probe(int id) = 0;
+    virtual clot_status probe_read(double* ms, int64_t* n) = 0;
 };
 
 namespace {
+
+// Launch, bracketed by probe events when this phase is the one being timed.
+#define CLOT_LAUNCH(id, ...)                                                     \
+    do {                                                                         \
+        const bool pr_ = (id) == probe_id && ev_used + 2 <= (int)evs.size();     \
+        if (pr_) (void)hipEventRecord(evs[ev_used], st);                         \
+        hipLaunchKernelGGL(__VA_ARGS__);                                         \
+        if (pr_) {                                                               \
+            (void)hipEventRecord(evs[ev_used + 1], st);                          \
+            ev_used += 2;                                                        \
+        }                                                                        \
+    } while (0)
 
 #define HIPCHK(x)                                                                       \
     do {                                                                                \
@@ -121,10 +137,66 @@ struct Ctx : clot_ctx {
     double* dstats = nullptr;         // [nch][NSTAT]
     int32_t* h_nact = nullptr;        // pinned
     int last_it[8] = {8, 8, 8, 8, 8, 8, 8, 8};
+    // multigrid hierarchy of the pressure preconditioner (level 0 = the mesh)
+    struct Level {
+        std::vector<ChanDev> ch;
+        std::vector<int32_t> t2c;
+        ChanDev* d_ch = nullptr;
+        int32_t* d_t2c = nullptr;
+        int32_t ntiles = 0;
+        int64_t N = 0, NFX = 0, NFY = 0, NFZ = 0;
+        T *x = nullptr, *y = nullptr, *b = nullptr, *dg = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr,
+          *cout = nullptr;
+        Grid grid() const { return Grid{d_ch, d_t2c, ntiles}; }
+    };
+    std::vector<Level> lev;
+    T mg_w = T(0.8);
+    T* mg_y0 = nullptr;      // level-0 smoother scratch
+    T* mg_z0 = nullptr;      // preconditioned residual z = M r
+    double* mg_inv = nullptr;  // per-channel inverse of the coarsest-level matrix
+    int probe_id = 0;
+    std::vector<hipEvent_t> evs;
+    int ev_used = 0;
+    double probe_ms = 0.0;
+    int64_t probe_n = 0;
     bool nonconv = false;
     Grid grid() const { return Grid{d_ch, d_t2c, ntiles}; }
     ~Ctx() override {
         if (h_nact) (void)hipHostFree(h_nact);
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    }
+    void probe_collect() {
+        for (int i = 0; i + 1 < ev_used; i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) {
+                probe_ms += ms;
+                probe_n += 1;
+            }
+        }
+        ev_used = 0;
+    }
+    clot_status probe(int id) override {
+        HIPCHK(hipStreamSynchronize(st));
+        probe_collect();
+        if (id < 0 || id >= CLOT_PROBE_NKERNELS) {
+            err = "unknown probe kernel";
+            return CLOT_EINVAL;
+        }
+        if (id && evs.empty()) {
+            evs.resize(2048);
+            for (auto& e : evs) HIPCHK(hipEventCreate(&e));
+        }
+        probe_id = id;
+        probe_ms = 0.0;
+        probe_n = 0;
+        return CLOT_OK;
+    }
+    clot_status probe_read(double* ms, int64_t* n) override {
+        HIPCHK(hipStreamSynchronize(st));
+        probe_collect();
+        *ms = probe_ms;
+        *n = probe_n;
+        return CLOT_OK;
     }
 
     // ---------------------------------------------------------------------------
@@ -182,6 +254,21 @@ struct Ctx : clot_ctx {
         sigw = cv.take<double>((size_t)nch * NHIST);
         push = cv.take<int32_t>((size_t)nch * 2);
         dstats = cv.take<double>((size_t)nch * NSTAT);
+        mg_y0 = cv.take<T>(N);
+        mg_z0 = cv.take<T>(N);
+        mg_inv = cv.take<double>((size_t)nch * MG_COARSE * MG_COARSE);
+        for (Level& L : lev) {
+            L.d_ch = cv.take<ChanDev>(nch);
+            L.d_t2c = cv.take<int32_t>(std::max(L.ntiles, 1));
+            L.x = cv.take<T>(L.N);
+            L.y = cv.take<T>(L.N);
+            L.b = cv.take<T>(L.N);
+            L.dg = cv.take<T>(L.N);
+            L.cout = cv.take<T>(L.N);
+            L.cx = cv.take<T>(L.NFX);
+            L.cy = cv.take<T>(L.NFY);
+            L.cz = cv.take<T>(L.NFZ);
+        }
         return cv.off + 256;
     }
 
@@ -267,7 +354,8 @@ struct Ctx : clot_ctx {
             // PISO corrections: fixed, or chosen from the viscous diffusion number
             const double hmin = std::min(h.dx, std::min(h.dy, d.dim == 3 ? h.dz : h.dy));
             const double Dn = p->nu * d.dt / (hmin * hmin);
-            h.ncorr = p->n_corr > 0 ? p->n_corr : (Dn <= 10.0 ? 2 : Dn <= 30.0 ? 3 : Dn <= 60.0 ? 4 : 5);
+            h.ncorr = p->n_corr > 0 ? p->n_corr
+                                    : (Dn <= 10.0 ? 2 : Dn <= 30.0 ? 3 : Dn <= 50.0 ? 4 : Dn <= 80.0 ? 5 : Dn <= 120.0 ? 6 : 8);
             if (h.ncorr > MAXCORR) h.ncorr = MAXCORR;
             maxcorr = std::max(maxcorr, h.ncorr);
             for (int q = 0; q < NHIST; ++q) h.hist_t[q] = -1e300;
@@ -279,6 +367,13 @@ struct Ctx : clot_ctx {
         NIN = in;
         NINJ = inj;
         ntiles = t0;
+        build_levels();
+        if (!lev.empty())
+            for (const ChanDev& c : lev.back().ch)
+                if (c.ncell > MG_COARSE) {
+                    err = "channel too long for the pressure multigrid hierarchy";
+                    return CLOT_EINVAL;
+                }
         const clot_params& q = *p;
         M = ModelDev{q.nu, q.C_CK, q.D_P, q.D_ADP, q.D_chem, q.P_diam, q.P_max, q.P_0, q.k_adh, q.kcoh_Pmax,
                      q.eta_t, q.eta_star, 0.0, q.k_adp, q.adp_crit, q.k_e2, q.e2_crit,
@@ -290,6 +385,56 @@ struct Ctx : clot_ctx {
         M.kappa_eta = Le * Le / 4.0;
         M.g0 = (std::pow(q.eta_star, 3) + std::pow(1.0 - q.eta_t, 3)) / std::pow(1.0 - q.eta_t, 3);
         return CLOT_OK;
+    }
+
+    // Level dims: halve every axis with >= 3 cells until the largest channel has
+    // <= MG_COARSE cells; smaller channels keep halving (down to 2 per axis).
+    void build_levels() {
+        const int nch = (int)ch.size();
+        lev.clear();
+        std::vector<std::array<int, 3>> dims(nch);
+        for (int i = 0; i < nch; ++i) dims[i] = {ch[i].d.nx, ch[i].d.ny, ch[i].d.nz};
+        auto ncells = [&](const std::array<int, 3>& d) { return (int64_t)d[0] * d[1] * d[2]; };
+        for (int l = 1; l < MG_MAXLEV; ++l) {
+            bool all_small = true;
+            for (int i = 0; i < nch; ++i) all_small &= ncells(dims[i]) <= MG_COARSE;
+            if (all_small) break;
+            for (int i = 0; i < nch; ++i)
+                for (int a = 0; a < 3; ++a)
+                    if (dims[i][a] >= 3) dims[i][a] = (dims[i][a] + 1) / 2;
+            Level L;
+            int64_t c0 = 0, fx = 0, fy = 0, fz = 0;
+            int32_t t0 = 0;
+            for (int i = 0; i < nch; ++i) {
+                ChanDev c{};
+                c.dim = ch[i].d.dim;
+                c.nx = dims[i][0];
+                c.ny = dims[i][1];
+                c.nz = dims[i][2];
+                c.ncell = ncells(dims[i]);
+                c.c0 = c0;
+                c0 += c.ncell;
+                c.fx0 = fx;
+                c.fy0 = fy;
+                c.fz0 = fz;
+                fx += (int64_t)(c.nx + 1) * c.ny * c.nz;
+                fy += (int64_t)c.nx * (c.ny + 1) * c.nz;
+                fz += c.dim == 3 ? (int64_t)c.nx * c.ny * (c.nz + 1) : 0;
+                c.nt = (int32_t)((c.ncell + TILE - 1) / TILE);
+                c.t0 = t0;
+                t0 += c.nt;
+                fastdiv_magic((uint32_t)c.nx, c.mnx, c.lnx);
+                fastdiv_magic((uint32_t)c.ny, c.mny, c.lny);
+                for (int t = 0; t < c.nt; ++t) L.t2c.push_back(i);
+                L.ch.push_back(c);
+            }
+            L.N = c0;
+            L.NFX = fx;
+            L.NFY = fy;
+            L.NFZ = std::max<int64_t>(fz, 1);
+            L.ntiles = t0;
+            lev.push_back(L);
+        }
     }
 
     clot_status upload_tables() {
@@ -318,6 +463,8 @@ struct Ctx : clot_ctx {
             c.jadh = h.jadh;
             c.t0 = h.t0;
             c.nt = h.nt;
+            fastdiv_magic((uint32_t)c.nx, c.mnx, c.lnx);
+            fastdiv_magic((uint32_t)c.ny, c.mny, c.lny);
             c.dx = h.dx;
             c.dy = h.dy;
             c.dz = h.dz;
@@ -330,6 +477,10 @@ struct Ctx : clot_ctx {
             for (int f = 0; f < h.ninj; ++f) f2c[h.inj0 + f] = i;
         }
         HIPCHK(hipMemcpyAsync(d_ch, dv.data(), nch * sizeof(ChanDev), hipMemcpyHostToDevice, st));
+        for (Level& L : lev) {
+            HIPCHK(hipMemcpyAsync(L.d_ch, L.ch.data(), nch * sizeof(ChanDev), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(L.d_t2c, L.t2c.data(), L.t2c.size() * 4, hipMemcpyHostToDevice, st));
+        }
         HIPCHK(hipMemcpyAsync(d_t2c, t2c.data(), t2c.size() * 4, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(d_f2c, f2c.data(), f2c.size() * 4, hipMemcpyHostToDevice, st));
         std::vector<int32_t> ones(nch, 1), cm((size_t)MAXCORR * nch, 0);
@@ -561,8 +712,9 @@ struct Ctx : clot_ctx {
     // ---------------------------------------------------------------------------
     // Krylov drivers
     int32_t poll() {
-        hipMemcpyAsync(h_nact, S.nact, 4, hipMemcpyDeviceToHost, st);
-        hipStreamSynchronize(st);
+        (void)hipMemcpyAsync(h_nact, S.nact, 4, hipMemcpyDeviceToHost, st);
+        (void)hipStreamSynchronize(st);
+        if (ev_used) probe_collect();
         return *h_nact;
     }
     void fill(int32_t* p, int32_t v, int64_t n) {
@@ -575,15 +727,18 @@ struct Ctx : clot_ctx {
     }
 
     template <class Op, int K>
-    int run_cg(const Op& op, KVec<T, K> V, double rtol, int tol_mode, const int32_t* mask, int slot) {
+    int run_cg(const Op& op, KVec<T, K> V, double rtol, int tol_mode, const int32_t* mask, int slot, int pa, int pb) {
         set_active(mask);
-        hipLaunchKernelGGL((k_cg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, rtol, tol_mode);
+        hipLaunchKernelGGL((k_cg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
+        finish<3 * K>(EpiCgInit<K>{rtol, tol_mode});
         int it = 0, par = 0;
         int chunk = std::max(2, last_it[slot]);
         while (it < prm.max_iter) {
             for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it) {
-                hipLaunchKernelGGL((k_cg_a<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
-                hipLaunchKernelGGL((k_cg_b<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                CLOT_LAUNCH(pa, (k_cg_a<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                finish<K>(EpiCgA<K>{});
+                CLOT_LAUNCH(pb, (k_cg_b<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                finish<2 * K>(EpiCgB<K>{});
                 par ^= 1;
             }
             if (poll() == 0) break;
@@ -594,16 +749,121 @@ struct Ctx : clot_ctx {
     }
 
     template <class Op, int K>
-    int run_bicg(const Op& op, KVec<T, K> V, double rtol, const int32_t* mask, int slot) {
+    int run_bicg(const Op& op, KVec<T, K> V, double rtol, const int32_t* mask, int slot, int p1) {
         set_active(mask);
-        hipLaunchKernelGGL((k_bicg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, rtol);
+        hipLaunchKernelGGL((k_bicg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
+        finish<2 * K>(EpiBicgInit<K>{rtol});
         int it = 0, par = 0;
         int chunk = std::max(2, last_it[slot]);
         while (it < prm.max_iter) {
             for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it) {
-                hipLaunchKernelGGL((k_bicg_1<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
-                hipLaunchKernelGGL((k_bicg_2<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
-                hipLaunchKernelGGL((k_bicg_3<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                CLOT_LAUNCH(p1, (k_bicg_1<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                finish<K>(EpiBicg1<K>{});
+                CLOT_LAUNCH(p1 + 1, (k_bicg_2<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                finish<2 * K>(EpiBicg2<K>{});
+                CLOT_LAUNCH(p1 + 2, (k_bicg_3<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+                finish<2 * K>(EpiBicg3<K>{});
+                par ^= 1;
+            }
+            if (poll() == 0) break;
+            chunk = 2;
+        }
+        last_it[slot] = std::max(1, it - 1);
+        return it;
+    }
+
+    template <int NV, class E>
+    void finish(const E& e) {
+        hipLaunchKernelGGL((k_finish<NV, E>), dim3((int)ch.size()), dim3(NT), 0, st, d_ch, S, e);
+    }
+
+    // Pressure preconditioner setup: coarse operators from the current rAU.
+    void mg_setup() {
+        FineCoefPres<T> fp{F.rAU};
+        for (size_t l = 0; l < lev.size(); ++l) {
+            Level& L = lev[l];
+            MGPair pr{l == 0 ? grid() : lev[l - 1].grid(), L.grid()};
+            if (l == 0) {
+                FineCoefLevel<T> fl{nullptr, nullptr, nullptr, nullptr};
+                hipLaunchKernelGGL((k_mg_setup<T, true>), dim3(L.ntiles), dim3(NT), 0, st, pr, fp, fl, L.cx, L.cy, L.cz,
+                                   L.cout, L.dg);
+            } else {
+                const Level& Fl = lev[l - 1];
+                FineCoefLevel<T> fl{Fl.cx, Fl.cy, Fl.cz, Fl.cout};
+                hipLaunchKernelGGL((k_mg_setup<T, false>), dim3(L.ntiles), dim3(NT), 0, st, pr, fp, fl, L.cx, L.cy,
+                                   L.cz, L.cout, L.dg);
+            }
+        }
+        if (!lev.empty()) {
+            Level& Lc = lev.back();
+            CoefOp<T> op{Lc.dg, Lc.cx, Lc.cy, Lc.cz};
+            hipLaunchKernelGGL(k_mg_coarse_setup<T>, dim3((int)ch.size()), dim3(MG_COARSE), 0, st, Lc.grid(), op, mg_inv,
+                               (int)ch.size());
+        }
+    }
+
+    // z = M r on level 0 (V-cycle); the last kernel also forms r.z and beta.
+    void vcycle(const T* r) {
+        const int nl = (int)lev.size();
+        PresOp<T, T> p0{F.rAU, F.dP};
+        const int32_t* act = S.chact;
+        if (nl == 0) {   // mesh already coarse: two Jacobi sweeps
+            hipLaunchKernelGGL((k_mg_pre<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), p0, r, mg_y0, mg_w, act);
+            hipLaunchKernelGGL((k_mg_post2<T, PresOp<T, T>, true>), dim3(ntiles), dim3(NT), 0, st, grid(), p0, r, mg_y0,
+                               mg_z0, mg_w, S);
+            finish<1>(EpiMgDot{});
+            return;
+        }
+        // down
+        hipLaunchKernelGGL((k_mg_pre<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), p0, r, mg_z0, mg_w, act);
+        hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT), 0, st,
+                           MGPair{grid(), lev[0].grid()}, p0, r, mg_z0, lev[0].b, act);
+        for (int l = 0; l + 1 < nl; ++l) {
+            Level& L = lev[l];
+            CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
+            hipLaunchKernelGGL((k_mg_pre<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), op, L.b, L.x, mg_w, act);
+            hipLaunchKernelGGL((k_mg_restrict<T, CoefOp<T>>), dim3(lev[l + 1].ntiles * (TILE / (NT / 8))), dim3(NT), 0,
+                               st, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, L.x, lev[l + 1].b, act);
+        }
+        {
+            Level& Lc = lev[nl - 1];
+            hipLaunchKernelGGL(k_mg_coarse<T>, dim3((int)ch.size()), dim3(MG_COARSE), 0, st, Lc.grid(), mg_inv, Lc.b, Lc.x,
+                               act, (int)ch.size());
+        }
+        // up
+        for (int l = nl - 2; l >= 0; --l) {
+            Level& L = lev[l];
+            CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
+            hipLaunchKernelGGL((k_mg_post1<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, MGPair{L.grid(), lev[l + 1].grid()},
+                               op, L.b, L.x, lev[l + 1].x, L.y, mg_w, act);
+            hipLaunchKernelGGL((k_mg_post2<T, CoefOp<T>, false>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), op, L.b, L.y,
+                               L.x, mg_w, S);
+        }
+        hipLaunchKernelGGL((k_mg_post1<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, MGPair{grid(), lev[0].grid()}, p0,
+                           r, mg_z0, lev[0].x, mg_y0, mg_w, act);
+        CLOT_LAUNCH(CLOT_PROBE_P_MG_POST, (k_mg_post2<T, PresOp<T, T>, true>), dim3(ntiles), dim3(NT), 0, st, grid(), p0,
+                    r, mg_y0, mg_z0, mg_w, S);
+        finish<1>(EpiMgDot{});
+    }
+
+    // Multigrid-preconditioned CG on the pressure correction.
+    int run_mgcg(KVec<T, 1> V, double rtol, int tol_mode, const int32_t* mask, int slot) {
+        PresOp<T, T> pop{F.rAU, F.dP};
+        set_active(mask);
+        hipLaunchKernelGGL((k_mgcg_init<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), pop, V, S);
+        finish<2>(EpiMgcgInit{rtol, tol_mode});
+        vcycle(V.r[0]);
+        int it = 0, par = 0;
+        int chunk = std::max(2, last_it[slot]);
+        while (it < prm.max_iter) {
+            for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it) {
+                CLOT_LAUNCH(CLOT_PROBE_P_CG_A, (k_mgcg_a<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), pop, V,
+                            mg_z0, S, par);
+                finish<1>(EpiCgA<1>{});
+                CLOT_LAUNCH(CLOT_PROBE_P_CG_B, (k_mgcg_b<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), pop, V,
+                            S, par);
+                finish<1>(EpiMgcgB{});
+                vcycle(V.r[0]);
                 par ^= 1;
             }
             if (poll() == 0) break;
@@ -683,7 +943,7 @@ struct Ctx : clot_ctx {
         // O-0 derived coefficients
         hipLaunchKernelGGL(k_derive<T>, gb, tb, 0, st, G, F, M);
         // O-1 momentum predictor
-        hipLaunchKernelGGL(k_mom_assemble<T>, gb, tb, 0, st, G, F, M);
+        CLOT_LAUNCH(CLOT_PROBE_MOM_ASM, k_mom_assemble<T>, gb, tb, 0, st, G, F, M);
         MomOp<T> mop{F.aP, F.phi[0], F.phi[1], F.phi[2], T(prm.nu)};
         {
             KVec<T, 3> V = bicg_vecs<3>(0);
@@ -691,15 +951,16 @@ struct Ctx : clot_ctx {
                 V.x[c] = F.u[c];
                 V.b[c] = F.bm[c];
             }
-            run_bicg<MomOp<T>, 3>(mop, V, prm.rtol_s, allmask, 0);
+            run_bicg<MomOp<T>, 3>(mop, V, prm.rtol_s, allmask, 0, CLOT_PROBE_MOM_B1);
             record(ST_MOM, ST_RESM, 3, false);
         }
         // O-2 PISO correctors
         for (int k = 0; k < maxcorr; ++k) {
             const int32_t* cm = corrmask + (size_t)k * nch;
-            hipLaunchKernelGGL(k_hbya<T>, gb, tb, 0, st, G, F, mop, cm);
-            hipLaunchKernelGGL(k_prhs<T>, gb, tb, 0, st, G, F, M, cm);
-            // FP64 iterative refinement around a T-precision PCG
+            CLOT_LAUNCH(CLOT_PROBE_HBYA, k_hbya<T>, gb, tb, 0, st, G, F, mop, cm);
+            CLOT_LAUNCH(CLOT_PROBE_PRHS, k_prhs<T>, gb, tb, 0, st, G, F, M, cm);
+            mg_setup();
+            // FP64 iterative refinement around a T-precision MG-PCG
             set_active(cm);
             // count of active channels for the residual kernel
             hipLaunchKernelGGL(k_count_active, dim3(1), dim3(64), 0, st, S.chact, S.nact, nch);
@@ -707,12 +968,12 @@ struct Ctx : clot_ctx {
             T* rin = pool[0];
             PresOp<T, T> pop{F.rAU, F.dP};
             for (int pass = 0; pass < 12; ++pass) {
-                hipLaunchKernelGGL(k_pres_resid<T>, gb, tb, 0, st, G, F, rin, e, S, prm.rtol_p,
-                                   prec == CLOT_FP64 ? 0.0 : prm.rtol_inner, pass, refmask);
+                CLOT_LAUNCH(CLOT_PROBE_P_RESID, k_pres_resid<T>, gb, tb, 0, st, G, F, rin, e, S);
+                finish<2>(EpiPresResid{prm.rtol_p, prec == CLOT_FP64 ? 0.0 : prm.rtol_inner, pass, refmask});
                 const int32_t need = poll();
                 if (need == 0) break;
                 KVec<T, 1> V = cg_vecs(e, rin);
-                run_cg<PresOp<T, T>, 1>(pop, V, 0.0, 1, refmask, 1 + std::min(k, 2));
+                run_mgcg(V, 0.0, 1, refmask, 1 + std::min(k, 2));
                 record(ST_P + std::min(k, MAXCORR - 1), ST_RESP, 1, pass > 0);
                 hipLaunchKernelGGL(k_pres_add<T>, gb, tb, 0, st, G, F, e, refmask);
                 set_active(refmask);
@@ -720,7 +981,7 @@ struct Ctx : clot_ctx {
             }
             hipLaunchKernelGGL(k_record_pass, dim3(1), dim3(64), 0, st, S.sc, dstats, NSTAT, nch,
                                ST_REF + std::min(k, MAXCORR - 1), ST_RESP, (int)ST_FAIL);
-            hipLaunchKernelGGL(k_correct<T>, gb, tb, 0, st, G, F, M, cm);
+            CLOT_LAUNCH(CLOT_PROBE_CORRECT, k_correct<T>, gb, tb, 0, st, G, F, M, cm);
         }
         // O-3 eta
         {
@@ -728,7 +989,7 @@ struct Ctx : clot_ctx {
             hipLaunchKernelGGL(k_eta_prep<T>, gb, tb, 0, st, G, F, M, rhs);
             EtaOp<T> eop{T(M.kappa_eta), F.dE};
             KVec<T, 1> V = cg_vecs(F.eta, rhs);
-            run_cg<EtaOp<T>, 1>(eop, V, prm.rtol_s, 0, allmask, 4);
+            run_cg<EtaOp<T>, 1>(eop, V, prm.rtol_s, 0, allmask, 4, CLOT_PROBE_ETA_CG_A, CLOT_PROBE_ETA_CG_B);
             record(ST_ETA, ST_RESE, 1, false);
         }
         // O-4 sigma
@@ -756,20 +1017,20 @@ struct Ctx : clot_ctx {
         top.phz = F.phin[2];
         top.Wc = F.Wc;
         top.Pmax = T(M.P_max);
-        hipLaunchKernelGGL(k_tr_assemble<T>, gb, tb, 0, st, G, F, top, M);
+        CLOT_LAUNCH(CLOT_PROBE_TR_ASM, k_tr_assemble<T>, gb, tb, 0, st, G, F, top, M);
         {
             KVec<T, NTR> V = bicg_vecs<NTR>(0);
             for (int k = 0; k < NTR; ++k) {
                 V.x[k] = F.xt[k];
                 V.b[k] = F.trb[k];
             }
-            run_bicg<TrOp<T>, NTR>(top, V, prm.rtol_s, allmask, 5);
+            run_bicg<TrOp<T>, NTR>(top, V, prm.rtol_s, allmask, 5, CLOT_PROBE_TR_B1);
             record(ST_TR, ST_REST, NTR, false);
         }
         // O-6 reactions (wall first: it reads the transported S1)
         if (NINJ > 0)
             hipLaunchKernelGGL(k_wall_rxn<T>, dim3((NINJ + NT - 1) / NT), tb, 0, st, d_ch, d_f2c, NINJ, F, M);
-        hipLaunchKernelGGL(k_rxn<T>, gb, tb, 0, st, G, F, M);
+        CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn<T>, gb, tb, 0, st, G, F, M);
         // O-7 rotate theta_B and the flux
         std::swap(F.thB, F.thB_prev);
         for (int c = 0; c < 3; ++c) std::swap(F.phi[c], F.phin[c]);
@@ -908,8 +1169,8 @@ clot_status clot_params_default(clot_params* p) {
     p->max_iter = 5000;
     p->marg_m = 19;
     p->marg_n = 2;
-    p->rtol_p = 1e-12;
-    p->rtol_s = 1e-12;
+    p->rtol_p = 1e-13;
+    p->rtol_s = 1e-13;
     p->rtol_inner = 1e-4;
     return CLOT_OK;
 }
@@ -992,6 +1253,14 @@ clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* 
         return CLOT_ESTATE;
     }
     return CLOT_OK;
+}
+clot_status clot_probe(clot_ctx* c, int32_t kernel) {
+    if (!c) return CLOT_EINVAL;
+    return c->probe(kernel);
+}
+clot_status clot_probe_read(clot_ctx* c, double* ms, int64_t* n) {
+    if (!c || !ms || !n) return CLOT_EINVAL;
+    return c->probe_read(ms, n);
 }
 void clot_destroy(clot_ctx* c) { delete c; }
 const char* clot_last_error(const clot_ctx* c) { return c ? c->err.c_str() : "null context"; }

@@ -13,7 +13,7 @@
 namespace clot {
 
 constexpr int NT = 256;           // threads per block (4 wavefronts of 64)
-constexpr int CPT = 4;            // cells per thread
+constexpr int CPT = 1;            // cells per thread
 constexpr int TILE = NT * CPT;    // cells per tile
 constexpr int NXCD = 8;
 constexpr int NSPC = 15;          // cell species
@@ -39,9 +39,22 @@ struct ChanDev {
     int32_t ninj, inj_i0, inj_ni, inj_k0, inj_nk;
     int32_t jadh;                 // adhesion layers (cells j < jadh over the patch)
     int32_t t0, nt;               // tile range
+    uint32_t mnx, lnx, mny, lny;  // magic multipliers/shifts for division by nx and ny
     double dx, dy, dz, V, Ax, Ay, Az;
     double dt;
 };
+
+// Round-up magic-number division of 32-bit unsigned n by a fixed d (host computes m, l).
+__host__ inline void fastdiv_magic(uint32_t d, uint32_t& m, uint32_t& l) {
+    l = 0;
+    while ((1ull << l) < d) ++l;
+    m = (uint32_t)((((unsigned __int128)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+}
+__device__ inline uint32_t fastdiv(uint32_t n, uint32_t m, uint32_t l) {
+    if (l == 0) return n;
+    const uint32_t t = __umulhi(m, n);
+    return (t + ((n - t) >> 1)) >> (l - 1);
+}
 
 // Model constants on the device (same names as clot_params).
 struct ModelDev {
@@ -76,10 +89,12 @@ struct Cell {
 __device__ inline Cell cell_at(const ChanDev& c, int64_t local) {
     Cell p;
     p.g = c.c0 + local;
-    p.i = (int32_t)(local % c.nx);
-    int64_t r = local / c.nx;
-    p.j = (int32_t)(r % c.ny);
-    p.k = (int32_t)(r / c.ny);
+    const uint32_t loc = (uint32_t)local;
+    const uint32_t r = fastdiv(loc, c.mnx, c.lnx);
+    p.i = (int32_t)(loc - r * (uint32_t)c.nx);
+    const uint32_t k = fastdiv(r, c.mny, c.lny);
+    p.j = (int32_t)(r - k * (uint32_t)c.ny);
+    p.k = (int32_t)k;
     return p;
 }
 
@@ -124,38 +139,17 @@ __device__ inline void block_sum(double (&v)[NV], double* lds /* NV*NT/64 */) {
     for (int q = 0; q < NV; ++q) v[q] = lds[NV * (NT / 64) + q];
 }
 
-// Returns true in the block that completes channel ch's reduction; sums[] then holds
-// the channel totals (in every thread of that block).
+// Writes the block's totals of v[] as the tile partials part[tile*NV + q].  The
+// per-channel totals are finished by k_finish (clot_krylov.h): a separate small
+// launch, so no block needs a device-wide fence (on a multi-XCD part each such
+// fence writes back the whole L2) and the summation order is fixed.
 template <int NV>
-__device__ inline bool channel_reduce(double (&v)[NV], double* part, uint32_t* ticket, const ChanDev& c,
-                                      int32_t tile, double* lds, double (&sums)[NV]) {
+__device__ inline void store_partials(double (&v)[NV], double* part, int32_t tile, double* lds) {
     block_sum<NV>(v, lds);
-    __shared__ uint32_t s_last;
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) part[(int64_t)tile * NV + q] = v[q];
-        __threadfence();
-        uint32_t t = atomicAdd(ticket, 1u);
-        s_last = (t == (uint32_t)(c.nt - 1)) ? 1u : 0u;
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    double acc[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    // strided partial sums, then a fixed-order block reduction: deterministic
-    for (int t = threadIdx.x; t < c.nt; t += NT) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            acc[q] += part[(int64_t)(c.t0 + t) * NV + q];
-        }
-    }
-    block_sum<NV>(acc, lds);
-#pragma unroll
-    for (int q = 0; q < NV; ++q) sums[q] = acc[q];
-    if (threadIdx.x == 0) *ticket = 0u;
-    return true;
 }
 
 }  // namespace clot

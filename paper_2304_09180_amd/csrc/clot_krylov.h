@@ -1,15 +1,16 @@
 // Batched, per-channel Krylov solvers as phase kernels (gfx950).
 //
 // K independent systems per channel share one launch.  Every dot product is an
-// FP64 per-tile partial finished by the last tile of the channel, which also
-// computes the recurrence scalars (alpha, beta, omega) and the convergence
-// decision on the device: the host never reads a scalar to continue.  A channel
-// whose systems have all converged stops doing work (its blocks return at entry)
-// and decrements the global active count that the host polls between chunks.
+// FP64 per-tile partial; a small finishing launch (one block per channel) adds a
+// channel's partials in tile order and runs the scalar epilogue of the phase:
+// the recurrence scalars (alpha, beta, omega) and the convergence decision stay on
+// the device and the host never reads a scalar to continue.  A channel whose
+// systems have all converged stops doing work (its blocks return at entry) and
+// decrements the global active count that the host polls between chunks.
 //
-// Jacobi-preconditioned CG (SPD: pressure, eta) and BiCGStab (momentum, transport).
-// The preconditioned direction vectors are formed on the fly from r, p and v at
-// each stencil point, so each iteration costs two (CG) or three (BiCGStab) passes.
+// Jacobi-preconditioned CG (SPD: eta) and BiCGStab (momentum, transport).  The
+// preconditioned direction vectors are formed on the fly from r, p and v at each
+// stencil point, so each iteration costs two (CG) or three (BiCGStab) passes.
 #pragma once
 #include "clot_ops.h"
 
@@ -26,7 +27,7 @@ struct KState {
     int32_t* chact;      // [nch] 1 while any system of the channel iterates
     int32_t* nact;       // global count of active channels
     double* part;        // [ntiles][NV]
-    uint32_t* tick;      // [nch]
+    uint32_t* tick;      // unused (kept for layout stability)
     int32_t maxit;
 };
 
@@ -46,7 +47,7 @@ struct KVec {
 #define CLOT_TILE_PROLOGUE(G)                                     \
     const int32_t tile = xcd_tile((int32_t)blockIdx.x, G.ntiles); \
     const int32_t chid = G.t2c[tile];                             \
-    const ChanDev& C = G.ch[chid];                                \
+    const ChanDev C = G.ch[chid];                                 \
     const int64_t tbase = (int64_t)(tile - C.t0) * TILE;
 
 #define CLOT_FOR_CELLS(local)                                        \
@@ -56,9 +57,185 @@ struct KVec {
 
 #define CLOT_END_CELLS }
 
+// Sums the tile partials of each active channel and runs the phase epilogue.
+template <int NV, class Epi>
+__global__ __launch_bounds__(NT) void k_finish(const ChanDev* chans, KState S, Epi epi) {
+    const int chid = blockIdx.x;
+    if (!S.chact[chid]) return;
+    const int32_t t0 = chans[chid].t0, nt = chans[chid].nt;
+    __shared__ double lds[5 * NV];
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    for (int t = threadIdx.x; t < nt; t += NT) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] += S.part[(int64_t)(t0 + t) * NV + q];
+    }
+    block_sum<NV>(acc, lds);
+    if (threadIdx.x == 0) epi(acc, S, chid);
+}
+
+// ---- epilogues ---------------------------------------------------------------------
 // tol_mode 0: tolerance rtol^2 ||b||^2; 1: tolerance already in SC_TOL2.
+template <int K>
+struct EpiCgInit {
+    double rtol;
+    int tol_mode;
+    __device__ void operator()(const double* sums, const KState& S, int ch) const {
+        int any = 0;
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, ch, k);
+            s[SC_RZ] = sums[3 * k];
+            s[SC_BB] = sums[3 * k + 1];
+            s[SC_RR] = sums[3 * k + 2];
+            s[SC_RR0] = sums[3 * k + 2];
+            if (tol_mode == 0) s[SC_TOL2] = rtol * rtol * sums[3 * k + 1];
+            s[SC_BETA] = 0.0;
+            s[SC_IT] = 0.0;
+            s[SC_FAIL] = 0.0;
+            const bool act = s[SC_BB] > 0.0 && s[SC_RR] > s[SC_TOL2];
+            s[SC_ACT] = act ? 1.0 : 0.0;
+            any |= act;
+        }
+        S.chact[ch] = any;
+        if (any) atomicAdd(S.nact, 1);
+    }
+};
+
+template <int K>
+struct EpiCgA {   // alpha = rz / (p.q)
+    __device__ void operator()(const double* sums, const KState& S, int ch) const {
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, ch, k);
+            if (s[SC_ACT] == 0.0) continue;
+            s[SC_PQ] = sums[k];
+            if (!(sums[k] > 0.0) || !isfinite(sums[k])) {
+                s[SC_ALPHA] = 0.0;
+                s[SC_ACT] = 0.0;
+                s[SC_FAIL] = 1.0;
+            } else {
+                s[SC_ALPHA] = s[SC_RZ] / sums[k];
+            }
+        }
+    }
+};
+
+template <int K>
+struct EpiCgB {   // beta, convergence
+    __device__ void operator()(const double* sums, const KState& S, int ch) const {
+        int any = 0;
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, ch, k);
+            if (s[SC_ACT] != 0.0) {
+                const double rz = sums[2 * k];
+                s[SC_BETA] = s[SC_RZ] != 0.0 ? rz / s[SC_RZ] : 0.0;
+                s[SC_RZ] = rz;
+                s[SC_RR] = sums[2 * k + 1];
+                s[SC_IT] += 1.0;
+                if (s[SC_RR] <= s[SC_TOL2]) s[SC_ACT] = 0.0;
+                else if (s[SC_IT] >= S.maxit || !isfinite(s[SC_RR])) {
+                    s[SC_ACT] = 0.0;
+                    s[SC_FAIL] = 1.0;
+                }
+            }
+            any |= s[SC_ACT] != 0.0;
+        }
+        if (!any) {
+            S.chact[ch] = 0;
+            atomicSub(S.nact, 1);
+        }
+    }
+};
+
+template <int K>
+struct EpiBicgInit {
+    double rtol;
+    __device__ void operator()(const double* sums, const KState& S, int ch) const {
+        int any = 0;
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, ch, k);
+            s[SC_BB] = sums[2 * k];
+            s[SC_RR] = sums[2 * k + 1];
+            s[SC_RR0] = sums[2 * k + 1];
+            s[SC_RHO] = sums[2 * k + 1];       // rhat . r with rhat = r
+            s[SC_TOL2] = rtol * rtol * sums[2 * k];
+            s[SC_ALPHA] = 1.0;
+            s[SC_OMEGA] = 1.0;
+            s[SC_BETA] = 0.0;
+            s[SC_IT] = 0.0;
+            s[SC_FAIL] = 0.0;
+            const bool act = s[SC_BB] > 0.0 && s[SC_RR] > s[SC_TOL2];
+            s[SC_ACT] = act ? 1.0 : 0.0;
+            any |= act;
+        }
+        S.chact[ch] = any;
+        if (any) atomicAdd(S.nact, 1);
+    }
+};
+
+template <int K>
+struct EpiBicg1 {   // alpha = rho / (rhat . v)
+    __device__ void operator()(const double* sums, const KState& S, int ch) const {
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, ch, k);
+            if (s[SC_ACT] == 0.0) continue;
+            if (sums[k] == 0.0 || !isfinite(sums[k])) {
+                s[SC_ACT] = 0.0;
+                s[SC_FAIL] = 1.0;
+                s[SC_ALPHA] = 0.0;
+            } else {
+                s[SC_ALPHA] = s[SC_RHO] / sums[k];
+            }
+        }
+    }
+};
+
+template <int K>
+struct EpiBicg2 {   // omega = (t.s)/(t.t)
+    __device__ void operator()(const double* sums, const KState& S, int ch) const {
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, ch, k);
+            if (s[SC_ACT] == 0.0) continue;
+            s[SC_TS] = sums[2 * k];
+            s[SC_TT] = sums[2 * k + 1];
+            s[SC_OMEGA] = sums[2 * k + 1] > 0.0 ? sums[2 * k] / sums[2 * k + 1] : 0.0;
+        }
+    }
+};
+
+template <int K>
+struct EpiBicg3 {   // rho_new, beta, convergence
+    __device__ void operator()(const double* sums, const KState& S, int ch) const {
+        int any = 0;
+        for (int k = 0; k < K; ++k) {
+            double* s = scp(S, ch, k);
+            if (s[SC_ACT] != 0.0) {
+                const double rho = sums[2 * k];
+                s[SC_RR] = sums[2 * k + 1];
+                s[SC_IT] += 1.0;
+                const double om = s[SC_OMEGA];
+                if (s[SC_RR] <= s[SC_TOL2]) {
+                    s[SC_ACT] = 0.0;
+                } else if (s[SC_IT] >= S.maxit || !isfinite(s[SC_RR]) || om == 0.0 || rho == 0.0) {
+                    s[SC_ACT] = 0.0;
+                    s[SC_FAIL] = 1.0;
+                } else {
+                    s[SC_BETA] = (rho / s[SC_RHO]) * (s[SC_ALPHA] / om);
+                    s[SC_RHO] = rho;
+                }
+            }
+            any |= s[SC_ACT] != 0.0;
+        }
+        if (!any) {
+            S.chact[ch] = 0;
+            atomicSub(S.nact, 1);
+        }
+    }
+};
+
+// ---- Jacobi PCG ---------------------------------------------------------------------
 template <class T, int K, class Op>
-__global__ __launch_bounds__(NT) void k_cg_init(Grid G, Op op, KVec<T, K> V, KState S, double rtol, int tol_mode) {
+__global__ __launch_bounds__(NT) void k_cg_init(Grid G, Op op, KVec<T, K> V, KState S) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
     __shared__ double lds[5 * 3 * K];
@@ -81,29 +258,10 @@ __global__ __launch_bounds__(NT) void k_cg_init(Grid G, Op op, KVec<T, K> V, KSt
             acc[3 * k + 2] += (double)r * (double)r;
         }
     CLOT_END_CELLS
-    double sums[3 * K];
-    if (channel_reduce<3 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
-        int any = 0;
-        for (int k = 0; k < K; ++k) {
-            double* s = scp(S, chid, k);
-            s[SC_RZ] = sums[3 * k];
-            s[SC_BB] = sums[3 * k + 1];
-            s[SC_RR] = sums[3 * k + 2];
-            s[SC_RR0] = sums[3 * k + 2];
-            if (tol_mode == 0) s[SC_TOL2] = rtol * rtol * sums[3 * k + 1];
-            s[SC_BETA] = 0.0;
-            s[SC_IT] = 0.0;
-            s[SC_FAIL] = 0.0;
-            const bool act = s[SC_BB] > 0.0 && s[SC_RR] > s[SC_TOL2];
-            s[SC_ACT] = act ? 1.0 : 0.0;
-            any |= act;
-        }
-        S.chact[chid] = any;
-        if (any) atomicAdd(S.nact, 1);
-    }
+    store_partials<3 * K>(acc, S.part, tile, lds);
 }
 
-// q = A p_new with p_new = z + beta p_old formed on the fly; alpha = rz / (p.q).
+// q = A p_new with p_new = z + beta p_old formed on the fly.
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_cg_a(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
@@ -127,7 +285,6 @@ __global__ __launch_bounds__(NT) void k_cg_a(Grid G, Op op, KVec<T, K> V, KState
             const T* r = V.r[k];
             const T* po = V.p[par][k];
             const T bk = (T)beta[k];
-            // neighbours' new direction: z_N + beta p_N with z_N = r_N / diag_N
             const T q = op.apply(k, C, P, [&](int64_t g) { return r[g] / op.diag(k, g) + bk * po[g]; });
             const T pn = r[P.g] / op.diag(k, P.g) + bk * po[P.g];
             V.p[par ^ 1][k][P.g] = pn;
@@ -135,24 +292,10 @@ __global__ __launch_bounds__(NT) void k_cg_a(Grid G, Op op, KVec<T, K> V, KState
             acc[k] += (double)pn * (double)q;
         }
     CLOT_END_CELLS
-    double sums[K];
-    if (channel_reduce<K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
-        for (int k = 0; k < K; ++k) {
-            double* s = scp(S, chid, k);
-            if (s[SC_ACT] == 0.0) continue;
-            s[SC_PQ] = sums[k];
-            if (!(sums[k] > 0.0) || !isfinite(sums[k])) {
-                s[SC_ALPHA] = 0.0;
-                s[SC_ACT] = 0.0;
-                s[SC_FAIL] = 1.0;
-            } else {
-                s[SC_ALPHA] = s[SC_RZ] / sums[k];
-            }
-        }
-    }
+    store_partials<K>(acc, S.part, tile, lds);
 }
 
-// x += alpha p; r -= alpha q; rz = r.z; convergence; beta for the next direction.
+// x += alpha p; r -= alpha q; r.z and r.r.
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_cg_b(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
@@ -169,51 +312,25 @@ __global__ __launch_bounds__(NT) void k_cg_b(Grid G, Op op, KVec<T, K> V, KState
         act[k] = s[SC_ACT] != 0.0;
     }
     CLOT_FOR_CELLS(local)
-        const Cell P = cell_at(C, local);
+        const int64_t g = C.c0 + local;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (!act[k]) continue;
             const T a = (T)alpha[k];
-            const T pn = V.p[par ^ 1][k][P.g];
-            V.x[k][P.g] += a * pn;
-            const T r = V.r[k][P.g] - a * V.t[k][P.g];
-            V.r[k][P.g] = r;
-            const T z = r / op.diag(k, P.g);
+            V.x[k][g] += a * V.p[par ^ 1][k][g];
+            const T r = V.r[k][g] - a * V.t[k][g];
+            V.r[k][g] = r;
+            const T z = r / op.diag(k, g);
             acc[2 * k] += (double)r * (double)z;
             acc[2 * k + 1] += (double)r * (double)r;
         }
     CLOT_END_CELLS
-    double sums[2 * K];
-    if (channel_reduce<2 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
-        int any = 0;
-        for (int k = 0; k < K; ++k) {
-            double* s = scp(S, chid, k);
-            if (s[SC_ACT] != 0.0) {
-                const double rz = sums[2 * k];
-                s[SC_BETA] = s[SC_RZ] != 0.0 ? rz / s[SC_RZ] : 0.0;
-                s[SC_RZ] = rz;
-                s[SC_RR] = sums[2 * k + 1];
-                s[SC_IT] += 1.0;
-                if (s[SC_RR] <= s[SC_TOL2]) s[SC_ACT] = 0.0;
-                else if (s[SC_IT] >= S.maxit || !isfinite(s[SC_RR])) {
-                    s[SC_ACT] = 0.0;
-                    s[SC_FAIL] = 1.0;
-                }
-            }
-            any |= s[SC_ACT] != 0.0;
-        }
-        if (!any) {
-            S.chact[chid] = 0;
-            atomicSub(S.nact, 1);
-        }
-    }
+    store_partials<2 * K>(acc, S.part, tile, lds);
 }
 
-// ------------------------------------------------------------------------------------
-// BiCGStab
-// ------------------------------------------------------------------------------------
+// ---- BiCGStab ----------------------------------------------------------------------
 template <class T, int K, class Op>
-__global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, KState S, double rtol) {
+__global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, KState S) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
     __shared__ double lds[5 * 2 * K];
@@ -236,31 +353,10 @@ __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, K
             acc[2 * k + 1] += (double)r * (double)r;
         }
     CLOT_END_CELLS
-    double sums[2 * K];
-    if (channel_reduce<2 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
-        int any = 0;
-        for (int k = 0; k < K; ++k) {
-            double* s = scp(S, chid, k);
-            s[SC_BB] = sums[2 * k];
-            s[SC_RR] = sums[2 * k + 1];
-            s[SC_RR0] = sums[2 * k + 1];
-            s[SC_RHO] = sums[2 * k + 1];       // rhat . r with rhat = r
-            s[SC_TOL2] = rtol * rtol * sums[2 * k];
-            s[SC_ALPHA] = 1.0;
-            s[SC_OMEGA] = 1.0;
-            s[SC_BETA] = 0.0;
-            s[SC_IT] = 0.0;
-            s[SC_FAIL] = 0.0;
-            const bool act = s[SC_BB] > 0.0 && s[SC_RR] > s[SC_TOL2];
-            s[SC_ACT] = act ? 1.0 : 0.0;
-            any |= act;
-        }
-        S.chact[chid] = any;
-        if (any) atomicAdd(S.nact, 1);
-    }
+    store_partials<2 * K>(acc, S.part, tile, lds);
 }
 
-// p_new = r + beta (p_old - omega v_old); v_new = A (p_new/diag); alpha = rho/(rhat.v_new)
+// p_new = r + beta (p_old - omega v_old); v_new = A (p_new/diag); rhat.v_new
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_1(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
@@ -293,23 +389,10 @@ __global__ __launch_bounds__(NT) void k_bicg_1(Grid G, Op op, KVec<T, K> V, KSta
             acc[k] += (double)V.rh[k][P.g] * (double)vn;
         }
     CLOT_END_CELLS
-    double sums[K];
-    if (channel_reduce<K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
-        for (int k = 0; k < K; ++k) {
-            double* s = scp(S, chid, k);
-            if (s[SC_ACT] == 0.0) continue;
-            if (sums[k] == 0.0 || !isfinite(sums[k])) {
-                s[SC_ACT] = 0.0;
-                s[SC_FAIL] = 1.0;
-                s[SC_ALPHA] = 0.0;
-            } else {
-                s[SC_ALPHA] = s[SC_RHO] / sums[k];
-            }
-        }
-    }
+    store_partials<K>(acc, S.part, tile, lds);
 }
 
-// s = r - alpha v; t = A (s/diag); omega = (t.s)/(t.t)
+// s = r - alpha v; t = A (s/diag); t.s, t.t
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_2(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
@@ -340,19 +423,10 @@ __global__ __launch_bounds__(NT) void k_bicg_2(Grid G, Op op, KVec<T, K> V, KSta
             acc[2 * k + 1] += (double)t * (double)t;
         }
     CLOT_END_CELLS
-    double sums[2 * K];
-    if (channel_reduce<2 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
-        for (int k = 0; k < K; ++k) {
-            double* s = scp(S, chid, k);
-            if (s[SC_ACT] == 0.0) continue;
-            s[SC_TS] = sums[2 * k];
-            s[SC_TT] = sums[2 * k + 1];
-            s[SC_OMEGA] = sums[2 * k + 1] > 0.0 ? sums[2 * k] / sums[2 * k + 1] : 0.0;
-        }
-    }
+    store_partials<2 * K>(acc, S.part, tile, lds);
 }
 
-// x += alpha p/diag + omega s/diag; r = s - omega t; rho_new = rhat.r; beta; convergence
+// x += alpha p/diag + omega s/diag; r = s - omega t; rhat.r, r.r
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_3(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
@@ -370,47 +444,21 @@ __global__ __launch_bounds__(NT) void k_bicg_3(Grid G, Op op, KVec<T, K> V, KSta
         act[k] = s[SC_ACT] != 0.0;
     }
     CLOT_FOR_CELLS(local)
-        const Cell P = cell_at(C, local);
+        const int64_t g = C.c0 + local;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (!act[k]) continue;
             const T a = (T)alpha[k], om = (T)omega[k];
-            const T d = op.diag(k, P.g);
-            const T sv = V.r[k][P.g] - a * V.v[par ^ 1][k][P.g];
-            V.x[k][P.g] += (a * V.p[par ^ 1][k][P.g] + om * sv) / d;
-            const T r = sv - om * V.t[k][P.g];
-            V.r[k][P.g] = r;
-            acc[2 * k] += (double)V.rh[k][P.g] * (double)r;
+            const T d = op.diag(k, g);
+            const T sv = V.r[k][g] - a * V.v[par ^ 1][k][g];
+            V.x[k][g] += (a * V.p[par ^ 1][k][g] + om * sv) / d;
+            const T r = sv - om * V.t[k][g];
+            V.r[k][g] = r;
+            acc[2 * k] += (double)V.rh[k][g] * (double)r;
             acc[2 * k + 1] += (double)r * (double)r;
         }
     CLOT_END_CELLS
-    double sums[2 * K];
-    if (channel_reduce<2 * K>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
-        int any = 0;
-        for (int k = 0; k < K; ++k) {
-            double* s = scp(S, chid, k);
-            if (s[SC_ACT] != 0.0) {
-                const double rho = sums[2 * k];
-                s[SC_RR] = sums[2 * k + 1];
-                s[SC_IT] += 1.0;
-                const double om = s[SC_OMEGA];
-                if (s[SC_RR] <= s[SC_TOL2]) {
-                    s[SC_ACT] = 0.0;
-                } else if (s[SC_IT] >= S.maxit || !isfinite(s[SC_RR]) || om == 0.0 || rho == 0.0) {
-                    s[SC_ACT] = 0.0;
-                    s[SC_FAIL] = 1.0;
-                } else {
-                    s[SC_BETA] = (rho / s[SC_RHO]) * (s[SC_ALPHA] / om);
-                    s[SC_RHO] = rho;
-                }
-            }
-            any |= s[SC_ACT] != 0.0;
-        }
-        if (!any) {
-            S.chact[chid] = 0;
-            atomicSub(S.nact, 1);
-        }
-    }
+    store_partials<2 * K>(acc, S.part, tile, lds);
 }
 
 }  // namespace clot

@@ -143,11 +143,9 @@ __global__ __launch_bounds__(NT) void k_prhs(Grid G, Fields<T> F, ModelDev M, co
 }
 
 // FP64 residual of the pressure system r = rhs - K p; stores r in the inner
-// right-hand side (arithmetic type T); sums ||r||^2 and ||rhs||^2 per channel and
-// decides on the device whether the channel needs another refinement pass.
+// right-hand side (arithmetic type T); partial sums of ||r||^2 and ||rhs||^2.
 template <class T>
-__global__ __launch_bounds__(NT) void k_pres_resid(Grid G, Fields<T> F, T* rin, T* ein, KState S, double rtol,
-                                                   double rtol_inner, int pass, int32_t* refmask) {
+__global__ __launch_bounds__(NT) void k_pres_resid(Grid G, Fields<T> F, T* rin, T* ein, KState S) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
     __shared__ double lds[5 * 2];
@@ -164,29 +162,36 @@ __global__ __launch_bounds__(NT) void k_pres_resid(Grid G, Fields<T> F, T* rin, 
         acc[0] += r * r;
         acc[1] += b * b;
     CLOT_END_CELLS
-    double sums[2];
-    if (channel_reduce<2>(acc, S.part, S.tick + chid, C, tile, lds, sums) && threadIdx.x == 0) {
-        double* s = scp(S, chid, 0);
-        // outer record: slot SC_RR0 keeps ||r|| of this pass for the stats
+    store_partials<2>(acc, S.part, tile, lds);
+}
+
+// Decides on the device whether a channel needs another refinement pass, and the
+// inner solve's target: a fraction of this residual, not below the outer goal.
+struct EpiPresResid {
+    double rtol, rtol_inner;
+    int pass;
+    int32_t* refmask;
+    __device__ void operator()(const double* sums, const KState& S, int ch) const {
+        double* s = scp(S, ch, 0);
         s[SC_RR0] = sums[0];
         s[SC_BB] = sums[1];
+        s[SC_PASS] = (double)pass;
         const double target2 = rtol * rtol * sums[1];
         if (sums[0] <= target2 || sums[1] == 0.0 || !isfinite(sums[0])) {
-            S.chact[chid] = 0;
-            refmask[chid] = 0;
+            S.chact[ch] = 0;
+            refmask[ch] = 0;
             atomicSub(S.nact, 1);
             s[SC_ACT] = 0.0;
             if (!isfinite(sums[0])) s[SC_FAIL] = 1.0;
         } else {
-            // inner solve target: a fraction of this residual, not below the outer goal
             const double inner2 = rtol_inner * rtol_inner * sums[0];
             s[SC_TOL2] = inner2 > 0.25 * target2 ? inner2 : 0.25 * target2;
             s[SC_ACT] = 1.0;
             s[SC_PASS] = (double)(pass + 1);
-            refmask[chid] = 1;
+            refmask[ch] = 1;
         }
     }
-}
+};
 
 // p += e (FP64 accumulation of the inner correction).
 template <class T>
