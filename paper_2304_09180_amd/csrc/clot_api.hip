@@ -774,7 +774,7 @@ struct Ctx : clot_ctx {
 
     template <int NV, class E>
     void finish(const E& e) {
-        hipLaunchKernelGGL((k_finish<NV, E>), dim3((int)ch.size()), dim3(NT), 0, st, d_ch, S, e);
+        hipLaunchKernelGGL((k_finish<NV, E>), dim3((int)ch.size()), dim3(FIN_BS), 0, st, d_ch, S, e);
     }
 
     // Pressure preconditioner setup: coarse operators from the current rAU.

@@ -120,23 +120,25 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double* lds /* NV*NT/64 */) {
+// Block-wide sums of NV values; lds holds NV*(BS/64 + 1) doubles.
+template <int NV, int BS = NT>
+__device__ inline void block_sum(double (&v)[NV], double* lds) {
+    constexpr int NW = BS / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         double s = wave_sum(v[q]);
-        if (lane == 0) lds[q * (NT / 64) + w] = s;
+        if (lane == 0) lds[q * NW + w] = s;
     }
     __syncthreads();
     if (threadIdx.x < NV) {
         double s = 0.0;
-        for (int ww = 0; ww < NT / 64; ++ww) s += lds[threadIdx.x * (NT / 64) + ww];
-        lds[NV * (NT / 64) + threadIdx.x] = s;
+        for (int ww = 0; ww < NW; ++ww) s += lds[threadIdx.x * NW + ww];
+        lds[NV * NW + threadIdx.x] = s;
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = lds[NV * (NT / 64) + q];
+    for (int q = 0; q < NV; ++q) v[q] = lds[NV * NW + q];
 }
 
 // Writes the block's totals of v[] as the tile partials part[tile*NV + q].  The

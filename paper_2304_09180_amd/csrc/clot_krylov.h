@@ -57,21 +57,23 @@ struct KVec {
 
 #define CLOT_END_CELLS }
 
-// Sums the tile partials of each active channel and runs the phase epilogue.
+// Sums the tile partials of each active channel (fixed order) and runs the phase
+// epilogue in thread 0.  One 1024-thread block per channel.
+constexpr int FIN_BS = 1024;
 template <int NV, class Epi>
-__global__ __launch_bounds__(NT) void k_finish(const ChanDev* chans, KState S, Epi epi) {
+__global__ __launch_bounds__(FIN_BS) void k_finish(const ChanDev* chans, KState S, Epi epi) {
     const int chid = blockIdx.x;
     if (!S.chact[chid]) return;
     const int32_t t0 = chans[chid].t0, nt = chans[chid].nt;
-    __shared__ double lds[5 * NV];
+    __shared__ double lds[NV * (FIN_BS / 64 + 1)];
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    for (int t = threadIdx.x; t < nt; t += NT) {
+    for (int t = threadIdx.x; t < nt; t += FIN_BS) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] += S.part[(int64_t)(t0 + t) * NV + q];
     }
-    block_sum<NV>(acc, lds);
+    block_sum<NV, FIN_BS>(acc, lds);
     if (threadIdx.x == 0) epi(acc, S, chid);
 }
 
