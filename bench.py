@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--probe", default="p_cg_a", help="kernel phase timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
+    ap.add_argument("--train-samples", type=int, default=400_000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -106,6 +108,65 @@ def cpu_baseline(desc):
             "seconds": el}
 
 
+def timed_steps(s, steps, probe):
+    """Runs `steps` steps between events on the library stream; returns (seconds,
+    probe ms, probe launches)."""
+    import torch
+    stream = s.stream
+    s.probe(probe)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step_async(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    pm, pn = s.probe_read()
+    s.probe(None)
+    return max(ms / 1e3, wall), pm, pn
+
+
+def kernel_us(s, probe, steps=2):
+    """Average launch time of one kernel phase over a few extra steps."""
+    _, pm, pn = timed_steps(s, steps, probe)
+    return round(1e3 * pm / pn, 3) if pn else None
+
+
+def surrogate_leg(desc, prec, args, xc, xf):
+    """Trains the reaction surrogate on the GPU (2-D channel states), then times the
+    same workload with the learned reaction step."""
+    from paper_2304_09180_amd import clot, surrogate
+    t0 = time.perf_counter()
+    states = surrogate.default_training_states(log=lambda m: print(m, file=sys.stderr, flush=True))
+    rows = surrogate.sample_rows(states, args.train_samples)
+    tr = surrogate.Trainer(rows, log=lambda m: print(m, file=sys.stderr, flush=True))
+    l0 = tr.loss()
+    hist = tr.train(epochs=12)
+    held = surrogate.sample_rows(states, 50_000, seed=99, dt_range=(2e-4, 1e-3))
+    held_net, held_zero = tr.heldout_gain(held)
+    t_train = time.perf_counter() - t0
+    blob = tr.blob()
+    s = clot.Solver([desc], prec)
+    s.init_state(0, xc, xf)
+    s.set_reaction_mode(clot.SURROGATE, blob, 1e-3)
+    for _ in range(args.warmup):
+        s.step(1)
+    el, _, _ = timed_steps(s, args.steps, "rxn")
+    st = s.stats(0)
+    ncell = desc["nx"] * desc["ny"] * desc["nz"]
+    out = {"value": ncell * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
+           "rxn_kernel_us": kernel_us(s, "rxn"), "fallback_kernel_us": kernel_us(s, "rxn_fallback"),
+           "fallback_frac": st["fallback_frac"], "resid_tol": 1e-3,
+           "training": {"samples": args.train_samples, "epochs": 12, "seconds": round(t_train, 2),
+                        "loss_start": l0, "loss_end": hist[-1],
+                        "heldout_mse_network": held_net, "heldout_mse_midpoint_alone": held_zero}}
+    s.close()
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -131,24 +192,10 @@ def main():
         s.step(1)
         print(f"# warmup step {w + 1}/{args.warmup} {s.stats(0)}", file=sys.stderr, flush=True)
 
-    stream = s.stream
-    s.probe(args.probe)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    s.step_async(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    probe_ms, probe_n = s.probe_read()
-    s.probe(None)
+    el, probe_ms, probe_n = timed_steps(s, args.steps, args.probe)
     st = s.stats(0)
-    print(f"# timed {args.steps} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms) {st}", file=sys.stderr, flush=True)
-
-    el = max(ms / 1e3, wall)
+    print(f"# timed {args.steps} steps: {el * 1e3:.1f} ms {st}", file=sys.stderr, flush=True)
+    rxn_us = kernel_us(s, "rxn")
     value = ncell * args.steps / el
     bpe = 4 if prec == clot.FP32_MIXED else 8
     nbytes = ARRAYS[args.probe](desc["dim"]) * bpe * ncell
@@ -169,8 +216,11 @@ def main():
                       "precision": "fp32 fields, fp64 reductions and pressure" if prec == clot.FP32_MIXED else "fp64",
                       "reaction": "plain RK4"},
            "solver": {k: st[k] for k in ("it_mom", "it_p", "it_eta", "it_tr", "refine_p")},
+           "rxn_kernel_us": rxn_us,
            "roofline": roof}
     s.close()
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(desc, prec, args, xc, xf)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc)
     print(json.dumps(out), flush=True)

@@ -63,6 +63,7 @@ typedef enum {
     CLOT_S1B, CLOT_S2B, CLOT_E1B, CLOT_E2B, CLOT_C1, CLOT_C2,   /* 15 cell species          */
     CLOT_E0, CLOT_C0,                                            /* injury-face species     */
     CLOT_ETA, CLOT_THETAB, CLOT_SIGMA,                           /* derived, read only      */
+    CLOT_HADH,                                                   /* adhesion mask, read only */
     CLOT_NFIELDS
 } clot_field;
 
@@ -177,10 +178,47 @@ typedef enum {
     CLOT_PROBE_PRHS = 16,
     CLOT_PROBE_MOM_ASM = 17,
     CLOT_PROBE_P_MG_POST = 18,  /* pressure multigrid: finest-level smoothing sweep + r.z  */
+    CLOT_PROBE_RXN_FALLBACK = 19, /* plain RK4 on the cells the surrogate rejected          */
     CLOT_PROBE_NKERNELS
 } clot_probe_kernel;
 clot_status clot_probe(clot_ctx* c, int32_t kernel);
 clot_status clot_probe_read(clot_ctx* c, double* total_ms, int64_t* launches);
+
+/* ---- learned reaction step: training and data (device pointers, caller's stream) ----
+ * The surrogate (clot_set_reaction_mode) predicts the reaction increment of one
+ * step as f (1 + clamp(sc_i c_i, -1/2, 1/2)) with f = Dt R(y + Dt R(y)/2) the
+ * explicit-midpoint increment and c = MLP(features): 32 inputs -> 64 tanh -> 64 tanh -> 16 outputs (14 used),
+ * BF16 weights/activations, FP32 accumulate.  The parameter vector (float32,
+ * clot_mlp_nparam() entries) is W1[64][32] b1[64] W2[64][64] b2[64] W3[16][64]
+ * b3[16]; the mode blob appends sf[14] and sc[14], the RMS over the training set of
+ * the scaled explicit increments f/s and of the relative corrections (RK4 - f)/|f|.  The plain RK4 step (section 3.2) is the judge: a cell whose
+ * relative midpoint defect exceeds resid_tol is recomputed by it.
+ * State rows for the batch calls: 18 float64 each = 14 species (Pmu Pma Pba Pbse S1
+ * S2 E1 E2 S1b S2b E1b E2b C1 C2), ADP, eta, H_adh, Dt. */
+int64_t clot_mlp_nparam(void);
+size_t clot_mlp_backward_workspace(int64_t n);
+/* y = MLP(x); x bf16 [n][32], y f32 [n][16]; cache (optional) bf16 [n][128] activations */
+clot_status clot_mlp_forward(const float* w_f32, const uint16_t* w_bf16, const uint16_t* x_bf16, int64_t n,
+                             float* y_f32, uint16_t* cache_bf16, void* hip_stream);
+/* dw = d loss / d params given dy = d loss / d y; part: clot_mlp_backward_workspace(n) bytes */
+clot_status clot_mlp_backward(const float* w_f32, const uint16_t* w_bf16, const uint16_t* x_bf16,
+                              const uint16_t* cache_bf16, const float* dy_f32, int64_t n, float* part, float* dw_f32,
+                              void* hip_stream);
+/* Adam step t (>= 1) on the float32 master parameters; refreshes the bf16 copy */
+clot_status clot_mlp_adam(float* w_f32, uint16_t* w_bf16, const float* grad, float* m, float* v, int64_t t,
+                          double lr, double beta1, double beta2, double eps, void* hip_stream);
+/* mean squared error over the first nuse outputs: dy, and per-256-sample loss partials */
+clot_status clot_mlp_mse(const float* y, const float* target, int64_t n, int32_t nuse, float* dy, double* loss_part,
+                         void* hip_stream);
+/* plain RK4 reaction increments (M_rxn sub-steps, FP64) of n state rows: inc [n][14] */
+clot_status clot_rxn_rk4_batch(const clot_params* p, const double* rows, int64_t n, double* inc, void* hip_stream);
+/* training set from rows and their RK4 increments: bf16 features [n][32] and f32 targets
+ * [n][16] with scales = sf[14], sc[14]; or, with stats != NULL, per-256-row block sums
+ * (42 per block): squares of f/s, squares of the relative corrections, count of f != 0 */
+clot_status clot_surr_dataset(const clot_params* p, const double* rows, const double* inc, int64_t n,
+                              const float* scales, uint16_t* x_bf16, float* target, double* stats, void* hip_stream);
+/* checks the MFMA operand layout: D = A B for 16x16 bf16 A, B (row major), f32 D */
+clot_status clot_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, void* hip_stream);
 
 void clot_destroy(clot_ctx* c);
 const char* clot_last_error(const clot_ctx* c);

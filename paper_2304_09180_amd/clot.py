@@ -19,7 +19,7 @@ PLAIN, SURROGATE = 0, 1
 
 FIELDS = ["UX", "UY", "UZ", "P", "PHIX", "PHIY", "PHIZ",
           "PMU", "PMA", "PBA", "PBSE", "ADP", "S1", "S2", "E1", "E2",
-          "S1B", "S2B", "E1B", "E2B", "C1", "C2", "E0", "C0", "ETA", "THETAB", "SIGMA"]
+          "S1B", "S2B", "E1B", "E2B", "C1", "C2", "E0", "C0", "ETA", "THETAB", "SIGMA", "HADH"]
 FIELD = {n: i for i, n in enumerate(FIELDS)}
 SPECIES_FIELDS = FIELDS[7:22]
 
@@ -88,6 +88,15 @@ def load():
         "clot_set_reaction_mode": ([P, C.c_int, P, C.c_size_t, C.c_double], C.c_int),
         "clot_probe": ([P, C.c_int32], C.c_int),
         "clot_probe_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+        "clot_mlp_nparam": ([], C.c_int64),
+        "clot_mlp_backward_workspace": ([C.c_int64], C.c_size_t),
+        "clot_mlp_forward": ([P, P, P, C.c_int64, P, P, P], C.c_int),
+        "clot_mlp_backward": ([P, P, P, P, P, C.c_int64, P, P, P], C.c_int),
+        "clot_mlp_adam": ([P, P, P, P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, P], C.c_int),
+        "clot_mlp_mse": ([P, P, C.c_int64, C.c_int32, P, P, P], C.c_int),
+        "clot_rxn_rk4_batch": ([C.POINTER(Params), P, C.c_int64, P, P], C.c_int),
+        "clot_surr_dataset": ([C.POINTER(Params), P, P, C.c_int64, P, P, P, P, P], C.c_int),
+        "clot_mfma_selftest": ([P, P, P, P], C.c_int),
         "clot_destroy": ([P], None),
         "clot_last_error": ([P], C.c_char_p),
     }
@@ -103,12 +112,14 @@ def exported_symbols():
     """Names the C header declares (for the load/export check)."""
     return ["clot_params_default", "clot_query_workspace", "clot_create", "clot_init_state", "clot_field_count",
             "clot_set_field", "clot_get_field", "clot_step", "clot_step_async", "clot_sync", "clot_get_stats",
-            "clot_set_reaction_mode", "clot_probe", "clot_probe_read", "clot_destroy", "clot_last_error"]
+            "clot_set_reaction_mode", "clot_probe", "clot_probe_read", "clot_destroy", "clot_last_error",
+            "clot_mlp_nparam", "clot_mlp_backward_workspace", "clot_mlp_forward", "clot_mlp_backward",
+            "clot_mlp_adam", "clot_mlp_mse", "clot_rxn_rk4_batch", "clot_surr_dataset", "clot_mfma_selftest"]
 
 
 PROBES = {"p_cg_a": 1, "p_cg_b": 2, "tr_b1": 3, "tr_b2": 4, "tr_b3": 5, "mom_b1": 6, "mom_b2": 7, "mom_b3": 8,
           "rxn": 9, "tr_asm": 10, "eta_cg_a": 11, "eta_cg_b": 12, "p_resid": 13, "correct": 14, "hbya": 15,
-          "prhs": 16, "mom_asm": 17, "p_mg_post": 18}
+          "prhs": 16, "mom_asm": 17, "p_mg_post": 18, "rxn_fallback": 19}
 
 
 def default_params(precision=FP64, **over) -> Params:
@@ -127,6 +138,16 @@ def default_params(precision=FP64, **over) -> Params:
 def channel_struct(d: dict) -> Channel:
     return Channel(d["dim"], d["nx"], d["ny"], d["nz"], d["Lx"], d["Ly"], d["Lz"], d["inj_x0"], d["inj_x1"],
                    d["inj_z0"], d["inj_z1"], d["shear"], d["K_y"], d["K_z"], d["dt"])
+
+
+def ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def check(st, what):
+    if st != 0:
+        raise ClotError(f"{what} failed: {STATUS.get(st, st)}")
 
 
 def _check(lib, ctx, st, what):
@@ -214,6 +235,14 @@ class Solver:
                 "it_tr": s.it_tr, "refine_p": list(s.refine_p), "res_mom": s.res_mom, "res_p": s.res_p,
                 "res_eta": s.res_eta, "res_tr": s.res_tr, "fallback_frac": s.fallback_frac, "steps": s.steps,
                 "t": s.t}
+
+    def set_reaction_mode(self, mode, blob=None, tol=1e-3):
+        """PLAIN, or SURROGATE with a float32 blob (MLP parameters + 28 scales)."""
+        if mode == PLAIN:
+            return _check(self.lib, self.ctx, self.lib.clot_set_reaction_mode(self.ctx, PLAIN, None, 0, 0.0), "rxn mode")
+        b = np.ascontiguousarray(blob, dtype=np.float32)
+        return _check(self.lib, self.ctx, self.lib.clot_set_reaction_mode(self.ctx, SURROGATE, b.ctypes.data, b.nbytes,
+                                                                         float(tol)), "rxn mode")
 
     def probe(self, name):
         """Start timing every launch of one kernel phase (name in PROBES, or None to stop)."""

@@ -3,6 +3,7 @@
 #include "../../include/clot.h"
 #include "clot_step.h"
 #include "clot_mg.h"
+#include "clot_surr.h"
 
 #include <algorithm>
 #include <array>
@@ -85,6 +86,7 @@ struct clot_ctx {
     virtual clot_status sync() = 0;
     virtual clot_status stats(int ch, clot_stats* s) const = 0;
     virtual clot_status probe(int id) = 0;
+    virtual clot_status set_rxn(clot_rxn_mode mode, const void* blob, size_t nb, double tol) = 0;
     virtual clot_status probe_read(double* ms, int64_t* n) = 0;
 };
 
@@ -154,6 +156,15 @@ struct Ctx : clot_ctx {
     T* mg_y0 = nullptr;      // level-0 smoother scratch
     T* mg_z0 = nullptr;      // preconditioned residual z = M r
     double* mg_inv = nullptr;  // per-channel inverse of the coarsest-level matrix
+    // reaction surrogate
+    clot_rxn_mode rxn_mode = CLOT_RXN_PLAIN;
+    float surr_tol = 1e-3f;
+    SurrTables surr_tb{};
+    uint16_t* mlp_wb = nullptr;
+    float* mlp_wf = nullptr;
+    int32_t* fb_list = nullptr;
+    int32_t* fb_count = nullptr;
+    int32_t* fb_chan = nullptr;
     int probe_id = 0;
     std::vector<hipEvent_t> evs;
     int ev_used = 0;
@@ -191,6 +202,41 @@ struct Ctx : clot_ctx {
         probe_n = 0;
         return CLOT_OK;
     }
+    clot_status set_rxn(clot_rxn_mode mode, const void* blob, size_t nb, double tol) override {
+        if (mode == CLOT_RXN_PLAIN) {
+            rxn_mode = mode;
+            return CLOT_OK;
+        }
+        if (mode != CLOT_RXN_SURROGATE || !blob || nb != (MLP_NPARAM + 2 * MLP_NSP) * sizeof(float) || !(tol >= 0.0)) {
+            err = "set_reaction_mode: expected a float32 blob of MLP parameters + 28 scales and tol >= 0";
+            return CLOT_EINVAL;
+        }
+        const float* f = (const float*)blob;
+        std::vector<uint16_t> wb(MLP_NPARAM);
+        for (int q = 0; q < MLP_NPARAM; ++q) {
+            if (!std::isfinite(f[q])) {
+                err = "set_reaction_mode: non-finite weight";
+                return CLOT_EINVAL;
+            }
+            wb[q] = f2bf(f[q]);
+        }
+        species_scales(M, surr_tb.s);
+        for (int i = 0; i < MLP_NSP; ++i) {
+            surr_tb.sf[i] = f[MLP_NPARAM + i];
+            surr_tb.sc[i] = f[MLP_NPARAM + MLP_NSP + i];
+            if (!(surr_tb.sf[i] > 0.f) || !(surr_tb.sc[i] > 0.f)) {
+                err = "set_reaction_mode: scales must be positive";
+                return CLOT_EINVAL;
+            }
+        }
+        HIPCHK(hipMemcpyAsync(mlp_wf, f, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(mlp_wb, wb.data(), MLP_NPARAM * sizeof(uint16_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        rxn_mode = mode;
+        surr_tol = (float)tol;
+        return CLOT_OK;
+    }
+
     clot_status probe_read(double* ms, int64_t* n) override {
         HIPCHK(hipStreamSynchronize(st));
         probe_collect();
@@ -257,6 +303,11 @@ struct Ctx : clot_ctx {
         mg_y0 = cv.take<T>(N);
         mg_z0 = cv.take<T>(N);
         mg_inv = cv.take<double>((size_t)nch * MG_COARSE * MG_COARSE);
+        mlp_wb = cv.take<uint16_t>(MLP_NPARAM);
+        mlp_wf = cv.take<float>(MLP_NPARAM);
+        fb_list = cv.take<int32_t>(N);
+        fb_count = cv.take<int32_t>(1);
+        fb_chan = cv.take<int32_t>(nch);
         for (Level& L : lev) {
             L.d_ch = cv.take<ChanDev>(nch);
             L.d_t2c = cv.take<int32_t>(std::max(L.ntiles, 1));
@@ -652,6 +703,7 @@ struct Ctx : clot_ctx {
             case CLOT_ETA: return {F.eta + h.c0, n, false, true};
             case CLOT_THETAB: return {F.thB_prev + h.c0, n, false, true};
             case CLOT_SIGMA: return {F.sigma + h.c0, n, false, true};
+            case CLOT_HADH: return {nullptr, n, false, true};
             default:
                 if (f >= CLOT_PMU && f <= CLOT_C2) return {F.spc[f - CLOT_PMU] + h.c0, n, false, false};
         }
@@ -660,7 +712,7 @@ struct Ctx : clot_ctx {
 
     clot_status count(int c, clot_field f, size_t* n) const override {
         FieldRef r = ref(c, f);
-        if (!r.ptr && r.n == 0 && f != CLOT_UZ && f != CLOT_PHIZ) {
+        if (!r.ptr && r.n == 0 && f != CLOT_UZ && f != CLOT_PHIZ && f != CLOT_HADH) {
             const_cast<Ctx*>(this)->err = "unknown field";
             return CLOT_EINVAL;
         }
@@ -697,6 +749,16 @@ struct Ctx : clot_ctx {
         if ((int64_t)n != r.n || (!h && n)) {
             err = "get_field: size mismatch";
             return CLOT_EINVAL;
+        }
+        if (f == CLOT_HADH) {   // adhesion mask: cells j < jadh over the injury patch
+            const ChanHost& q = ch[c];
+            for (int k = 0; k < q.d.nz; ++k)
+                for (int j = 0; j < q.d.ny; ++j)
+                    for (int i = 0; i < q.d.nx; ++i)
+                        h[i + (int64_t)q.d.nx * (j + (int64_t)q.d.ny * k)] =
+                            (j < q.jadh && i >= q.inj_i0 && i < q.inj_i0 + q.inj_ni && k >= q.inj_k0 &&
+                             k < q.inj_k0 + q.inj_nk) ? 1.0 : 0.0;
+            return CLOT_OK;
         }
         HIPCHK(hipStreamSynchronize(st));
         if (r.dbl) {
@@ -1030,7 +1092,20 @@ struct Ctx : clot_ctx {
         // O-6 reactions (wall first: it reads the transported S1)
         if (NINJ > 0)
             hipLaunchKernelGGL(k_wall_rxn<T>, dim3((NINJ + NT - 1) / NT), tb, 0, st, d_ch, d_f2c, NINJ, F, M);
-        CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn<T>, gb, tb, 0, st, G, F, M);
+        if (rxn_mode == CLOT_RXN_SURROGATE) {
+            fill(fb_count, 0, 1);
+            fill(fb_chan, 0, nch);
+            MLPWeights w{mlp_wb + MLP_OFF_W1, mlp_wb + MLP_OFF_W2, mlp_wb + MLP_OFF_W3,
+                         mlp_wf + MLP_OFF_B1, mlp_wf + MLP_OFF_B2, mlp_wf + MLP_OFF_B3};
+            CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn_surr<T>, gb, dim3(256), 0, st, G, F, M, w, surr_tb, surr_tol, fb_list,
+                        fb_count, fb_chan);
+            CLOT_LAUNCH(CLOT_PROBE_RXN_FALLBACK, k_rxn_list<T>, dim3((N + NT - 1) / NT), tb, 0, st, d_ch, nch, F, M,
+                        fb_list, fb_count);
+            hipLaunchKernelGGL(k_record_fallback, dim3(1), dim3(64), 0, st, fb_chan, d_ch, dstats, NSTAT, nch,
+                               (int)ST_FALLBACK);
+        } else {
+            CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn<T>, gb, tb, 0, st, G, F, M);
+        }
         // O-7 rotate theta_B and the flux
         std::swap(F.thB, F.thB_prev);
         for (int c = 0; c < 3; ++c) std::swap(F.phi[c], F.phin[c]);
@@ -1090,6 +1165,19 @@ static clot_ctx* make_ctx(clot_precision prec) {
 template <class T>
 static size_t ws_size(Ctx<T>* c) {
     return c->layout(nullptr);
+}
+
+static ModelDev model_from_params(const clot_params& q) {
+    ModelDev M{q.nu, q.C_CK, q.D_P, q.D_ADP, q.D_chem, q.P_diam, q.P_max, q.P_0, q.k_adh, q.kcoh_Pmax,
+               q.eta_t, q.eta_star, 0.0, q.k_adp, q.adp_crit, q.k_e2, q.e2_crit,
+               q.A_hat, q.tau_f, q.dtau, q.N_A, q.N1, q.N2,
+               q.kC0p, q.kC0m, q.kC0cat, q.kC1p, q.kC1m, q.kC1cat, q.kC2p, q.kC2m, q.kC2cat,
+               q.kS1p, q.kS1m, q.kE1p, q.kE1m, q.kS2p, q.kS2m, q.kE2p, q.kE2m,
+               q.S1_0, q.S2_0, q.E0_0, q.p_out, 0.0, q.M_rxn};
+    const double Le = q.L_eta_over_Pdiam * q.P_diam;
+    M.kappa_eta = Le * Le / 4.0;
+    M.g0 = (std::pow(q.eta_star, 3) + std::pow(1.0 - q.eta_t, 3)) / std::pow(1.0 - q.eta_t, 3);
+    return M;
 }
 
 template <class T>
@@ -1248,10 +1336,95 @@ clot_status clot_get_stats(const clot_ctx* c, int32_t chn, clot_stats* s) {
 }
 clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* blob, size_t nb, double tol) {
     if (!c) return CLOT_EINVAL;
-    if (mode != CLOT_RXN_PLAIN) {
-        c->err = "surrogate reaction mode is not available in this build";
-        return CLOT_ESTATE;
+    return c->set_rxn(mode, blob, nb, tol);
+}
+
+// ---- surrogate training and data preparation (device pointers, caller's stream) ----
+#define CHK_LAUNCH()                                              \
+    do {                                                          \
+        if (hipGetLastError() != hipSuccess) return CLOT_EHIP;    \
+    } while (0)
+
+static MLPWeights mlp_ptrs(const float* wf, const uint16_t* wb) {
+    return MLPWeights{wb + MLP_OFF_W1, wb + MLP_OFF_W2, wb + MLP_OFF_W3, wf + MLP_OFF_B1, wf + MLP_OFF_B2, wf + MLP_OFF_B3};
+}
+
+int64_t clot_mlp_nparam(void) { return MLP_NPARAM; }
+
+size_t clot_mlp_backward_workspace(int64_t n) {
+    const int64_t nblk = (n + 63) / 64;
+    return (size_t)nblk * MLP_NPARAM * sizeof(float);
+}
+
+clot_status clot_mlp_forward(const float* wf, const uint16_t* wb, const uint16_t* x, int64_t n, float* y, uint16_t* cache,
+                             void* stream) {
+    if (!wf || !wb || !x || !y || n < 0) return CLOT_EINVAL;
+    if (n == 0) return CLOT_OK;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, (hipStream_t)stream, mlp_ptrs(wf, wb), x,
+                       n, y, cache);
+    CHK_LAUNCH();
+    return CLOT_OK;
+}
+
+clot_status clot_mlp_backward(const float* wf, const uint16_t* wb, const uint16_t* x, const uint16_t* cache,
+                              const float* dy, int64_t n, float* part, float* dw, void* stream) {
+    if (!wf || !wb || !x || !cache || !dy || !part || !dw || n <= 0) return CLOT_EINVAL;
+    const int nblk = (int)((n + 63) / 64);
+    hipLaunchKernelGGL(k_mlp_backward, dim3(nblk), dim3(256), 0, (hipStream_t)stream, mlp_ptrs(wf, wb), x, cache, dy, n,
+                       part);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)stream, part, nblk, dw);
+    CHK_LAUNCH();
+    return CLOT_OK;
+}
+
+clot_status clot_mlp_adam(float* wf, uint16_t* wb, const float* g, float* m, float* v, int64_t t, double lr, double b1,
+                          double b2, double eps, void* stream) {
+    if (!wf || !wb || !g || !m || !v || t < 1) return CLOT_EINVAL;
+    const float bc1 = (float)(1.0 - std::pow(b1, (double)t)), bc2 = (float)(1.0 - std::pow(b2, (double)t));
+    hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)stream, wf, wb, g, m, v,
+                       (int64_t)MLP_NPARAM, (float)lr, (float)b1, (float)b2, (float)eps, bc1, bc2);
+    CHK_LAUNCH();
+    return CLOT_OK;
+}
+
+clot_status clot_mlp_mse(const float* y, const float* t, int64_t n, int32_t nuse, float* dy, double* lpart,
+                         void* stream) {
+    if (!y || !t || !dy || !lpart || n <= 0 || nuse < 1 || nuse > MLP_OUT) return CLOT_EINVAL;
+    hipLaunchKernelGGL(k_mlp_mse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, y, t, n, nuse, dy,
+                       lpart);
+    CHK_LAUNCH();
+    return CLOT_OK;
+}
+
+clot_status clot_rxn_rk4_batch(const clot_params* p, const double* rows, int64_t n, double* inc, void* stream) {
+    if (!p || !rows || !inc || n < 0 || p->M_rxn < 1) return CLOT_EINVAL;
+    if (n == 0) return CLOT_OK;
+    hipLaunchKernelGGL(k_rxn_batch, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, (hipStream_t)stream, rows, n,
+                       model_from_params(*p), inc);
+    CHK_LAUNCH();
+    return CLOT_OK;
+}
+
+clot_status clot_surr_dataset(const clot_params* p, const double* rows, const double* inc, int64_t n,
+                              const float* scales, uint16_t* x, float* t, double* stats, void* stream) {
+    if (!p || !rows || !inc || n <= 0 || (!stats && (!scales || !x || !t))) return CLOT_EINVAL;
+    const ModelDev M = model_from_params(*p);
+    SurrTables tb{};
+    species_scales(M, tb.s);
+    for (int i = 0; i < MLP_NSP; ++i) {
+        tb.sf[i] = scales ? scales[i] : 1.f;
+        tb.sc[i] = scales ? scales[MLP_NSP + i] : 1.f;
     }
+    hipLaunchKernelGGL(k_surr_dataset, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, (hipStream_t)stream, rows, inc, n,
+                       M, tb, x, t, stats);
+    CHK_LAUNCH();
+    return CLOT_OK;
+}
+
+clot_status clot_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, void* stream) {
+    if (!A || !B || !D) return CLOT_EINVAL;
+    hipLaunchKernelGGL(k_mfma_selftest, dim3(1), dim3(64), 0, (hipStream_t)stream, A, B, D);
+    CHK_LAUNCH();
     return CLOT_OK;
 }
 clot_status clot_probe(clot_ctx* c, int32_t kernel) {

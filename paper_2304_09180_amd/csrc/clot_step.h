@@ -407,6 +407,26 @@ __device__ inline T binding_g(T eta, const ModelDev& M) {
     return T(M.g0) * e3 / (s3 + e3);
 }
 
+// M_rxn classical RK4 sub-steps of size h on one cell's 14 reacting species.
+template <class T>
+__device__ inline void rk4_cell(T (&y)[NRX], T adp, T gam, T hadh, T h, const ModelDev& M) {
+    for (int m = 0; m < M.M_rxn; ++m) {
+        T k1[NRX], k2[NRX], k3[NRX], k4[NRX], w[NRX];
+        rxn_rhs(y, adp, gam, hadh, M, k1);
+#pragma unroll
+        for (int q = 0; q < NRX; ++q) w[q] = y[q] + T(0.5) * h * k1[q];
+        rxn_rhs(w, adp, gam, hadh, M, k2);
+#pragma unroll
+        for (int q = 0; q < NRX; ++q) w[q] = y[q] + T(0.5) * h * k2[q];
+        rxn_rhs(w, adp, gam, hadh, M, k3);
+#pragma unroll
+        for (int q = 0; q < NRX; ++q) w[q] = y[q] + h * k3[q];
+        rxn_rhs(w, adp, gam, hadh, M, k4);
+#pragma unroll
+        for (int q = 0; q < NRX; ++q) y[q] += h / T(6) * (k1[q] + T(2) * k2[q] + T(2) * k3[q] + k4[q]);
+    }
+}
+
 // Reactive wall: S1 wall value from the Robin balance with the transported S1,
 // then M_rxn RK4 sub-steps of eqs. seBound_E0/C0 per injury face (Appendix B).
 template <class T>
@@ -469,22 +489,7 @@ __global__ __launch_bounds__(NT) void k_rxn(Grid G, Fields<T> F, ModelDev M) {
         const bool hin = P.j < C.jadh && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
                          P.k < C.inj_k0 + C.inj_nk;
         const T hadh = hin ? T(1) : T(0);
-        const T h = T(C.dt / M.M_rxn);
-        for (int m = 0; m < M.M_rxn; ++m) {
-            T k1[NRX], k2[NRX], k3[NRX], k4[NRX], w[NRX];
-            rxn_rhs(y, adp, gam, hadh, M, k1);
-#pragma unroll
-            for (int q = 0; q < NRX; ++q) w[q] = y[q] + T(0.5) * h * k1[q];
-            rxn_rhs(w, adp, gam, hadh, M, k2);
-#pragma unroll
-            for (int q = 0; q < NRX; ++q) w[q] = y[q] + T(0.5) * h * k2[q];
-            rxn_rhs(w, adp, gam, hadh, M, k3);
-#pragma unroll
-            for (int q = 0; q < NRX; ++q) w[q] = y[q] + h * k3[q];
-            rxn_rhs(w, adp, gam, hadh, M, k4);
-#pragma unroll
-            for (int q = 0; q < NRX; ++q) y[q] += h / T(6) * (k1[q] + T(2) * k2[q] + T(2) * k3[q] + k4[q]);
-        }
+        rk4_cell(y, adp, gam, hadh, T(C.dt / M.M_rxn), M);
         F.spc[PMU][g] = y[0];
         F.spc[PMA][g] = y[1];
         F.spc[PBA][g] = y[2];
@@ -538,6 +543,13 @@ __global__ void k_record_pass(const double* sc, double* stats, int nstat, int nc
         if (s[SC_BB] > 0.0) stats[(int64_t)c * nstat + slot_res] = sqrt(s[SC_RR0] / s[SC_BB]);
         stats[(int64_t)c * nstat + slot_fail] = fmax(stats[(int64_t)c * nstat + slot_fail], s[SC_FAIL]);
     }
+}
+
+// Surrogate fallback fraction per channel.
+__global__ void k_record_fallback(const int32_t* fb_chan, const ChanDev* chans, double* stats, int nstat, int nch,
+                                  int slot) {
+    for (int c = threadIdx.x; c < nch; c += blockDim.x)
+        stats[(int64_t)c * nstat + slot] = (double)fb_chan[c] / (double)chans[c].ncell;
 }
 
 // Small utility kernels (graph-safe replacements for memset).

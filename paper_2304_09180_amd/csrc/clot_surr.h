@@ -1,0 +1,289 @@
+// Learned reaction step (gfx950).
+//
+// The surrogate predicts the reaction increment of one transport step Dt as the
+// explicit-midpoint increment f = Dt R(y + Dt R(y)/2) (two right-hand sides) times a
+// learned relative correction:
+//     Delta_i = f_i (1 + clamp(sc_i c_i, -1/2, 1/2)),   c = MLP(features),
+// with sc_i the RMS over the training set of (Delta_RK4 - f)_i / |f_i| (the RK4
+// increment's relative departure from f), so the network output is O(1), a cell at
+// a fixed point stays exact, and a poor network can move an increment by at most
+// half of itself.  Features (32), signed-log scaled: slog(y_i/s_i) for the 14
+// species, slog(f_i/(s_i sf_i)) with sf_i the RMS of f/s, ADP/ADP*, g(eta), H_adh,
+// log10(Dt)+5.  The same device function builds the
+// features for training and inference.  A cell is accepted when its midpoint defect
+// in species scales,  max_i |Delta_i - Dt R_i(y + Delta/2)| / s_i,  is below the
+// residual tolerance; otherwise it is queued for the plain RK4 step (so a zero
+// tolerance sends every cell to the plain integrator).
+#pragma once
+#include "clot_mlp.h"
+#include "clot_step.h"
+
+namespace clot {
+
+struct SurrTables {
+    float s[MLP_NSP];      // species scales
+    float sf[MLP_NSP];     // RMS of Dt R / s over the training set
+    float sc[MLP_NSP];     // RMS of the relative corrections over the training set
+};
+
+// Signed logarithm mapping |v| in [1e-12, 1] onto [0, 1] (zero below 1e-12).
+__device__ inline float slog(double v) {
+    const double a = fabs(v);
+    if (!(a > 1e-12)) return 0.f;
+    const float m = (float)((log10(a) + 12.0) / 12.0);
+    return v < 0 ? -m : m;
+}
+
+__host__ __device__ inline void species_scales(const ModelDev& M, float (&s)[MLP_NSP]) {
+    // Pmu Pma Pba Pbse S1 S2 E1 E2 S1b S2b E1b E2b C1 C2
+    const float pm = (float)M.P_max, a = (float)M.S1_0, b = (float)M.S2_0;
+    const float v[MLP_NSP] = {pm, pm, pm, pm, a, b, a, b, a, b, a, b, b, b};
+    for (int i = 0; i < MLP_NSP; ++i) s[i] = v[i];
+}
+
+// Features of one state; also returns the explicit-midpoint increment f (unscaled).
+template <class T>
+__device__ inline void surr_features(const T (&y)[NRX], T adp, T gam, T hadh, T dt, const ModelDev& M,
+                                     const SurrTables& tb, float (&x)[MLP_IN], T (&f)[NRX]) {
+    T k1[NRX], ym[NRX];
+    rxn_rhs(y, adp, gam, hadh, M, k1);
+#pragma unroll
+    for (int i = 0; i < NRX; ++i) ym[i] = y[i] + T(0.5) * dt * k1[i];
+    rxn_rhs(ym, adp, gam, hadh, M, f);
+#pragma unroll
+    for (int i = 0; i < NRX; ++i) {
+        f[i] *= dt;
+        x[i] = slog((double)y[i] / tb.s[i]);
+        x[NRX + i] = slog((double)f[i] / ((double)tb.s[i] * tb.sf[i]));
+    }
+    x[28] = (float)(adp / T(M.adp_crit));
+    x[29] = (float)gam;
+    x[30] = (float)hadh;
+    x[31] = (float)(log10((double)dt) + 5.0);
+}
+
+// Midpoint defect of an increment in species scales (one right-hand-side evaluation).
+template <class T>
+__device__ inline float surr_defect(const T (&y)[NRX], const T (&inc)[NRX], T adp, T gam, T hadh, T dt,
+                                    const ModelDev& M, const SurrTables& tb) {
+    T ym[NRX], fm[NRX];
+#pragma unroll
+    for (int i = 0; i < NRX; ++i) ym[i] = y[i] + T(0.5) * inc[i];
+    rxn_rhs(ym, adp, gam, hadh, M, fm);
+    float worst = 0.f;
+#pragma unroll
+    for (int i = 0; i < NRX; ++i) {
+        const float r = (float)(fabs(inc[i] - dt * fm[i]) / T(tb.s[i]));
+        worst = (r > worst || r != r) ? r : worst;
+    }
+    return worst;
+}
+
+template <class T>
+__device__ inline void load_rxn_state(const Fields<T>& F, int64_t g, T (&y)[NRX]) {
+    y[0] = F.xt[0][g];
+    y[1] = F.xt[1][g];
+    y[2] = F.spc[PBA][g];
+    y[3] = F.spc[PBSE][g];
+    y[4] = F.xt[2][g];
+    y[5] = F.xt[3][g];
+    y[6] = F.xt[4][g];
+    y[7] = F.xt[5][g];
+    y[8] = F.spc[S1B][g];
+    y[9] = F.spc[S2B][g];
+    y[10] = F.spc[E1B][g];
+    y[11] = F.spc[E2B][g];
+    y[12] = F.spc[C1][g];
+    y[13] = F.spc[C2][g];
+}
+
+template <class T>
+__device__ inline void store_rxn_state(const Fields<T>& F, int64_t g, const T (&y)[NRX], T adp) {
+    F.spc[PMU][g] = y[0];
+    F.spc[PMA][g] = y[1];
+    F.spc[PBA][g] = y[2];
+    F.spc[PBSE][g] = y[3];
+    F.spc[S1][g] = y[4];
+    F.spc[S2][g] = y[5];
+    F.spc[E1][g] = y[6];
+    F.spc[E2][g] = y[7];
+    F.spc[S1B][g] = y[8];
+    F.spc[S2B][g] = y[9];
+    F.spc[E1B][g] = y[10];
+    F.spc[E2B][g] = y[11];
+    F.spc[C1][g] = y[12];
+    F.spc[C2][g] = y[13];
+    F.spc[ADP][g] = adp;
+}
+
+template <class T>
+__device__ inline bool adhesion_cell(const ChanDev& C, const Cell& P) {
+    return P.j < C.jadh && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
+           P.k < C.inj_k0 + C.inj_nk;
+}
+
+// Surrogate reaction step.  One lane per cell does the per-cell work; the MLP runs on
+// MFMA over four groups of 16 cells per wave.  Rejected cells are appended to a list.
+template <class T>
+__global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev M, MLPWeights w, SurrTables tb,
+                                                  float tol, int32_t* fb_list, int32_t* fb_count, int32_t* fb_chan) {
+    CLOT_TILE_PROLOGUE(G)
+    __shared__ uint16_t sX[4][64 * MLP_IN];
+    __shared__ uint16_t sH1[4][16 * MLP_H];
+    __shared__ uint16_t sH2[4][16 * MLP_H];
+    __shared__ float sO[4][64 * MLP_OUT];
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t local = tbase + threadIdx.x;
+    const bool own = local < C.ncell;
+    T y[NRX], f[NRX];
+    T adp = T(0), gam = T(0), hadh = T(0);
+    const T dt = T(C.dt);
+    int64_t g = 0;
+    float x[MLP_IN];
+    if (own) {
+        const Cell P = cell_at(C, local);
+        g = P.g;
+        load_rxn_state(F, g, y);
+        adp = F.xt[6][g];
+        gam = binding_g<T>(F.eta[g], M);
+        hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
+        surr_features(y, adp, gam, hadh, dt, M, tb, x, f);
+    } else {
+#pragma unroll
+        for (int i = 0; i < MLP_IN; ++i) x[i] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < MLP_IN; ++i) sX[wv][l * MLP_IN + i] = f2bf(x[i]);
+    __syncthreads();
+    for (int grp = 0; grp < 4; ++grp)
+        mlp_forward16(w, sX[wv] + grp * 16 * MLP_IN, sH1[wv], sH2[wv], sO[wv] + grp * 16 * MLP_OUT);
+    if (!own) return;
+    T inc[NRX];
+#pragma unroll
+    for (int i = 0; i < NRX; ++i) {
+        float r = tb.sc[i] * sO[wv][l * MLP_OUT + i];
+        r = r > 0.5f ? 0.5f : (r < -0.5f ? -0.5f : r);
+        inc[i] = f[i] * (T(1) + T(r));
+    }
+    const float d = surr_defect(y, inc, adp, gam, hadh, dt, M, tb);
+    if (d < tol) {
+#pragma unroll
+        for (int i = 0; i < NRX; ++i) y[i] += inc[i];
+        store_rxn_state(F, g, y, adp);
+    } else {
+        const int32_t slot = atomicAdd(fb_count, 1);
+        fb_list[slot] = (int32_t)g;
+        atomicAdd(&fb_chan[chid], 1);
+    }
+}
+
+// Plain RK4 reaction step (as k_rxn) for the listed cells.
+template <class T>
+__global__ __launch_bounds__(NT) void k_rxn_list(const ChanDev* chans, int nch, Fields<T> F, ModelDev M,
+                                                 const int32_t* fb_list, const int32_t* fb_count) {
+    const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (q >= *fb_count) return;
+    const int64_t g = fb_list[q];
+    // find the channel of cell g (channels are few; binary search over c0)
+    int lo = 0, hi = nch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chans[mid].c0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const ChanDev C = chans[lo];
+    const Cell P = cell_at(C, g - C.c0);
+    T y[NRX];
+    load_rxn_state(F, g, y);
+    const T adp = F.xt[6][g];
+    const T gam = binding_g<T>(F.eta[g], M);
+    const T hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
+    rk4_cell(y, adp, gam, hadh, T(C.dt / M.M_rxn), M);
+    store_rxn_state(F, g, y, adp);
+}
+
+// ---------------------------------------------------------------------------------
+// Batch kernels on arbitrary states (training data).  A state row has 18 doubles:
+// 14 species (RXN order), ADP, eta, H_adh, Dt.
+// ---------------------------------------------------------------------------------
+constexpr int SURR_ROW = 18;
+
+__device__ inline void unpack_row(const double* r, const ModelDev& M, double (&y)[NRX], double& adp, double& gam,
+                                  double& hadh, double& dt) {
+#pragma unroll
+    for (int i = 0; i < NRX; ++i) y[i] = r[i];
+    adp = r[14];
+    gam = binding_g<double>(r[15], M);
+    hadh = r[16];
+    dt = r[17];
+}
+
+// Plain RK4 increments (M_rxn sub-steps, FP64) of each state.
+__global__ __launch_bounds__(NT) void k_rxn_batch(const double* rows, int64_t n, ModelDev M, double* inc) {
+    const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (q >= n) return;
+    double y[NRX], adp, gam, hadh, dt;
+    unpack_row(rows + q * SURR_ROW, M, y, adp, gam, hadh, dt);
+    double y0[NRX];
+#pragma unroll
+    for (int i = 0; i < NRX; ++i) y0[i] = y[i];
+    const double h = dt / M.M_rxn;
+    for (int m = 0; m < M.M_rxn; ++m) {
+        double k1[NRX], k2[NRX], k3[NRX], k4[NRX], w[NRX];
+        rxn_rhs(y, adp, gam, hadh, M, k1);
+        for (int i = 0; i < NRX; ++i) w[i] = y[i] + 0.5 * h * k1[i];
+        rxn_rhs(w, adp, gam, hadh, M, k2);
+        for (int i = 0; i < NRX; ++i) w[i] = y[i] + 0.5 * h * k2[i];
+        rxn_rhs(w, adp, gam, hadh, M, k3);
+        for (int i = 0; i < NRX; ++i) w[i] = y[i] + h * k3[i];
+        rxn_rhs(w, adp, gam, hadh, M, k4);
+        for (int i = 0; i < NRX; ++i) y[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    }
+    for (int i = 0; i < NRX; ++i) inc[q * NRX + i] = y[i] - y0[i];
+}
+
+// Training set: bf16 features [n][32] and f32 targets [n][16]: relative corrections
+// (Delta_RK4 - f)/|f| clamped to [-1/2, 1/2] (the range the step applies), in units
+// of sc_i, and zero where |f_i| <= 1e-12 s_i (negligible rates, where the relative
+// correction is noise); outputs 14..15 zero.  With stats != NULL it instead
+// accumulates per-block sums (42 per block): the squares of f/s, the squares of the
+// clamped relative corrections, and the count of rows with non-negligible f.
+__global__ __launch_bounds__(NT) void k_surr_dataset(const double* rows, const double* inc, int64_t n, ModelDev M,
+                                                     SurrTables tb, uint16_t* x, float* t, double* stats) {
+    const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
+    __shared__ double lds[42 * (NT / 64 + 1)];
+    double acc[42];
+#pragma unroll
+    for (int i = 0; i < 42; ++i) acc[i] = 0.0;
+    if (q < n) {
+        double y[NRX], adp, gam, hadh, dt, f[NRX];
+        unpack_row(rows + q * SURR_ROW, M, y, adp, gam, hadh, dt);
+        float xf[MLP_IN];
+        surr_features<double>(y, adp, gam, hadh, dt, M, tb, xf, f);
+        for (int i = 0; i < NRX; ++i) {
+            const bool live = fabs(f[i]) > 1e-12 * tb.s[i];
+            double rel = live ? (inc[q * NRX + i] - f[i]) / fabs(f[i]) : 0.0;
+            rel = rel > 0.5 ? 0.5 : (rel < -0.5 ? -0.5 : rel);
+            if (stats) {
+                const double fs = f[i] / tb.s[i];
+                acc[i] = fs * fs;
+                acc[NRX + i] = rel * rel;
+                acc[2 * NRX + i] = live ? 1.0 : 0.0;
+            } else {
+                t[q * MLP_OUT + i] = (float)(rel / tb.sc[i]);
+            }
+        }
+        if (!stats) {
+            t[q * MLP_OUT + 14] = 0.f;
+            t[q * MLP_OUT + 15] = 0.f;
+            for (int i = 0; i < MLP_IN; ++i) x[q * MLP_IN + i] = f2bf(xf[i]);
+        }
+    }
+    if (stats) {
+        block_sum<42>(acc, lds);
+        if (threadIdx.x == 0)
+            for (int i = 0; i < 42; ++i) stats[(int64_t)blockIdx.x * 42 + i] = acc[i];
+    }
+}
+
+}  // namespace clot

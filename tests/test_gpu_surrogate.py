@@ -1,0 +1,148 @@
+"""GPU tests of the learned reaction step: MFMA layout, forward/backward against the
+FP64 NumPy reference, training, parity with the FP64 oracle and the fallback."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import clot_inputs as ci
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def test_mfma_operand_layout():
+    torch = _torch()
+    from oracle import mlp_ref
+    from paper_2304_09180_amd import clot
+    lib = clot.load()
+    rng = np.random.default_rng(0)
+    A = mlp_ref.bf16_round(rng.normal(0, 1, (16, 16)))
+    B = mlp_ref.bf16_round(rng.normal(0, 1, (16, 16)))
+    a = torch.from_numpy(mlp_ref.bf16_bits(A).view(np.int16)).cuda()
+    b = torch.from_numpy(mlp_ref.bf16_bits(B).view(np.int16)).cuda()
+    d = torch.zeros((16, 16), dtype=torch.float32, device="cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    clot.check(lib.clot_mfma_selftest(clot.ptr(a), clot.ptr(b), clot.ptr(d), st), "selftest")
+    torch.cuda.synchronize()
+    assert np.allclose(d.cpu().numpy(), A @ B, rtol=1e-5, atol=1e-5)
+
+
+def _random_case(n, seed):
+    from oracle import mlp_ref
+    rng = np.random.default_rng(seed)
+    w = rng.normal(0, 0.25, mlp_ref.NPARAM).astype(np.float32)
+    x = mlp_ref.bf16_round(rng.normal(0, 1, (n, 32)))
+    dy = rng.normal(0, 1e-3, (n, 16)).astype(np.float32)
+    return w, x, dy
+
+
+def test_mlp_forward_and_backward_match_fp64_reference():
+    torch = _torch()
+    from oracle import mlp_ref
+    from paper_2304_09180_amd import clot
+    lib = clot.load()
+    n = 1000                       # not a multiple of the 64-sample block: ragged tail
+    w, x, dy = _random_case(n, 1)
+    wq = mlp_ref.bf16_round(w)     # the kernels multiply bf16 weights (biases stay f32)
+    for name, (o, sz) in {"b1": (2048, 64), "b2": (2048 + 64 + 4096, 64), "b3": (2048 + 64 + 4096 + 64 + 1024, 16)}.items():
+        wq[o:o + sz] = w[o:o + sz]
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    wf = torch.from_numpy(w).cuda()
+    wb = torch.from_numpy(mlp_ref.bf16_bits(w).view(np.int16)).cuda()
+    xt = torch.from_numpy(mlp_ref.bf16_bits(x).view(np.int16)).cuda()
+    y = torch.empty((n, 16), dtype=torch.float32, device="cuda")
+    cache = torch.empty((n, 128), dtype=torch.int16, device="cuda")
+    clot.check(lib.clot_mlp_forward(clot.ptr(wf), clot.ptr(wb), clot.ptr(xt), n, clot.ptr(y), clot.ptr(cache), st), "fwd")
+    dyt = torch.from_numpy(dy).cuda()
+    part = torch.empty(int(lib.clot_mlp_backward_workspace(n)) // 4, dtype=torch.float32, device="cuda")
+    dw = torch.empty(mlp_ref.NPARAM, dtype=torch.float32, device="cuda")
+    clot.check(lib.clot_mlp_backward(clot.ptr(wf), clot.ptr(wb), clot.ptr(xt), clot.ptr(cache), clot.ptr(dyt), n,
+                                     clot.ptr(part), clot.ptr(dw), st), "bwd")
+    torch.cuda.synchronize()
+    y_ref, c_ref = mlp_ref.forward(wq, x)
+    g_ref = mlp_ref.backward(wq, c_ref, mlp_ref.bf16_round(dy))
+    yg = y.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(yg - y_ref) / np.linalg.norm(y_ref) < 1e-2
+    gg = dw.cpu().numpy().astype(np.float64)
+    for name, lo, hi in (("W1", 0, 2048), ("W2", 2112, 6208), ("W3", 6272, 7296), ("b1", 2048, 2112),
+                         ("b2", 6208, 6272), ("b3", 7296, 7312)):
+        err = np.linalg.norm(gg[lo:hi] - g_ref[lo:hi]) / np.linalg.norm(g_ref[lo:hi])
+        assert err < 2e-2, (name, err)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    from paper_2304_09180_amd import surrogate
+    d1 = ci.workload("channel2d_64x16")
+    d2 = ci.channel(2, 256, 64, shear=1000.0, dt=2e-5, seed=2)
+    states = surrogate.collect_states([(d1, 100), (d2, 200)], log=lambda *a: None)
+    rows = surrogate.sample_rows(states, 200_000)
+    tr = surrogate.Trainer(rows, log=print)
+    l0 = tr.loss()
+    hist = tr.train(epochs=12)
+    held = surrogate.sample_rows(states, 50_000, seed=99, dt_range=(2e-4, 1e-3))
+    gain = tr.heldout_gain(held)
+    return tr, l0, hist, gain
+
+
+def test_training_on_gpu_reduces_the_loss_and_beats_the_midpoint_step(trained):
+    tr, l0, hist, (held_net, held_zero) = trained
+    print("loss", l0, "->", hist[-1], "held-out (Dt 2e-4..1e-3): network", held_net, "midpoint alone", held_zero)
+    # targets are relative departures of RK4 from the midpoint increment in units of
+    # their RMS; the network starts at zero output (the midpoint increment itself)
+    assert 0.0 < l0 < 1.0
+    assert hist[-1] < 0.7 * l0
+    # on unseen states with larger steps the network removes at least a quarter of
+    # the midpoint step's (mean-square) error with respect to RK4
+    assert held_net < 0.75 * held_zero
+
+
+def _run(d, steps, mode, blob=None, tol=1e-3):
+    from paper_2304_09180_amd import clot
+    s = clot.Solver([d], clot.FP32_MIXED)
+    xc, xf = ci.noise(d)
+    s.init_state(0, xc, xf)
+    if mode == "surrogate":
+        s.set_reaction_mode(clot.SURROGATE, blob, tol)
+    s.step(steps)
+    out = s.fields(0)
+    st = s.stats(0)
+    s.close()
+    return out, st
+
+
+def test_surrogate_step_parity_gain_and_fallback(trained):
+    from oracle import clot_oracle as oc
+    tr = trained[0]
+    d = ci.channel(2, 64, 16, shear=1000.0, dt=1e-4, steps=60, seed=5)
+    steps = d["steps"]
+    xc, xf = ci.noise(d)
+    o = oc.Oracle(d, xc, xf)
+    for _ in range(steps):
+        o.step()
+    ref = o.fields()
+    plain, _ = _run(d, steps, "plain")
+    surr, st_s = _run(d, steps, "surrogate", tr.blob(), 1e-3)
+    euler, _ = _run(d, steps, "surrogate", tr.zero_blob(), 1e9)       # no network: the midpoint increment
+    allfb, st_f = _run(d, steps, "surrogate", tr.blob(), 0.0)          # every cell falls back
+    print("fallback fraction", st_s["fallback_frac"], st_f["fallback_frac"])
+
+    def err(a, name):
+        return np.linalg.norm(a[name] - ref[name]) / max(np.linalg.norm(ref[name]), 1e-300)
+
+    names = ["UX", "PMU", "PBSE", "S1", "S2", "E1", "S1B", "S2B"]
+    for n in names:
+        assert err(surr, n) <= 1e-3, (n, err(surr, n))
+    # what the network gains over the explicit increment alone, on the bound platelets
+    e_surr, e_euler, e_plain = err(surr, "PBSE"), err(euler, "PBSE"), err(plain, "PBSE")
+    print(f"PBSE rel l2: plain {e_plain:.3e} surrogate {e_surr:.3e} midpoint alone {e_euler:.3e}")
+    for n in ("PBSE", "S1B", "S2B"):
+        print(n, "surrogate", err(surr, n), "midpoint alone", err(euler, n))
+    # with a zero tolerance every changed cell is recomputed by the plain RK4 step
+    for n in names + ["PMA", "PBA", "E2", "C1", "C2"]:
+        assert np.array_equal(allfb[n], plain[n]), n
