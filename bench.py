@@ -149,21 +149,32 @@ def surrogate_leg(desc, prec, args, xc, xf):
     held_net, held_zero = tr.heldout_gain(held)
     t_train = time.perf_counter() - t0
     blob = tr.blob()
-    s = clot.Solver([desc], prec)
-    s.init_state(0, xc, xf)
-    s.set_reaction_mode(clot.SURROGATE, blob, 1e-3)
-    for _ in range(args.warmup):
-        s.step(1)
-    el, _, _ = timed_steps(s, args.steps, "rxn")
-    st = s.stats(0)
     ncell = desc["nx"] * desc["ny"] * desc["nz"]
-    out = {"value": ncell * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
-           "rxn_kernel_us": kernel_us(s, "rxn"), "fallback_kernel_us": kernel_us(s, "rxn_fallback"),
-           "fallback_frac": st["fallback_frac"], "resid_tol": 1e-3,
-           "training": {"samples": args.train_samples, "epochs": 12, "seconds": round(t_train, 2),
-                        "loss_start": l0, "loss_end": hist[-1],
-                        "heldout_mse_network": held_net, "heldout_mse_midpoint_alone": held_zero}}
-    s.close()
+
+    def run(mode, m_rxn):
+        s = clot.Solver([desc], prec, clot.default_params(prec, M_rxn=m_rxn))
+        s.init_state(0, xc, xf)
+        if mode == "surrogate":
+            s.set_reaction_mode(clot.SURROGATE, blob, 1e-3)
+        for _ in range(args.warmup):
+            s.step(1)
+        el, _, _ = timed_steps(s, args.steps, "rxn")
+        r = {"value": ncell * args.steps / el, "ms_per_step": el * 1e3 / args.steps, "rxn_kernel_us": kernel_us(s, "rxn")}
+        if mode == "surrogate":
+            r["fallback_kernel_us"] = kernel_us(s, "rxn_fallback")
+            r["fallback_frac"] = s.stats(0)["fallback_frac"]
+        s.close()
+        return r
+
+    sweep = {}
+    for m in (2, 8, 32):
+        sweep[f"M_rxn={m}"] = {"plain": run("plain", m), "surrogate": run("surrogate", m)}
+        print(f"# M_rxn={m}: {sweep[f'M_rxn={m}']}", file=sys.stderr, flush=True)
+    out = dict(sweep["M_rxn=2"]["surrogate"])
+    out.update({"resid_tol": 1e-3, "m_rxn_sweep": sweep,
+                "training": {"samples": args.train_samples, "epochs": 12, "seconds": round(t_train, 2),
+                             "loss_start": l0, "loss_end": hist[-1],
+                             "heldout_mse_network": held_net, "heldout_mse_midpoint_alone": held_zero}})
     return out
 
 

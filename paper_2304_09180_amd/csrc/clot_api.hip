@@ -220,7 +220,6 @@ struct Ctx : clot_ctx {
             }
             wb[q] = f2bf(f[q]);
         }
-        species_scales(M, surr_tb.s);
         for (int i = 0; i < MLP_NSP; ++i) {
             surr_tb.sf[i] = f[MLP_NPARAM + i];
             surr_tb.sc[i] = f[MLP_NPARAM + MLP_NSP + i];
@@ -229,6 +228,7 @@ struct Ctx : clot_ctx {
                 return CLOT_EINVAL;
             }
         }
+        surr_tables_finish(M, surr_tb);
         HIPCHK(hipMemcpyAsync(mlp_wf, f, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(mlp_wb, wb.data(), MLP_NPARAM * sizeof(uint16_t), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1099,7 +1099,7 @@ struct Ctx : clot_ctx {
                          mlp_wf + MLP_OFF_B1, mlp_wf + MLP_OFF_B2, mlp_wf + MLP_OFF_B3};
             CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn_surr<T>, gb, dim3(256), 0, st, G, F, M, w, surr_tb, surr_tol, fb_list,
                         fb_count, fb_chan);
-            CLOT_LAUNCH(CLOT_PROBE_RXN_FALLBACK, k_rxn_list<T>, dim3((N + NT - 1) / NT), tb, 0, st, d_ch, nch, F, M,
+            CLOT_LAUNCH(CLOT_PROBE_RXN_FALLBACK, k_rxn_list<T>, dim3((unsigned)std::min<int64_t>((N + NT - 1) / NT, 1024)), tb, 0, st, d_ch, nch, F, M,
                         fb_list, fb_count);
             hipLaunchKernelGGL(k_record_fallback, dim3(1), dim3(64), 0, st, fb_chan, d_ch, dstats, NSTAT, nch,
                                (int)ST_FALLBACK);
@@ -1360,7 +1360,7 @@ clot_status clot_mlp_forward(const float* wf, const uint16_t* wb, const uint16_t
                              void* stream) {
     if (!wf || !wb || !x || !y || n < 0) return CLOT_EINVAL;
     if (n == 0) return CLOT_OK;
-    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, (hipStream_t)stream, mlp_ptrs(wf, wb), x,
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, mlp_ptrs(wf, wb), x,
                        n, y, cache);
     CHK_LAUNCH();
     return CLOT_OK;
@@ -1410,11 +1410,11 @@ clot_status clot_surr_dataset(const clot_params* p, const double* rows, const do
     if (!p || !rows || !inc || n <= 0 || (!stats && (!scales || !x || !t))) return CLOT_EINVAL;
     const ModelDev M = model_from_params(*p);
     SurrTables tb{};
-    species_scales(M, tb.s);
     for (int i = 0; i < MLP_NSP; ++i) {
         tb.sf[i] = scales ? scales[i] : 1.f;
         tb.sc[i] = scales ? scales[MLP_NSP + i] : 1.f;
     }
+    surr_tables_finish(M, tb);
     hipLaunchKernelGGL(k_surr_dataset, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, (hipStream_t)stream, rows, inc, n,
                        M, tb, x, t, stats);
     CHK_LAUNCH();

@@ -43,6 +43,15 @@ __host__ __device__ inline float bf2f(uint16_t h) {
     return v.f;
 }
 
+// Four floats to bf16 with the hardware round-to-nearest-even conversion
+// (v_cvt_pk_bf16_f32; the same rounding as f2bf for finite values).
+__device__ inline bf16x4 pack4_bf16(float a, float b, float c, float d) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef __bf16 h4 __attribute__((ext_vector_type(4)));
+    const h4 h = __builtin_convertvector((f4){a, b, c, d}, h4);
+    return __builtin_bit_cast(bf16x4, h);
+}
+
 __device__ inline f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -93,10 +102,9 @@ __global__ void k_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D) 
 }
 
 // ---------------------------------------------------------------------------------
-// Wave-level MLP forward for 16 cells.  X: cell-major bf16 inputs [16][32] (LDS);
-// W*: bf16 weights row-major; b*: float biases.  Writes the 16 outputs per cell as
-// out[16 cells][16] (LDS, float) and, when H1/H2 are given, the bf16 tanh
-// activations cell-major [16][64] (for the backward pass).
+// Wave-level MLP forward for 16 cells, chained through registers: the D tile of one
+// layer's 16-unit block is the B operand of the next layer's matching k block, so
+// only the inputs and the outputs pass through memory.
 // ---------------------------------------------------------------------------------
 struct MLPWeights {
     const uint16_t* W1;
@@ -107,72 +115,97 @@ struct MLPWeights {
     const float* b3;
 };
 
-__device__ inline void mlp_forward16(const MLPWeights& w, const uint16_t* X, uint16_t* H1, uint16_t* H2, float* out) {
-    const int l = threadIdx.x & 63;
-    const int col = l & 15, rq = 4 * (l >> 4);
-    // layer 1: H1 (64 x 16) = W1 (64 x 32) X^T
+// tanh(x) = 1 - 2/(1 + e^{2x}), with the hardware exp2 and reciprocal: absolute
+// error a few 1e-7, far below the bf16 rounding the activations then take; +-inf
+// saturate to +-1.
+__device__ inline float fast_tanh(float x) {
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);   // 2 log2(e)
+    return fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + e), 1.f);
+}
+
+__device__ inline bf16x4 act_bf16(f32x4 c, const float* b, int u0) {
+    const float4 bb = *reinterpret_cast<const float4*>(b + u0);
+    return pack4_bf16(fast_tanh(c[0] + bb.x), fast_tanh(c[1] + bb.y), fast_tanh(c[2] + bb.z), fast_tanh(c[3] + bb.w));
+}
+
+// The A operands of all three layers for one wave (28 x 4 bf16 per lane).
+struct MLPRegs {
+    bf16x4 w1[4][2], w2[4][4], w3[4];
+    __device__ inline void load(const MLPWeights& w) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) w1[rb][kb] = load_a(w.W1, MLP_IN, 16 * rb, 16 * kb);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) w2[rb][kb] = load_a(w.W2, MLP_H, 16 * rb, 16 * kb);
+        }
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) w3[kb] = load_a(w.W3, MLP_H, 0, 16 * kb);
+    }
+};
+
+// x[kb]: B operands of the 16 cells' inputs (k block kb of 32).  Returns lane l's
+// outputs 4*(l/16)+e of cell l%16; h1/h2 receive the bf16 activations of units
+// 16*rb + 4*(l/16) + e of that cell.
+__device__ inline f32x4 mlp_chain16(const MLPRegs& R, const MLPWeights& w, const bf16x4 (&x)[2], bf16x4 (&h1)[4],
+                                    bf16x4 (&h2)[4]) {
+    const int rq = 4 * ((threadIdx.x & 63) >> 4);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        c = mfma16(R.w1[rb][0], x[0], c);
+        c = mfma16(R.w1[rb][1], x[1], c);
+        h1[rb] = act_bf16(c, w.b1, 16 * rb + rq);
+    }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
         f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb) c = mfma16(load_a(w.W1, MLP_IN, 16 * rb, 16 * kb), load_b_cm(X, MLP_IN, 16 * kb, 0), c);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int u = 16 * rb + rq + e;
-            H1[col * MLP_H + u] = f2bf(tanhf(c[e] + w.b1[u]));
-        }
+        for (int kb = 0; kb < 4; ++kb) c = mfma16(R.w2[rb][kb], h1[kb], c);
+        h2[rb] = act_bf16(c, w.b2, 16 * rb + rq);
     }
-    __syncthreads();
-    // layer 2
+    const float4 b3 = *reinterpret_cast<const float4*>(w.b3 + rq);
+    f32x4 c = {b3.x, b3.y, b3.z, b3.w};
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-        f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) c = mfma16(load_a(w.W2, MLP_H, 16 * rb, 16 * kb), load_b_cm(H1, MLP_H, 16 * kb, 0), c);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int u = 16 * rb + rq + e;
-            H2[col * MLP_H + u] = f2bf(tanhf(c[e] + w.b2[u]));
-        }
-    }
-    __syncthreads();
-    // layer 3 (linear)
-    {
-        f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) c = mfma16(load_a(w.W3, MLP_H, 0, 16 * kb), load_b_cm(H2, MLP_H, 16 * kb, 0), c);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) out[col * MLP_OUT + rq + e] = c[e] + w.b3[rq + e];
-    }
-    __syncthreads();
+    for (int kb = 0; kb < 4; ++kb) c = mfma16(R.w3[kb], h2[kb], c);
+    return c;
 }
 
 // Forward over a batch: x bf16 [n][32] (cell-major), y f32 [n][16]; cache (optional)
-// bf16 [n][128] = h1, h2.  One wave per 16 samples; 4 waves per block.
+// bf16 [n][128] = h1, h2.  One wave per 64 samples (four groups of 16); 4 waves per
+// block.
 __global__ __launch_bounds__(256) void k_mlp_forward(MLPWeights w, const uint16_t* x, int64_t n, float* y,
                                                      uint16_t* cache) {
-    __shared__ uint16_t sX[4][16 * MLP_IN];
-    __shared__ uint16_t sH1[4][16 * MLP_H];
-    __shared__ uint16_t sH2[4][16 * MLP_H];
-    __shared__ float sO[4][16 * MLP_OUT];
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int64_t c0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
-    for (int q = l; q < 16 * MLP_IN; q += 64) {
-        const int64_t c = c0 + q / MLP_IN;
-        sX[wv][q] = c < n ? x[c * MLP_IN + q % MLP_IN] : (uint16_t)0;
-    }
-    __syncthreads();
-    mlp_forward16(w, sX[wv], sH1[wv], sH2[wv], sO[wv]);
-    for (int q = l; q < 16 * MLP_OUT; q += 64) {
-        const int64_t c = c0 + q / MLP_OUT;
-        if (c < n) y[c * MLP_OUT + q % MLP_OUT] = sO[wv][q];
-    }
-    if (cache) {
-        for (int q = l; q < 16 * MLP_H; q += 64) {
-            const int64_t c = c0 + q / MLP_H;
-            if (c < n) {
-                cache[c * 2 * MLP_H + q % MLP_H] = sH1[wv][q];
-                cache[c * 2 * MLP_H + MLP_H + q % MLP_H] = sH2[wv][q];
+    const int rq = 4 * (l >> 4);
+    MLPRegs R;
+    R.load(w);
+    for (int grp = 0; grp < 4; ++grp) {
+        const int64_t c = ((int64_t)blockIdx.x * 4 + wv) * 64 + 16 * grp + (l & 15);
+        const bool in = c < n;
+        bf16x4 xb[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            if (in) {
+                const uint2 v = *reinterpret_cast<const uint2*>(x + c * MLP_IN + 16 * kb + rq);
+                xb[kb][0] = (short)(v.x & 0xFFFF);
+                xb[kb][1] = (short)(v.x >> 16);
+                xb[kb][2] = (short)(v.y & 0xFFFF);
+                xb[kb][3] = (short)(v.y >> 16);
+            } else {
+                xb[kb] = bf16x4{0, 0, 0, 0};
+            }
+        }
+        bf16x4 h1[4], h2[4];
+        const f32x4 o = mlp_chain16(R, w, xb, h1, h2);
+        if (in) {
+            *reinterpret_cast<float4*>(y + c * MLP_OUT + rq) = make_float4(o[0], o[1], o[2], o[3]);
+            if (cache) {
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    *reinterpret_cast<bf16x4*>(cache + c * 2 * MLP_H + 16 * rb + rq) = h1[rb];
+                    *reinterpret_cast<bf16x4*>(cache + c * 2 * MLP_H + MLP_H + 16 * rb + rq) = h2[rb];
+                }
             }
         }
     }

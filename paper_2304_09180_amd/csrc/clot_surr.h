@@ -24,15 +24,9 @@ struct SurrTables {
     float s[MLP_NSP];      // species scales
     float sf[MLP_NSP];     // RMS of Dt R / s over the training set
     float sc[MLP_NSP];     // RMS of the relative corrections over the training set
+    float inv_s[MLP_NSP];  // 1/s
+    float inv_f[MLP_NSP];  // 1/(s sf)
 };
-
-// Signed logarithm mapping |v| in [1e-12, 1] onto [0, 1] (zero below 1e-12).
-__device__ inline float slog(double v) {
-    const double a = fabs(v);
-    if (!(a > 1e-12)) return 0.f;
-    const float m = (float)((log10(a) + 12.0) / 12.0);
-    return v < 0 ? -m : m;
-}
 
 __host__ __device__ inline void species_scales(const ModelDev& M, float (&s)[MLP_NSP]) {
     // Pmu Pma Pba Pbse S1 S2 E1 E2 S1b S2b E1b E2b C1 C2
@@ -41,7 +35,24 @@ __host__ __device__ inline void species_scales(const ModelDev& M, float (&s)[MLP
     for (int i = 0; i < MLP_NSP; ++i) s[i] = v[i];
 }
 
-// Features of one state; also returns the explicit-midpoint increment f (unscaled).
+// Fills the species scales and the reciprocals from sf and sc.
+inline void surr_tables_finish(const ModelDev& M, SurrTables& tb) {
+    species_scales(M, tb.s);
+    for (int i = 0; i < MLP_NSP; ++i) {
+        tb.inv_s[i] = 1.f / tb.s[i];
+        tb.inv_f[i] = 1.f / (tb.s[i] * tb.sf[i]);
+    }
+}
+
+// Signed logarithm of a scaled value: |v| in [1e-12, 1] maps onto [0, 1], zero below
+// 1e-12 (single precision: the feature is rounded to bf16 afterwards).
+__device__ inline float slog(float v) {
+    const float a = fabsf(v);
+    if (!(a > 1e-12f)) return 0.f;
+    const float m = fmaf(__log2f(a), 0.025085832972f, 1.f);   // (log10|v| + 12)/12
+    return copysignf(m, v);
+}
+
 template <class T>
 __device__ inline void surr_features(const T (&y)[NRX], T adp, T gam, T hadh, T dt, const ModelDev& M,
                                      const SurrTables& tb, float (&x)[MLP_IN], T (&f)[NRX]) {
@@ -53,13 +64,13 @@ __device__ inline void surr_features(const T (&y)[NRX], T adp, T gam, T hadh, T 
 #pragma unroll
     for (int i = 0; i < NRX; ++i) {
         f[i] *= dt;
-        x[i] = slog((double)y[i] / tb.s[i]);
-        x[NRX + i] = slog((double)f[i] / ((double)tb.s[i] * tb.sf[i]));
+        x[i] = slog((float)y[i] * tb.inv_s[i]);
+        x[NRX + i] = slog((float)f[i] * tb.inv_f[i]);
     }
     x[28] = (float)(adp / T(M.adp_crit));
     x[29] = (float)gam;
     x[30] = (float)hadh;
-    x[31] = (float)(log10((double)dt) + 5.0);
+    x[31] = fmaf(__log2f((float)dt), 0.30102999566f, 5.f);   // log10(Dt) + 5
 }
 
 // Midpoint defect of an increment in species scales (one right-hand-side evaluation).
@@ -73,7 +84,7 @@ __device__ inline float surr_defect(const T (&y)[NRX], const T (&inc)[NRX], T ad
     float worst = 0.f;
 #pragma unroll
     for (int i = 0; i < NRX; ++i) {
-        const float r = (float)(fabs(inc[i] - dt * fm[i]) / T(tb.s[i]));
+        const float r = (float)fabs(inc[i] - dt * fm[i]) * tb.inv_s[i];
         worst = (r > worst || r != r) ? r : worst;
     }
     return worst;
@@ -122,46 +133,72 @@ __device__ inline bool adhesion_cell(const ChanDev& C, const Cell& P) {
            P.k < C.inj_k0 + C.inj_nk;
 }
 
-// Surrogate reaction step.  One lane per cell does the per-cell work; the MLP runs on
-// MFMA over four groups of 16 cells per wave.  Rejected cells are appended to a list.
+// Surrogate reaction step.  One lane per cell does the per-cell work; the wave then
+// runs the MLP on MFMA over its four groups of 16 cells, inputs and outputs passing
+// through a per-wave LDS tile.  Rejected cells are appended to a list.
+constexpr int SURR_XLD = 36;   // bf16 row stride of the input tile (conflict-free B reads)
+constexpr int SURR_OLD = 17;   // float row stride of the output tile
+constexpr int SURR_WAVE_BYTES = 64 * SURR_XLD * 2;
+static_assert(64 * SURR_OLD * 4 <= SURR_WAVE_BYTES, "output tile fits the input tile");
+
 template <class T>
 __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev M, MLPWeights w, SurrTables tb,
                                                   float tol, int32_t* fb_list, int32_t* fb_count, int32_t* fb_chan) {
     CLOT_TILE_PROLOGUE(G)
-    __shared__ uint16_t sX[4][64 * MLP_IN];
-    __shared__ uint16_t sH1[4][16 * MLP_H];
-    __shared__ uint16_t sH2[4][16 * MLP_H];
-    __shared__ float sO[4][64 * MLP_OUT];
+    __shared__ __align__(16) unsigned char tileb[4][SURR_WAVE_BYTES];
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    uint16_t* sX = reinterpret_cast<uint16_t*>(tileb[wv]);
+    float* sO = reinterpret_cast<float*>(tileb[wv]);
     const int64_t local = tbase + threadIdx.x;
     const bool own = local < C.ncell;
     T y[NRX], f[NRX];
     T adp = T(0), gam = T(0), hadh = T(0);
     const T dt = T(C.dt);
     int64_t g = 0;
-    float x[MLP_IN];
-    if (own) {
-        const Cell P = cell_at(C, local);
-        g = P.g;
-        load_rxn_state(F, g, y);
-        adp = F.xt[6][g];
-        gam = binding_g<T>(F.eta[g], M);
-        hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
-        surr_features(y, adp, gam, hadh, dt, M, tb, x, f);
-    } else {
+    {
+        float x[MLP_IN];
+        if (own) {
+            const Cell P = cell_at(C, local);
+            g = P.g;
+            load_rxn_state(F, g, y);
+            adp = F.xt[6][g];
+            gam = binding_g<T>(F.eta[g], M);
+            hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
+            surr_features(y, adp, gam, hadh, dt, M, tb, x, f);
+        } else {
 #pragma unroll
-        for (int i = 0; i < MLP_IN; ++i) x[i] = 0.f;
+            for (int i = 0; i < MLP_IN; ++i) x[i] = 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < MLP_IN; i += 4)
+            *reinterpret_cast<bf16x4*>(sX + l * SURR_XLD + i) = pack4_bf16(x[i], x[i + 1], x[i + 2], x[i + 3]);
     }
-#pragma unroll
-    for (int i = 0; i < MLP_IN; ++i) sX[wv][l * MLP_IN + i] = f2bf(x[i]);
     __syncthreads();
+    const int rq = 4 * (l >> 4);
+    bf16x4 xb[4][2];
+#pragma unroll
     for (int grp = 0; grp < 4; ++grp)
-        mlp_forward16(w, sX[wv] + grp * 16 * MLP_IN, sH1[wv], sH2[wv], sO[wv] + grp * 16 * MLP_OUT);
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) xb[grp][kb] = load_b_cm(sX, SURR_XLD, 16 * kb, 16 * grp);
+    __syncthreads();   // the output tile overwrites the input tile
+    MLPRegs R;
+    R.load(w);
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+        bf16x4 h1[4], h2[4];
+        const f32x4 o = mlp_chain16(R, w, xb[grp], h1, h2);
+        float* q = sO + (16 * grp + (l & 15)) * SURR_OLD + rq;
+        q[0] = o[0];
+        q[1] = o[1];
+        q[2] = o[2];
+        q[3] = o[3];
+    }
+    __syncthreads();
     if (!own) return;
     T inc[NRX];
 #pragma unroll
     for (int i = 0; i < NRX; ++i) {
-        float r = tb.sc[i] * sO[wv][l * MLP_OUT + i];
+        float r = tb.sc[i] * sO[l * SURR_OLD + i];
         r = r > 0.5f ? 0.5f : (r < -0.5f ? -0.5f : r);
         inc[i] = f[i] * (T(1) + T(r));
     }
@@ -181,8 +218,8 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
 template <class T>
 __global__ __launch_bounds__(NT) void k_rxn_list(const ChanDev* chans, int nch, Fields<T> F, ModelDev M,
                                                  const int32_t* fb_list, const int32_t* fb_count) {
-    const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (q >= *fb_count) return;
+    const int32_t nfb = *fb_count;
+    for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < nfb; q += (int64_t)gridDim.x * NT) {
     const int64_t g = fb_list[q];
     // find the channel of cell g (channels are few; binary search over c0)
     int lo = 0, hi = nch - 1;
@@ -200,6 +237,7 @@ __global__ __launch_bounds__(NT) void k_rxn_list(const ChanDev* chans, int nch, 
     const T hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
     rk4_cell(y, adp, gam, hadh, T(C.dt / M.M_rxn), M);
     store_rxn_state(F, g, y, adp);
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -276,7 +314,8 @@ __global__ __launch_bounds__(NT) void k_surr_dataset(const double* rows, const d
         if (!stats) {
             t[q * MLP_OUT + 14] = 0.f;
             t[q * MLP_OUT + 15] = 0.f;
-            for (int i = 0; i < MLP_IN; ++i) x[q * MLP_IN + i] = f2bf(xf[i]);
+            for (int i = 0; i < MLP_IN; i += 4)
+                *reinterpret_cast<bf16x4*>(x + q * MLP_IN + i) = pack4_bf16(xf[i], xf[i + 1], xf[i + 2], xf[i + 3]);
         }
     }
     if (stats) {
