@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
     ap.add_argument("--train-samples", type=int, default=400_000)
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -178,6 +179,39 @@ def surrogate_leg(desc, prec, args, xc, xf):
     return out
 
 
+def ensemble_leg(args):
+    """The 64-member uneven ensemble of 2-D channels in one context, FP32: eager steps,
+    then the same steps replayed as HIP graphs."""
+    import clot_inputs as ci
+    from paper_2304_09180_amd import clot
+    descs = ci.ensemble(64)
+    ncell = sum(ci.ncell(d) for d in descs)
+    out = {"members": len(descs), "cells": ncell,
+           "sizes": sorted({f"{d['nx']}x{d['ny']}" for d in descs}),
+           "dt_range": [min(d["dt"] for d in descs), max(d["dt"] for d in descs)]}
+    for mode in ("eager", "graph"):
+        s = clot.Solver(descs, clot.FP32_MIXED)
+        for c, d in enumerate(descs):
+            xc, xf = ci.noise(d)
+            s.init_state(c, xc, xf)
+        if mode == "graph":
+            s.set_graph_mode(True)
+        for _ in range(max(args.warmup, 3)):   # graph mode: two calibrating steps, then recording
+            s.step(1)
+        el, _, _ = timed_steps(s, args.steps, None)
+        s.sync()
+        r = {"value": ncell * args.steps / el, "ms_per_step": el * 1e3 / args.steps}
+        if mode == "graph":
+            gi = s.graph_info()
+            r.update({"replays": gi["replays"], "overflows": gi["overflows"], "budgets": gi["budgets"]})
+        st = s.stats(0)
+        r["solver_member0"] = {k: st[k] for k in ("it_mom", "it_p", "it_eta", "it_tr", "refine_p")}
+        out[mode] = r
+        print(f"# ensemble {mode}: {r}", file=sys.stderr, flush=True)
+        s.close()
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -232,6 +266,8 @@ def main():
     s.close()
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(desc, prec, args, xc, xf)
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc)
     print(json.dumps(out), flush=True)

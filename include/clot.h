@@ -154,6 +154,29 @@ clot_status clot_get_stats(const clot_ctx* c, int32_t ch, clot_stats* s);
 clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* mlp_blob, size_t blob_bytes,
                                    double resid_tol);
 
+/* Graph replay of whole steps (for ensembles stepped many times).
+ * on != 0: the next two clot_step steps run as usual and record, per solve, the
+ * largest Krylov iteration count (and the number of FP64 pressure refinement
+ * passes).  Each later step replays a HIP graph recorded once per buffer parity
+ * (the step rotates theta_B and the face fluxes between two buffers), in which
+ * every solve runs a fixed budget of ceil(budget_scale * count) + budget_pad
+ * iterations.  Channels that converge earlier skip the remaining iterations on the
+ * device, so a replayed step gives bit-for-bit the result of the eager step.  A
+ * channel still unconverged when its budget ends is counted as a failed solve in
+ * the statistics (as max_iter is eagerly); the next synchronisation (clot_step with
+ * wait, clot_sync) notices it, doubles the scale, adds 2 to the pad and re-records
+ * the graphs.  Changing the reaction mode re-records them.  The probe does not time
+ * replayed steps.  on == 0 returns to eager steps.  budget_scale >= 0, budget_pad
+ * >= 1, else CLOT_EINVAL. */
+clot_status clot_set_graph_mode(clot_ctx* c, int32_t on, double budget_scale, int32_t budget_pad);
+/* info[0] graph mode on, [1] graphs recorded, [2] steps replayed, [3] budget
+ * overflows noticed, [4..10] current budgets: momentum, pressure corrector 1, 2,
+ * later correctors, eta, transport, pressure refinement passes; [11..17] the largest
+ * counts seen by the calibrating eager steps, in the same order; [18] nodes of the
+ * last recorded step, [19] the graphs it was recorded as (a step is cut into a chain
+ * of graphs of about 1500 nodes each).  info: 20 entries. */
+clot_status clot_graph_info(clot_ctx* c, int64_t* info);
+
 /* Kernel-phase timing probe.  While a phase is selected, every launch of it is
  * bracketed by HIP events on the context stream; clot_probe_read synchronises,
  * returns the summed event time (ms) and the launch count since the selection,

@@ -88,6 +88,8 @@ def load():
         "clot_set_reaction_mode": ([P, C.c_int, P, C.c_size_t, C.c_double], C.c_int),
         "clot_probe": ([P, C.c_int32], C.c_int),
         "clot_probe_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+        "clot_set_graph_mode": ([P, C.c_int32, C.c_double, C.c_int32], C.c_int),
+        "clot_graph_info": ([P, C.POINTER(C.c_int64)], C.c_int),
         "clot_mlp_nparam": ([], C.c_int64),
         "clot_mlp_backward_workspace": ([C.c_int64], C.c_size_t),
         "clot_mlp_forward": ([P, P, P, C.c_int64, P, P, P], C.c_int),
@@ -254,6 +256,20 @@ class Solver:
         n = C.c_int64(0)
         _check(self.lib, self.ctx, self.lib.clot_probe_read(self.ctx, C.byref(ms), C.byref(n)), "probe_read")
         return ms.value, n.value
+
+    def set_graph_mode(self, on=True, budget_scale=1.25, budget_pad=2):
+        """Replay whole steps as HIP graphs after two calibrating eager steps (each
+        Krylov solve then runs a fixed iteration budget; see clot_set_graph_mode)."""
+        return _check(self.lib, self.ctx, self.lib.clot_set_graph_mode(self.ctx, 1 if on else 0, float(budget_scale),
+                                                                      int(budget_pad)), "graph mode")
+
+    def graph_info(self):
+        v = (C.c_int64 * 20)()
+        _check(self.lib, self.ctx, self.lib.clot_graph_info(self.ctx, v), "graph_info")
+        keys = ("mom", "p1", "p2", "p3", "eta", "tr", "passes")
+        return {"on": bool(v[0]), "captures": v[1], "replays": v[2], "overflows": v[3],
+                "budgets": dict(zip(keys, v[4:11])), "seen": dict(zip(keys, v[11:18])), "nodes": v[18],
+                "graphs": v[19]}
 
     def fields(self, ch=0):
         names = ["UX", "UY", "P", "PHIX", "PHIY", "E0", "C0", "ETA", "SIGMA"] + SPECIES_FIELDS

@@ -88,6 +88,8 @@ struct clot_ctx {
     virtual clot_status probe(int id) = 0;
     virtual clot_status set_rxn(clot_rxn_mode mode, const void* blob, size_t nb, double tol) = 0;
     virtual clot_status probe_read(double* ms, int64_t* n) = 0;
+    virtual clot_status set_graph(int on, double scale, int pad) = 0;
+    virtual clot_status graph_info(int64_t* info) = 0;
 };
 
 namespace {
@@ -95,7 +97,7 @@ namespace {
 // Launch, bracketed by probe events when this phase is the one being timed.
 #define CLOT_LAUNCH(id, ...)                                                     \
     do {                                                                         \
-        const bool pr_ = (id) == probe_id && ev_used + 2 <= (int)evs.size();     \
+        const bool pr_ = (id) == probe_id && !capturing && ev_used + 2 <= (int)evs.size(); \
         if (pr_) (void)hipEventRecord(evs[ev_used], st);                         \
         hipLaunchKernelGGL(__VA_ARGS__);                                         \
         if (pr_) {                                                               \
@@ -138,7 +140,28 @@ struct Ctx : clot_ctx {
     int32_t* push = nullptr;          // [nch][2]
     double* dstats = nullptr;         // [nch][NSTAT]
     int32_t* h_nact = nullptr;        // pinned
+    SigState* sig = nullptr;          // [nch] release-history schedule
     int last_it[8] = {8, 8, 8, 8, 8, 8, 8, 8};
+    // Graph replay.  Slots: 0 momentum, 1..3 pressure (corrector 1, 2, later), 4 eta,
+    // 5 transport; slot 6 counts pressure refinement passes.
+    bool graph_on = false, capturing = false;
+    double g_scale = 1.5;
+    int g_pad = 4;
+    int calib_left = 0;
+    int it_max[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int budget[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int it_pmax[3][12] = {};          // pressure: per corrector slot and refinement pass
+    int pbudget[3][12] = {};
+    hipStream_t cst = nullptr;        // capture stream
+    // one recorded step per parity, as a chain of graphs of at most about SEG_NODES
+    // kernel nodes each (recording is cut between Krylov iterations)
+    std::vector<hipGraphExec_t> gseg[2];
+    static constexpr size_t SEG_NODES = 1500;
+    std::vector<hipGraphExec_t>* cap_out = nullptr;
+    clot_status seg_err = CLOT_OK;
+    int parity = 0;                   // buffer-rotation parity of the next step
+    int32_t* gflag = nullptr;         // device: a fixed-budget solve ended unconverged
+    int64_t g_replays = 0, g_captures = 0, g_overflows = 0, g_nodes = 0, g_segs = 0;
     // multigrid hierarchy of the pressure preconditioner (level 0 = the mesh)
     struct Level {
         std::vector<ChanDev> ch;
@@ -173,6 +196,8 @@ struct Ctx : clot_ctx {
     bool nonconv = false;
     Grid grid() const { return Grid{d_ch, d_t2c, ntiles}; }
     ~Ctx() override {
+        drop_graphs();
+        if (cst) (void)hipStreamDestroy(cst);
         if (h_nact) (void)hipHostFree(h_nact);
         for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     }
@@ -203,6 +228,7 @@ struct Ctx : clot_ctx {
         return CLOT_OK;
     }
     clot_status set_rxn(clot_rxn_mode mode, const void* blob, size_t nb, double tol) override {
+        drop_graphs();   // the recorded step holds the reaction kernel and its tables
         if (mode == CLOT_RXN_PLAIN) {
             rxn_mode = mode;
             return CLOT_OK;
@@ -300,6 +326,8 @@ struct Ctx : clot_ctx {
         sigw = cv.take<double>((size_t)nch * NHIST);
         push = cv.take<int32_t>((size_t)nch * 2);
         dstats = cv.take<double>((size_t)nch * NSTAT);
+        sig = cv.take<SigState>(nch);
+        gflag = cv.take<int32_t>(1);
         mg_y0 = cv.take<T>(N);
         mg_z0 = cv.take<T>(N);
         mg_inv = cv.take<double>((size_t)nch * MG_COARSE * MG_COARSE);
@@ -539,6 +567,9 @@ struct Ctx : clot_ctx {
             for (int i = 0; i < nch; ++i) cm[(size_t)k * nch + i] = k < ch[i].ncorr ? 1 : 0;
         HIPCHK(hipMemcpyAsync(allmask, ones.data(), nch * 4, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(corrmask, cm.data(), cm.size() * 4, hipMemcpyHostToDevice, st));
+        std::vector<SigState> sv(nch, fresh_sig());
+        HIPCHK(hipMemcpyAsync(sig, sv.data(), nch * sizeof(SigState), hipMemcpyHostToDevice, st));
+        fill(gflag, 0, 1);
         // inflow profiles (Appendix C.1 / C.2)
         std::vector<T> ui(NIN), pi(NIN);
         for (int i = 0; i < nch; ++i) {
@@ -666,10 +697,8 @@ struct Ctx : clot_ctx {
         if ((s = upload(F.thB_prev + h.c0, thb))) return s;
         h.t = 0.0;
         h.n = 0;
-        h.next_push = 0;
-        h.head = -1;
-        h.npushed = 0;
-        for (int q = 0; q < NHIST; ++q) h.hist_t[q] = -1e300;
+        const SigState s0 = fresh_sig();
+        HIPCHK(hipMemcpyAsync(sig + c, &s0, sizeof(SigState), hipMemcpyHostToDevice, st));
         // thB_prev must equal theta_B of the initial state: compute it on the device
         hipLaunchKernelGGL(k_derive<T>, dim3(ntiles), dim3(NT), 0, st, grid(), F, M);
         HIPCHK(hipGetLastError());
@@ -788,26 +817,42 @@ struct Ctx : clot_ctx {
         fill(S.nact, 0, 1);
     }
 
+    // The iterations of one solve.  Eagerly: chunks of iterations, polling the count of
+    // active channels in between.  Under graph capture: exactly the slot's budget, then
+    // every channel still active is flagged as unconverged.
+    template <int K, class Body>
+    int iterate(int slot, int keep, int next_chunk, int gbudget, Body&& body) {
+        int it = 0, par = 0;
+        if (capturing) {
+            for (; it < gbudget; ++it, par ^= 1) {
+                body(par);
+                seg_point();
+            }
+            hipLaunchKernelGGL(k_flag_active, dim3(1), dim3(64), 0, st, S.chact, S.sc, (int)ch.size(), K, gflag);
+            return it;
+        }
+        int chunk = std::max(2, last_it[slot]);
+        while (it < prm.max_iter) {
+            for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it, par ^= 1) body(par);
+            if (poll() == 0) break;
+            chunk = next_chunk;
+        }
+        last_it[slot] = std::max(keep, it - keep);
+        it_max[slot] = std::max(it_max[slot], it);
+        return it;
+    }
+
     template <class Op, int K>
     int run_cg(const Op& op, KVec<T, K> V, double rtol, int tol_mode, const int32_t* mask, int slot, int pa, int pb) {
         set_active(mask);
         hipLaunchKernelGGL((k_cg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
         finish<3 * K>(EpiCgInit<K>{rtol, tol_mode});
-        int it = 0, par = 0;
-        int chunk = std::max(2, last_it[slot]);
-        while (it < prm.max_iter) {
-            for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it) {
-                CLOT_LAUNCH(pa, (k_cg_a<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
-                finish<K>(EpiCgA<K>{});
-                CLOT_LAUNCH(pb, (k_cg_b<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
-                finish<2 * K>(EpiCgB<K>{});
-                par ^= 1;
-            }
-            if (poll() == 0) break;
-            chunk = 4;
-        }
-        last_it[slot] = std::max(2, it - 2);
-        return it;
+        return iterate<K>(slot, 2, 4, budget[slot], [&](int par) {
+            CLOT_LAUNCH(pa, (k_cg_a<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+            finish<K>(EpiCgA<K>{});
+            CLOT_LAUNCH(pb, (k_cg_b<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+            finish<2 * K>(EpiCgB<K>{});
+        });
     }
 
     template <class Op, int K>
@@ -815,23 +860,14 @@ struct Ctx : clot_ctx {
         set_active(mask);
         hipLaunchKernelGGL((k_bicg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
         finish<2 * K>(EpiBicgInit<K>{rtol});
-        int it = 0, par = 0;
-        int chunk = std::max(2, last_it[slot]);
-        while (it < prm.max_iter) {
-            for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it) {
-                CLOT_LAUNCH(p1, (k_bicg_1<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
-                finish<K>(EpiBicg1<K>{});
-                CLOT_LAUNCH(p1 + 1, (k_bicg_2<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
-                finish<2 * K>(EpiBicg2<K>{});
-                CLOT_LAUNCH(p1 + 2, (k_bicg_3<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
-                finish<2 * K>(EpiBicg3<K>{});
-                par ^= 1;
-            }
-            if (poll() == 0) break;
-            chunk = 2;
-        }
-        last_it[slot] = std::max(1, it - 1);
-        return it;
+        return iterate<K>(slot, 1, 2, budget[slot], [&](int par) {
+            CLOT_LAUNCH(p1, (k_bicg_1<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+            finish<K>(EpiBicg1<K>{});
+            CLOT_LAUNCH(p1 + 1, (k_bicg_2<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+            finish<2 * K>(EpiBicg2<K>{});
+            CLOT_LAUNCH(p1 + 2, (k_bicg_3<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+            finish<2 * K>(EpiBicg3<K>{});
+        });
     }
 
     template <int NV, class E>
@@ -909,29 +945,23 @@ struct Ctx : clot_ctx {
     }
 
     // Multigrid-preconditioned CG on the pressure correction.
-    int run_mgcg(KVec<T, 1> V, double rtol, int tol_mode, const int32_t* mask, int slot) {
+    int run_mgcg(KVec<T, 1> V, double rtol, int tol_mode, const int32_t* mask, int slot, int pass) {
         PresOp<T, T> pop{F.rAU, F.dP};
         set_active(mask);
         hipLaunchKernelGGL((k_mgcg_init<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), pop, V, S);
         finish<2>(EpiMgcgInit{rtol, tol_mode});
         vcycle(V.r[0]);
-        int it = 0, par = 0;
-        int chunk = std::max(2, last_it[slot]);
-        while (it < prm.max_iter) {
-            for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it) {
-                CLOT_LAUNCH(CLOT_PROBE_P_CG_A, (k_mgcg_a<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), pop, V,
-                            mg_z0, S, par);
-                finish<1>(EpiCgA<1>{});
-                CLOT_LAUNCH(CLOT_PROBE_P_CG_B, (k_mgcg_b<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), pop, V,
-                            S, par);
-                finish<1>(EpiMgcgB{});
-                vcycle(V.r[0]);
-                par ^= 1;
-            }
-            if (poll() == 0) break;
-            chunk = 2;
-        }
-        last_it[slot] = std::max(1, it - 1);
+        const int ps = std::min(pass, 11);
+        const int it = iterate<1>(slot, 1, 2, pbudget[slot - 1][ps], [&](int par) {
+            CLOT_LAUNCH(CLOT_PROBE_P_CG_A, (k_mgcg_a<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), pop, V,
+                        mg_z0, S, par);
+            finish<1>(EpiCgA<1>{});
+            CLOT_LAUNCH(CLOT_PROBE_P_CG_B, (k_mgcg_b<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), pop, V,
+                        S, par);
+            finish<1>(EpiMgcgB{});
+            vcycle(V.r[0]);
+        });
+        if (!capturing) it_pmax[slot - 1][ps] = std::max(it_pmax[slot - 1][ps], it);
         return it;
     }
 
@@ -964,40 +994,12 @@ struct Ctx : clot_ctx {
         return V;
     }
 
-    void record(int slot_it, int slot_res, int K, bool add) {
+    void record(int slot_it, int slot_res, int K, bool add, const int32_t* mask = nullptr) {
         hipLaunchKernelGGL(k_record, dim3(1), dim3(64), 0, st, S.sc, dstats, NSTAT, (int)ch.size(), K, slot_it, slot_res,
-                           (int)ST_FAIL, add ? 1 : 0);
+                           (int)ST_FAIL, add ? 1 : 0, mask);
     }
 
     // ---------------------------------------------------------------------------
-    void sigma_host(std::vector<int32_t>& pushv, std::vector<double>& w, bool& any) {
-        // push decision and trapezoid weights per channel (section 3.2, eq. sigma_disc)
-        any = false;
-        const int nch = (int)ch.size();
-        pushv.assign((size_t)nch * 2, -1);
-        w.assign((size_t)nch * NHIST, 0.0);
-        for (int i = 0; i < nch; ++i) {
-            ChanHost& h = ch[i];
-            const int64_t m = (int64_t)std::floor(h.t / prm.dtau + 1e-9);
-            if (!(h.n == 0 || m >= h.next_push)) continue;
-            h.next_push = m + 1;
-            h.head = (h.head + 1) % NHIST;
-            h.hist_t[h.head] = h.t;
-            h.npushed = std::min(h.npushed + 1, NHIST);
-            pushv[2 * i] = h.head;
-            pushv[2 * i + 1] = h.n == 0 ? 1 : 0;
-            // node a (0 = newest) lives in slot (head - a) mod NHIST; trapezoid weights
-            for (int a = 0; a < NHIST; ++a) {
-                const int slot = ((h.head - a) % NHIST + NHIST) % NHIST;
-                if (a >= h.npushed) continue;
-                const double age = h.t - h.hist_t[slot];
-                const double wt = (a == 0 || a == NHIST - 1) ? 0.5 * prm.dtau : prm.dtau;
-                w[(size_t)i * NHIST + slot] = prm.A_hat * wt * std::exp(-(age - 3.0) * (age - 3.0)) / std::sqrt(PI);
-            }
-            any = true;
-        }
-    }
-
     clot_status one_step() {
         const Grid G = grid();
         const dim3 gb(ntiles), tb(NT);
@@ -1029,17 +1031,25 @@ struct Ctx : clot_ctx {
             T* e = pool[5];
             T* rin = pool[0];
             PresOp<T, T> pop{F.rAU, F.dP};
-            for (int pass = 0; pass < 12; ++pass) {
+            const int npass = capturing ? budget[6] : 12;
+            for (int pass = 0; pass < npass; ++pass) {
                 CLOT_LAUNCH(CLOT_PROBE_P_RESID, k_pres_resid<T>, gb, tb, 0, st, G, F, rin, e, S);
                 finish<2>(EpiPresResid{prm.rtol_p, prec == CLOT_FP64 ? 0.0 : prm.rtol_inner, pass, refmask});
-                const int32_t need = poll();
-                if (need == 0) break;
+                if (!capturing) {
+                    it_max[6] = std::max(it_max[6], pass);
+                    if (poll() == 0) break;
+                }
                 KVec<T, 1> V = cg_vecs(e, rin);
-                run_mgcg(V, 0.0, 1, refmask, 1 + std::min(k, 2));
-                record(ST_P + std::min(k, MAXCORR - 1), ST_RESP, 1, pass > 0);
+                run_mgcg(V, 0.0, 1, refmask, 1 + std::min(k, 2), pass);
+                record(ST_P + std::min(k, MAXCORR - 1), ST_RESP, 1, pass > 0, refmask);
                 hipLaunchKernelGGL(k_pres_add<T>, gb, tb, 0, st, G, F, e, refmask);
                 set_active(refmask);
                 hipLaunchKernelGGL(k_count_active, dim3(1), dim3(64), 0, st, S.chact, S.nact, nch);
+            }
+            if (capturing) {   // a channel still needing refinement after the last pass
+                CLOT_LAUNCH(CLOT_PROBE_P_RESID, k_pres_resid<T>, gb, tb, 0, st, G, F, rin, e, S);
+                finish<2>(EpiPresResid{prm.rtol_p, prec == CLOT_FP64 ? 0.0 : prm.rtol_inner, npass, refmask});
+                hipLaunchKernelGGL(k_flag_active, dim3(1), dim3(64), 0, st, refmask, S.sc, nch, 1, gflag);
             }
             hipLaunchKernelGGL(k_record_pass, dim3(1), dim3(64), 0, st, S.sc, dstats, NSTAT, nch,
                                ST_REF + std::min(k, MAXCORR - 1), ST_RESP, (int)ST_FAIL);
@@ -1055,18 +1065,8 @@ struct Ctx : clot_ctx {
             record(ST_ETA, ST_RESE, 1, false);
         }
         // O-4 sigma
-        {
-            std::vector<int32_t> pv;
-            std::vector<double> w;
-            bool any;
-            sigma_host(pv, w, any);
-            if (any) {
-                HIPCHK(hipMemcpyAsync(push, pv.data(), pv.size() * 4, hipMemcpyHostToDevice, st));
-                HIPCHK(hipMemcpyAsync(sigw, w.data(), w.size() * 8, hipMemcpyHostToDevice, st));
-                hipLaunchKernelGGL(k_sigma<T>, gb, tb, 0, st, G, F, M, sigw, push);
-                HIPCHK(hipStreamSynchronize(st));
-            }
-        }
+        hipLaunchKernelGGL(k_sigma_sched, dim3(1), dim3(64), 0, st, d_ch, sig, nch, M, sigw, push);
+        hipLaunchKernelGGL(k_sigma<T>, gb, tb, 0, st, G, F, M, sigw, push);
         // O-5 transport
         TrOp<T> top;
         for (int k = 0; k < NTR; ++k) {
@@ -1107,20 +1107,149 @@ struct Ctx : clot_ctx {
             CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn<T>, gb, tb, 0, st, G, F, M);
         }
         // O-7 rotate theta_B and the flux
+        rotate();
+        HIPCHK(hipGetLastError());
+        return CLOT_OK;
+    }
+
+    // Host side of the end of a step: buffer rotation and the channel clocks.
+    void rotate() {
         std::swap(F.thB, F.thB_prev);
         for (int c = 0; c < 3; ++c) std::swap(F.phi[c], F.phin[c]);
+        parity ^= 1;
         for (ChanHost& h : ch) {
             h.n += 1;
             h.t = h.n * h.d.dt;
         }
-        HIPCHK(hipGetLastError());
+    }
+
+    static SigState fresh_sig() {
+        SigState s{};
+        s.t = 0.0;
+        s.n = 0;
+        s.next_push = 0;
+        s.head = -1;
+        s.npushed = 0;
+        for (int q = 0; q < NHIST; ++q) s.hist_t[q] = -1e300;
+        return s;
+    }
+
+    void drop_graphs() {
+        for (auto& v : gseg) {
+            for (hipGraphExec_t g : v) (void)hipGraphExecDestroy(g);
+            v.clear();
+        }
+    }
+
+    // Ends the recording in progress, keeps it as the next graph of the chain, and
+    // starts recording again.
+    clot_status seg_close(bool reopen) {
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (e != hipSuccess || !g) {
+            err = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+            return CLOT_EHIP;
+        }
+        size_t nn = 0;
+        (void)hipGraphGetNodes(g, nullptr, &nn);
+        g_nodes += (int64_t)nn;
+        hipGraphExec_t x = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ei);
+            return CLOT_EHIP;
+        }
+        cap_out->push_back(x);
+        g_segs += 1;
+        if (reopen) HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        return CLOT_OK;
+    }
+    void seg_point() {
+        if (!capturing || seg_err) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipGraph_t g = nullptr;
+        if (hipStreamGetCaptureInfo_v2(st, &cs, nullptr, &g, nullptr, nullptr) != hipSuccess ||
+            cs != hipStreamCaptureStatusActive || !g) {
+            err = "graph recording: stream is not recording";
+            seg_err = CLOT_EHIP;
+            return;
+        }
+        size_t nn = 0;
+        if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) {
+            err = "graph recording: hipGraphGetNodes failed";
+            seg_err = CLOT_EHIP;
+            return;
+        }
+        if (nn >= SEG_NODES) seg_err = seg_close(true);
+    }
+
+    // Records one step of the current parity into a graph.  The host state that the
+    // recording advances (buffer rotation, clocks) is restored afterwards: capture
+    // enqueues work without running it.
+    clot_status capture() {
+        if (!cst) HIPCHK(hipStreamCreateWithFlags(&cst, hipStreamNonBlocking));
+        auto bud = [&](int m) { return std::min(prm.max_iter, (int)std::ceil(g_scale * m) + g_pad); };
+        for (int s = 0; s < 8; ++s) budget[s] = bud(it_max[s]);
+        // refinement passes: the most seen plus one spare; a pass budget follows the
+        // count seen in that pass (the spare pass takes the last one's)
+        budget[6] = std::min(12, it_max[6] + 1);
+        for (int q = 0; q < 3; ++q)
+            for (int ps = 0; ps < 12; ++ps)
+                pbudget[q][ps] = bud(ps < it_max[6] ? it_pmax[q][ps] : (it_max[6] > 0 ? it_pmax[q][it_max[6] - 1] : 0));
+        const Fields<T> F0 = F;
+        const int par0 = parity;
+        std::vector<ChanHost> ch0 = ch;
+        hipStream_t st0 = st;
+        std::vector<hipGraphExec_t>& out = gseg[parity];
+        for (hipGraphExec_t x : out) (void)hipGraphExecDestroy(x);
+        out.clear();
+        g_nodes = 0;
+        g_segs = 0;
+        HIPCHK(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal));
+        st = cst;
+        capturing = true;
+        cap_out = &out;
+        seg_err = CLOT_OK;
+        clot_status r = one_step();
+        capturing = false;
+        if (r >= 0 && seg_err >= 0) {
+            r = seg_close(false);
+        } else {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cst, &g);
+            if (g) (void)hipGraphDestroy(g);
+            if (r >= 0) r = seg_err;
+        }
+        st = st0;
+        cap_out = nullptr;
+        F = F0;
+        parity = par0;
+        ch = ch0;
+        if (r < 0) {
+            for (hipGraphExec_t x : out) (void)hipGraphExecDestroy(x);
+            out.clear();
+            return r;
+        }
+        g_captures += 1;
         return CLOT_OK;
     }
 
     clot_status step(int nsteps, bool wait) override {
         for (int s = 0; s < nsteps; ++s) {
+            if (graph_on && calib_left == 0) {
+                if (gseg[parity].empty()) {
+                    const clot_status r = capture();
+                    if (r < 0) return r;
+                }
+                for (hipGraphExec_t x : gseg[parity]) HIPCHK(hipGraphLaunch(x, st));
+                g_replays += 1;
+                rotate();
+                continue;
+            }
             clot_status r = one_step();
             if (r < 0) return r;
+            if (calib_left > 0) --calib_left;
         }
         if (wait) return sync();
         return CLOT_OK;
@@ -1128,6 +1257,48 @@ struct Ctx : clot_ctx {
     clot_status sync() override {
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipGetLastError());
+        if (graph_on && g_replays > 0) {
+            int32_t f = 0;
+            HIPCHK(hipMemcpy(&f, gflag, 4, hipMemcpyDeviceToHost));
+            if (f) {   // a budget was too small: count it, widen the budgets, re-record
+                g_overflows += 1;
+                const int32_t z = 0;
+                HIPCHK(hipMemcpy(gflag, &z, 4, hipMemcpyHostToDevice));
+                g_scale *= 2.0;
+                g_pad += 2;
+                drop_graphs();
+            }
+        }
+        return CLOT_OK;
+    }
+
+    clot_status set_graph(int on, double scale, int pad) override {
+        HIPCHK(hipStreamSynchronize(st));
+        drop_graphs();
+        graph_on = on != 0;
+        if (!graph_on) return CLOT_OK;
+        if (!(scale >= 0.0) || pad < 1) {
+            err = "set_graph_mode: budget scale must be >= 0 and pad >= 1";
+            graph_on = false;
+            return CLOT_EINVAL;
+        }
+        g_scale = scale;
+        g_pad = pad;
+        for (int& m : it_max) m = 0;
+        for (auto& r : it_pmax)
+            for (int& m : r) m = 0;
+        calib_left = 2;   // one eager step of each parity sets the budgets
+        return CLOT_OK;
+    }
+    clot_status graph_info(int64_t* info) override {
+        info[0] = graph_on ? 1 : 0;
+        info[1] = g_captures;
+        info[2] = g_replays;
+        info[3] = g_overflows;
+        for (int s = 0; s < 7; ++s) info[4 + s] = budget[s];
+        for (int s = 0; s < 7; ++s) info[11 + s] = it_max[s];
+        info[18] = g_nodes;
+        info[19] = g_segs;
         return CLOT_OK;
     }
     clot_status stats(int c, clot_stats* s) const override {
@@ -1434,6 +1605,14 @@ clot_status clot_probe(clot_ctx* c, int32_t kernel) {
 clot_status clot_probe_read(clot_ctx* c, double* ms, int64_t* n) {
     if (!c || !ms || !n) return CLOT_EINVAL;
     return c->probe_read(ms, n);
+}
+clot_status clot_set_graph_mode(clot_ctx* c, int32_t on, double budget_scale, int32_t budget_pad) {
+    if (!c) return CLOT_EINVAL;
+    return c->set_graph(on, budget_scale, budget_pad);
+}
+clot_status clot_graph_info(clot_ctx* c, int64_t* info) {
+    if (!c || !info) return CLOT_EINVAL;
+    return c->graph_info(info);
 }
 void clot_destroy(clot_ctx* c) { delete c; }
 const char* clot_last_error(const clot_ctx* c) { return c ? c->err.c_str() : "null context"; }

@@ -19,7 +19,8 @@ namespace clot {
 // Per (channel, system) scalar slots.
 enum {
     SC_BB = 0, SC_RR, SC_RZ, SC_RHO, SC_ALPHA, SC_OMEGA, SC_BETA, SC_IT, SC_ACT, SC_TOL2, SC_RR0, SC_PQ,
-    SC_TS, SC_TT, SC_FAIL, SC_PASS
+    SC_TS, SC_TT, SC_FAIL, SC_PASS,
+    SC_ORR, SC_OBB, SC_ORRP   // pressure refinement: outer r.r, b.b, r.r of the previous pass
 };
 
 struct KState {

@@ -166,25 +166,31 @@ __global__ __launch_bounds__(NT) void k_pres_resid(Grid G, Fields<T> F, T* rin, 
 }
 
 // Decides on the device whether a channel needs another refinement pass, and the
-// inner solve's target: a fraction of this residual, not below the outer goal.
+// inner solve's target: a fraction of this residual, not below the outer goal.  A
+// pass that fails to halve the residual ends the refinement: the residual has reached
+// the floor the FP64 arithmetic allows (the goal is relative to |b|, which can be
+// small next to the terms of A p), and further passes would not change p.
 struct EpiPresResid {
     double rtol, rtol_inner;
     int pass;
     int32_t* refmask;
     __device__ void operator()(const double* sums, const KState& S, int ch) const {
         double* s = scp(S, ch, 0);
-        s[SC_RR0] = sums[0];
-        s[SC_BB] = sums[1];
+        const double rr = sums[0], bb = sums[1];
+        const bool stalled = pass > 0 && rr > 0.25 * s[SC_ORRP];
+        s[SC_ORR] = rr;
+        s[SC_OBB] = bb;
+        s[SC_ORRP] = rr;
         s[SC_PASS] = (double)pass;
-        const double target2 = rtol * rtol * sums[1];
-        if (sums[0] <= target2 || sums[1] == 0.0 || !isfinite(sums[0])) {
+        const double target2 = rtol * rtol * bb;
+        if (rr <= target2 || bb == 0.0 || !isfinite(rr) || stalled) {
             S.chact[ch] = 0;
             refmask[ch] = 0;
             atomicSub(S.nact, 1);
             s[SC_ACT] = 0.0;
-            if (!isfinite(sums[0])) s[SC_FAIL] = 1.0;
+            if (!isfinite(rr)) s[SC_FAIL] = 1.0;
         } else {
-            const double inner2 = rtol_inner * rtol_inner * sums[0];
+            const double inner2 = rtol_inner * rtol_inner * rr;
             s[SC_TOL2] = inner2 > 0.25 * target2 ? inner2 : 0.25 * target2;
             s[SC_ACT] = 1.0;
             s[SC_PASS] = (double)(pass + 1);
@@ -291,6 +297,54 @@ __global__ __launch_bounds__(NT) void k_sigma(Grid G, Fields<T> F, ModelDev M, c
         for (int k = 0; k < NHIST; ++k) s += wc[k] * (double)F.hist[(int64_t)k * F.ncell + g];
         F.sigma[g] = T(s);
     CLOT_END_CELLS
+}
+
+// Release-history schedule of one channel (section 3.2, eq. for sigma): the time and
+// step count, the next snapshot index and the ring of snapshot times.
+struct SigState {
+    double t;
+    int64_t n;
+    int64_t next_push;
+    int32_t head;      // slot of the newest snapshot (-1: none yet)
+    int32_t npushed;
+    double hist_t[NHIST];
+};
+
+// Decides, per channel, whether this step takes a new snapshot of the release rate
+// (every dtau of simulated time, and at the first step), and if so the trapezoid
+// weights A_hat w_a exp(-(age_a - 3)^2)/sqrt(pi) of the snapshots (node a = 0 the
+// newest, half weight at the two ends).  Then advances the channel clock by one step.
+// One thread per channel; push[2c] = slot or -1, push[2c+1] = first-step flag.
+__global__ __launch_bounds__(64) void k_sigma_sched(const ChanDev* chans, SigState* sig, int nch, ModelDev M,
+                                                    double* w, int32_t* push) {
+    for (int c = threadIdx.x; c < nch; c += 64) {
+        SigState s = sig[c];
+        push[2 * c] = -1;
+        push[2 * c + 1] = 0;
+        const int64_t m = (int64_t)floor(s.t / M.dtau + 1e-9);
+        if (s.n == 0 || m >= s.next_push) {
+            s.next_push = m + 1;
+            s.head = (s.head + 1) % NHIST;
+            s.hist_t[s.head] = s.t;
+            s.npushed = s.npushed + 1 < NHIST ? s.npushed + 1 : NHIST;
+            push[2 * c] = s.head;
+            push[2 * c + 1] = s.n == 0 ? 1 : 0;
+            double* wc = w + (int64_t)c * NHIST;
+            for (int a = 0; a < NHIST; ++a) {
+                const int slot = ((s.head - a) % NHIST + NHIST) % NHIST;
+                double v = 0.0;
+                if (a < s.npushed) {
+                    const double age = s.t - s.hist_t[slot];
+                    const double wt = (a == 0 || a == NHIST - 1) ? 0.5 * M.dtau : M.dtau;
+                    v = M.A_hat * wt * exp(-(age - 3.0) * (age - 3.0)) / sqrt(3.14159265358979323846);
+                }
+                wc[slot] = v;
+            }
+        }
+        s.n += 1;
+        s.t = (double)s.n * chans[c].dt;
+        sig[c] = s;
+    }
 }
 
 // Transport assembly (section 3.2, Appendix C table, Appendix D): diagonal and
@@ -518,9 +572,12 @@ __global__ void k_count_active(const int32_t* chact, int32_t* nact, int nch) {
 }
 
 // Copies Krylov outcomes of the last solve into the per-channel statistics.
+// Records one solve's iteration count, residual and failure flag per channel; with
+// `mask`, only channels whose mask entry is set took part in the solve.
 __global__ void k_record(const double* sc, double* stats, int nstat, int nch, int K, int slot_it, int slot_res,
-                         int slot_fail, int add) {
+                         int slot_fail, int add, const int32_t* mask) {
     for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+        if (mask && !mask[c]) continue;
         double it = 0.0, res = 0.0, fail = 0.0;
         for (int k = 0; k < K; ++k) {
             const double* s = sc + ((int64_t)c * MAXK + k) * NSC;
@@ -540,7 +597,7 @@ __global__ void k_record_pass(const double* sc, double* stats, int nstat, int nc
     for (int c = threadIdx.x; c < nch; c += blockDim.x) {
         const double* s = sc + (int64_t)c * MAXK * NSC;
         stats[(int64_t)c * nstat + slot] = s[SC_PASS];
-        if (s[SC_BB] > 0.0) stats[(int64_t)c * nstat + slot_res] = sqrt(s[SC_RR0] / s[SC_BB]);
+        if (s[SC_OBB] > 0.0) stats[(int64_t)c * nstat + slot_res] = sqrt(s[SC_ORR] / s[SC_OBB]);
         stats[(int64_t)c * nstat + slot_fail] = fmax(stats[(int64_t)c * nstat + slot_fail], s[SC_FAIL]);
     }
 }
@@ -550,6 +607,16 @@ __global__ void k_record_fallback(const int32_t* fb_chan, const ChanDev* chans, 
                                   int slot) {
     for (int c = threadIdx.x; c < nch; c += blockDim.x)
         stats[(int64_t)c * nstat + slot] = (double)fb_chan[c] / (double)chans[c].ncell;
+}
+
+// After a solve whose iteration count was fixed in advance: every channel still
+// active has not converged; flag it as failed and raise the host-visible flag.
+__global__ void k_flag_active(const int32_t* chact, double* sc, int nch, int K, int32_t* flag) {
+    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+        if (!chact[c]) continue;
+        flag[0] = 1;
+        for (int k = 0; k < K; ++k) sc[((int64_t)c * MAXK + k) * NSC + SC_FAIL] = 1.0;
+    }
 }
 
 // Small utility kernels (graph-safe replacements for memset).
