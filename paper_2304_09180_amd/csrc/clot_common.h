@@ -13,7 +13,10 @@
 namespace clot {
 
 constexpr int NT = 256;           // threads per block (4 wavefronts of 64)
-constexpr int CPT = 1;            // cells per thread
+#ifndef CLOT_CPT
+#define CLOT_CPT 1
+#endif
+constexpr int CPT = CLOT_CPT;     // cells per thread (a build option: 1, 2 or 4)
 constexpr int TILE = NT * CPT;    // cells per tile
 constexpr int NXCD = 8;
 constexpr int NSPC = 15;          // cell species

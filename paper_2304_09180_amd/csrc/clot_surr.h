@@ -149,68 +149,72 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     uint16_t* sX = reinterpret_cast<uint16_t*>(tileb[wv]);
     float* sO = reinterpret_cast<float*>(tileb[wv]);
-    const int64_t local = tbase + threadIdx.x;
-    const bool own = local < C.ncell;
-    T y[NRX], f[NRX];
-    T adp = T(0), gam = T(0), hadh = T(0);
-    const T dt = T(C.dt);
-    int64_t g = 0;
-    {
-        float x[MLP_IN];
-        if (own) {
-            const Cell P = cell_at(C, local);
-            g = P.g;
-            load_rxn_state(F, g, y);
-            adp = F.xt[6][g];
-            gam = binding_g<T>(F.eta[g], M);
-            hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
-            surr_features(y, adp, gam, hadh, dt, M, tb, x, f);
-        } else {
-#pragma unroll
-            for (int i = 0; i < MLP_IN; ++i) x[i] = 0.f;
-        }
-#pragma unroll
-        for (int i = 0; i < MLP_IN; i += 4)
-            *reinterpret_cast<bf16x4*>(sX + l * SURR_XLD + i) = pack4_bf16(x[i], x[i + 1], x[i + 2], x[i + 3]);
-    }
-    __syncthreads();
     const int rq = 4 * (l >> 4);
-    bf16x4 xb[4][2];
-#pragma unroll
-    for (int grp = 0; grp < 4; ++grp)
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) xb[grp][kb] = load_b_cm(sX, SURR_XLD, 16 * kb, 16 * grp);
-    __syncthreads();   // the output tile overwrites the input tile
     MLPRegs R;
     R.load(w);
+    for (int sub = 0; sub < TILE / 256; ++sub) {   // 256 cells per pass
+        const int64_t local = tbase + sub * 256 + threadIdx.x;
+        const bool own = local < C.ncell;
+        T y[NRX], f[NRX];
+        T adp = T(0), gam = T(0), hadh = T(0);
+        const T dt = T(C.dt);
+        int64_t g = 0;
+        {
+            float x[MLP_IN];
+            if (own) {
+                const Cell P = cell_at(C, local);
+                g = P.g;
+                load_rxn_state(F, g, y);
+                adp = F.xt[6][g];
+                gam = binding_g<T>(F.eta[g], M);
+                hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
+                surr_features(y, adp, gam, hadh, dt, M, tb, x, f);
+            } else {
 #pragma unroll
-    for (int grp = 0; grp < 4; ++grp) {
-        bf16x4 h1[4], h2[4];
-        const f32x4 o = mlp_chain16(R, w, xb[grp], h1, h2);
-        float* q = sO + (16 * grp + (l & 15)) * SURR_OLD + rq;
-        q[0] = o[0];
-        q[1] = o[1];
-        q[2] = o[2];
-        q[3] = o[3];
-    }
-    __syncthreads();
-    if (!own) return;
-    T inc[NRX];
+                for (int i = 0; i < MLP_IN; ++i) x[i] = 0.f;
+            }
 #pragma unroll
-    for (int i = 0; i < NRX; ++i) {
-        float r = tb.sc[i] * sO[l * SURR_OLD + i];
-        r = r > 0.5f ? 0.5f : (r < -0.5f ? -0.5f : r);
-        inc[i] = f[i] * (T(1) + T(r));
-    }
-    const float d = surr_defect(y, inc, adp, gam, hadh, dt, M, tb);
-    if (d < tol) {
+            for (int i = 0; i < MLP_IN; i += 4)
+                *reinterpret_cast<bf16x4*>(sX + l * SURR_XLD + i) = pack4_bf16(x[i], x[i + 1], x[i + 2], x[i + 3]);
+        }
+        __syncthreads();
+        bf16x4 xb[4][2];
 #pragma unroll
-        for (int i = 0; i < NRX; ++i) y[i] += inc[i];
-        store_rxn_state(F, g, y, adp);
-    } else {
-        const int32_t slot = atomicAdd(fb_count, 1);
-        fb_list[slot] = (int32_t)g;
-        atomicAdd(&fb_chan[chid], 1);
+        for (int grp = 0; grp < 4; ++grp)
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) xb[grp][kb] = load_b_cm(sX, SURR_XLD, 16 * kb, 16 * grp);
+        __syncthreads();   // the output tile overwrites the input tile
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp) {
+            bf16x4 h1[4], h2[4];
+            const f32x4 o = mlp_chain16(R, w, xb[grp], h1, h2);
+            float* q = sO + (16 * grp + (l & 15)) * SURR_OLD + rq;
+            q[0] = o[0];
+            q[1] = o[1];
+            q[2] = o[2];
+            q[3] = o[3];
+        }
+        __syncthreads();
+        if (own) {
+            T inc[NRX];
+#pragma unroll
+            for (int i = 0; i < NRX; ++i) {
+                float r = tb.sc[i] * sO[l * SURR_OLD + i];
+                r = r > 0.5f ? 0.5f : (r < -0.5f ? -0.5f : r);
+                inc[i] = f[i] * (T(1) + T(r));
+            }
+            const float d = surr_defect(y, inc, adp, gam, hadh, dt, M, tb);
+            if (d < tol) {
+#pragma unroll
+                for (int i = 0; i < NRX; ++i) y[i] += inc[i];
+                store_rxn_state(F, g, y, adp);
+            } else {
+                const int32_t slot = atomicAdd(fb_count, 1);
+                fb_list[slot] = (int32_t)g;
+                atomicAdd(&fb_chan[chid], 1);
+            }
+        }
+        __syncthreads();   // the next pass rewrites the tile
     }
 }
 
