@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="channel3d_256x64x64")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--tile", default="auto", choices=["auto", "256", "512", "1024"],
+                    help="cells per block; auto runs the tile autotuner on each workload first")
     ap.add_argument("--probe", default="p_cg_a", help="kernel phase timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
@@ -136,7 +138,16 @@ def kernel_us(s, probe, steps=2):
     return round(1e3 * pm / pn, 3) if pn else None
 
 
-def surrogate_leg(desc, prec, args, xc, xf):
+def pick_tile(descs, prec, args):
+    """The tile for a workload: given, or tuned (whole-step timing of each candidate)."""
+    if args.tile != "auto":
+        return int(args.tile), None
+    from paper_2304_09180_amd import autotune
+    e = autotune.tune(descs, prec, log=lambda m: print(m, file=sys.stderr, flush=True))
+    return e["tile"], e
+
+
+def surrogate_leg(desc, prec, args, xc, xf, tile):
     """Trains the reaction surrogate on the GPU (2-D channel states), then times the
     same workload with the learned reaction step."""
     from paper_2304_09180_amd import clot, surrogate
@@ -153,7 +164,7 @@ def surrogate_leg(desc, prec, args, xc, xf):
     ncell = desc["nx"] * desc["ny"] * desc["nz"]
 
     def run(mode, m_rxn):
-        s = clot.Solver([desc], prec, clot.default_params(prec, M_rxn=m_rxn))
+        s = clot.Solver([desc], prec, clot.default_params(prec, M_rxn=m_rxn), tile=tile)
         s.init_state(0, xc, xf)
         if mode == "surrogate":
             s.set_reaction_mode(clot.SURROGATE, blob, 1e-3)
@@ -186,11 +197,14 @@ def ensemble_leg(args):
     from paper_2304_09180_amd import clot
     descs = ci.ensemble(64)
     ncell = sum(ci.ncell(d) for d in descs)
+    tile, tuned = pick_tile(descs, clot.FP32_MIXED, args)
     out = {"members": len(descs), "cells": ncell,
            "sizes": sorted({f"{d['nx']}x{d['ny']}" for d in descs}),
-           "dt_range": [min(d["dt"] for d in descs), max(d["dt"] for d in descs)]}
+           "dt_range": [min(d["dt"] for d in descs), max(d["dt"] for d in descs)], "tile": tile}
+    if tuned:
+        out["autotune"] = {"ms_per_step": tuned["ms_per_step"], "kernel_us": tuned["kernel_us"]}
     for mode in ("eager", "graph"):
-        s = clot.Solver(descs, clot.FP32_MIXED)
+        s = clot.Solver(descs, clot.FP32_MIXED, tile=tile)
         for c, d in enumerate(descs):
             xc, xf = ci.noise(d)
             s.init_state(c, xc, xf)
@@ -227,7 +241,8 @@ def main():
 
     desc = ci.workload(args.workload)
     prec = clot.FP32_MIXED if args.precision == "fp32" else clot.FP64
-    s = clot.Solver([desc], prec)
+    tile, tuned = pick_tile([desc], prec, args)
+    s = clot.Solver([desc], prec, tile=tile)
     xc, xf = ci.noise(desc)
     s.init_state(0, xc, xf)
     ncell = desc["nx"] * desc["ny"] * desc["nz"]
@@ -256,16 +271,18 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if prec == clot.FP32_MIXED else "f64", "data": "synthetic",
-           "config": {"workload": args.workload, "cells": ncell, "dim": desc["dim"],
+           "config": {"workload": args.workload, "cells": ncell, "dim": desc["dim"], "tile": tile,
                       "grid": [desc["nx"], desc["ny"], desc["nz"]], "dt": desc["dt"], "shear": desc["shear"],
                       "precision": "fp32 fields, fp64 reductions and pressure" if prec == clot.FP32_MIXED else "fp64",
                       "reaction": "plain RK4"},
            "solver": {k: st[k] for k in ("it_mom", "it_p", "it_eta", "it_tr", "refine_p")},
            "rxn_kernel_us": rxn_us,
            "roofline": roof}
+    if tuned:
+        out["autotune"] = {"ms_per_step": tuned["ms_per_step"], "kernel_us": tuned["kernel_us"]}
     s.close()
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_leg(desc, prec, args, xc, xf)
+        out["surrogate"] = surrogate_leg(desc, prec, args, xc, xf, tile)
     if not args.no_ensemble:
         out["ensemble"] = ensemble_leg(args)
     if not args.no_cpu_baseline:

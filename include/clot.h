@@ -154,13 +154,19 @@ clot_status clot_get_stats(const clot_ctx* c, int32_t ch, clot_stats* s);
 clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* mlp_blob, size_t blob_bytes,
                                    double resid_tol);
 
+/* Cells per tile this library was built for (256, 512 or 1024): a tile is the
+ * group of cells one 256-thread block owns, with its own partial sums.  The tile
+ * size is a build option; the autotuner chooses among the built libraries. */
+int32_t clot_tile_cells(void);
+
 /* Graph replay of whole steps (for ensembles stepped many times).
  * on != 0: the next two clot_step steps run as usual and record, per solve, the
  * largest Krylov iteration count (and the number of FP64 pressure refinement
  * passes).  Each later step replays a HIP graph recorded once per buffer parity
  * (the step rotates theta_B and the face fluxes between two buffers), in which
  * every solve runs a fixed budget of ceil(budget_scale * count) + budget_pad
- * iterations.  Channels that converge earlier skip the remaining iterations on the
+ * iterations, and the pressure corrector the number of refinement passes seen (one
+ * more per overflow noticed so far).  Channels that converge earlier skip the remaining iterations on the
  * device, so a replayed step gives bit-for-bit the result of the eager step.  A
  * channel still unconverged when its budget ends is counted as a failed solve in
  * the statistics (as max_iter is eagerly); the next synchronisation (clot_step with

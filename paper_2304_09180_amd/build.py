@@ -1,4 +1,10 @@
-"""Builds libclot.so in-tree with hipcc for gfx950."""
+"""Builds the clotting-step library in-tree with hipcc for gfx950, once per tile size.
+
+A tile is the group of cells one 256-thread block owns (its partial sums, its
+channel); the tile size is fixed at compile time, so each candidate size is its own
+library: libclot.so (256 cells, one per thread), libclot_t512.so and
+libclot_t1024.so (two and four cells per thread).  The autotuner picks among them.
+"""
 from __future__ import annotations
 
 import os
@@ -7,24 +13,37 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(HERE, "csrc", "clot_api.hip")]
-OUT = os.path.join(HERE, "libclot.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # no packed-FP32 instructions anywhere in this library
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
+TILES = (256, 512, 1024)
 
 
-def build(verbose: bool = False) -> str:
-    cmd = [HIPCC, *FLAGS, "-o", OUT + ".tmp", *SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libclot.so")
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+def lib_name(tile: int) -> str:
+    return "libclot.so" if tile == 256 else f"libclot_t{tile}.so"
+
+
+def build(verbose: bool = False, tiles=TILES) -> list[str]:
+    procs = []
+    for tile in tiles:
+        out = os.path.join(HERE, lib_name(tile))
+        cmd = [HIPCC, *FLAGS, f"-DCLOT_CPT={tile // 256}", "-o", out + ".tmp", *SRC]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((out, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    failed = []
+    for out, p in procs:
+        log, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(log)
+            failed.append(out)
+        else:
+            os.replace(out + ".tmp", out)
+    if failed:
+        raise RuntimeError("hipcc failed building " + ", ".join(os.path.basename(f) for f in failed))
+    return [out for out, _ in procs]
 
 
 if __name__ == "__main__":

@@ -12,7 +12,15 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libclot.so")
+TILES = (256, 512, 1024)
+
+
+def lib_path(tile: int = 256) -> str:
+    """The library built for `tile` cells per block (see build.py)."""
+    return os.path.join(_HERE, "libclot.so" if tile == 256 else f"libclot_t{tile}.so")
+
+
+LIB_PATH = lib_path(256)
 
 FP64, FP32_MIXED = 0, 1
 PLAIN, SURROGATE = 0, 1
@@ -60,17 +68,20 @@ class ClotError(RuntimeError):
     pass
 
 
-_lib = None
+_libs = {}
 
 
-def load():
-    """Load libclot.so; raises if the HIP library has not been built."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ClotError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
-    lib = C.CDLL(LIB_PATH)
+def load(tile: int = 256):
+    """Load the library built for `tile` cells per block; raises if it has not been
+    built."""
+    if tile in _libs:
+        return _libs[tile]
+    if tile not in TILES:
+        raise ClotError(f"no library for tile {tile}: choose one of {TILES}")
+    path = lib_path(tile)
+    if not os.path.exists(path):
+        raise ClotError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = C.CDLL(path)
     P = C.c_void_p
     sig = {
         "clot_params_default": ([C.POINTER(Params)], C.c_int),
@@ -99,6 +110,7 @@ def load():
         "clot_rxn_rk4_batch": ([C.POINTER(Params), P, C.c_int64, P, P], C.c_int),
         "clot_surr_dataset": ([C.POINTER(Params), P, P, C.c_int64, P, P, P, P, P], C.c_int),
         "clot_mfma_selftest": ([P, P, P, P], C.c_int),
+        "clot_tile_cells": ([], C.c_int32),
         "clot_destroy": ([P], None),
         "clot_last_error": ([P], C.c_char_p),
     }
@@ -106,7 +118,9 @@ def load():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = res
-    _lib = lib
+    if lib.clot_tile_cells() != tile:
+        raise ClotError(f"{path} was built for {lib.clot_tile_cells()} cells per tile, not {tile}")
+    _libs[tile] = lib
     return lib
 
 
@@ -166,9 +180,10 @@ class Solver:
     stream (or the one passed in).
     """
 
-    def __init__(self, descs, precision=FP64, params: Params | None = None, device="cuda", stream=None):
+    def __init__(self, descs, precision=FP64, params: Params | None = None, device="cuda", stream=None, tile=256):
         import torch
-        self.lib = load()
+        self.tile = tile
+        self.lib = load(tile)
         if not torch.cuda.is_available():
             raise ClotError("no GPU visible: the clotting-step library runs only on the GPU")
         self.descs = list(descs)
@@ -257,7 +272,7 @@ class Solver:
         _check(self.lib, self.ctx, self.lib.clot_probe_read(self.ctx, C.byref(ms), C.byref(n)), "probe_read")
         return ms.value, n.value
 
-    def set_graph_mode(self, on=True, budget_scale=1.25, budget_pad=2):
+    def set_graph_mode(self, on=True, budget_scale=1.1, budget_pad=1):
         """Replay whole steps as HIP graphs after two calibrating eager steps (each
         Krylov solve then runs a fixed iteration budget; see clot_set_graph_mode)."""
         return _check(self.lib, self.ctx, self.lib.clot_set_graph_mode(self.ctx, 1 if on else 0, float(budget_scale),

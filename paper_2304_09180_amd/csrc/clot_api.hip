@@ -145,8 +145,8 @@ struct Ctx : clot_ctx {
     // Graph replay.  Slots: 0 momentum, 1..3 pressure (corrector 1, 2, later), 4 eta,
     // 5 transport; slot 6 counts pressure refinement passes.
     bool graph_on = false, capturing = false;
-    double g_scale = 1.5;
-    int g_pad = 4;
+    double g_scale = 1.1;
+    int g_pad = 1;
     int calib_left = 0;
     int it_max[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int budget[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1191,9 +1191,10 @@ struct Ctx : clot_ctx {
         if (!cst) HIPCHK(hipStreamCreateWithFlags(&cst, hipStreamNonBlocking));
         auto bud = [&](int m) { return std::min(prm.max_iter, (int)std::ceil(g_scale * m) + g_pad); };
         for (int s = 0; s < 8; ++s) budget[s] = bud(it_max[s]);
-        // refinement passes: the most seen plus one spare; a pass budget follows the
-        // count seen in that pass (the spare pass takes the last one's)
-        budget[6] = std::min(12, it_max[6] + 1);
+        // refinement passes: the most seen (plus one per budget overflow so far); a
+        // pass budget follows the count seen in that pass (an extra pass takes the
+        // last one's)
+        budget[6] = std::min(12, it_max[6] + (int)g_overflows);
         for (int q = 0; q < 3; ++q)
             for (int ps = 0; ps < 12; ++ps)
                 pbudget[q][ps] = bud(ps < it_max[6] ? it_pmax[q][ps] : (it_max[6] > 0 ? it_pmax[q][it_max[6] - 1] : 0));
@@ -1606,6 +1607,7 @@ clot_status clot_probe_read(clot_ctx* c, double* ms, int64_t* n) {
     if (!c || !ms || !n) return CLOT_EINVAL;
     return c->probe_read(ms, n);
 }
+int32_t clot_tile_cells(void) { return TILE; }
 clot_status clot_set_graph_mode(clot_ctx* c, int32_t on, double budget_scale, int32_t budget_pad) {
     if (!c) return CLOT_EINVAL;
     return c->set_graph(on, budget_scale, budget_pad);

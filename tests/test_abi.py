@@ -7,7 +7,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "clot.h")
-LIB = os.path.join(ROOT, "paper_2304_09180_amd", "libclot.so")
+PKG = os.path.join(ROOT, "paper_2304_09180_amd")
+LIB = os.path.join(PKG, "libclot.so")
+VARIANTS = {256: LIB, 512: os.path.join(PKG, "libclot_t512.so"), 1024: os.path.join(PKG, "libclot_t1024.so")}
 
 
 def declared():
@@ -21,11 +23,16 @@ def test_header_declares_the_abi():
         assert n in names
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libclot.so not built")
-def test_library_exports_every_declared_symbol():
-    lib = ctypes.CDLL(LIB)
+@pytest.mark.parametrize("tile", sorted(VARIANTS))
+def test_library_exports_every_declared_symbol(tile):
+    path = VARIANTS[tile]
+    if not os.path.exists(path):
+        pytest.skip(f"{os.path.basename(path)} not built")
+    lib = ctypes.CDLL(path)
     for n in declared():
         assert hasattr(lib, n), n
+    lib.clot_tile_cells.restype = ctypes.c_int32
+    assert lib.clot_tile_cells() == tile
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libclot.so not built")

@@ -1,0 +1,52 @@
+"""GPU checks of the tile variants and the autotuner: every tile size matches the
+FP64 oracle, and tuning stores and reuses its choice."""
+import numpy as np
+import pytest
+
+import clot_inputs as ci
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("tile", [512, 1024])
+def test_tile_variant_matches_oracle_fp64(tile):
+    from oracle import clot_oracle as oc
+    from paper_2304_09180_amd import clot
+    # two uneven channels: the second spans several tiles of every size plus a ragged tail
+    descs = [ci.channel(2, 40, 12, shear=1000.0, dt=1e-4, seed=3),
+             ci.channel(2, 72, 20, shear=600.0, dt=1e-4, seed=4, inj_frac=0.4)]
+    s = clot.Solver(descs, clot.FP64, tile=tile)
+    refs = []
+    for c, d in enumerate(descs):
+        xc, xf = ci.noise(d)
+        s.init_state(c, xc, xf)
+        o = oc.Oracle(d, xc, xf)
+        for _ in range(5):
+            o.step()
+        refs.append(o.fields())
+    s.step(5)
+    for c, ref in enumerate(refs):
+        got = s.fields(c)
+        for name in ("UX", "P", "ETA", "PMU", "PBSE", "S1", "E1", "C2", "S1B"):
+            r = ref[name]
+            err = np.linalg.norm(got[name] - r) / max(np.linalg.norm(r), 1e-300)
+            assert err <= 1e-10, (tile, c, name, err)
+    s.close()
+
+
+def test_autotune_stores_and_reuses_its_choice(tmp_path):
+    from paper_2304_09180_amd import autotune, clot
+    descs = [ci.channel(2, 128, 32, shear=800.0, seed=1), ci.channel(2, 64, 16, shear=300.0, seed=2)]
+    path = str(tmp_path / "tune.json")
+    e = autotune.tune(descs, clot.FP32_MIXED, steps=3, warmup=2, repeats=2, cache=path, log=print)
+    assert e["tile"] in clot.TILES
+    assert set(e["ms_per_step"]) == {str(t) for t in clot.TILES}
+    assert all(v > 0 for v in e["ms_per_step"].values())
+    assert all(e["kernel_us"][str(t)]["p_cg_a"] > 0 for t in clot.TILES)
+    # a second call answers from the cache (planted entry is returned as is)
+    data = autotune.load_cache(path)
+    key = autotune.cache_key(descs, clot.FP32_MIXED, autotune.arch_name())
+    other = 1024 if e["tile"] != 1024 else 256
+    data[key]["tile"] = other
+    autotune.store_cache(path, key, data[key])
+    assert autotune.tune(descs, clot.FP32_MIXED, cache=path)["tile"] == other
