@@ -83,7 +83,9 @@ typedef struct {
     double dt;
 } clot_channel;
 
-/* Model constants (Appendix E) and solver settings. */
+/* Model constants (Appendix E) and solver settings.  The release history (section
+ * 3.2, eq. for sigma) keeps tau_f/dtau + 1 = 25 snapshots: tau_f/dtau must be 24,
+ * else clot_create returns CLOT_EINVAL. */
 typedef struct {
     double nu, C_CK, D_P, D_ADP, D_chem, P_diam, P_max, P_0, k_adh, kcoh_Pmax;
     double eta_t, eta_star, L_eta_over_Pdiam, k_adp, adp_crit, k_e2, e2_crit;
@@ -92,7 +94,9 @@ typedef struct {
     double kS1p, kS1m, kE1p, kE1m, kS2p, kS2m, kE2p, kE2m;
     double S1_0, S2_0, E0_0, p_out;
     int32_t M_rxn;        /* reaction sub-steps per step (section 3.2; default 2)          */
-    int32_t n_corr;       /* PISO pressure corrections per step                            */
+    int32_t n_corr;       /* PISO pressure corrections per step; 0 = by the diffusion number
+                             D = nu dt / h_min^2: 2 (D <= 10), 3 (30), 4 (50), 5 (80),
+                             6 (120), else 8                                              */
     int32_t max_iter;     /* per linear solve                                              */
     int32_t marg_m, marg_n;
     double rtol_p;        /* pressure: ||b - A p|| <= rtol_p ||b|| (FP64 residual)           */
@@ -112,8 +116,10 @@ typedef struct {
 
 typedef struct clot_ctx clot_ctx;
 
-/* Fills the Appendix E constants; M_rxn = 2, n_corr = 3, tolerances of the precision
- * contract.  Never fails for a non-NULL pointer. */
+/* Fills the Appendix E constants; M_rxn = 2, n_corr = 0 (automatic), max_iter 5000,
+ * rtol_p = rtol_s = 1e-13, rtol_inner = 1e-4 (FP64 settings; the FP32 path is run
+ * with rtol_s 1e-7, rtol_p 1e-10, rtol_inner 1e-3).  Never fails for a non-NULL
+ * pointer. */
 clot_status clot_params_default(clot_params* p);
 
 /* Bytes of device workspace clot_create needs for these channels and precision. */

@@ -354,6 +354,12 @@ struct Ctx : clot_ctx {
     // ---------------------------------------------------------------------------
     clot_status setup(const clot_channel* cs, int nch, const clot_params* p) {
         prm = *p;
+        // the release history holds tau_f/dtau + 1 snapshots in a ring of fixed length
+        if (!(prm.dtau > 0) || !(prm.tau_f > 0) || std::fabs(prm.tau_f / prm.dtau - (NHIST - 1)) > 1e-9 * (NHIST - 1)) {
+            err = "params: tau_f/dtau must equal " + std::to_string(NHIST - 1) + " (release history of " +
+                  std::to_string(NHIST) + " snapshots)";
+            return CLOT_EINVAL;
+        }
         ch.resize(nch);
         int64_t c0 = 0, fx = 0, fy = 0, fz = 0, in = 0, inj = 0;
         int32_t t0 = 0;

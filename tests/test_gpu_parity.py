@@ -118,3 +118,29 @@ def test_fp64_batched_uneven_channels_match_single_runs():
         # each channel keeps its own dt; run the oracle with that channel alone
         ref = run_oracle(d, 3)
         compare(g, ref, 1e-10)
+
+
+def test_fp64_release_history_pushes_match_oracle():
+    """A release-history schedule short enough to push a snapshot every two or three
+    steps (dtau = 2.5e-4 s, tau_f = 24 dtau) and a large A_hat, so that sigma and ADP
+    carry the trapezoid of several snapshots of different ages."""
+    from oracle import clot_oracle as oc
+    from paper_2304_09180_amd import clot
+    over = dict(dtau=2.5e-4, tau_f=6e-3, A_hat=1e3)
+    d = ci.channel(2, 40, 12, shear=1000.0, dt=1e-4, seed=21)
+    steps = 12
+    xc, xf = ci.noise(d)
+    o = oc.Oracle(d, xc, xf, oc.Params(**over))
+    for _ in range(steps):
+        o.step()
+    ref = o.fields()
+    assert np.abs(ref["SIGMA"]).max() > 0.0
+    gpu, st = run_gpu([d], clot.FP64, steps, clot.default_params(clot.FP64, **over))
+    compare(gpu[0], ref, 1e-10)
+
+
+def test_release_history_length_is_checked():
+    from paper_2304_09180_amd import clot
+    d = ci.channel(2, 40, 12, seed=21)
+    with pytest.raises(clot.ClotError):
+        clot.Solver([d], clot.FP64, clot.default_params(clot.FP64, dtau=0.5))
