@@ -102,6 +102,9 @@ typedef struct {
     double rtol_p;        /* pressure: ||b - A p|| <= rtol_p ||b|| (FP64 residual)           */
     double rtol_s;        /* momentum, eta, transport                                      */
     double rtol_inner;    /* FP32 inner pressure solve of each refinement pass             */
+    int32_t mg_tail;      /* pressure multigrid: the levels whose channels all have at most
+                             this many cells run as one launch (one block per channel);
+                             0 = every level its own launches.  Default 4096.            */
 } clot_params;
 
 /* Per-channel statistics of the last step. */

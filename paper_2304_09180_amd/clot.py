@@ -54,7 +54,8 @@ class Params(C.Structure):
     _fields_ = ([(n, C.c_double) for n in _PARAM_DOUBLES_A] +
                 [("M_rxn", C.c_int32), ("n_corr", C.c_int32), ("max_iter", C.c_int32),
                  ("marg_m", C.c_int32), ("marg_n", C.c_int32),
-                 ("rtol_p", C.c_double), ("rtol_s", C.c_double), ("rtol_inner", C.c_double)])
+                 ("rtol_p", C.c_double), ("rtol_s", C.c_double), ("rtol_inner", C.c_double),
+                 ("mg_tail", C.c_int32)])
 
 
 class Stats(C.Structure):
@@ -144,7 +145,7 @@ def default_params(precision=FP64, **over) -> Params:
     if precision == FP32_MIXED:
         p.rtol_s = 1e-7
         p.rtol_p = 1e-10
-        p.rtol_inner = 1e-3
+        p.rtol_inner = 1e-4
         p.max_iter = 400
     for k, v in over.items():
         setattr(p, k, v)

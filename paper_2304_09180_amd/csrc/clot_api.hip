@@ -176,6 +176,8 @@ struct Ctx : clot_ctx {
     };
     std::vector<Level> lev;
     T mg_w = T(0.8);
+    int mg_t0 = -1;          // first level run by the fused tail launch (-1: none)
+    size_t mg_tail_lds = 0;  // its dynamic LDS bytes
     T* mg_y0 = nullptr;      // level-0 smoother scratch
     T* mg_z0 = nullptr;      // preconditioned residual z = M r
     double* mg_inv = nullptr;  // per-channel inverse of the coarsest-level matrix
@@ -459,6 +461,47 @@ struct Ctx : clot_ctx {
                     err = "channel too long for the pressure multigrid hierarchy";
                     return CLOT_EINVAL;
                 }
+        // fused launch for the trailing levels whose channels all fit the cell threshold
+        // and, with every level's arrays, the LDS of one block
+        mg_t0 = -1;
+        mg_tail_lds = 0;
+        if (p->mg_tail > 0 && !lev.empty()) {
+            int dev = 0, lds_max = 65536;
+            if (hipGetDevice(&dev) == hipSuccess)
+                (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+            // less the kernel's static LDS (level table, coarse right-hand side) and a margin
+            const int64_t limit = (int64_t)lds_max - (int64_t)(MG_MAXLEV * sizeof(TailLds)) - 1024;
+            const int nl = (int)lev.size();
+            auto bytes_from = [&](int t) {
+                int64_t worst = 0;
+                for (int i = 0; i < nch; ++i) {
+                    int64_t e = 0;
+                    for (int l = t; l < nl; ++l) {
+                        const ChanDev& c = lev[l].ch[i];
+                        e += tail_level_elems(c.dim, c.nx, c.ny, c.nz, l == nl - 1, (int)sizeof(T));
+                    }
+                    worst = std::max(worst, e * (int64_t)sizeof(T));
+                }
+                return worst;
+            };
+            int t = nl;
+            while (t > 0) {
+                int64_t mx = 0;
+                for (const ChanDev& c : lev[t - 1].ch) mx = std::max(mx, c.ncell);
+                if (mx > p->mg_tail || bytes_from(t - 1) > limit) break;
+                --t;
+            }
+            if (t < nl) {
+                mg_t0 = t;
+                mg_tail_lds = (size_t)bytes_from(t);
+                if (mg_tail_lds > 65536 &&
+                    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail<T>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mg_tail_lds) != hipSuccess) {
+                    err = "multigrid tail: cannot raise the dynamic LDS limit";
+                    return CLOT_EHIP;
+                }
+            }
+        }
         const clot_params& q = *p;
         M = ModelDev{q.nu, q.C_CK, q.D_P, q.D_ADP, q.D_chem, q.P_diam, q.P_max, q.P_0, q.k_adh, q.kcoh_Pmax,
                      q.eta_t, q.eta_star, 0.0, q.k_adp, q.adp_crit, q.k_e2, q.e2_crit,
@@ -922,20 +965,29 @@ struct Ctx : clot_ctx {
         hipLaunchKernelGGL((k_mg_pre<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), p0, r, mg_z0, mg_w, act);
         hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT), 0, st,
                            MGPair{grid(), lev[0].grid()}, p0, r, mg_z0, lev[0].b, act);
-        for (int l = 0; l + 1 < nl; ++l) {
+        const int t0 = mg_t0 >= 0 ? mg_t0 : nl - 1;   // levels from t0 on: fused launch or coarse solve
+        for (int l = 0; l < t0; ++l) {
             Level& L = lev[l];
             CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
             hipLaunchKernelGGL((k_mg_pre<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), op, L.b, L.x, mg_w, act);
             hipLaunchKernelGGL((k_mg_restrict<T, CoefOp<T>>), dim3(lev[l + 1].ntiles * (TILE / (NT / 8))), dim3(NT), 0,
                                st, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, L.x, lev[l + 1].b, act);
         }
-        {
+        if (mg_t0 >= 0) {
+            MGTail<T> tl{};
+            tl.n = nl - t0;
+            for (int l = t0; l < nl; ++l) {
+                Level& L = lev[l];
+                tl.L[l - t0] = MGTailLevel<T>{L.d_ch, L.x, L.y, L.b, L.dg, L.cx, L.cy, L.cz, L.cout};
+            }
+            hipLaunchKernelGGL(k_mg_tail<T>, dim3((int)ch.size()), dim3(MG_TAIL_BS), mg_tail_lds, st, tl, mg_w, mg_inv, act);
+        } else {
             Level& Lc = lev[nl - 1];
             hipLaunchKernelGGL(k_mg_coarse<T>, dim3((int)ch.size()), dim3(MG_COARSE), 0, st, Lc.grid(), mg_inv, Lc.b, Lc.x,
                                act, (int)ch.size());
         }
         // up
-        for (int l = nl - 2; l >= 0; --l) {
+        for (int l = t0 - 1; l >= 0; --l) {
             Level& L = lev[l];
             CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
             hipLaunchKernelGGL((k_mg_post1<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, MGPair{L.grid(), lev[l + 1].grid()},
@@ -973,7 +1025,7 @@ struct Ctx : clot_ctx {
 
     template <int K>
     KVec<T, K> bicg_vecs(int first) {
-        KVec<T, K> V;
+        KVec<T, K> V{};
         for (int k = 0; k < K; ++k) {
             T** b = pool + 7 + 7 * (first + k);
             V.r[k] = b[0];
@@ -987,7 +1039,7 @@ struct Ctx : clot_ctx {
         return V;
     }
     KVec<T, 1> cg_vecs(T* x, const T* b) {
-        KVec<T, 1> V;
+        KVec<T, 1> V{};
         V.x[0] = x;
         V.b[0] = b;
         V.r[0] = pool[1];
@@ -1438,6 +1490,7 @@ clot_status clot_params_default(clot_params* p) {
     p->rtol_p = 1e-13;
     p->rtol_s = 1e-13;
     p->rtol_inner = 1e-4;
+    p->mg_tail = 4096;
     return CLOT_OK;
 }
 
@@ -1464,7 +1517,7 @@ clot_status clot_create(const clot_channel* chs, int32_t n_ch, const clot_params
                         size_t wsb, void* stream, clot_ctx** out) {
     if (!chs || n_ch < 1 || !p || !ws || !out || (prec != CLOT_FP64 && prec != CLOT_FP32_MIXED)) return CLOT_EINVAL;
     *out = nullptr;
-    if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1) return CLOT_EINVAL;
+    if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1 || p->mg_tail < 0) return CLOT_EINVAL;
     clot_ctx* c = make_ctx(prec);
     c->prec = prec;
     clot_status s = prec == CLOT_FP64 ? create_t(static_cast<Ctx<double>*>(c), chs, n_ch, p, ws, wsb, stream)

@@ -312,6 +312,215 @@ __global__ __launch_bounds__(MG_COARSE) void k_mg_coarse(Grid G, const double* i
 }
 
 // ------------------------------------------------------------------------------------
+// The small end of the hierarchy in one launch: for the levels whose every channel
+// has at most a few thousand cells (the separate launches of those levels cost more
+// than their work), one 1024-thread block per channel runs the rest of the V-cycle
+// in LDS: it loads the levels' coefficients and the restricted residual once, does
+// the pre-smoothing and restriction down to the coarsest level, the dense solve, the
+// prolongation and post-smoothing back up, with block barriers between the passes,
+// and writes back the correction of the first tail level.  Every cell update is the
+// expression of the separate kernels above (the eight-value restriction sum in the
+// same pairwise order), so the result is the same bit for bit.
+// ------------------------------------------------------------------------------------
+constexpr int MG_TAIL_BS = 1024;
+
+template <class T>
+struct MGTailLevel {
+    const ChanDev* ch;
+    T *x, *y, *b, *dg, *cx, *cy, *cz, *cout;
+};
+template <class T>
+struct MGTail {
+    MGTailLevel<T> L[MG_MAXLEV];
+    int n;      // levels in the tail; the last is the coarsest
+};
+
+// Element counts of one channel's level arrays held in LDS: b, x, y, dg (cells) and
+// the three face-coefficient arrays; the coarsest level keeps b and x only.
+__host__ __device__ inline int64_t tail_align(int64_t e, int bytes) {
+    const int64_t q = 16 / bytes;   // keep every array 16-byte aligned
+    return (e + q - 1) / q * q;
+}
+__host__ __device__ inline int64_t tail_level_elems(int dim, int nx, int ny, int nz, bool coarsest, int bytes) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (coarsest) return 2 * tail_align(n, bytes);
+    const int64_t fx = (int64_t)(nx + 1) * ny * nz, fy = (int64_t)nx * (ny + 1) * nz;
+    const int64_t fz = dim == 3 ? (int64_t)nx * ny * (nz + 1) : 0;
+    return 4 * tail_align(n, bytes) + tail_align(fx, bytes) + tail_align(fy, bytes) + tail_align(fz, bytes);
+}
+
+// One tail level as the block sees it: the channel's level table with zero offsets
+// (the arrays are the block's own) and the element offsets of its LDS arrays.
+struct TailLds {
+    ChanDev C;
+    int32_t ob, ox, oy, odg, ocx, ocy, ocz;
+    int32_t nfx, nfy, nfz;
+};
+
+// dst[q] = src[q] for q < n, the block's threads each issuing U loads before storing.
+template <class T>
+__device__ inline void tail_copy_in(T* dst, const T* __restrict__ src, int64_t n) {
+    constexpr int U = 4;
+    for (int64_t q0 = threadIdx.x; q0 < n; q0 += U * MG_TAIL_BS) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + (int64_t)u * MG_TAIL_BS;
+            v[u] = q < n ? src[q] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + (int64_t)u * MG_TAIL_BS;
+            if (q < n) dst[q] = v[u];
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const double* inv, const int32_t* chact) {
+    const int chid = blockIdx.x;
+    if (!chact[chid]) return;
+    extern __shared__ __align__(16) unsigned char tail_lds[];
+    T* const lds = reinterpret_cast<T*>(tail_lds);
+    __shared__ TailLds tv[MG_MAXLEV];
+    const int nl = tl.n;
+    // carve the LDS arrays (thread 0), then copy the coefficients and the top level's b in
+    if (threadIdx.x == 0) {
+        const int bytes = (int)sizeof(T);
+        int64_t o = 0;
+        for (int l = 0; l < nl; ++l) {
+            TailLds& v = tv[l];
+            v.C = tl.L[l].ch[chid];
+            v.C.c0 = 0;
+            v.C.fx0 = 0;
+            v.C.fy0 = 0;
+            v.C.fz0 = 0;
+            const int64_t n = v.C.ncell;
+            v.ob = (int32_t)o;
+            o += tail_align(n, bytes);
+            v.ox = (int32_t)o;
+            o += tail_align(n, bytes);
+            v.oy = v.odg = v.ocx = v.ocy = v.ocz = 0;
+            v.nfx = (v.C.nx + 1) * v.C.ny * v.C.nz;
+            v.nfy = v.C.nx * (v.C.ny + 1) * v.C.nz;
+            v.nfz = v.C.dim == 3 ? v.C.nx * v.C.ny * (v.C.nz + 1) : 0;
+            if (l + 1 == nl) break;
+            v.oy = (int32_t)o;
+            o += tail_align(n, bytes);
+            v.odg = (int32_t)o;
+            o += tail_align(n, bytes);
+            v.ocx = (int32_t)o;
+            o += tail_align(v.nfx, bytes);
+            v.ocy = (int32_t)o;
+            o += tail_align(v.nfy, bytes);
+            v.ocz = (int32_t)o;
+            o += tail_align(v.nfz, bytes);
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < nl; ++l) {
+        const MGTailLevel<T>& Lv = tl.L[l];
+        const ChanDev& C = tl.L[l].ch[chid];
+        const TailLds& v = tv[l];
+        tail_copy_in(lds + v.odg, Lv.dg + C.c0, C.ncell);
+        tail_copy_in(lds + v.ocx, Lv.cx + C.fx0, v.nfx);
+        tail_copy_in(lds + v.ocy, Lv.cy + C.fy0, v.nfy);
+        tail_copy_in(lds + v.ocz, Lv.cz + C.fz0, v.nfz);
+    }
+    {
+        const ChanDev& C0 = tl.L[0].ch[chid];
+        tail_copy_in(lds + tv[0].ob, tl.L[0].b + C0.c0, C0.ncell);
+    }
+    __syncthreads();
+    // down: two Jacobi sweeps (from zero) and the residual restriction per level
+    for (int l = 0; l + 1 < nl; ++l) {
+        const TailLds& v = tv[l];
+        const ChanDev& C = v.C;
+        const CoefOp<T> op{lds + v.odg, lds + v.ocx, lds + v.ocy, lds + v.ocz};
+        const T* b = lds + v.ob;
+        T* x = lds + v.ox;
+        for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
+            const Cell P = cell_at(C, local);
+            auto x1 = [&](int64_t g) { return w * b[g] / op.diag(0, g); };
+            const T ax = op.apply(0, C, P, x1);
+            x[P.g] = x1(P.g) + w * (b[P.g] - ax) / op.diag(0, P.g);
+        }
+        __syncthreads();
+        const ChanDev& Cc = tv[l + 1].C;
+        T* bc = lds + tv[l + 1].ob;
+        const bool ax0 = C.nx != Cc.nx, ax1 = C.ny != Cc.ny, ax2 = C.nz != Cc.nz;
+        for (int64_t local = threadIdx.x; local < Cc.ncell; local += MG_TAIL_BS) {
+            const Cell P = cell_at(Cc, local);
+            T r[8];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                const int di = f & 1, dj = (f >> 1) & 1, dk = f >> 2;
+                const int i = ax0 ? 2 * P.i + di : P.i + 8 * di;
+                const int j = ax1 ? 2 * P.j + dj : P.j + 8 * dj;
+                const int k = ax2 ? 2 * P.k + dk : P.k + 8 * dk;
+                const bool in = (ax0 || di == 0) && (ax1 || dj == 0) && (ax2 || dk == 0) && i < C.nx && j < C.ny &&
+                                k < C.nz;
+                r[f] = T(0);
+                if (in) {
+                    Cell Q;
+                    Q.i = i;
+                    Q.j = j;
+                    Q.k = k;
+                    Q.g = i + (int64_t)C.nx * (j + (int64_t)C.ny * k);
+                    r[f] = b[Q.g] - op.apply(0, C, Q, [&](int64_t g) { return x[g]; });
+                }
+            }
+            // the butterfly order of the shuffle reduction: pairs, then pairs of pairs
+            const T s01 = r[0] + r[1], s23 = r[2] + r[3], s45 = r[4] + r[5], s67 = r[6] + r[7];
+            bc[P.g] = (s01 + s23) + (s45 + s67);
+        }
+        __syncthreads();
+    }
+    // coarsest level: x = A^-1 b (dense inverse, FP64 accumulation)
+    {
+        const TailLds& v = tv[nl - 1];
+        const int n = (int)v.C.ncell;
+        __shared__ double bs[MG_COARSE];
+        if (threadIdx.x < MG_COARSE) bs[threadIdx.x] = (int)threadIdx.x < n ? (double)lds[v.ob + threadIdx.x] : 0.0;
+        __syncthreads();
+        if ((int)threadIdx.x < n) {
+            const double* row = inv + ((int64_t)chid * MG_COARSE + threadIdx.x) * MG_COARSE;
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += row[j] * bs[j];
+            lds[v.ox + threadIdx.x] = T(s);
+        }
+        __syncthreads();
+    }
+    // up: prolongation by injection fused into the first sweep, then the second sweep
+    for (int l = nl - 2; l >= 0; --l) {
+        const TailLds& v = tv[l];
+        const ChanDev& C = v.C;
+        const ChanDev& Cc = tv[l + 1].C;
+        const T* xc = lds + tv[l + 1].ox;
+        const CoefOp<T> op{lds + v.odg, lds + v.ocx, lds + v.ocy, lds + v.ocz};
+        const T* b = lds + v.ob;
+        T* x = lds + v.ox;
+        T* y = lds + v.oy;
+        for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
+            const Cell P = cell_at(C, local);
+            auto x1 = [&](int64_t g) { return x[g] + xc[coarse_of(C, Cc, g)]; };
+            const T ax = op.apply(0, C, P, x1);
+            y[P.g] = x1(P.g) + w * (b[P.g] - ax) / op.diag(0, P.g);
+        }
+        __syncthreads();
+        for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
+            const Cell P = cell_at(C, local);
+            const T ay = op.apply(0, C, P, [&](int64_t g) { return y[g]; });
+            x[P.g] = y[P.g] + w * (b[P.g] - ay) / op.diag(0, P.g);
+        }
+        __syncthreads();
+    }
+    // the first tail level's correction, for the prolongation of the level above
+    const ChanDev& C0 = tl.L[0].ch[chid];
+    for (int64_t q = threadIdx.x; q < C0.ncell; q += MG_TAIL_BS) tl.L[0].x[C0.c0 + q] = lds[tv[0].ox + q];
+}
+
+// ------------------------------------------------------------------------------------
 // CG driven by the V-cycle: z is stored by the preconditioner.
 // ------------------------------------------------------------------------------------
 

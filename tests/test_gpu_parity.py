@@ -144,3 +144,20 @@ def test_release_history_length_is_checked():
     d = ci.channel(2, 40, 12, seed=21)
     with pytest.raises(clot.ClotError):
         clot.Solver([d], clot.FP64, clot.default_params(clot.FP64, dtau=0.5))
+
+
+@pytest.mark.parametrize("prec_name,descs", [
+    ("FP32_MIXED", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5)]),
+    ("FP32_MIXED", [ci.channel(3, 48, 16, 16, shear=800.0, dt=5e-5, seed=6)]),
+    ("FP64", [ci.channel(2, 40, 12, seed=7), ci.channel(2, 128, 32, shear=400.0, seed=8)]),
+])
+def test_fused_multigrid_tail_is_bitwise_equal_to_separate_launches(prec_name, descs):
+    """The small levels of the pressure V-cycle in one launch (default) against one
+    launch per level and pass (mg_tail = 0)."""
+    from paper_2304_09180_amd import clot
+    prec = getattr(clot, prec_name)
+    fused, _ = run_gpu(descs, prec, 6)
+    sep, _ = run_gpu(descs, prec, 6, clot.default_params(prec, mg_tail=0))
+    for c in range(len(descs)):
+        for name in fused[c]:
+            assert np.array_equal(fused[c][name], sep[c][name]), (c, name)
