@@ -439,11 +439,15 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
         const CoefOp<T> op{lds + v.odg, lds + v.ocx, lds + v.ocy, lds + v.ocz};
         const T* b = lds + v.ob;
         T* x = lds + v.ox;
+        T* y = lds + v.oy;
+        // first sweep from zero, stored (the same value the separate kernel forms at
+        // each neighbour), then the second sweep
+        for (int64_t g = threadIdx.x; g < C.ncell; g += MG_TAIL_BS) y[g] = w * b[g] / op.diag(0, g);
+        __syncthreads();
         for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
             const Cell P = cell_at(C, local);
-            auto x1 = [&](int64_t g) { return w * b[g] / op.diag(0, g); };
-            const T ax = op.apply(0, C, P, x1);
-            x[P.g] = x1(P.g) + w * (b[P.g] - ax) / op.diag(0, P.g);
+            const T ax = op.apply(0, C, P, [&](int64_t g) { return y[g]; });
+            x[P.g] = y[P.g] + w * (b[P.g] - ax) / op.diag(0, P.g);
         }
         __syncthreads();
         const ChanDev& Cc = tv[l + 1].C;
@@ -501,11 +505,13 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
         const T* b = lds + v.ob;
         T* x = lds + v.ox;
         T* y = lds + v.oy;
+        // prolongation by injection, in place, then the first sweep
+        for (int64_t g = threadIdx.x; g < C.ncell; g += MG_TAIL_BS) x[g] = x[g] + xc[coarse_of(C, Cc, g)];
+        __syncthreads();
         for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
             const Cell P = cell_at(C, local);
-            auto x1 = [&](int64_t g) { return x[g] + xc[coarse_of(C, Cc, g)]; };
-            const T ax = op.apply(0, C, P, x1);
-            y[P.g] = x1(P.g) + w * (b[P.g] - ax) / op.diag(0, P.g);
+            const T ax = op.apply(0, C, P, [&](int64_t g) { return x[g]; });
+            y[P.g] = x[P.g] + w * (b[P.g] - ax) / op.diag(0, P.g);
         }
         __syncthreads();
         for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
