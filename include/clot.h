@@ -105,6 +105,8 @@ typedef struct {
     int32_t mg_tail;      /* pressure multigrid: the levels whose channels all have at most
                              this many cells run as one launch (one block per channel);
                              0 = every level its own launches.  Default 4096.            */
+    int32_t mg_sweeps;    /* pressure multigrid: weighted-Jacobi sweeps before and after each
+                             restriction, 1 or 2 (default 2)                               */
 } clot_params;
 
 /* Per-channel statistics of the last step. */

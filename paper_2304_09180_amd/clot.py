@@ -55,7 +55,7 @@ class Params(C.Structure):
                 [("M_rxn", C.c_int32), ("n_corr", C.c_int32), ("max_iter", C.c_int32),
                  ("marg_m", C.c_int32), ("marg_n", C.c_int32),
                  ("rtol_p", C.c_double), ("rtol_s", C.c_double), ("rtol_inner", C.c_double),
-                 ("mg_tail", C.c_int32)])
+                 ("mg_tail", C.c_int32), ("mg_sweeps", C.c_int32)])
 
 
 class Stats(C.Structure):

@@ -961,31 +961,58 @@ struct Ctx : clot_ctx {
             finish<1>(EpiMgDot{});
             return;
         }
+        const int t0 = mg_t0 >= 0 ? mg_t0 : nl - 1;   // levels from t0 on: fused launch or coarse solve
+        auto tail_or_coarse = [&]() {
+            if (mg_t0 >= 0) {
+                MGTail<T> tl{};
+                tl.n = nl - t0;
+                for (int l = t0; l < nl; ++l) {
+                    Level& L = lev[l];
+                    tl.L[l - t0] = MGTailLevel<T>{L.d_ch, L.x, L.y, L.b, L.dg, L.cx, L.cy, L.cz, L.cout};
+                }
+                hipLaunchKernelGGL(k_mg_tail<T>, dim3((int)ch.size()), dim3(MG_TAIL_BS), mg_tail_lds, st, tl, mg_w, mg_inv,
+                                   act, (int)prm.mg_sweeps);
+            } else {
+                Level& Lc = lev[nl - 1];
+                hipLaunchKernelGGL(k_mg_coarse<T>, dim3((int)ch.size()), dim3(MG_COARSE), 0, st, Lc.grid(), mg_inv, Lc.b,
+                                   Lc.x, act, (int)ch.size());
+            }
+        };
+        if (prm.mg_sweeps == 1) {
+            // one sweep each way: the pre-sweep from zero is formed inside the restriction
+            hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>, true>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT),
+                               0, st, MGPair{grid(), lev[0].grid()}, p0, r, (const T*)nullptr, lev[0].b, act, mg_w);
+            for (int l = 0; l < t0; ++l) {
+                Level& L = lev[l];
+                CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
+                hipLaunchKernelGGL((k_mg_restrict<T, CoefOp<T>, true>), dim3(lev[l + 1].ntiles * (TILE / (NT / 8))),
+                                   dim3(NT), 0, st, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, (const T*)nullptr,
+                                   lev[l + 1].b, act, mg_w);
+            }
+            tail_or_coarse();
+            for (int l = t0 - 1; l >= 0; --l) {
+                Level& L = lev[l];
+                CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
+                hipLaunchKernelGGL((k_mg_post_one<T, CoefOp<T>, false>), dim3(L.ntiles), dim3(NT), 0, st,
+                                   MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, lev[l + 1].x, L.x, mg_w, S);
+            }
+            CLOT_LAUNCH(CLOT_PROBE_P_MG_POST, (k_mg_post_one<T, PresOp<T, T>, true>), dim3(ntiles), dim3(NT), 0, st,
+                        MGPair{grid(), lev[0].grid()}, p0, r, lev[0].x, mg_z0, mg_w, S);
+            finish<1>(EpiMgDot{});
+            return;
+        }
         // down
         hipLaunchKernelGGL((k_mg_pre<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, grid(), p0, r, mg_z0, mg_w, act);
-        hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT), 0, st,
-                           MGPair{grid(), lev[0].grid()}, p0, r, mg_z0, lev[0].b, act);
-        const int t0 = mg_t0 >= 0 ? mg_t0 : nl - 1;   // levels from t0 on: fused launch or coarse solve
+        hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>, false>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT), 0,
+                           st, MGPair{grid(), lev[0].grid()}, p0, r, mg_z0, lev[0].b, act, mg_w);
         for (int l = 0; l < t0; ++l) {
             Level& L = lev[l];
             CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
             hipLaunchKernelGGL((k_mg_pre<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), op, L.b, L.x, mg_w, act);
-            hipLaunchKernelGGL((k_mg_restrict<T, CoefOp<T>>), dim3(lev[l + 1].ntiles * (TILE / (NT / 8))), dim3(NT), 0,
-                               st, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, L.x, lev[l + 1].b, act);
+            hipLaunchKernelGGL((k_mg_restrict<T, CoefOp<T>, false>), dim3(lev[l + 1].ntiles * (TILE / (NT / 8))), dim3(NT),
+                               0, st, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, L.x, lev[l + 1].b, act, mg_w);
         }
-        if (mg_t0 >= 0) {
-            MGTail<T> tl{};
-            tl.n = nl - t0;
-            for (int l = t0; l < nl; ++l) {
-                Level& L = lev[l];
-                tl.L[l - t0] = MGTailLevel<T>{L.d_ch, L.x, L.y, L.b, L.dg, L.cx, L.cy, L.cz, L.cout};
-            }
-            hipLaunchKernelGGL(k_mg_tail<T>, dim3((int)ch.size()), dim3(MG_TAIL_BS), mg_tail_lds, st, tl, mg_w, mg_inv, act);
-        } else {
-            Level& Lc = lev[nl - 1];
-            hipLaunchKernelGGL(k_mg_coarse<T>, dim3((int)ch.size()), dim3(MG_COARSE), 0, st, Lc.grid(), mg_inv, Lc.b, Lc.x,
-                               act, (int)ch.size());
-        }
+        tail_or_coarse();
         // up
         for (int l = t0 - 1; l >= 0; --l) {
             Level& L = lev[l];
@@ -1491,6 +1518,7 @@ clot_status clot_params_default(clot_params* p) {
     p->rtol_s = 1e-13;
     p->rtol_inner = 1e-4;
     p->mg_tail = 4096;
+    p->mg_sweeps = 2;
     return CLOT_OK;
 }
 
@@ -1517,7 +1545,9 @@ clot_status clot_create(const clot_channel* chs, int32_t n_ch, const clot_params
                         size_t wsb, void* stream, clot_ctx** out) {
     if (!chs || n_ch < 1 || !p || !ws || !out || (prec != CLOT_FP64 && prec != CLOT_FP32_MIXED)) return CLOT_EINVAL;
     *out = nullptr;
-    if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1 || p->mg_tail < 0) return CLOT_EINVAL;
+    if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1 || p->mg_tail < 0 ||
+        (p->mg_sweeps != 1 && p->mg_sweeps != 2))
+        return CLOT_EINVAL;
     clot_ctx* c = make_ctx(prec);
     c->prec = prec;
     clot_status s = prec == CLOT_FP64 ? create_t(static_cast<Ctx<double>*>(c), chs, n_ch, p, ws, wsb, stream)

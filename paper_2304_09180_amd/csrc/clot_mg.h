@@ -153,13 +153,14 @@ __global__ __launch_bounds__(NT) void k_mg_pre(Grid G, Op op, const T* b, T* x, 
     CLOT_END_CELLS
 }
 
-// Restriction by summation of the fine residual over each aggregate.  Eight lanes
+// Restriction by summation of the fine residual over each aggregate (with ONFLY
+// the smoothed x is the single sweep from zero, w D^-1 b, formed where it is read).  Eight lanes
 // share a coarse cell (one per fine cell of the 2x2x2 aggregate), so the fine
 // stencils are evaluated in parallel; the eight values are added by lane shuffles.
 // Launch: 8 blocks per coarse tile (32 coarse cells per block).
-template <class T, class Op>
+template <class T, class Op, bool ONFLY>
 __global__ __launch_bounds__(NT) void k_mg_restrict(MGPair L, Op op, const T* b, const T* x, T* bc,
-                                                    const int32_t* chact) {
+                                                    const int32_t* chact, T w) {
     constexpr int CPB = NT / 8;                      // coarse cells per block
     constexpr int BPT = TILE / CPB;                  // blocks per coarse tile
     const int32_t tile = xcd_tile((int32_t)blockIdx.x / BPT, L.coarse.ntiles);
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(MGPair L, Op op, const T* b,
             Q.j = j;
             Q.k = k;
             Q.g = Fc.c0 + i + (int64_t)Fc.nx * (j + (int64_t)Fc.ny * k);
-            v = b[Q.g] - op.apply(0, Fc, Q, [&](int64_t g) { return x[g]; });
+            v = b[Q.g] - op.apply(0, Fc, Q, [&](int64_t g) { return ONFLY ? w * b[g] / op.diag(0, g) : x[g]; });
         }
     }
     v += __shfl_xor(v, 1, 64);
@@ -235,6 +236,27 @@ __global__ __launch_bounds__(NT) void k_mg_post2(Grid G, Op op, const T* b, cons
         const T z = y[P.g] + w * (b[P.g] - ay) / op.diag(0, P.g);
         x[P.g] = z;
         if (DOT) acc[0] += (double)b[P.g] * (double)z;
+    CLOT_END_CELLS
+    if (DOT) store_partials<1>(acc, S.part, tile, lds);
+}
+
+// One post-smoothing sweep with the prolonged correction (the single-sweep cycle):
+// x1 = w D^-1 b + P xc (formed on the fly), z = x1 + w D^-1 (b - A x1); on the
+// finest level also r.z for the outer CG.
+template <class T, class Op, bool DOT>
+__global__ __launch_bounds__(NT) void k_mg_post_one(MGPair L, Op op, const T* b, const T* xc, T* z, T w, KState S) {
+    CLOT_TILE_PROLOGUE(L.fine)
+    if (!S.chact[chid]) return;
+    const ChanDev Cc = L.coarse.ch[chid];
+    __shared__ double lds[5];
+    double acc[1] = {0.0};
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        auto x1 = [&](int64_t g) { return w * b[g] / op.diag(0, g) + xc[coarse_of(C, Cc, g)]; };
+        const T ax = op.apply(0, C, P, x1);
+        const T zz = x1(P.g) + w * (b[P.g] - ax) / op.diag(0, P.g);
+        z[P.g] = zz;
+        if (DOT) acc[0] += (double)b[P.g] * (double)zz;
     CLOT_END_CELLS
     if (DOT) store_partials<1>(acc, S.part, tile, lds);
 }
@@ -377,7 +399,8 @@ __device__ inline void tail_copy_in(T* dst, const T* __restrict__ src, int64_t n
 }
 
 template <class T>
-__global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const double* inv, const int32_t* chact) {
+__global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const double* inv, const int32_t* chact,
+                                                        int sweeps) {
     const int chid = blockIdx.x;
     if (!chact[chid]) return;
     extern __shared__ __align__(16) unsigned char tail_lds[];
@@ -441,15 +464,18 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
         T* x = lds + v.ox;
         T* y = lds + v.oy;
         // first sweep from zero, stored (the same value the separate kernel forms at
-        // each neighbour), then the second sweep
-        for (int64_t g = threadIdx.x; g < C.ncell; g += MG_TAIL_BS) y[g] = w * b[g] / op.diag(0, g);
+        // each neighbour), then (two-sweep cycle) the second sweep
+        T* x1 = sweeps == 2 ? y : x;
+        for (int64_t g = threadIdx.x; g < C.ncell; g += MG_TAIL_BS) x1[g] = w * b[g] / op.diag(0, g);
         __syncthreads();
-        for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
-            const Cell P = cell_at(C, local);
-            const T ax = op.apply(0, C, P, [&](int64_t g) { return y[g]; });
-            x[P.g] = y[P.g] + w * (b[P.g] - ax) / op.diag(0, P.g);
+        if (sweeps == 2) {
+            for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
+                const Cell P = cell_at(C, local);
+                const T ax = op.apply(0, C, P, [&](int64_t g) { return y[g]; });
+                x[P.g] = y[P.g] + w * (b[P.g] - ax) / op.diag(0, P.g);
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const ChanDev& Cc = tv[l + 1].C;
         T* bc = lds + tv[l + 1].ob;
         const bool ax0 = C.nx != Cc.nx, ax1 = C.ny != Cc.ny, ax2 = C.nz != Cc.nz;
@@ -500,7 +526,9 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
         const TailLds& v = tv[l];
         const ChanDev& C = v.C;
         const ChanDev& Cc = tv[l + 1].C;
-        const T* xc = lds + tv[l + 1].ox;
+        // the finished correction of the level below: x after two sweeps, y after one
+        // (the coarsest level's is x, from the dense solve)
+        const T* xc = lds + ((l + 1 == nl - 1 || sweeps == 2) ? tv[l + 1].ox : tv[l + 1].oy);
         const CoefOp<T> op{lds + v.odg, lds + v.ocx, lds + v.ocy, lds + v.ocz};
         const T* b = lds + v.ob;
         T* x = lds + v.ox;
@@ -514,16 +542,19 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
             y[P.g] = x[P.g] + w * (b[P.g] - ax) / op.diag(0, P.g);
         }
         __syncthreads();
-        for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
-            const Cell P = cell_at(C, local);
-            const T ay = op.apply(0, C, P, [&](int64_t g) { return y[g]; });
-            x[P.g] = y[P.g] + w * (b[P.g] - ay) / op.diag(0, P.g);
+        if (sweeps == 2) {
+            for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
+                const Cell P = cell_at(C, local);
+                const T ay = op.apply(0, C, P, [&](int64_t g) { return y[g]; });
+                x[P.g] = y[P.g] + w * (b[P.g] - ay) / op.diag(0, P.g);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     // the first tail level's correction, for the prolongation of the level above
     const ChanDev& C0 = tl.L[0].ch[chid];
-    for (int64_t q = threadIdx.x; q < C0.ncell; q += MG_TAIL_BS) tl.L[0].x[C0.c0 + q] = lds[tv[0].ox + q];
+    const int32_t o0 = (nl == 1 || sweeps == 2) ? tv[0].ox : tv[0].oy;
+    for (int64_t q = threadIdx.x; q < C0.ncell; q += MG_TAIL_BS) tl.L[0].x[C0.c0 + q] = lds[o0 + q];
 }
 
 // ------------------------------------------------------------------------------------

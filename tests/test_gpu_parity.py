@@ -161,3 +161,16 @@ def test_fused_multigrid_tail_is_bitwise_equal_to_separate_launches(prec_name, d
     for c in range(len(descs)):
         for name in fused[c]:
             assert np.array_equal(fused[c][name], sep[c][name]), (c, name)
+
+
+@pytest.mark.parametrize("descs,steps", [
+    ([ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=11)], 5),
+    ([ci.channel(3, 24, 10, 9, shear=1000.0, dt=1e-4, seed=12), ci.channel(2, 128, 32, shear=400.0, seed=13)], 4),
+])
+def test_fp64_single_sweep_multigrid_matches_oracle(descs, steps):
+    """The pressure preconditioner with one Jacobi sweep each way changes only the
+    iteration count: the converged step still matches the oracle."""
+    from paper_2304_09180_amd import clot
+    gpu, st = run_gpu(descs, clot.FP64, steps, clot.default_params(clot.FP64, mg_sweeps=1))
+    for c, d in enumerate(descs):
+        compare(gpu[c], run_oracle(d, steps), 1e-10)
