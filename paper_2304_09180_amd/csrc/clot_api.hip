@@ -314,6 +314,7 @@ struct Ctx : clot_ctx {
         F.rhs_p = cv.take<double>(N);
         for (int k = 0; k < NTR; ++k) F.trd[k] = cv.take<T>(N);
         for (int k = 0; k < NTR; ++k) F.trb[k] = cv.take<T>(N);
+        for (int k = 0; k < NTR; ++k) F.trc[k] = cv.take<T>((size_t)6 * N);
         for (int q = 0; q < NPOOL; ++q) pool[q] = cv.take<T>(N);
         F.ncell = N;
         S.maxit = prm.max_iter;
@@ -1157,6 +1158,7 @@ struct Ctx : clot_ctx {
         for (int k = 0; k < NTR; ++k) {
             top.Cn[k] = F.spc[tr_species(k)];
             top.dg[k] = F.trd[k];
+            top.cf[k] = F.trc[k];
             top.Dk[k] = tr_diffusivity<T>(k, M);
         }
         top.phx = F.phin[0];
@@ -1164,6 +1166,7 @@ struct Ctx : clot_ctx {
         top.phz = F.phin[2];
         top.Wc = F.Wc;
         top.Pmax = T(M.P_max);
+        top.n = N;
         CLOT_LAUNCH(CLOT_PROBE_TR_ASM, k_tr_assemble<T>, gb, tb, 0, st, G, F, top, M);
         {
             KVec<T, NTR> V = bicg_vecs<NTR>(0);

@@ -40,6 +40,7 @@ struct Fields {
     double* rhs_p;        // pressure right-hand side
     T* trd[NTR];          // transport diagonals
     T* trb[NTR];          // transport right-hand sides
+    T* trc[NTR];      // transport off-diagonal couplings, 6 slots x ncell per species
     int64_t ncell;
 };
 
@@ -234,6 +235,8 @@ template <class T>
 struct TrOp {
     const T* Cn[NTR];     // start-of-step species, indexed by transported slot
     const T* dg[NTR];     // diagonals
+    const T* cf[NTR];     // off-diagonal couplings stored by the assembly: slot s at s*n + g
+    int64_t n;            // cells of the context (slot stride)
     const T* phx;
     const T* phy;
     const T* phz;
@@ -241,40 +244,20 @@ struct TrOp {
     T Dk[NTR];
     T Pmax;
     __device__ T diag(int k, int64_t g) const { return dg[k][g]; }
+    // The couplings are frozen over the step (TVD weights and hindrance from C^n):
+    // the assembly stores them once (row P: to P+x, P-x, P+y, P-y, P+z, P-z).
     template <class XV>
     __device__ T apply(int k, const ChanDev& C, const Cell& P, XV xv) const {
-        const bool plt = k < 2;
-        const T* c = Cn[k];
+        const T* c = cf[k] + P.g;
         T y = dg[k][P.g] * xv(P.g);
-        T ad = T(C.Ax / C.dx);
-        if (P.i < C.nx - 1) {
-            FaceCoef<T> f = tr_face(c, Wc, plt, Dk[k], ad, P.g, 1, P.i, C.nx, phx[fx_id(C, P.i + 1, P.j, P.k)], Pmax);
-            y += f.oLR * xv(P.g + 1);
-        }
-        if (P.i > 0) {
-            FaceCoef<T> f = tr_face(c, Wc, plt, Dk[k], ad, P.g - 1, 1, P.i - 1, C.nx, phx[fx_id(C, P.i, P.j, P.k)], Pmax);
-            y += f.oRL * xv(P.g - 1);
-        }
-        ad = T(C.Ay / C.dy);
-        if (P.j < C.ny - 1) {
-            FaceCoef<T> f = tr_face(c, Wc, plt, Dk[k], ad, P.g, C.nx, P.j, C.ny, phy[fy_id(C, P.i, P.j + 1, P.k)], Pmax);
-            y += f.oLR * xv(P.g + C.nx);
-        }
-        if (P.j > 0) {
-            FaceCoef<T> f = tr_face(c, Wc, plt, Dk[k], ad, P.g - C.nx, C.nx, P.j - 1, C.ny, phy[fy_id(C, P.i, P.j, P.k)], Pmax);
-            y += f.oRL * xv(P.g - C.nx);
-        }
+        if (P.i < C.nx - 1) y += c[0] * xv(P.g + 1);
+        if (P.i > 0) y += c[n] * xv(P.g - 1);
+        if (P.j < C.ny - 1) y += c[2 * n] * xv(P.g + C.nx);
+        if (P.j > 0) y += c[3 * n] * xv(P.g - C.nx);
         if (C.dim == 3) {
             const int64_t sz = (int64_t)C.nx * C.ny;
-            ad = T(C.Az / C.dz);
-            if (P.k < C.nz - 1) {
-                FaceCoef<T> f = tr_face(c, Wc, plt, Dk[k], ad, P.g, sz, P.k, C.nz, phz[fz_id(C, P.i, P.j, P.k + 1)], Pmax);
-                y += f.oLR * xv(P.g + sz);
-            }
-            if (P.k > 0) {
-                FaceCoef<T> f = tr_face(c, Wc, plt, Dk[k], ad, P.g - sz, sz, P.k - 1, C.nz, phz[fz_id(C, P.i, P.j, P.k)], Pmax);
-                y += f.oRL * xv(P.g - sz);
-            }
+            if (P.k < C.nz - 1) y += c[4 * n] * xv(P.g + sz);
+            if (P.k > 0) y += c[5 * n] * xv(P.g - sz);
         }
         return y;
     }

@@ -371,24 +371,49 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             T d = V * rdt;
             T b = V * rdt * cn;
             if (sp == ADP) b += V * F.sigma[g];
+            // couplings of this row, stored for the solver's stencil products, and the
+            // diagonal (same faces, same order as the products)
+            T* cf = F.trc[k] + g;
+            const int64_t n = F.ncell;
+            T o[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
             T ad = T(C.Ax / C.dx);
-            if (P.i < C.nx - 1)
-                d += tr_face(c, F.Wc, plt, D, ad, g, 1, P.i, C.nx, F.phin[0][fx_id(C, P.i + 1, P.j, P.k)], op.Pmax).dL;
-            if (P.i > 0)
-                d += tr_face(c, F.Wc, plt, D, ad, g - 1, 1, P.i - 1, C.nx, F.phin[0][fx_id(C, P.i, P.j, P.k)], op.Pmax).dR;
+            if (P.i < C.nx - 1) {
+                const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, 1, P.i, C.nx, F.phin[0][fx_id(C, P.i + 1, P.j, P.k)], op.Pmax);
+                d += f.dL;
+                o[0] = f.oLR;
+            }
+            if (P.i > 0) {
+                const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g - 1, 1, P.i - 1, C.nx, F.phin[0][fx_id(C, P.i, P.j, P.k)], op.Pmax);
+                d += f.dR;
+                o[1] = f.oRL;
+            }
             ad = T(C.Ay / C.dy);
-            if (P.j < C.ny - 1)
-                d += tr_face(c, F.Wc, plt, D, ad, g, C.nx, P.j, C.ny, F.phin[1][fy_id(C, P.i, P.j + 1, P.k)], op.Pmax).dL;
-            if (P.j > 0)
-                d += tr_face(c, F.Wc, plt, D, ad, g - C.nx, C.nx, P.j - 1, C.ny, F.phin[1][fy_id(C, P.i, P.j, P.k)], op.Pmax).dR;
+            if (P.j < C.ny - 1) {
+                const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, C.nx, P.j, C.ny, F.phin[1][fy_id(C, P.i, P.j + 1, P.k)], op.Pmax);
+                d += f.dL;
+                o[2] = f.oLR;
+            }
+            if (P.j > 0) {
+                const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g - C.nx, C.nx, P.j - 1, C.ny, F.phin[1][fy_id(C, P.i, P.j, P.k)], op.Pmax);
+                d += f.dR;
+                o[3] = f.oRL;
+            }
             if (C.dim == 3) {
                 const int64_t sz = (int64_t)C.nx * C.ny;
                 ad = T(C.Az / C.dz);
-                if (P.k < C.nz - 1)
-                    d += tr_face(c, F.Wc, plt, D, ad, g, sz, P.k, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k + 1)], op.Pmax).dL;
-                if (P.k > 0)
-                    d += tr_face(c, F.Wc, plt, D, ad, g - sz, sz, P.k - 1, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k)], op.Pmax).dR;
+                if (P.k < C.nz - 1) {
+                    const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, sz, P.k, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k + 1)], op.Pmax);
+                    d += f.dL;
+                    o[4] = f.oLR;
+                }
+                if (P.k > 0) {
+                    const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g - sz, sz, P.k - 1, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k)], op.Pmax);
+                    d += f.dR;
+                    o[5] = f.oRL;
+                }
             }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) cf[q * n] = o[q];
             const T W = plt ? Wp : T(1);
             if (P.i == 0) {
                 const T fo = -fin;       // outward flux through the inlet face
