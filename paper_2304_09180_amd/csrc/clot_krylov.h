@@ -30,9 +30,12 @@ struct KState {
     double* part;        // [ntiles][NV]
     uint32_t* tick;      // unused (kept for layout stability)
     int32_t maxit;
+    int32_t sc_ch0;      // channel whose slots sc starts at (0: the whole table)
 };
 
-__device__ inline double* scp(const KState& S, int ch, int k) { return S.sc + ((int64_t)ch * MAXK + k) * NSC; }
+__device__ inline double* scp(const KState& S, int ch, int k) {
+    return S.sc + ((int64_t)(ch - S.sc_ch0) * MAXK + k) * NSC;
+}
 
 template <class T, int K>
 struct KVec {
@@ -67,6 +70,11 @@ __global__ __launch_bounds__(FIN_BS) void k_finish(const ChanDev* chans, KState 
     if (!S.chact[chid]) return;
     const int32_t t0 = chans[chid].t0, nt = chans[chid].nt;
     __shared__ double lds[NV * (FIN_BS / 64 + 1)];
+    // the channel's scalar slots, staged in LDS by all threads so that the epilogue
+    // (one thread, system after system) does not wait on memory for each of them
+    __shared__ double scl[MAXK * NSC];
+    double* scg = S.sc + (int64_t)chid * MAXK * NSC;
+    for (int q = threadIdx.x; q < MAXK * NSC; q += FIN_BS) scl[q] = scg[q];
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
@@ -74,8 +82,15 @@ __global__ __launch_bounds__(FIN_BS) void k_finish(const ChanDev* chans, KState 
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] += S.part[(int64_t)(t0 + t) * NV + q];
     }
-    block_sum<NV, FIN_BS>(acc, lds);
-    if (threadIdx.x == 0) epi(acc, S, chid);
+    block_sum<NV, FIN_BS>(acc, lds);   // its barriers also publish scl
+    if (threadIdx.x == 0) {
+        KState SL = S;
+        SL.sc = scl;
+        SL.sc_ch0 = chid;
+        epi(acc, SL, chid);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < MAXK * NSC; q += FIN_BS) scg[q] = scl[q];
 }
 
 // ---- epilogues ---------------------------------------------------------------------
