@@ -909,7 +909,7 @@ struct Ctx : clot_ctx {
     int run_bicg(const Op& op, KVec<T, K> V, double rtol, const int32_t* mask, int slot, int p1) {
         set_active(mask);
         hipLaunchKernelGGL((k_bicg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
-        finish<2 * K>(EpiBicgInit<K>{rtol});
+        finish<3 * K>(EpiBicgInit<K>{rtol});
         return iterate<K>(slot, 1, 2, budget[slot], [&](int par) {
             CLOT_LAUNCH(p1, (k_bicg_1<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
             finish<K>(EpiBicg1<K>{});
@@ -1159,6 +1159,10 @@ struct Ctx : clot_ctx {
             top.Cn[k] = F.spc[tr_species(k)];
             top.dg[k] = F.trd[k];
             top.cf[k] = F.trc[k];
+            const int sp = tr_species(k);
+            top.scale[k] = T(sp == PMU || sp == PMA ? M.P_max
+                             : sp == S1 || sp == E1 ? M.S1_0
+                             : sp == S2 || sp == E2 ? M.S2_0 : M.adp_crit);
             top.Dk[k] = tr_diffusivity<T>(k, M);
         }
         top.phx = F.phin[0];

@@ -165,6 +165,12 @@ struct EpiCgB {   // beta, convergence
     }
 };
 
+// Tolerance: |r|^2 <= max(rtol^2 |b|^2, floor).  In FP32 the floor is what a change
+// of 1e-30 of the field's scale in every cell would leave (sum of (1e-30 s d_ii)^2,
+// and at least 1e-34 per cell): a species not yet produced (1e-33 of its scale, say)
+// has nothing to converge at that level, and its iterates would otherwise reach the
+// FP32 denormal range, where BiCGStab's recurrences break down.  Real but small fields
+// (an enzyme at 1e-8 of its scale) lie far above it.  FP64 has no floor.
 template <int K>
 struct EpiBicgInit {
     double rtol;
@@ -172,11 +178,12 @@ struct EpiBicgInit {
         int any = 0;
         for (int k = 0; k < K; ++k) {
             double* s = scp(S, ch, k);
-            s[SC_BB] = sums[2 * k];
-            s[SC_RR] = sums[2 * k + 1];
-            s[SC_RR0] = sums[2 * k + 1];
-            s[SC_RHO] = sums[2 * k + 1];       // rhat . r with rhat = r
-            s[SC_TOL2] = rtol * rtol * sums[2 * k];
+            s[SC_BB] = sums[3 * k];
+            s[SC_RR] = sums[3 * k + 1];
+            s[SC_RR0] = sums[3 * k + 1];
+            s[SC_RHO] = sums[3 * k + 1];       // rhat . r with rhat = r
+            const double rel2 = rtol * rtol * sums[3 * k];
+            s[SC_TOL2] = rel2 > sums[3 * k + 2] ? rel2 : sums[3 * k + 2];
             s[SC_ALPHA] = 1.0;
             s[SC_OMEGA] = 1.0;
             s[SC_BETA] = 0.0;
@@ -351,10 +358,10 @@ template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, KState S) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
-    __shared__ double lds[5 * 2 * K];
-    double acc[2 * K];
+    __shared__ double lds[5 * 3 * K];
+    double acc[3 * K];
 #pragma unroll
-    for (int q = 0; q < 2 * K; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 3 * K; ++q) acc[q] = 0.0;
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
 #pragma unroll
@@ -367,11 +374,19 @@ __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, K
             V.rh[k][P.g] = r;
             V.p[0][k][P.g] = T(0);
             V.v[0][k][P.g] = T(0);
-            acc[2 * k] += (double)b * (double)b;
-            acc[2 * k + 1] += (double)r * (double)r;
+            acc[3 * k] += (double)b * (double)b;
+            acc[3 * k + 1] += (double)r * (double)r;
+            // FP32: 1e-30 of the scale, and no residual below 1e-34 (the normal range
+            // ends at 1.2e-38); FP64: no floor
+            double f = 0.0;
+            if (sizeof(T) == 4) {
+                f = 1e-30 * (double)op.floor_scale(k) * (double)op.diag(k, P.g);
+                f = f > 1e-34 ? f : 1e-34;
+            }
+            acc[3 * k + 2] += f * f;
         }
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, tile, lds);
+    store_partials<3 * K>(acc, S.part, tile, lds);
 }
 
 // p_new = r + beta (p_old - omega v_old); v_new = A (p_new/diag); rhat.v_new

@@ -62,6 +62,7 @@ struct MomOp {
     const T* phz;
     T nu;
     __device__ T diag(int, int64_t g) const { return aP[g]; }
+    __device__ T floor_scale(int) const { return T(0); }   // no absolute floor
     template <class XV>
     __device__ T offsum(const ChanDev& C, const Cell& P, XV xv) const {
         T s = T(0);
@@ -237,6 +238,7 @@ struct TrOp {
     const T* dg[NTR];     // diagonals
     const T* cf[NTR];     // off-diagonal couplings stored by the assembly: slot s at s*n + g
     int64_t n;            // cells of the context (slot stride)
+    T scale[NTR];         // species scales for the absolute floor of the solve's tolerance
     const T* phx;
     const T* phy;
     const T* phz;
@@ -244,6 +246,7 @@ struct TrOp {
     T Dk[NTR];
     T Pmax;
     __device__ T diag(int k, int64_t g) const { return dg[k][g]; }
+    __device__ T floor_scale(int k) const { return scale[k]; }
     // The couplings are frozen over the step (TVD weights and hindrance from C^n):
     // the assembly stores them once (row P: to P+x, P-x, P+y, P-y, P+z, P-z).
     template <class XV>

@@ -1,0 +1,41 @@
+"""Relative-l2 parity metric shared by the GPU tests.
+
+Fields that stay near zero make the relative l2 of the field itself 0/0 or dominated
+by round-off carried from larger fields; the denominator is floored at
+1e-12 * s * sqrt(N) with s the field's scale (the survey's AMB-29 reading), and
+velocity and flux components are measured against the norm of the whole vector."""
+import numpy as np
+
+# Scales for the relative-l2 floor of fields that stay near zero: err = ||a-b|| / max(||b||, 1e-12 s sqrt(N)).
+SCALE = {"UX": 62.5, "UY": 62.5, "UZ": 62.5, "P": 2e4, "PMU": 2.5e5, "PMA": 2.5e5, "PBA": 6.67e7, "PBSE": 6.67e7,
+         "ADP": 2e-3, "S1": 1.7e-4, "S2": 1.4e-3, "E1": 1.7e-4, "E2": 1.4e-3, "S1B": 1.7e-4, "S2B": 1.4e-3,
+         "E1B": 1.7e-4, "E2B": 1.4e-3, "C1": 1.4e-3, "C2": 1.4e-3, "E0": 1.5e-7, "C0": 1.5e-7, "ETA": 1.0,
+         "SIGMA": 1.0, "PHIX": 1e-2, "PHIY": 1e-2, "PHIZ": 1e-2}
+
+
+def rel_l2(a, b, name):
+    floor = 1e-12 * SCALE[name] * np.sqrt(max(b.size, 1))
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), floor)
+
+
+VECTOR = {"UX": ("UX", "UY", "UZ"), "UY": ("UX", "UY", "UZ"), "UZ": ("UX", "UY", "UZ"),
+          "PHIX": ("PHIX", "PHIY", "PHIZ"), "PHIY": ("PHIX", "PHIY", "PHIZ"), "PHIZ": ("PHIX", "PHIY", "PHIZ")}
+
+
+def compare(gpu, ref, tol, names=None):
+    """Relative l2 per field; velocity and flux components are measured against the
+    norm of the whole vector (the transverse components are ~1e-3 of the axial one)."""
+    worst = {}
+    for n in (names or ref.keys()):
+        if n not in gpu:
+            continue
+        if n in VECTOR:
+            den = np.sqrt(sum(np.linalg.norm(ref[c]) ** 2 for c in VECTOR[n] if c in ref))
+            worst[n] = np.linalg.norm(gpu[n] - ref[n]) / den
+        else:
+            worst[n] = rel_l2(gpu[n], ref[n], n)
+    bad = {k: v for k, v in worst.items() if not v <= tol}
+    print({k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+    assert not bad, bad
+
+
