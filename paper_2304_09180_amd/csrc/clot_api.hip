@@ -602,6 +602,10 @@ struct Ctx : clot_ctx {
             c.Ay = h.dx * h.dz;
             c.Az = h.dx * h.dy;
             c.dt = h.d.dt;
+            c.gx = c.Ax / c.dx;
+            c.gy = c.Ay / c.dy;
+            c.gz = c.Az / c.dz;
+            c.rdt = 1.0 / c.dt;
             for (int t = 0; t < h.nt; ++t) t2c[h.t0 + t] = i;
             for (int f = 0; f < h.ninj; ++f) f2c[h.inj0 + f] = i;
         }

@@ -45,6 +45,7 @@ struct ChanDev {
     uint32_t mnx, lnx, mny, lny;  // magic multipliers/shifts for division by nx and ny
     double dx, dy, dz, V, Ax, Ay, Az;
     double dt;
+    double gx, gy, gz, rdt;       // Ax/dx, Ay/dy, Az/dz, 1/dt (per channel, from the host)
 };
 
 // Round-up magic-number division of 32-bit unsigned n by a fixed d (host computes m, l).

@@ -50,10 +50,10 @@ template <class T>
 struct FineCoefPres {      // level 0: c_f = (rAU_L + rAU_R)/2 * A/d, outlet 2 A/dx rAU_P
     const T* rAU;
     __device__ T face(const ChanDev& C, int ax, int64_t gL, int64_t gR) const {
-        const double a = ax == 0 ? C.Ax / C.dx : ax == 1 ? C.Ay / C.dy : C.Az / C.dz;
+        const double a = ax == 0 ? C.gx : ax == 1 ? C.gy : C.gz;
         return T(0.5 * a) * (rAU[gL] + rAU[gR]);
     }
-    __device__ T outlet(const ChanDev& C, int64_t g) const { return T(2.0 * C.Ax / C.dx) * rAU[g]; }
+    __device__ T outlet(const ChanDev& C, int64_t g) const { return T(2.0 * C.gx) * rAU[g]; }
 };
 
 template <class T>

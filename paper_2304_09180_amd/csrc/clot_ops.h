@@ -66,15 +66,15 @@ struct MomOp {
     template <class XV>
     __device__ T offsum(const ChanDev& C, const Cell& P, XV xv) const {
         T s = T(0);
-        T d = nu * T(C.Ax / C.dx);
+        T d = nu * T(C.gx);
         if (P.i > 0) s += (T(-0.5) * phx[fx_id(C, P.i, P.j, P.k)] - d) * xv(P.g - 1);
         if (P.i < C.nx - 1) s += (T(0.5) * phx[fx_id(C, P.i + 1, P.j, P.k)] - d) * xv(P.g + 1);
-        d = nu * T(C.Ay / C.dy);
+        d = nu * T(C.gy);
         if (P.j > 0) s += (T(-0.5) * phy[fy_id(C, P.i, P.j, P.k)] - d) * xv(P.g - C.nx);
         if (P.j < C.ny - 1) s += (T(0.5) * phy[fy_id(C, P.i, P.j + 1, P.k)] - d) * xv(P.g + C.nx);
         if (C.dim == 3) {
             const int64_t sz = (int64_t)C.nx * C.ny;
-            d = nu * T(C.Az / C.dz);
+            d = nu * T(C.gz);
             if (P.k > 0) s += (T(-0.5) * phz[fz_id(C, P.i, P.j, P.k)] - d) * xv(P.g - sz);
             if (P.k < C.nz - 1) s += (T(0.5) * phz[fz_id(C, P.i, P.j, P.k + 1)] - d) * xv(P.g + sz);
         }
@@ -99,15 +99,15 @@ struct PresOp {
     __device__ A offsum(const ChanDev& C, const Cell& P, XV xv) const {
         const A rP = A(rAU[P.g]);
         A s = A(0);
-        A g = A(0.5 * C.Ax / C.dx);
+        A g = A(0.5 * C.gx);
         if (P.i > 0) s += g * (rP + A(rAU[P.g - 1])) * xv(P.g - 1);
         if (P.i < C.nx - 1) s += g * (rP + A(rAU[P.g + 1])) * xv(P.g + 1);
-        g = A(0.5 * C.Ay / C.dy);
+        g = A(0.5 * C.gy);
         if (P.j > 0) s += g * (rP + A(rAU[P.g - C.nx])) * xv(P.g - C.nx);
         if (P.j < C.ny - 1) s += g * (rP + A(rAU[P.g + C.nx])) * xv(P.g + C.nx);
         if (C.dim == 3) {
             const int64_t sz = (int64_t)C.nx * C.ny;
-            g = A(0.5 * C.Az / C.dz);
+            g = A(0.5 * C.gz);
             if (P.k > 0) s += g * (rP + A(rAU[P.g - sz])) * xv(P.g - sz);
             if (P.k < C.nz - 1) s += g * (rP + A(rAU[P.g + sz])) * xv(P.g + sz);
         }
@@ -117,16 +117,16 @@ struct PresOp {
     __device__ A diag_exact(const ChanDev& C, const Cell& P) const {
         const A rP = A(rAU[P.g]);
         A s = A(0);
-        A g = A(0.5 * C.Ax / C.dx);
+        A g = A(0.5 * C.gx);
         if (P.i > 0) s += g * (rP + A(rAU[P.g - 1]));
         if (P.i < C.nx - 1) s += g * (rP + A(rAU[P.g + 1]));
-        else s += A(2.0 * C.Ax / C.dx) * rP;
-        g = A(0.5 * C.Ay / C.dy);
+        else s += A(2.0 * C.gx) * rP;
+        g = A(0.5 * C.gy);
         if (P.j > 0) s += g * (rP + A(rAU[P.g - C.nx]));
         if (P.j < C.ny - 1) s += g * (rP + A(rAU[P.g + C.nx]));
         if (C.dim == 3) {
             const int64_t sz = (int64_t)C.nx * C.ny;
-            g = A(0.5 * C.Az / C.dz);
+            g = A(0.5 * C.gz);
             if (P.k > 0) s += g * (rP + A(rAU[P.g - sz]));
             if (P.k < C.nz - 1) s += g * (rP + A(rAU[P.g + sz]));
         }
@@ -146,7 +146,7 @@ struct EtaOp {
     T kappa;
     const T* dE;          // stored diagonal (geometry only)
     __device__ static T diag_of(T kappa, const ChanDev& C, const Cell& P) {
-        T gx = kappa * T(C.Ax / C.dx), gy = kappa * T(C.Ay / C.dy), gz = kappa * T(C.Az / C.dz);
+        T gx = kappa * T(C.gx), gy = kappa * T(C.gy), gz = kappa * T(C.gz);
         T d = T(C.V);
         d += gx * T((P.i > 0) + (P.i < C.nx - 1));
         d += gy * T((P.j > 0) + (P.j < C.ny - 1));
@@ -156,7 +156,7 @@ struct EtaOp {
     __device__ T diag(int, int64_t g) const { return dE[g]; }
     template <class XV>
     __device__ T apply(int k, const ChanDev& C, const Cell& P, XV xv) const {
-        T gx = kappa * T(C.Ax / C.dx), gy = kappa * T(C.Ay / C.dy), gz = kappa * T(C.Az / C.dz);
+        T gx = kappa * T(C.gx), gy = kappa * T(C.gy), gz = kappa * T(C.gz);
         T s = T(0);
         if (P.i > 0) s += gx * xv(P.g - 1);
         if (P.i < C.nx - 1) s += gx * xv(P.g + 1);

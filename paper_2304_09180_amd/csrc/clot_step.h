@@ -29,14 +29,14 @@ __global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelD
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
         const int64_t g = P.g;
-        const T V = T(C.V), rdt = T(1.0 / C.dt), nu = T(M.nu);
+        const T V = T(C.V), rdt = T(C.rdt), nu = T(M.nu);
         const T s = T(0.6) * F.thB[g];
         const T om = T(1) - s;
         const T alpha = T(M.C_CK) * s * s / (om * om * om);
         T aP = V * rdt + nu * alpha * V;
         T srcx = T(0);
         // x faces: inlet (fixed value) at i = 0, outlet (zero gradient) at i = nx-1
-        const T dfx = nu * T(C.Ax / C.dx);
+        const T dfx = nu * T(C.gx);
         const T fw = F.phi[0][fx_id(C, P.i, P.j, P.k)];
         const T fe = F.phi[0][fx_id(C, P.i + 1, P.j, P.k)];
         if (P.i > 0) aP += T(-0.5) * fw + dfx;
@@ -48,13 +48,13 @@ __global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelD
         if (P.i < C.nx - 1) aP += T(0.5) * fe + dfx;
         else aP += fe;
         // y faces: no-slip walls
-        const T dfy = nu * T(C.Ay / C.dy);
+        const T dfy = nu * T(C.gy);
         const T fs = F.phi[1][fy_id(C, P.i, P.j, P.k)];
         const T fn = F.phi[1][fy_id(C, P.i, P.j + 1, P.k)];
         aP += (P.j > 0) ? T(-0.5) * fs + dfy : T(2) * dfy;
         aP += (P.j < C.ny - 1) ? T(0.5) * fn + dfy : T(2) * dfy;
         if (C.dim == 3) {
-            const T dfz = nu * T(C.Az / C.dz);
+            const T dfz = nu * T(C.gz);
             const T fb = F.phi[2][fz_id(C, P.i, P.j, P.k)];
             const T ff = F.phi[2][fz_id(C, P.i, P.j, P.k + 1)];
             aP += (P.k > 0) ? T(-0.5) * fb + dfz : T(2) * dfz;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_prhs(Grid G, Fields<T> F, ModelDev M, co
             if (P.k > 0) div -= 0.5 * C.Az * (hz + (double)F.HbyA[2][g - sz]);
         }
         double rhs = -div;
-        if (P.i == C.nx - 1) rhs += 2.0 * C.Ax / C.dx * (double)F.rAU[g] * M.p_out;
+        if (P.i == C.nx - 1) rhs += 2.0 * C.gx * (double)F.rAU[g] * M.p_out;
         F.rhs_p[g] = rhs;
         F.dP[g] = T(op.diag_exact(C, P));
     CLOT_END_CELLS
@@ -226,10 +226,10 @@ __global__ __launch_bounds__(NT) void k_correct(Grid G, Fields<T> F, ModelDev M,
         // x faces
         {
             double f = phiH_x(C, F, P, P.i);
-            if (P.i > 0) f -= 0.5 * (rP + (double)F.rAU[g - 1]) * C.Ax / C.dx * (pP - p[g - 1]);
+            if (P.i > 0) f -= 0.5 * (rP + (double)F.rAU[g - 1]) * C.gx * (pP - p[g - 1]);
             F.phin[0][fx_id(C, P.i, P.j, P.k)] = T(f);
             if (P.i == C.nx - 1) {
-                double fo = phiH_x(C, F, P, C.nx) - rP * 2.0 * C.Ax / C.dx * (M.p_out - pP);
+                double fo = phiH_x(C, F, P, C.nx) - rP * 2.0 * C.gx * (M.p_out - pP);
                 F.phin[0][fx_id(C, C.nx, P.j, P.k)] = T(fo);
             }
         }
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(NT) void k_correct(Grid G, Fields<T> F, ModelDev M,
             double f = 0.0;
             if (P.j > 0)
                 f = 0.5 * C.Ay * ((double)F.HbyA[1][g - C.nx] + (double)F.HbyA[1][g]) -
-                    0.5 * (rP + (double)F.rAU[g - C.nx]) * C.Ay / C.dy * (pP - p[g - C.nx]);
+                    0.5 * (rP + (double)F.rAU[g - C.nx]) * C.gy * (pP - p[g - C.nx]);
             F.phin[1][fy_id(C, P.i, P.j, P.k)] = T(f);
             if (P.j == C.ny - 1) F.phin[1][fy_id(C, P.i, C.ny, P.k)] = T(0);
         }
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(NT) void k_correct(Grid G, Fields<T> F, ModelDev M,
             double f = 0.0;
             if (P.k > 0)
                 f = 0.5 * C.Az * ((double)F.HbyA[2][g - sz] + (double)F.HbyA[2][g]) -
-                    0.5 * (rP + (double)F.rAU[g - sz]) * C.Az / C.dz * (pP - p[g - sz]);
+                    0.5 * (rP + (double)F.rAU[g - sz]) * C.gz * (pP - p[g - sz]);
             F.phin[2][fz_id(C, P.i, P.j, P.k)] = T(f);
             if (P.k == C.nz - 1) F.phin[2][fz_id(C, P.i, P.j, C.nz)] = T(0);
         }
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
         const int64_t g = P.g;
-        const T V = T(C.V), rdt = T(1.0 / C.dt);
+        const T V = T(C.V), rdt = T(C.rdt);
         const T Wp = F.Wc[g];
         const bool inj = P.j == 0 && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
                          P.k < C.inj_k0 + C.inj_nk;
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             T* cf = F.trc[k] + g;
             const int64_t n = F.ncell;
             T o[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-            T ad = T(C.Ax / C.dx);
+            T ad = T(C.gx);
             if (P.i < C.nx - 1) {
                 const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, 1, P.i, C.nx, F.phin[0][fx_id(C, P.i + 1, P.j, P.k)], op.Pmax);
                 d += f.dL;
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
                 d += f.dR;
                 o[1] = f.oRL;
             }
-            ad = T(C.Ay / C.dy);
+            ad = T(C.gy);
             if (P.j < C.ny - 1) {
                 const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, C.nx, P.j, C.ny, F.phin[1][fy_id(C, P.i, P.j + 1, P.k)], op.Pmax);
                 d += f.dL;
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             }
             if (C.dim == 3) {
                 const int64_t sz = (int64_t)C.nx * C.ny;
-                ad = T(C.Az / C.dz);
+                ad = T(C.gz);
                 if (P.k < C.nz - 1) {
                     const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, sz, P.k, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k + 1)], op.Pmax);
                     d += f.dL;
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
                 const bool fixed = (sp == PMU || sp == S1 || sp == S2);
                 if (fixed) {
                     const T cb = sp == PMU ? F.pmu_in[C.in0 + P.j + (int64_t)C.ny * P.k] : (sp == S1 ? T(M.S1_0) : T(M.S2_0));
-                    const T gg = T(2) * W * D * T(C.Ax / C.dx);
+                    const T gg = T(2) * W * D * T(C.gx);
                     d += gg;
                     b += gg * cb - W * fo * cb;
                 } else {
