@@ -139,7 +139,15 @@ struct Ctx : clot_ctx {
     double* sigw = nullptr;           // [nch][NHIST]
     int32_t* push = nullptr;          // [nch][2]
     double* dstats = nullptr;         // [nch][NSTAT]
-    int32_t* h_nact = nullptr;        // pinned
+    int32_t* h_nact = nullptr;        // pinned: [0] active channels; [4..5] eta solve info
+    // the concurrent eta solve
+    KState Se{};
+    T* eta_v[5] = {};                 // right-hand side, r, p (two), t
+    int32_t* eta_info = nullptr;      // device: [channels still iterating, largest iteration count]
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_derive = nullptr, ev_eta = nullptr, ev_info = nullptr;
+    int eta_budget = 32;
+    int fixed_iters = 0;
     SigState* sig = nullptr;          // [nch] release-history schedule
     int last_it[8] = {8, 8, 8, 8, 8, 8, 8, 8};
     // Graph replay.  Slots: 0 momentum, 1..3 pressure (corrector 1, 2, later), 4 eta,
@@ -199,6 +207,11 @@ struct Ctx : clot_ctx {
     Grid grid() const { return Grid{d_ch, d_t2c, ntiles}; }
     ~Ctx() override {
         drop_graphs();
+        if (st2) (void)hipStreamSynchronize(st2);
+        if (ev_derive) (void)hipEventDestroy(ev_derive);
+        if (ev_eta) (void)hipEventDestroy(ev_eta);
+        if (ev_info) (void)hipEventDestroy(ev_info);
+        if (st2) (void)hipStreamDestroy(st2);
         if (cst) (void)hipStreamDestroy(cst);
         if (h_nact) (void)hipHostFree(h_nact);
         for (hipEvent_t e : evs) (void)hipEventDestroy(e);
@@ -215,6 +228,7 @@ struct Ctx : clot_ctx {
     }
     clot_status probe(int id) override {
         HIPCHK(hipStreamSynchronize(st));
+        if (st2) HIPCHK(hipStreamSynchronize(st2));
         probe_collect();
         if (id < 0 || id >= CLOT_PROBE_NKERNELS) {
             err = "unknown probe kernel";
@@ -267,6 +281,7 @@ struct Ctx : clot_ctx {
 
     clot_status probe_read(double* ms, int64_t* n) override {
         HIPCHK(hipStreamSynchronize(st));
+        if (st2) HIPCHK(hipStreamSynchronize(st2));
         probe_collect();
         *ms = probe_ms;
         *n = probe_n;
@@ -331,6 +346,13 @@ struct Ctx : clot_ctx {
         dstats = cv.take<double>((size_t)nch * NSTAT);
         sig = cv.take<SigState>(nch);
         gflag = cv.take<int32_t>(1);
+        Se.maxit = prm.max_iter;
+        Se.sc = cv.take<double>((size_t)nch * MAXK * NSC);
+        Se.chact = cv.take<int32_t>(nch);
+        Se.nact = cv.take<int32_t>(1);
+        Se.part = cv.take<double>((size_t)ntiles * NPART);
+        for (int q = 0; q < 5; ++q) eta_v[q] = cv.take<T>(N);
+        eta_info = cv.take<int32_t>(2);
         mg_y0 = cv.take<T>(N);
         mg_z0 = cv.take<T>(N);
         mg_inv = cv.take<double>((size_t)nch * MG_COARSE * MG_COARSE);
@@ -875,8 +897,12 @@ struct Ctx : clot_ctx {
     // active channels in between.  Under graph capture: exactly the slot's budget, then
     // every channel still active is flagged as unconverged.
     template <int K, class Body>
-    int iterate(int slot, int keep, int next_chunk, int gbudget, Body&& body) {
-        int it = 0, par = 0;
+    int iterate(int slot, int keep, int next_chunk, int gbudget, Body&& body, int par0 = 0, int done = 0) {
+        int it = 0, par = par0;
+        if (fixed_iters > 0) {   // a solve on the side stream: no polls, no failure flag
+            for (; it < fixed_iters; ++it, par ^= 1) body(par);
+            return it;
+        }
         if (capturing) {
             for (; it < gbudget; ++it, par ^= 1) {
                 body(par);
@@ -886,8 +912,8 @@ struct Ctx : clot_ctx {
             return it;
         }
         int chunk = std::max(2, last_it[slot]);
-        while (it < prm.max_iter) {
-            for (int c = 0; c < chunk && it < prm.max_iter; ++c, ++it, par ^= 1) body(par);
+        while (it + done < prm.max_iter) {
+            for (int c = 0; c < chunk && it + done < prm.max_iter; ++c, ++it, par ^= 1) body(par);
             if (poll() == 0) break;
             chunk = next_chunk;
         }
@@ -901,12 +927,96 @@ struct Ctx : clot_ctx {
         set_active(mask);
         hipLaunchKernelGGL((k_cg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
         finish<3 * K>(EpiCgInit<K>{rtol, tol_mode});
+        return cg_iterations<Op, K>(op, V, slot, pa, pb, 0, 0);
+    }
+    // CG iterations of a started solve (par0: parity of the next iteration's vectors,
+    // done: iterations already taken)
+    template <class Op, int K>
+    int cg_iterations(const Op& op, KVec<T, K> V, int slot, int pa, int pb, int par0, int done) {
         return iterate<K>(slot, 2, 4, budget[slot], [&](int par) {
             CLOT_LAUNCH(pa, (k_cg_a<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
             finish<K>(EpiCgA<K>{});
             CLOT_LAUNCH(pb, (k_cg_b<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
             finish<2 * K>(EpiCgB<K>{});
-        });
+        }, par0, done);
+    }
+
+    // ---------------------------------------------------------------------------
+    // The eta solve depends only on theta_B of the step's start: eagerly it runs on a
+    // second stream, concurrently with the flow and transport solves, for a fixed
+    // number of iterations (converged channels skip the rest); the main stream joins
+    // it before the transport solve, whose first poll also brings back the count of
+    // channels still iterating, and a solve that needs more iterations finishes on
+    // the main stream with the usual polls.
+    KVec<T, 1> eta_vecs() {
+        KVec<T, 1> V{};
+        V.x[0] = F.eta;
+        V.b[0] = eta_v[0];
+        V.r[0] = eta_v[1];
+        V.rh[0] = eta_v[1];
+        V.p[0][0] = eta_v[2];
+        V.p[1][0] = eta_v[3];
+        V.v[0][0] = eta_v[2];
+        V.v[1][0] = eta_v[3];
+        V.t[0] = eta_v[4];
+        return V;
+    }
+    EtaOp<T> eta_op() const { return EtaOp<T>{T(M.kappa_eta), F.dE}; }
+    void eta_start() {
+        hipLaunchKernelGGL(k_eta_prep<T>, dim3(ntiles), dim3(NT), 0, st, grid(), F, M, eta_v[0]);
+        EtaOp<T> eop = eta_op();
+        KVec<T, 1> V = eta_vecs();
+        set_active(allmask);
+        hipLaunchKernelGGL((k_cg_init<T, 1, EtaOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), eop, V, S);
+        finish<3>(EpiCgInit<1>{prm.rtol_s, 0});
+    }
+    void side_swap() {
+        std::swap(S, Se);
+        std::swap(st, st2);
+    }
+    clot_status eta_side_launch() {
+        if (!st2) {
+            HIPCHK(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&ev_derive, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&ev_eta, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&ev_info, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(ev_derive, st));
+        HIPCHK(hipStreamWaitEvent(st2, ev_derive, 0));
+        side_swap();
+        eta_start();
+        fixed_iters = eta_budget;
+        cg_iterations<EtaOp<T>, 1>(eta_op(), eta_vecs(), 4, CLOT_PROBE_ETA_CG_A, CLOT_PROBE_ETA_CG_B, 0, 0);
+        fixed_iters = 0;
+        hipLaunchKernelGGL(k_solve_info, dim3(1), dim3(64), 0, st, S.sc, S.nact, (int)ch.size(), eta_info);
+        side_swap();
+        HIPCHK(hipEventRecord(ev_eta, st2));
+        return CLOT_OK;
+    }
+    clot_status eta_side_join() {
+        HIPCHK(hipStreamWaitEvent(st, ev_eta, 0));
+        HIPCHK(hipMemcpyAsync(h_nact + 4, eta_info, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(ev_info, st));
+        return CLOT_OK;
+    }
+    // after a poll of the main stream: finish the eta solve if its budget fell short
+    clot_status eta_side_finish() {
+        HIPCHK(hipEventSynchronize(ev_info));   // already complete after the transport solve's polls
+        const int32_t still = h_nact[4], its = h_nact[5];
+        int total = its;
+        if (still > 0) {
+            std::swap(S, Se);
+            total = eta_budget + cg_iterations<EtaOp<T>, 1>(eta_op(), eta_vecs(), 4, CLOT_PROBE_ETA_CG_A,
+                                                            CLOT_PROBE_ETA_CG_B, eta_budget & 1, eta_budget);
+            std::swap(S, Se);
+            eta_budget = std::min(prm.max_iter, 2 * eta_budget);
+        } else {
+            eta_budget = std::min(prm.max_iter, std::max(8, (int)std::ceil(1.25 * its) + 4));
+        }
+        it_max[4] = std::max(it_max[4], total);   // for graph budgets
+        hipLaunchKernelGGL(k_record, dim3(1), dim3(64), 0, st, Se.sc, dstats, NSTAT, (int)ch.size(), 1, (int)ST_ETA,
+                           (int)ST_RESE, (int)ST_FAIL, 0, (const int32_t*)nullptr);
+        return CLOT_OK;
     }
 
     template <class Op, int K>
@@ -1096,6 +1206,12 @@ struct Ctx : clot_ctx {
         const int nch = (int)ch.size();
         // O-0 derived coefficients
         hipLaunchKernelGGL(k_derive<T>, gb, tb, 0, st, G, F, M);
+        // O-3 eta (needs only theta_B): on the side stream when not recording a graph
+        const bool eta_side = !capturing;
+        if (eta_side) {
+            const clot_status r = eta_side_launch();
+            if (r < 0) return r;
+        }
         // O-1 momentum predictor
         CLOT_LAUNCH(CLOT_PROBE_MOM_ASM, k_mom_assemble<T>, gb, tb, 0, st, G, F, M);
         MomOp<T> mop{F.aP, F.phi[0], F.phi[1], F.phi[2], T(prm.nu)};
@@ -1146,12 +1262,9 @@ struct Ctx : clot_ctx {
             CLOT_LAUNCH(CLOT_PROBE_CORRECT, k_correct<T>, gb, tb, 0, st, G, F, M, cm);
         }
         // O-3 eta
-        {
-            T* rhs = pool[0];
-            hipLaunchKernelGGL(k_eta_prep<T>, gb, tb, 0, st, G, F, M, rhs);
-            EtaOp<T> eop{T(M.kappa_eta), F.dE};
-            KVec<T, 1> V = cg_vecs(F.eta, rhs);
-            run_cg<EtaOp<T>, 1>(eop, V, prm.rtol_s, 0, allmask, 4, CLOT_PROBE_ETA_CG_A, CLOT_PROBE_ETA_CG_B);
+        if (!eta_side) {
+            eta_start();
+            cg_iterations<EtaOp<T>, 1>(eta_op(), eta_vecs(), 4, CLOT_PROBE_ETA_CG_A, CLOT_PROBE_ETA_CG_B, 0, 0);
             record(ST_ETA, ST_RESE, 1, false);
         }
         // O-4 sigma
@@ -1176,6 +1289,10 @@ struct Ctx : clot_ctx {
         top.Pmax = T(M.P_max);
         top.n = N;
         CLOT_LAUNCH(CLOT_PROBE_TR_ASM, k_tr_assemble<T>, gb, tb, 0, st, G, F, top, M);
+        if (eta_side) {
+            const clot_status r = eta_side_join();
+            if (r < 0) return r;
+        }
         {
             KVec<T, NTR> V = bicg_vecs<NTR>(0);
             for (int k = 0; k < NTR; ++k) {
@@ -1184,6 +1301,10 @@ struct Ctx : clot_ctx {
             }
             run_bicg<TrOp<T>, NTR>(top, V, prm.rtol_s, allmask, 5, CLOT_PROBE_TR_B1);
             record(ST_TR, ST_REST, NTR, false);
+        }
+        if (eta_side) {   // the transport solve's polls have synchronised the main stream
+            const clot_status r = eta_side_finish();
+            if (r < 0) return r;
         }
         // O-6 reactions (wall first: it reads the transported S1)
         if (NINJ > 0)

@@ -644,6 +644,18 @@ __global__ void k_flag_active(const int32_t* chact, double* sc, int nch, int K, 
     }
 }
 
+// Count of channels still iterating and the largest iteration count of a solve.
+__global__ void k_solve_info(const double* sc, const int32_t* nact, int nch, int32_t* out) {
+    if (threadIdx.x != 0) return;
+    int m = 0;
+    for (int c = 0; c < nch; ++c) {
+        const int it = (int)sc[(int64_t)c * MAXK * NSC + SC_IT];
+        m = it > m ? it : m;
+    }
+    out[0] = *nact;
+    out[1] = m;
+}
+
 // Small utility kernels (graph-safe replacements for memset).
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
