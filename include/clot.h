@@ -133,7 +133,11 @@ clot_status clot_query_workspace(const clot_channel* ch, int32_t n_ch, clot_prec
 /* Creates a context over n_ch independent channels.  dev_workspace: device memory of
  * at least the queried size, 256-byte aligned; hip_stream: a hipStream_t (NULL =
  * default stream).  Builds the mesh tables and the inflow profiles; all fields are
- * zero until clot_init_state or clot_set_field. */
+ * zero until clot_init_state or clot_set_field.  On its first step the context
+ * creates one internal non-blocking stream of default priority, on which the eta
+ * solve and the pressure preconditioner set-up run concurrently with the rest of the
+ * step; it is joined into hip_stream by events within every step, so a step's
+ * results are ordered on hip_stream.  It is destroyed with the context. */
 clot_status clot_create(const clot_channel* ch, int32_t n_ch, const clot_params* p, clot_precision prec,
                         void* dev_workspace, size_t ws_bytes, void* hip_stream, clot_ctx** out);
 
