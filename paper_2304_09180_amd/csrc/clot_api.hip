@@ -145,7 +145,7 @@ struct Ctx : clot_ctx {
     T* eta_v[5] = {};                 // right-hand side, r, p (two), t
     int32_t* eta_info = nullptr;      // device: [channels still iterating, largest iteration count]
     hipStream_t st2 = nullptr;
-    hipEvent_t ev_derive = nullptr, ev_eta = nullptr, ev_info = nullptr;
+    hipEvent_t ev_derive = nullptr, ev_eta = nullptr, ev_info = nullptr, ev_asm = nullptr, ev_mg = nullptr;
     int eta_budget = 32;
     int fixed_iters = 0;
     SigState* sig = nullptr;          // [nch] release-history schedule
@@ -211,6 +211,8 @@ struct Ctx : clot_ctx {
         if (ev_derive) (void)hipEventDestroy(ev_derive);
         if (ev_eta) (void)hipEventDestroy(ev_eta);
         if (ev_info) (void)hipEventDestroy(ev_info);
+        if (ev_asm) (void)hipEventDestroy(ev_asm);
+        if (ev_mg) (void)hipEventDestroy(ev_mg);
         if (st2) (void)hipStreamDestroy(st2);
         if (cst) (void)hipStreamDestroy(cst);
         if (h_nact) (void)hipHostFree(h_nact);
@@ -980,6 +982,8 @@ struct Ctx : clot_ctx {
             HIPCHK(hipEventCreateWithFlags(&ev_derive, hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&ev_eta, hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&ev_info, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&ev_asm, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&ev_mg, hipEventDisableTiming));
         }
         HIPCHK(hipEventRecord(ev_derive, st));
         HIPCHK(hipStreamWaitEvent(st2, ev_derive, 0));
@@ -1214,6 +1218,18 @@ struct Ctx : clot_ctx {
         }
         // O-1 momentum predictor
         CLOT_LAUNCH(CLOT_PROBE_MOM_ASM, k_mom_assemble<T>, gb, tb, 0, st, G, F, M);
+        // the pressure preconditioner depends only on rAU: built once per step, on the
+        // side stream (behind eta) while the momentum predictor is solved
+        if (eta_side) {
+            HIPCHK(hipEventRecord(ev_asm, st));
+            HIPCHK(hipStreamWaitEvent(st2, ev_asm, 0));
+            std::swap(st, st2);
+            mg_setup();
+            std::swap(st, st2);
+            HIPCHK(hipEventRecord(ev_mg, st2));
+        } else {
+            mg_setup();
+        }
         MomOp<T> mop{F.aP, F.phi[0], F.phi[1], F.phi[2], T(prm.nu)};
         {
             KVec<T, 3> V = bicg_vecs<3>(0);
@@ -1229,7 +1245,7 @@ struct Ctx : clot_ctx {
             const int32_t* cm = corrmask + (size_t)k * nch;
             CLOT_LAUNCH(CLOT_PROBE_HBYA, k_hbya<T>, gb, tb, 0, st, G, F, mop, cm);
             CLOT_LAUNCH(CLOT_PROBE_PRHS, k_prhs<T>, gb, tb, 0, st, G, F, M, cm);
-            mg_setup();
+            if (k == 0 && eta_side) HIPCHK(hipStreamWaitEvent(st, ev_mg, 0));
             // FP64 iterative refinement around a T-precision MG-PCG
             set_active(cm);
             // count of active channels for the residual kernel

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelD
             aP += (P.k < C.nz - 1) ? T(0.5) * ff + dfz : T(2) * dfz;
         }
         F.aP[g] = aP;
+        F.rAU[g] = T(C.V) / aP;   // fixed for the step: the pressure hierarchy is built from it once
         // Gauss-linear gradient of the old pressure (outlet face p_out, others p_P)
         const double pP = F.p[g];
         const double pw = P.i > 0 ? 0.5 * (F.p[g - 1] + pP) : pP;
@@ -88,7 +89,8 @@ __global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelD
     CLOT_END_CELLS
 }
 
-// PISO: H = src - sum a_N u_N with the latest u; HbyA = H / aP; rAU = V / aP.
+// PISO: H = src - sum a_N u_N with the latest u; HbyA = H / aP (rAU = V / aP comes
+// from the assembly).
 template <class T>
 __global__ __launch_bounds__(NT) void k_hbya(Grid G, Fields<T> F, MomOp<T> op, const int32_t* mask) {
     CLOT_TILE_PROLOGUE(G)
@@ -102,7 +104,6 @@ __global__ __launch_bounds__(NT) void k_hbya(Grid G, Fields<T> F, MomOp<T> op, c
             F.HbyA[c][P.g] = (F.src[c][P.g] - off) / aP;
         }
         if (C.dim == 2) F.HbyA[2][P.g] = T(0);
-        F.rAU[P.g] = T(C.V) / aP;
     CLOT_END_CELLS
 }
 
