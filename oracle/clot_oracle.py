@@ -101,6 +101,12 @@ class Params:
     n_corr: int = 0                # 0: chosen from the viscous diffusion number (see n_correctors)
     marg_m: int = 19
     marg_n: int = 2
+    # time integration (Appendix D table): Crank-Nicolson off-centring psi of every ddt
+    # term (0 = implicit Euler), and the variable step that holds the largest cell
+    # Courant number at max_co (0 = the channel's fixed dt)
+    ddt_psi: float = 0.0
+    max_co: float = 0.0
+    dt_growth: float = 1.2
 
 
 # --------------------------------------------------------------------------------------
@@ -406,6 +412,7 @@ class Oracle:
         self.m = Mesh(desc)
         self.desc = desc
         self.dt = desc["dt"]
+        self.dt_max = desc["dt"]
         self._init_state(xi_cell, xi_face, inlet_u)
 
     # ---- O-init -------------------------------------------------------------------
@@ -454,6 +461,15 @@ class Oracle:
         self.s1w = np.zeros(m.nface)
         self.t = 0.0
         self.n = 0
+        self.dt = self.dt_max
+        # stored time derivatives of the fields with a ddt term (Crank-Nicolson history)
+        self.ddt0u = np.zeros((3, m.n))
+        self.ddt0c = {name: np.zeros(m.n) for name in TRANSPORTED}
+        if p.max_co > 0.0:
+            # a variable step starts at the largest step the initial flux allows
+            co = self.courant()
+            if co > p.max_co:
+                self.dt = p.max_co * self.dt / co
         self.next_push = 0
         self.stats = {}
 
@@ -464,6 +480,44 @@ class Oracle:
     def thetaT(self):
         c = self.c
         return (c[SP["Pmu"]] + c[SP["Pma"]] + c[SP["Pba"]] + c[SP["Pbse"]]) / self.p.P_max
+
+    # ---- time scheme -----------------------------------------------------------------
+    def ddt_coeffs(self):
+        """(k, w) of this step's time derivative of a field f (Appendix D table,
+        CrankNicolson psi): ddt f = k (f^{n+1} - f^n)/dt - w D^n, with D^n the stored
+        derivative of the previous step, itself updated as D^{n+1} = k (f^{n+1} - f^n)/dt
+        - w D^n.  When D^n solves the previous step's equation this is the theta scheme
+        with weight 1/(1+psi) on the new and psi/(1+psi) on the old right-hand side
+        (psi = 1: trapezoidal Crank-Nicolson, psi = 0: implicit Euler).  The first step
+        has no stored derivative and is implicit Euler."""
+        psi = self.p.ddt_psi
+        if psi == 0.0 or self.n == 0:
+            return 1.0, 0.0
+        return 1.0 + psi, psi
+
+    def courant(self):
+        """Largest cell Courant number 0.5 dt sum_f |phi_f| / V with the current flux."""
+        m = self.m
+        tot = np.zeros(m.shape)
+        for a, (ax, A, d) in enumerate(m.axes):
+            hi = [slice(None)] * 3
+            lo = [slice(None)] * 3
+            hi[ax] = slice(1, None)
+            lo[ax] = slice(0, -1)
+            tot += np.abs(self.phi[a][tuple(hi)]) + np.abs(self.phi[a][tuple(lo)])
+        return 0.5 * self.dt * float(tot.max()) / m.V
+
+    def next_dt(self):
+        """Variable step (Appendix D: the step keeps the Courant number at or below
+        maxCo): the step after this one is the largest that holds the largest cell
+        Courant number of the current flux at max_co, grows by at most dt_growth per
+        step and never exceeds the channel's dt."""
+        p = self.p
+        co = self.courant()
+        cand = min(self.dt_max, p.dt_growth * self.dt)
+        if co > 0.0:
+            cand = min(cand, p.max_co * self.dt / co)
+        return cand
 
     # ---- helpers ---------------------------------------------------------------------
     def _grad(self, phi_cell, low_value, high_value):
@@ -495,15 +549,18 @@ class Oracle:
 
     # ---- O-1 momentum ------------------------------------------------------------------
     def momentum_system(self, alpha):
-        """Implicit-Euler momentum matrix with phi^n convection (Gauss linear), nu Laplacian,
-        implicit Darcy nu*alpha*V on the diagonal, and boundary terms (Appendix C table).
+        """Momentum matrix with the ddt scheme of ddt_coeffs, phi^n convection (Gauss
+        linear), nu Laplacian, implicit Darcy nu*alpha*V on the diagonal, and boundary
+        terms (Appendix C table).
 
-        Returns (System, src) with src[c] = V u_c^n/dt + boundary sources (no pressure)."""
+        Returns (System, src) with src[c] = k V u_c^n/dt + w V D_c^n + boundary sources
+        (no pressure)."""
         m, p, dt = self.m, self.p, self.dt
+        k, w = self.ddt_coeffs()
         S = System(m.n)
-        S.diag += m.V / dt + p.nu * alpha * m.V
+        S.diag += k * m.V / dt + p.nu * alpha * m.V
         src = np.zeros((3, m.n))
-        src += m.V * self.u / dt
+        src += k * m.V * self.u / dt + w * m.V * self.ddt0u
         ids = m.idx
         for a, (ax, A, d) in enumerate(m.axes):
             L, R = _pair_slices(ax)
@@ -536,13 +593,15 @@ class Oracle:
             return self.p.n_corr
         m = self.m
         h = min(m.dx, m.dy, m.dz if m.dim == 3 else m.dy)
-        Dn = self.p.nu * self.dt / (h * h)
+        Dn = self.p.nu * self.dt_max / (h * h)     # the largest step (variable steps never exceed it)
         return 2 if Dn <= 10.0 else 3 if Dn <= 30.0 else 4 if Dn <= 50.0 else 5 if Dn <= 80.0 else 6 if Dn <= 120.0 else 8
 
     def flow_step(self, alpha):
         """Momentum predictor + n_corr PISO correctors (section 3.2); updates u, p, phi."""
         m, p = self.m, self.p
         ncomp = m.dim
+        u_old = self.u.copy()
+        k_dt, w_dt = self.ddt_coeffs()
         S, src = self.momentum_system(alpha)
         M = S.matrix()
         Noff = S.offdiag()
@@ -604,6 +663,7 @@ class Oracle:
             gp = self.grad_p(self.p_)
             for c in range(ncomp):
                 self.u[c] = HbyA[c] - rAU * gp[c]
+        self.ddt0u = k_dt * (self.u - u_old) / self.dt - w_dt * self.ddt0u
         self.stats["rAU"] = rAU
 
     def continuity_residual(self):
@@ -669,14 +729,15 @@ class Oracle:
     def transport_system(self, name, thetaT):
         """Implicit upwind-biased TVD transport system of one scalar (Appendix D, App. C table)."""
         m, p, dt = self.m, self.p, self.dt
+        k_dt, w_dt = self.ddt_coeffs()
         platelet = name in ("Pmu", "Pma")
         D = p.D_P if platelet else (p.D_ADP if name == "ADP" else p.D_chem)
         Cn = self.c[SP[name]]
         C3 = Cn.reshape(m.shape)
         T3 = thetaT.reshape(m.shape)
         S = System(m.n)
-        S.diag += m.V / dt
-        S.rhs = m.V * Cn / dt
+        S.diag += k_dt * m.V / dt
+        S.rhs = k_dt * m.V * Cn / dt + w_dt * m.V * self.ddt0c[name]
         if name == "ADP":
             S.rhs = S.rhs + m.V * self.sigma
         ids = m.idx
@@ -764,11 +825,16 @@ class Oracle:
         return S
 
     def transport(self, thetaT):
+        """The 7 transport solves; each species' stored time derivative is that of its
+        transport sub-step (from C^n to the transported value; the reactions that follow
+        in the fractional step are not part of it)."""
         out = {}
         for name in TRANSPORTED:
             S = self.transport_system(name, thetaT)
             out[name] = solve(S.matrix(), S.rhs, spd=False)
+        k_dt, w_dt = self.ddt_coeffs()
         for name, v in out.items():
+            self.ddt0c[name] = k_dt * (v - self.c[SP[name]]) / self.dt - w_dt * self.ddt0c[name]
             self.c[SP[name]] = v
 
     # ---- O-6 reactions ---------------------------------------------------------------------------
@@ -809,7 +875,12 @@ class Oracle:
             self.reactions()
         self.thetaB_prev = thB
         self.n += 1
-        self.t = self.n * self.dt
+        if self.p.max_co > 0.0:
+            self.t += self.dt
+            self.stats["co"] = self.courant()
+            self.dt = self.next_dt()
+        else:
+            self.t = self.n * self.dt
 
     def fields(self):
         """Dict of float64 arrays keyed by library field names."""
