@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
     ap.add_argument("--train-samples", type=int, default=400_000)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-time-scheme", action="store_true",
+                    help="skip the Crank-Nicolson / variable-step leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -190,6 +192,27 @@ def surrogate_leg(desc, prec, args, xc, xf, tile):
     return out
 
 
+def time_scheme_leg(desc, prec, args, xc, xf, tile):
+    """The same workload with Crank-Nicolson 0.9 on every ddt term and the variable step
+    at maxCo 0.75 (the channel's dt is the largest step): cost per step against the
+    implicit-Euler fixed step, and the simulated time it covers."""
+    import torch
+    from paper_2304_09180_amd import clot
+    prm = clot.default_params(prec, ddt_psi=0.9, max_co=0.75)
+    s = clot.Solver([desc], prec, prm, tile=tile)
+    s.init_state(0, xc, xf)
+    for _ in range(max(1, args.warmup)):
+        s.step(1)
+    t0 = s.stats(0)["t"]
+    el, _, _ = timed_steps(s, args.steps, args.probe)
+    st = s.stats(0)
+    s.close()
+    torch.cuda.synchronize()
+    return {"ddt": "CrankNicolson 0.9", "max_co": 0.75, "ms_per_step": round(el * 1e3 / args.steps, 4),
+            "dt_last": st["dt"], "simulated_s_per_wall_s": round((st["t"] - t0) / el, 6), "status": st["status"],
+            "solver": {k: st[k] for k in ("it_mom", "it_p", "it_eta", "it_tr", "refine_p")}}
+
+
 def ensemble_leg(args):
     """The 64-member uneven ensemble of 2-D channels in one context, FP32: eager steps,
     then the same steps replayed as HIP graphs."""
@@ -281,6 +304,8 @@ def main():
     if tuned:
         out["autotune"] = {"ms_per_step": tuned["ms_per_step"], "kernel_us": tuned["kernel_us"]}
     s.close()
+    if not args.no_time_scheme:
+        out["time_scheme"] = time_scheme_leg(desc, prec, args, xc, xf, tile)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(desc, prec, args, xc, xf, tile)
     if not args.no_ensemble:

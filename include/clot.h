@@ -107,16 +107,34 @@ typedef struct {
                              0 = every level its own launches.  Default 4096.            */
     int32_t mg_sweeps;    /* pressure multigrid: weighted-Jacobi sweeps before and after each
                              restriction, 1 or 2 (default 2)                               */
+    double ddt_psi;       /* Crank-Nicolson off-centring of every ddt term (Appendix D
+                             table), in [0,1]; 0 = implicit Euler (default).  The time
+                             derivative over a step is k (f' - f)/dt - w D, D the stored
+                             derivative of the previous step (updated by the same
+                             expression), k = 1+psi, w = psi; the first step after
+                             clot_init_state is implicit Euler.  A species' stored
+                             derivative is that of its transport sub-step.               */
+    double max_co;        /* > 0: variable step (Appendix D: maxCo) holding the largest cell
+                             Courant number 0.5 dt sum_f |phi_f| / V of the current flux at
+                             max_co; the channel's dt is the largest step, the first step
+                             the largest the initial flux allows.  0 = the channel's fixed
+                             dt (default).  The corrector count (n_corr = 0) follows the
+                             channel's dt.                                               */
+    double dt_growth;     /* variable step: largest growth factor per step, >= 1 (default 1.2) */
 } clot_params;
 
 /* Per-channel statistics of the last step. */
 typedef struct {
     int32_t it_mom, it_p[8], it_eta, it_tr;   /* Krylov iterations (it_p per corrector)   */
     int32_t refine_p[8];                        /* FP64 refinement passes per corrector      */
-    double res_mom, res_p, res_eta, res_tr;     /* final relative residuals                  */
+    double res_mom, res_p, res_eta, res_tr;     /* final relative residuals, max over the
+                                                   solve's systems; an FP32 transport species
+                                                   stopped by the absolute floor is measured
+                                                   against the norm that floor stands for      */
     double fallback_frac;                       /* surrogate cells sent to the plain RK4     */
     int64_t steps;
-    double t;
+    double t;                                   /* simulated time                            */
+    double dt;                                  /* step the next clot_step takes             */
 } clot_stats;
 
 typedef struct clot_ctx clot_ctx;
@@ -265,6 +283,8 @@ clot_status clot_surr_dataset(const clot_params* p, const double* rows, const do
 clot_status clot_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, void* hip_stream);
 
 void clot_destroy(clot_ctx* c);
+/* the context's last error message; with c == NULL, that of the last failed clot_create
+ * on the calling thread */
 const char* clot_last_error(const clot_ctx* c);
 
 #ifdef __cplusplus

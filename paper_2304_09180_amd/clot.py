@@ -55,14 +55,15 @@ class Params(C.Structure):
                 [("M_rxn", C.c_int32), ("n_corr", C.c_int32), ("max_iter", C.c_int32),
                  ("marg_m", C.c_int32), ("marg_n", C.c_int32),
                  ("rtol_p", C.c_double), ("rtol_s", C.c_double), ("rtol_inner", C.c_double),
-                 ("mg_tail", C.c_int32), ("mg_sweeps", C.c_int32)])
+                 ("mg_tail", C.c_int32), ("mg_sweeps", C.c_int32),
+                 ("ddt_psi", C.c_double), ("max_co", C.c_double), ("dt_growth", C.c_double)])
 
 
 class Stats(C.Structure):
     _fields_ = [("it_mom", C.c_int32), ("it_p", C.c_int32 * 8), ("it_eta", C.c_int32), ("it_tr", C.c_int32),
                 ("refine_p", C.c_int32 * 8),
                 ("res_mom", C.c_double), ("res_p", C.c_double), ("res_eta", C.c_double), ("res_tr", C.c_double),
-                ("fallback_frac", C.c_double), ("steps", C.c_int64), ("t", C.c_double)]
+                ("fallback_frac", C.c_double), ("steps", C.c_int64), ("t", C.c_double), ("dt", C.c_double)]
 
 
 class ClotError(RuntimeError):
@@ -82,6 +83,11 @@ def load(tile: int = 256):
     path = lib_path(tile)
     if not os.path.exists(path):
         raise ClotError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    # One HIP runtime per process: torch's bundled runtime carries the soname this
+    # library links against, so loading torch first binds the library to it.  The
+    # other order loads a second HIP/HSA runtime next to torch's (torch names the
+    # unversioned file), and that second runtime finds no device.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P = C.c_void_p
     sig = {
@@ -169,7 +175,7 @@ def check(st, what):
 
 def _check(lib, ctx, st, what):
     if st < 0:
-        msg = lib.clot_last_error(ctx).decode() if ctx else ""
+        msg = lib.clot_last_error(ctx).decode()
         raise ClotError(f"{what} failed: {STATUS.get(st, st)} {msg}")
     return st
 
@@ -252,7 +258,7 @@ class Solver:
         return {"status": STATUS.get(st, st), "it_mom": s.it_mom, "it_p": list(s.it_p), "it_eta": s.it_eta,
                 "it_tr": s.it_tr, "refine_p": list(s.refine_p), "res_mom": s.res_mom, "res_p": s.res_p,
                 "res_eta": s.res_eta, "res_tr": s.res_tr, "fallback_frac": s.fallback_frac, "steps": s.steps,
-                "t": s.t}
+                "t": s.t, "dt": s.dt}
 
     def set_reaction_mode(self, mode, blob=None, tol=1e-3):
         """PLAIN, or SURROGATE with a float32 blob (MLP parameters + 28 scales)."""

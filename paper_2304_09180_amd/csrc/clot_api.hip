@@ -126,6 +126,7 @@ struct Ctx : clot_ctx {
     int maxcorr = 2;
     // device tables
     ChanDev* d_ch = nullptr;
+    std::vector<ChanDev> hch;   // host copy of the channel table as uploaded (clock reset)
     int32_t* d_t2c = nullptr;
     int32_t* d_f2c = nullptr;
     Fields<T> F{};
@@ -332,6 +333,9 @@ struct Ctx : clot_ctx {
         for (int k = 0; k < NTR; ++k) F.trd[k] = cv.take<T>(N);
         for (int k = 0; k < NTR; ++k) F.trb[k] = cv.take<T>(N);
         for (int k = 0; k < NTR; ++k) F.trc[k] = cv.take<T>((size_t)6 * N);
+        for (int c = 0; c < 3; ++c) F.ddt0u[c] = cv.take<T>(N);
+        for (int k = 0; k < NTR; ++k) F.ddt0c[k] = cv.take<T>(N);
+        F.co_part = cv.take<double>(ntiles);
         for (int q = 0; q < NPOOL; ++q) pool[q] = cv.take<T>(N);
         F.ncell = N;
         S.maxit = prm.max_iter;
@@ -537,6 +541,9 @@ struct Ctx : clot_ctx {
         const double Le = q.L_eta_over_Pdiam * q.P_diam;
         M.kappa_eta = Le * Le / 4.0;
         M.g0 = (std::pow(q.eta_star, 3) + std::pow(1.0 - q.eta_t, 3)) / std::pow(1.0 - q.eta_t, 3);
+        M.psi = q.ddt_psi;
+        M.max_co = q.max_co;
+        M.dt_growth = q.dt_growth;
         return CLOT_OK;
     }
 
@@ -630,10 +637,14 @@ struct Ctx : clot_ctx {
             c.gy = c.Ay / c.dy;
             c.gz = c.Az / c.dz;
             c.rdt = 1.0 / c.dt;
+            c.ddtk = 1.0;
+            c.ddtw = 0.0;
+            c.dtmax = h.d.dt;
             for (int t = 0; t < h.nt; ++t) t2c[h.t0 + t] = i;
             for (int f = 0; f < h.ninj; ++f) f2c[h.inj0 + f] = i;
         }
         HIPCHK(hipMemcpyAsync(d_ch, dv.data(), nch * sizeof(ChanDev), hipMemcpyHostToDevice, st));
+        hch = dv;
         for (Level& L : lev) {
             HIPCHK(hipMemcpyAsync(L.d_ch, L.ch.data(), nch * sizeof(ChanDev), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(L.d_t2c, L.t2c.data(), L.t2c.size() * 4, hipMemcpyHostToDevice, st));
@@ -775,6 +786,32 @@ struct Ctx : clot_ctx {
         if ((s = upload(F.thB_prev + h.c0, thb))) return s;
         h.t = 0.0;
         h.n = 0;
+        // the clock: the channel's step, or with a variable step the largest the initial
+        // flux allows (cell Courant number 0.5 dt sum_f |phi_f| / V, x faces only carry
+        // flux); implicit Euler first; no time-derivative history
+        {
+            ChanDev cd = hch[c];
+            cd.dt = h.d.dt;
+            if (prm.max_co > 0.0) {
+                double mx = 0.0;
+                for (int64_t r = 0; r < (int64_t)h.d.ny * h.d.nz; ++r)
+                    for (int i = 0; i < h.d.nx; ++i) {
+                        const double* f = fxv.data() + (int64_t)(h.d.nx + 1) * r + i;
+                        mx = std::max(mx, (std::fabs(f[1]) + std::fabs(f[0])) + 0.0);
+                    }
+                const double co = 0.5 * cd.dt * mx / cd.V;
+                if (co > prm.max_co) cd.dt = prm.max_co * cd.dt / co;
+            }
+            cd.rdt = 1.0 / cd.dt;
+            cd.ddtk = 1.0;
+            cd.ddtw = 0.0;
+            hch[c] = cd;
+            HIPCHK(hipMemcpyAsync(d_ch + c, &hch[c], sizeof(ChanDev), hipMemcpyHostToDevice, st));
+            for (int q = 0; q < 3; ++q)
+                if ((s = upload(F.ddt0u[q] + h.c0, zero))) return s;
+            for (int k = 0; k < NTR; ++k)
+                if ((s = upload(F.ddt0c[k] + h.c0, zero))) return s;
+        }
         const SigState s0 = fresh_sig();
         HIPCHK(hipMemcpyAsync(sig + c, &s0, sizeof(SigState), hipMemcpyHostToDevice, st));
         // thB_prev must equal theta_B of the initial state: compute it on the device
@@ -1322,6 +1359,8 @@ struct Ctx : clot_ctx {
             const clot_status r = eta_side_finish();
             if (r < 0) return r;
         }
+        // Crank-Nicolson history of u and the transported species (before the reactions)
+        if (M.psi > 0.0) hipLaunchKernelGGL(k_ddt_close<T>, gb, tb, 0, st, G, F);
         // O-6 reactions (wall first: it reads the transported S1)
         if (NINJ > 0)
             hipLaunchKernelGGL(k_wall_rxn<T>, dim3((NINJ + NT - 1) / NT), tb, 0, st, d_ch, d_f2c, NINJ, F, M);
@@ -1339,6 +1378,9 @@ struct Ctx : clot_ctx {
         } else {
             CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn<T>, gb, tb, 0, st, G, F, M);
         }
+        // the next step's ddt coefficients and variable step
+        if (M.psi > 0.0 || M.max_co > 0.0)
+            hipLaunchKernelGGL(k_time_end, dim3(nch), dim3(256), 0, st, d_ch, (const double*)F.co_part, M);
         // O-7 rotate theta_B and the flux
         rotate();
         HIPCHK(hipGetLastError());
@@ -1552,7 +1594,13 @@ struct Ctx : clot_ctx {
         s->res_tr = v[ST_REST];
         s->fallback_frac = v[ST_FALLBACK];
         s->steps = ch[c].n;
-        s->t = ch[c].t;
+        SigState sg;
+        ChanDev cd;
+        if (hipMemcpy(&sg, sig + c, sizeof(SigState), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&cd, d_ch + c, sizeof(ChanDev), hipMemcpyDeviceToHost) != hipSuccess)
+            return CLOT_EHIP;
+        s->t = sg.t;
+        s->dt = cd.dt;
         return v[ST_FAIL] > 0 ? CLOT_W_NOTCONV : CLOT_OK;
     }
 };
@@ -1582,6 +1630,9 @@ static ModelDev model_from_params(const clot_params& q) {
     const double Le = q.L_eta_over_Pdiam * q.P_diam;
     M.kappa_eta = Le * Le / 4.0;
     M.g0 = (std::pow(q.eta_star, 3) + std::pow(1.0 - q.eta_t, 3)) / std::pow(1.0 - q.eta_t, 3);
+    M.psi = q.ddt_psi;
+    M.max_co = q.max_co;
+    M.dt_growth = q.dt_growth;
     return M;
 }
 
@@ -1601,12 +1652,23 @@ static clot_status create_t(Ctx<T>* c, const clot_channel* chs, int n_ch, const 
     }
     c->layout((char*)ws);
     c->st = (hipStream_t)stream;
-    if (hipHostMalloc((void**)&c->h_nact, 64, hipHostMallocDefault) != hipSuccess) {
-        c->err = "hipHostMalloc failed";
+    hipError_t he = hipHostMalloc((void**)&c->h_nact, 64, hipHostMallocDefault);
+    if (he != hipSuccess) {
+        // an error left by an earlier call can surface here: clear it and try once more
+        (void)hipGetLastError();
+        he = hipHostMalloc((void**)&c->h_nact, 64, hipHostMallocDefault);
+    }
+    if (he != hipSuccess) {
+        c->h_nact = nullptr;
+        c->err = std::string("hipHostMalloc of the 64-byte poll buffer failed: ") + hipGetErrorName(he) + " (" +
+                 hipGetErrorString(he) + ")";
         return CLOT_EHIP;
     }
     return c->upload_tables();
 }
+
+// Message of the last failed clot_create on this thread (its context no longer exists).
+static thread_local std::string g_create_err;
 
 extern "C" {
 
@@ -1667,6 +1729,9 @@ clot_status clot_params_default(clot_params* p) {
     p->rtol_inner = 1e-4;
     p->mg_tail = 4096;
     p->mg_sweeps = 2;
+    p->ddt_psi = 0.0;
+    p->max_co = 0.0;
+    p->dt_growth = 1.2;
     return CLOT_OK;
 }
 
@@ -1694,16 +1759,19 @@ clot_status clot_create(const clot_channel* chs, int32_t n_ch, const clot_params
     if (!chs || n_ch < 1 || !p || !ws || !out || (prec != CLOT_FP64 && prec != CLOT_FP32_MIXED)) return CLOT_EINVAL;
     *out = nullptr;
     if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1 || p->mg_tail < 0 ||
-        (p->mg_sweeps != 1 && p->mg_sweeps != 2))
+        (p->mg_sweeps != 1 && p->mg_sweeps != 2) || !(p->ddt_psi >= 0.0 && p->ddt_psi <= 1.0) ||
+        !(p->max_co >= 0.0) || !(p->dt_growth >= 1.0))
         return CLOT_EINVAL;
     clot_ctx* c = make_ctx(prec);
     c->prec = prec;
     clot_status s = prec == CLOT_FP64 ? create_t(static_cast<Ctx<double>*>(c), chs, n_ch, p, ws, wsb, stream)
                                       : create_t(static_cast<Ctx<float>*>(c), chs, n_ch, p, ws, wsb, stream);
     if (s < 0) {
+        g_create_err = c->err;
         delete c;
         return s;
     }
+    g_create_err.clear();
     *out = c;
     return CLOT_OK;
 }
@@ -1854,6 +1922,9 @@ clot_status clot_graph_info(clot_ctx* c, int64_t* info) {
     return c->graph_info(info);
 }
 void clot_destroy(clot_ctx* c) { delete c; }
-const char* clot_last_error(const clot_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* clot_last_error(const clot_ctx* c) {
+    if (c) return c->err.c_str();
+    return g_create_err.empty() ? "null context" : g_create_err.c_str();
+}
 
 }  // extern "C"

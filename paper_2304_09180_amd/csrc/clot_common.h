@@ -44,8 +44,10 @@ struct ChanDev {
     int32_t t0, nt;               // tile range
     uint32_t mnx, lnx, mny, lny;  // magic multipliers/shifts for division by nx and ny
     double dx, dy, dz, V, Ax, Ay, Az;
-    double dt;
-    double gx, gy, gz, rdt;       // Ax/dx, Ay/dy, Az/dz, 1/dt (per channel, from the host)
+    double dt;                    // this step (rewritten on the device by a variable step)
+    double gx, gy, gz, rdt;       // Ax/dx, Ay/dy, Az/dz, 1/dt
+    double ddtk, ddtw;            // this step's ddt coefficients k, w (k (f'-f)/dt - w D)
+    double dtmax;                 // the channel's given step: the largest a variable step takes
 };
 
 // Round-up magic-number division of 32-bit unsigned n by a fixed d (host computes m, l).
@@ -70,6 +72,7 @@ struct ModelDev {
     double S1_0, S2_0, E0_0, p_out;
     double g0;
     int32_t M_rxn;
+    double psi, max_co, dt_growth;   // time scheme: Crank-Nicolson off-centring, variable step
 };
 
 // Launch-wide tables.
@@ -143,6 +146,19 @@ __device__ inline void block_sum(double (&v)[NV], double* lds) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = lds[NV * NW + q];
+}
+
+// Block-wide maximum of v, returned to every thread; lds holds BS/64 doubles.
+template <int BS = NT>
+__device__ inline double block_max(double v, double* lds) {
+    constexpr int NW = BS / 64;
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = lds[0];
+    for (int w = 1; w < NW; ++w) m = fmax(m, lds[w]);
+    __syncthreads();
+    return m;
 }
 
 // Writes the block's totals of v[] as the tile partials part[tile*NV + q].  The

@@ -20,7 +20,8 @@ namespace clot {
 enum {
     SC_BB = 0, SC_RR, SC_RZ, SC_RHO, SC_ALPHA, SC_OMEGA, SC_BETA, SC_IT, SC_ACT, SC_TOL2, SC_RR0, SC_PQ,
     SC_TS, SC_TT, SC_FAIL, SC_PASS,
-    SC_ORR, SC_OBB, SC_ORRP   // pressure refinement: outer r.r, b.b, r.r of the previous pass
+    SC_ORR, SC_OBB, SC_ORRP,  // pressure refinement: outer r.r, b.b, r.r of the previous pass
+    SC_BBS                    // squared norm the reported relative residual is taken against
 };
 
 struct KState {
@@ -105,6 +106,7 @@ struct EpiCgInit {
             double* s = scp(S, ch, k);
             s[SC_RZ] = sums[3 * k];
             s[SC_BB] = sums[3 * k + 1];
+            s[SC_BBS] = sums[3 * k + 1];
             s[SC_RR] = sums[3 * k + 2];
             s[SC_RR0] = sums[3 * k + 2];
             if (tol_mode == 0) s[SC_TOL2] = rtol * rtol * sums[3 * k + 1];
@@ -184,6 +186,8 @@ struct EpiBicgInit {
             s[SC_RHO] = sums[3 * k + 1];       // rhat . r with rhat = r
             const double rel2 = rtol * rtol * sums[3 * k];
             s[SC_TOL2] = rel2 > sums[3 * k + 2] ? rel2 : sums[3 * k + 2];
+            // a floored system reports its residual against the norm its floor stands for
+            s[SC_BBS] = (rel2 >= sums[3 * k + 2] || rtol <= 0.0) ? sums[3 * k] : sums[3 * k + 2] / (rtol * rtol);
             s[SC_ALPHA] = 1.0;
             s[SC_OMEGA] = 1.0;
             s[SC_BETA] = 0.0;

@@ -588,6 +588,7 @@ struct EpiMgcgInit {
     __device__ void operator()(const double* sums, const KState& S, int ch) const {
         double* s = scp(S, ch, 0);
         s[SC_BB] = sums[0];
+        s[SC_BBS] = sums[0];
         s[SC_RR] = sums[1];
         s[SC_RR0] = sums[1];
         if (tol_mode == 0) s[SC_TOL2] = rtol * rtol * sums[0];

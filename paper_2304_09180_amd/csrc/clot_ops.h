@@ -41,6 +41,9 @@ struct Fields {
     T* trd[NTR];          // transport diagonals
     T* trb[NTR];          // transport right-hand sides
     T* trc[NTR];      // transport off-diagonal couplings, 6 slots x ncell per species
+    T* ddt0u[3];          // Crank-Nicolson history: stored time derivative of u
+    T* ddt0c[NTR];        // ... and of each transported species (its transport sub-step)
+    double* co_part;      // variable step: per tile, the largest sum_f |phi_f| of its cells
     int64_t ncell;
 };
 

@@ -20,9 +20,12 @@ __global__ __launch_bounds__(NT) void k_derive(Grid G, Fields<T> F, ModelDev M) 
 }
 
 // Momentum predictor matrix diagonal and right-hand sides (section 3.2; Appendix D
-// schemes; Appendix C boundary table).  Implicit Euler, Gauss-linear convection
-// with the old flux, nu Laplacian, implicit Darcy nu alpha(theta_B) V with the
-// Carman-Kozeny alpha, Gauss-linear pressure gradient of the old pressure.
+// schemes; Appendix C boundary table).  Time derivative k (u' - u)/dt - w D (implicit
+// Euler: k = 1, w = 0; Crank-Nicolson psi: k = 1+psi, w = psi with the stored
+// derivative D), Gauss-linear convection with the old flux, nu Laplacian, implicit
+// Darcy nu alpha(theta_B) V with the Carman-Kozeny alpha, Gauss-linear gradient of the
+// old pressure.  With Crank-Nicolson, D is replaced by -(k/dt u + w D); the step's end
+// adds k/dt u' (k_ddt_close).
 template <class T>
 __global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelDev M) {
     CLOT_TILE_PROLOGUE(G)
@@ -30,10 +33,11 @@ __global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelD
         const Cell P = cell_at(C, local);
         const int64_t g = P.g;
         const T V = T(C.V), rdt = T(C.rdt), nu = T(M.nu);
+        const T kd = T(C.ddtk), kvr = kd * V * rdt;
         const T s = T(0.6) * F.thB[g];
         const T om = T(1) - s;
         const T alpha = T(M.C_CK) * s * s / (om * om * om);
-        T aP = V * rdt + nu * alpha * V;
+        T aP = kvr + nu * alpha * V;
         T srcx = T(0);
         // x faces: inlet (fixed value) at i = 0, outlet (zero gradient) at i = nx-1
         const T dfx = nu * T(C.gx);
@@ -69,8 +73,16 @@ __global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelD
         const double ps = P.j > 0 ? 0.5 * (F.p[g - C.nx] + pP) : pP;
         const double pn = P.j < C.ny - 1 ? 0.5 * (F.p[g + C.nx] + pP) : pP;
         const double gx = (pe - pw) / C.dx, gy = (pn - ps) / C.dy;
-        const T sx = V * rdt * F.u[0][g] + srcx;
-        const T sy = V * rdt * F.u[1][g];
+        T sx = kvr * F.u[0][g] + srcx;
+        T sy = kvr * F.u[1][g];
+        if (M.psi > 0.0) {
+            const T w = T(C.ddtw), kr = kd * rdt;
+            const T q0 = F.ddt0u[0][g], q1 = F.ddt0u[1][g];
+            sx += w * V * q0;
+            sy += w * V * q1;
+            F.ddt0u[0][g] = -(kr * F.u[0][g] + w * q0);
+            F.ddt0u[1][g] = -(kr * F.u[1][g] + w * q1);
+        }
         F.src[0][g] = sx;
         F.src[1][g] = sy;
         F.bm[0][g] = T((double)sx - C.V * gx);
@@ -79,7 +91,13 @@ __global__ __launch_bounds__(NT) void k_mom_assemble(Grid G, Fields<T> F, ModelD
             const int64_t sz = (int64_t)C.nx * C.ny;
             const double pb = P.k > 0 ? 0.5 * (F.p[g - sz] + pP) : pP;
             const double pf = P.k < C.nz - 1 ? 0.5 * (F.p[g + sz] + pP) : pP;
-            const T sz_ = V * rdt * F.u[2][g];
+            T sz_ = kvr * F.u[2][g];
+            if (M.psi > 0.0) {
+                const T w = T(C.ddtw), kr = kd * rdt;
+                const T q2 = F.ddt0u[2][g];
+                sz_ += w * V * q2;
+                F.ddt0u[2][g] = -(kr * F.u[2][g] + w * q2);
+            }
             F.src[2][g] = sz_;
             F.bm[2][g] = T((double)sz_ - C.V * (pf - pb) / C.dz);
         } else {
@@ -343,20 +361,38 @@ __global__ __launch_bounds__(64) void k_sigma_sched(const ChanDev* chans, SigSta
             }
         }
         s.n += 1;
-        s.t = (double)s.n * chans[c].dt;
+        // fixed step: t = n dt; variable step: the sum of the steps taken
+        s.t = M.max_co > 0.0 ? s.t + chans[c].dt : (double)s.n * chans[c].dt;
         sig[c] = s;
     }
 }
 
 // Transport assembly (section 3.2, Appendix C table, Appendix D): diagonal and
-// right-hand side of the 7 implicit TVD transport systems; initial guess C^n.
+// right-hand side of the 7 implicit TVD transport systems; initial guess C^n.  The
+// time derivative is that of the momentum assembly (k, w and the stored derivative
+// of each species' transport sub-step).  With a variable step, each tile also stores
+// the largest sum_f |phi_f| of its cells (the new flux) for the next step's Courant
+// limit.
 template <class T>
 __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T> op, ModelDev M) {
     CLOT_TILE_PROLOGUE(G)
+    double co_mx = 0.0;
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
         const int64_t g = P.g;
         const T V = T(C.V), rdt = T(C.rdt);
+        const T kd = T(C.ddtk), kvr = kd * V * rdt;
+        if (M.max_co > 0.0) {
+            // face order as the cell Courant number is defined: x, y, z, high + low face
+            double sf = fabs((double)F.phin[0][fx_id(C, P.i + 1, P.j, P.k)]) +
+                        fabs((double)F.phin[0][fx_id(C, P.i, P.j, P.k)]);
+            sf += fabs((double)F.phin[1][fy_id(C, P.i, P.j + 1, P.k)]) +
+                  fabs((double)F.phin[1][fy_id(C, P.i, P.j, P.k)]);
+            if (C.dim == 3)
+                sf += fabs((double)F.phin[2][fz_id(C, P.i, P.j, P.k + 1)]) +
+                      fabs((double)F.phin[2][fz_id(C, P.i, P.j, P.k)]);
+            co_mx = fmax(co_mx, sf);
+        }
         const T Wp = F.Wc[g];
         const bool inj = P.j == 0 && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
                          P.k < C.inj_k0 + C.inj_nk;
@@ -369,9 +405,16 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             const T* c = op.Cn[k];
             const T D = op.Dk[k];
             const T cn = c[g];
-            T d = V * rdt;
-            T b = V * rdt * cn;
+            T d = kvr;
+            T b = kvr * cn;
             if (sp == ADP) b += V * F.sigma[g];
+            if (M.psi > 0.0) {
+                const T w = T(C.ddtw), kr = kd * rdt;
+                T* hq = F.ddt0c[k] + g;
+                const T q = *hq;
+                b += w * V * q;
+                *hq = -(kr * cn + w * q);
+            }
             // couplings of this row, stored for the solver's stencil products, and the
             // diagonal (same faces, same order as the products)
             T* cf = F.trc[k] + g;
@@ -444,6 +487,57 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             F.xt[k][g] = cn;
         }
     CLOT_END_CELLS
+    if (M.max_co > 0.0) {
+        __shared__ double lds[NT / 64];
+        co_mx = block_max(co_mx, lds);
+        if (threadIdx.x == 0) F.co_part[tile] = co_mx;
+    }
+}
+
+// Crank-Nicolson history at the end of the transport sub-step: the assemblies left
+// -(k/dt f + w D) in the history; adding k/dt f' leaves D' = k (f' - f)/dt - w D for
+// u (final after the correctors) and each transported species (its transport solution).
+template <class T>
+__global__ __launch_bounds__(NT) void k_ddt_close(Grid G, Fields<T> F) {
+    CLOT_TILE_PROLOGUE(G)
+    const T kr = T(C.ddtk) * T(C.rdt);
+    CLOT_FOR_CELLS(local)
+        const int64_t g = C.c0 + local;
+        for (int c = 0; c < C.dim; ++c) F.ddt0u[c][g] += kr * F.u[c][g];
+#pragma unroll
+        for (int k = 0; k < NTR; ++k) F.ddt0c[k][g] += kr * F.xt[k][g];
+    CLOT_END_CELLS
+}
+
+// End of a step, one block per channel, after every kernel that reads the step's dt:
+// the Crank-Nicolson coefficients of the steps after the first (k = 1+psi, w = psi),
+// and the variable step (Appendix D, maxCo): the largest that holds the largest cell
+// Courant number 0.5 dt sum_f |phi_f| / V of the new flux at max_co, at most dt_growth
+// times this one and at most the channel's dt.
+__global__ __launch_bounds__(256) void k_time_end(ChanDev* chans, const double* co_part, ModelDev M) {
+    __shared__ double lds[4];
+    const int c = blockIdx.x;
+    const int32_t t0 = chans[c].t0, nt = chans[c].nt;
+    double mx = 0.0;
+    if (M.max_co > 0.0) {
+        for (int t = threadIdx.x; t < nt; t += 256) mx = fmax(mx, co_part[t0 + t]);
+        mx = block_max<256>(mx, lds);
+    }
+    if (threadIdx.x == 0) {
+        ChanDev& C = chans[c];
+        if (M.psi > 0.0) {
+            C.ddtk = 1.0 + M.psi;
+            C.ddtw = M.psi;
+        }
+        if (M.max_co > 0.0) {
+            const double dt = C.dt;
+            const double co = 0.5 * dt * mx / C.V;
+            double nd = fmin(C.dtmax, M.dt_growth * dt);
+            if (co > 0.0) nd = fmin(nd, M.max_co * dt / co);
+            C.dt = nd;
+            C.rdt = 1.0 / nd;
+        }
+    }
 }
 
 // Reaction right-hand side (Appendix A platelet equations, Appendix B coagulation
@@ -608,7 +702,7 @@ __global__ void k_record(const double* sc, double* stats, int nstat, int nch, in
         for (int k = 0; k < K; ++k) {
             const double* s = sc + ((int64_t)c * MAXK + k) * NSC;
             it = fmax(it, s[SC_IT]);
-            if (s[SC_BB] > 0.0) res = fmax(res, sqrt(s[SC_RR] / s[SC_BB]));
+            if (s[SC_BBS] > 0.0) res = fmax(res, sqrt(s[SC_RR] / s[SC_BBS]));
             fail = fmax(fail, s[SC_FAIL]);
         }
         double* st = stats + (int64_t)c * nstat;
