@@ -376,23 +376,11 @@ __global__ __launch_bounds__(64) void k_sigma_sched(const ChanDev* chans, SigSta
 template <class T>
 __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T> op, ModelDev M) {
     CLOT_TILE_PROLOGUE(G)
-    double co_mx = 0.0;
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
         const int64_t g = P.g;
         const T V = T(C.V), rdt = T(C.rdt);
         const T kd = T(C.ddtk), kvr = kd * V * rdt;
-        if (M.max_co > 0.0) {
-            // face order as the cell Courant number is defined: x, y, z, high + low face
-            double sf = fabs((double)F.phin[0][fx_id(C, P.i + 1, P.j, P.k)]) +
-                        fabs((double)F.phin[0][fx_id(C, P.i, P.j, P.k)]);
-            sf += fabs((double)F.phin[1][fy_id(C, P.i, P.j + 1, P.k)]) +
-                  fabs((double)F.phin[1][fy_id(C, P.i, P.j, P.k)]);
-            if (C.dim == 3)
-                sf += fabs((double)F.phin[2][fz_id(C, P.i, P.j, P.k + 1)]) +
-                      fabs((double)F.phin[2][fz_id(C, P.i, P.j, P.k)]);
-            co_mx = fmax(co_mx, sf);
-        }
         const T Wp = F.Wc[g];
         const bool inj = P.j == 0 && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
                          P.k < C.inj_k0 + C.inj_nk;
@@ -487,7 +475,20 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             F.xt[k][g] = cn;
         }
     CLOT_END_CELLS
-    if (M.max_co > 0.0) {
+    if (M.max_co > 0.0) {   // a pass of its own: inside the loop above it doubles the register use
+        double co_mx = 0.0;
+        CLOT_FOR_CELLS(local)
+            const Cell P = cell_at(C, local);
+            // face order as the cell Courant number is defined: x, y, z, high + low face
+            double sf = fabs((double)F.phin[0][fx_id(C, P.i + 1, P.j, P.k)]) +
+                        fabs((double)F.phin[0][fx_id(C, P.i, P.j, P.k)]);
+            sf += fabs((double)F.phin[1][fy_id(C, P.i, P.j + 1, P.k)]) +
+                  fabs((double)F.phin[1][fy_id(C, P.i, P.j, P.k)]);
+            if (C.dim == 3)
+                sf += fabs((double)F.phin[2][fz_id(C, P.i, P.j, P.k + 1)]) +
+                      fabs((double)F.phin[2][fz_id(C, P.i, P.j, P.k)]);
+            co_mx = fmax(co_mx, sf);
+        CLOT_END_CELLS
         __shared__ double lds[NT / 64];
         co_mx = block_max(co_mx, lds);
         if (threadIdx.x == 0) F.co_part[tile] = co_mx;
