@@ -31,6 +31,8 @@ def compare(gpu, ref, tol, names=None):
             continue
         if n in VECTOR:
             den = np.sqrt(sum(np.linalg.norm(ref[c]) ** 2 for c in VECTOR[n] if c in ref))
+            size = sum(ref[c].size for c in VECTOR[n] if c in ref)
+            den = max(den, 1e-12 * SCALE[n] * np.sqrt(max(size, 1)))    # no flow: a zero vector
             worst[n] = np.linalg.norm(gpu[n] - ref[n]) / den
         else:
             worst[n] = rel_l2(gpu[n], ref[n], n)
