@@ -5,6 +5,8 @@
 #include "clot_mg.h"
 #include "clot_surr.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -95,14 +97,22 @@ struct clot_ctx {
 namespace {
 
 // Launch, bracketed by probe events when this phase is the one being timed.
+// A probed launch carries its start and stop events in the dispatch itself, so the
+// interval between them is the kernel's execution, as a profiler records it.
+template <typename F, typename... Args>
+static inline void probed_launch(hipEvent_t e0, hipEvent_t e1, F kernel, dim3 grid, dim3 block, uint32_t shmem,
+                                 hipStream_t stream, Args... args) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, e0, e1, 0u, args...);
+}
+
 #define CLOT_LAUNCH(id, ...)                                                     \
     do {                                                                         \
         const bool pr_ = (id) == probe_id && !capturing && ev_used + 2 <= (int)evs.size(); \
-        if (pr_) (void)hipEventRecord(evs[ev_used], st);                         \
-        hipLaunchKernelGGL(__VA_ARGS__);                                         \
         if (pr_) {                                                               \
-            (void)hipEventRecord(evs[ev_used + 1], st);                          \
+            probed_launch(evs[ev_used], evs[ev_used + 1], __VA_ARGS__);          \
             ev_used += 2;                                                        \
+        } else {                                                                 \
+            hipLaunchKernelGGL(__VA_ARGS__);                                     \
         }                                                                        \
     } while (0)
 
