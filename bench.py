@@ -87,7 +87,8 @@ def copy_calibration(mib):
 
 def cpu_baseline(desc):
     """FP64 oracle on a bounded sample: the same channel geometry, shear and seed on a
-    grid 4x coarser per axis, 2 steps; reported as cell-timesteps/s."""
+    grid 4x coarser per axis, 5 timed steps (about 10 s of one core); reported as
+    cell-timesteps/s."""
     import numpy as np
     import clot_inputs as ci
     from oracle import clot_oracle as oc
@@ -101,7 +102,7 @@ def cpu_baseline(desc):
     xc, xf = ci.noise(d)
     o = oc.Oracle(d, xc, xf)
     o.step()                        # first step outside the timing (imports, caches)
-    n = 2
+    n = 5
     t0 = time.perf_counter()
     for _ in range(n):
         o.step()

@@ -77,6 +77,18 @@ def test_fp32_mixed_2d_50_steps():
                                  "E2B", "C1", "C2", "E0", "C0"])
 
 
+def test_fp32_mixed_3d_ragged_20_steps():
+    """The FP32 path on a ragged 3-D duct (tiles cut across rows and planes)."""
+    from paper_2304_09180_amd import clot
+    d = ci.channel(3, 24, 10, 9, shear=800.0, seed=5)
+    (g,), (st,) = run_gpu([d], clot.FP32_MIXED, 20)
+    print(st, flush=True)
+    ref = run_oracle(d, 20)
+    assert velocity_err(g, ref, 3) < 1e-5
+    compare(g, ref, 1e-5, names=["PMU", "PMA", "PBA", "PBSE", "ADP", "S1", "S2", "E1", "E2", "S1B", "S2B", "E1B",
+                                 "E2B", "C1", "C2", "E0", "C0"])
+
+
 def test_fp64_batched_uneven_channels_match_single_runs():
     from paper_2304_09180_amd import clot
     ds = [ci.channel(2, 32, 8, shear=300.0, steps=3, seed=11, inj_frac=0.3),
