@@ -146,3 +146,42 @@ def test_surrogate_step_parity_gain_and_fallback(trained):
     # with a zero tolerance every changed cell is recomputed by the plain RK4 step
     for n in names + ["PMA", "PBA", "E2", "C1", "C2"]:
         assert np.array_equal(allfb[n], plain[n]), n
+
+
+def test_surrogate_under_crank_nicolson_and_variable_step(trained):
+    """The learned step under the time options (its features carry log dt, here set by
+    the Courant limit): against the oracle at the surrogate tolerance, and bit for bit
+    the plain step when every cell falls back."""
+    from oracle import clot_oracle as oc
+    from paper_2304_09180_amd import clot
+    tr = trained[0]
+    d = ci.channel(2, 64, 16, shear=1000.0, dt=4e-4, seed=6)
+    steps = 40
+    over = dict(ddt_psi=0.9, max_co=0.75)
+    xc, xf = ci.noise(d)
+    o = oc.Oracle(d, xc, xf, oc.Params(**over))
+    for _ in range(steps):
+        o.step()
+    ref = o.fields()
+
+    def run(blob, tol):
+        s = clot.Solver([d], clot.FP32_MIXED, clot.default_params(clot.FP32_MIXED, **over))
+        s.init_state(0, xc, xf)
+        if blob is not None:
+            s.set_reaction_mode(clot.SURROGATE, blob, tol)
+        s.step(steps)
+        out, st = s.fields(0), s.stats(0)
+        s.close()
+        return out, st
+    plain, st_p = run(None, 0.0)
+    surr, st_s = run(tr.blob(), 1e-3)
+    allfb, _ = run(tr.blob(), 0.0)
+    print("dt", st_s["dt"], "oracle dt", o.dt, "fallback", st_s["fallback_frac"])
+    assert st_s["dt"] == pytest.approx(o.dt, rel=1e-4)
+
+    def err(a, name):
+        return np.linalg.norm(a[name] - ref[name]) / max(np.linalg.norm(ref[name]), 1e-300)
+    for n in ["UX", "PMU", "PBSE", "S1", "S2", "E1", "S1B", "S2B"]:
+        assert err(surr, n) <= 1e-3, (n, err(surr, n))
+    for n in ["UX", "PMU", "PMA", "PBA", "PBSE", "S1", "S2", "E1", "E2", "S1B", "S2B", "C1", "C2"]:
+        assert np.array_equal(allfb[n], plain[n]), n
