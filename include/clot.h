@@ -46,6 +46,8 @@ typedef enum {
     CLOT_OK = 0,
     CLOT_W_NOTCONV = 1,     /* a linear solve stopped at max_iter; the step completed        */
     CLOT_W_FALLBACK = 2,    /* surrogate step: some cells fell back to the plain integrator  */
+    CLOT_W_NONFINITE = 3,   /* a linear solve met a NaN or infinity (in the fields or its
+                               system) and stopped; the fields are not valid                 */
     CLOT_EINVAL = -1,       /* bad argument                                                  */
     CLOT_ENOMEM = -2,       /* workspace too small                                           */
     CLOT_EWORKSPACE = -3,   /* workspace pointer misaligned                                  */
@@ -179,7 +181,21 @@ clot_status clot_step(clot_ctx* c, int32_t nsteps);
 clot_status clot_step_async(clot_ctx* c, int32_t nsteps);
 clot_status clot_sync(clot_ctx* c);
 
+/* Statistics of channel ch's last step.  Returns CLOT_OK, or the worst warning of any
+ * step since the channel's last clot_init_state: CLOT_W_NOTCONV, CLOT_W_NONFINITE. */
 clot_status clot_get_stats(const clot_ctx* c, int32_t ch, clot_stats* s);
+
+/* Checkpoint and resume.  A context's state is its device workspace and its host side
+ * (channel clocks and step counts, buffer parity, solver budgets, reaction mode); it
+ * goes to and from a host blob of clot_state_size bytes, owned by the caller.
+ * clot_load_state accepts a blob saved from a context created with the same channels
+ * (dimensions and grids), precision and workspace size, else CLOT_EINVAL and the
+ * context is unchanged; the model parameters remain the loading context's.  Both calls
+ * wait for the context's streams; recorded graphs are dropped on load (graph mode
+ * calibrates again).  Steps after a load continue bit for bit as from the saved one. */
+clot_status clot_state_size(const clot_ctx* c, size_t* bytes);
+clot_status clot_save_state(clot_ctx* c, void* host, size_t bytes);
+clot_status clot_load_state(clot_ctx* c, const void* host, size_t bytes);
 
 /* Selects the reaction integrator.  mode CLOT_RXN_SURROGATE takes a weight blob
  * (layout of clot_mlp_layout) and a residual threshold; a cell whose residual

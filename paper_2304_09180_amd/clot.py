@@ -31,7 +31,7 @@ FIELDS = ["UX", "UY", "UZ", "P", "PHIX", "PHIY", "PHIZ",
 FIELD = {n: i for i, n in enumerate(FIELDS)}
 SPECIES_FIELDS = FIELDS[7:22]
 
-STATUS = {0: "OK", 1: "W_NOTCONV", 2: "W_FALLBACK", -1: "EINVAL", -2: "ENOMEM", -3: "EWORKSPACE",
+STATUS = {0: "OK", 1: "W_NOTCONV", 2: "W_FALLBACK", 3: "W_NONFINITE", -1: "EINVAL", -2: "ENOMEM", -3: "EWORKSPACE",
           -4: "EHIP", -5: "ESTATE", -6: "ENAN"}
 
 
@@ -103,6 +103,9 @@ def load(tile: int = 256):
         "clot_step_async": ([P, C.c_int32], C.c_int),
         "clot_sync": ([P], C.c_int),
         "clot_get_stats": ([P, C.c_int32, C.POINTER(Stats)], C.c_int),
+        "clot_state_size": ([P, C.POINTER(C.c_size_t)], C.c_int),
+        "clot_save_state": ([P, P, C.c_size_t], C.c_int),
+        "clot_load_state": ([P, P, C.c_size_t], C.c_int),
         "clot_set_reaction_mode": ([P, C.c_int, P, C.c_size_t, C.c_double], C.c_int),
         "clot_probe": ([P, C.c_int32], C.c_int),
         "clot_probe_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
@@ -259,6 +262,19 @@ class Solver:
                 "it_tr": s.it_tr, "refine_p": list(s.refine_p), "res_mom": s.res_mom, "res_p": s.res_p,
                 "res_eta": s.res_eta, "res_tr": s.res_tr, "fallback_frac": s.fallback_frac, "steps": s.steps,
                 "t": s.t, "dt": s.dt}
+
+    def save_state(self) -> np.ndarray:
+        """The context's state (device workspace and host side) as a uint8 host array."""
+        n = C.c_size_t(0)
+        _check(self.lib, self.ctx, self.lib.clot_state_size(self.ctx, C.byref(n)), "state_size")
+        buf = np.empty(int(n.value), dtype=np.uint8)
+        _check(self.lib, self.ctx, self.lib.clot_save_state(self.ctx, buf.ctypes.data, buf.size), "save_state")
+        return buf
+
+    def load_state(self, buf) -> None:
+        """Restores a state saved from a context of the same channels and precision."""
+        b = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(self.lib, self.ctx, self.lib.clot_load_state(self.ctx, b.ctypes.data, b.size), "load_state")
 
     def set_reaction_mode(self, mode, blob=None, tol=1e-3):
         """PLAIN, or SURROGATE with a float32 blob (MLP parameters + 28 scales)."""

@@ -92,6 +92,9 @@ struct clot_ctx {
     virtual clot_status probe_read(double* ms, int64_t* n) = 0;
     virtual clot_status set_graph(int on, double scale, int pad) = 0;
     virtual clot_status graph_info(int64_t* info) = 0;
+    virtual clot_status state_size(size_t* bytes) const = 0;
+    virtual clot_status save_state(void* host, size_t bytes) = 0;
+    virtual clot_status load_state(const void* host, size_t bytes) = 0;
 };
 
 namespace {
@@ -137,6 +140,8 @@ struct Ctx : clot_ctx {
     // device tables
     ChanDev* d_ch = nullptr;
     std::vector<ChanDev> hch;   // host copy of the channel table as uploaded (clock reset)
+    char* ws_base = nullptr;    // the caller's workspace (every device array of the context)
+    size_t ws_bytes = 0;
     int32_t* d_t2c = nullptr;
     int32_t* d_f2c = nullptr;
     Fields<T> F{};
@@ -796,6 +801,10 @@ struct Ctx : clot_ctx {
         if ((s = upload(F.thB_prev + h.c0, thb))) return s;
         h.t = 0.0;
         h.n = 0;
+        {   // statistics (and the failure status they carry) start afresh
+            const std::vector<double> zs(NSTAT, 0.0);
+            HIPCHK(hipMemcpy(dstats + (size_t)c * NSTAT, zs.data(), NSTAT * 8, hipMemcpyHostToDevice));
+        }
         // the clock: the channel's step, or with a variable step the largest the initial
         // flux allows (cell Courant number 0.5 dt sum_f |phi_f| / V, x faces only carry
         // flux); implicit Euler first; no time-derivative history
@@ -1587,6 +1596,118 @@ struct Ctx : clot_ctx {
         info[19] = g_segs;
         return CLOT_OK;
     }
+    // ---- checkpoint and resume ----------------------------------------------------
+    struct StateHead {
+        uint64_t magic;
+        int32_t version, prec, nch, parity;
+        int64_t N, NFX, NFY, NFZ, NINJ, ntiles, ws;
+        int32_t eta_budget, rxn_mode;
+        float surr_tol, pad;
+        int32_t last_it[8];
+        SurrTables surr_tb;
+    };
+    struct StateChan {
+        int64_t n;
+        double t;
+        int32_t dim, nx, ny, nz;
+    };
+    static constexpr uint64_t STATE_MAGIC = 0x54415453544f4c43ull;   // "CLOTSTAT"
+    clot_status state_size(size_t* bytes) const override {
+        *bytes = sizeof(StateHead) + ch.size() * sizeof(StateChan) + ws_bytes;
+        return CLOT_OK;
+    }
+    clot_status save_state(void* host, size_t bytes) override {
+        size_t need = 0;
+        state_size(&need);
+        if (!host || bytes < need) {
+            err = "save_state: buffer of " + std::to_string(need) + " bytes needed";
+            return CLOT_EINVAL;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (st2) HIPCHK(hipStreamSynchronize(st2));
+        StateHead h{};
+        h.magic = STATE_MAGIC;
+        h.version = 1;
+        h.prec = (int32_t)prec;
+        h.nch = (int32_t)ch.size();
+        h.parity = parity;
+        h.N = N;
+        h.NFX = NFX;
+        h.NFY = NFY;
+        h.NFZ = NFZ;
+        h.NINJ = NINJ;
+        h.ntiles = ntiles;
+        h.ws = (int64_t)ws_bytes;
+        h.eta_budget = eta_budget;
+        h.rxn_mode = (int32_t)rxn_mode;
+        h.surr_tol = surr_tol;
+        for (int i = 0; i < 8; ++i) h.last_it[i] = last_it[i];
+        h.surr_tb = surr_tb;
+        char* p = static_cast<char*>(host);
+        std::memcpy(p, &h, sizeof(h));
+        p += sizeof(h);
+        for (const ChanHost& c : ch) {
+            StateChan sc{c.n, c.t, c.d.dim, c.d.nx, c.d.ny, c.d.nz};
+            std::memcpy(p, &sc, sizeof(sc));
+            p += sizeof(sc);
+        }
+        HIPCHK(hipMemcpy(p, ws_base, ws_bytes, hipMemcpyDeviceToHost));
+        return CLOT_OK;
+    }
+    clot_status load_state(const void* host, size_t bytes) override {
+        size_t need = 0;
+        state_size(&need);
+        if (!host || bytes < need) {
+            err = "load_state: blob of " + std::to_string(need) + " bytes expected";
+            return CLOT_EINVAL;
+        }
+        StateHead h;
+        const char* p = static_cast<const char*>(host);
+        std::memcpy(&h, p, sizeof(h));
+        p += sizeof(h);
+        if (h.magic != STATE_MAGIC || h.version != 1 || h.prec != (int32_t)prec || h.nch != (int32_t)ch.size() ||
+            h.N != N || h.NFX != NFX || h.NFY != NFY || h.NFZ != NFZ || h.NINJ != NINJ || h.ntiles != ntiles ||
+            h.ws != (int64_t)ws_bytes || (h.parity != 0 && h.parity != 1)) {
+            err = "load_state: the blob was saved from a context of another layout";
+            return CLOT_EINVAL;
+        }
+        std::vector<StateChan> sc(ch.size());
+        for (size_t i = 0; i < ch.size(); ++i) {
+            std::memcpy(&sc[i], p, sizeof(StateChan));
+            p += sizeof(StateChan);
+            const clot_channel& d = ch[i].d;
+            if (sc[i].dim != d.dim || sc[i].nx != d.nx || sc[i].ny != d.ny || sc[i].nz != d.nz) {
+                err = "load_state: channel " + std::to_string(i) + " differs from the saved one";
+                return CLOT_EINVAL;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (st2) HIPCHK(hipStreamSynchronize(st2));
+        drop_graphs();
+        HIPCHK(hipMemcpy(ws_base, p, ws_bytes, hipMemcpyHostToDevice));
+        for (size_t i = 0; i < ch.size(); ++i) {
+            ch[i].n = sc[i].n;
+            ch[i].t = sc[i].t;
+        }
+        if (parity != h.parity) {   // the buffer pair that holds the current flux and theta_B
+            std::swap(F.thB, F.thB_prev);
+            for (int c = 0; c < 3; ++c) std::swap(F.phi[c], F.phin[c]);
+            parity = h.parity;
+        }
+        eta_budget = h.eta_budget;
+        for (int i = 0; i < 8; ++i) last_it[i] = h.last_it[i];
+        rxn_mode = (clot_rxn_mode)h.rxn_mode;
+        surr_tol = h.surr_tol;
+        surr_tb = h.surr_tb;
+        if (graph_on) {             // budgets are measured again
+            for (int& m : it_max) m = 0;
+            for (auto& r : it_pmax)
+                for (int& m : r) m = 0;
+            calib_left = 2;
+        }
+        return CLOT_OK;
+    }
+
     clot_status stats(int c, clot_stats* s) const override {
         std::vector<double> v(NSTAT);
         if (hipMemcpy(v.data(), dstats + (size_t)c * NSTAT, NSTAT * 8, hipMemcpyDeviceToHost) != hipSuccess) return CLOT_EHIP;
@@ -1611,7 +1732,7 @@ struct Ctx : clot_ctx {
             return CLOT_EHIP;
         s->t = sg.t;
         s->dt = cd.dt;
-        return v[ST_FAIL] > 0 ? CLOT_W_NOTCONV : CLOT_OK;
+        return v[ST_FAIL] >= 2 ? CLOT_W_NONFINITE : v[ST_FAIL] > 0 ? CLOT_W_NOTCONV : CLOT_OK;
     }
 };
 
@@ -1661,6 +1782,8 @@ static clot_status create_t(Ctx<T>* c, const clot_channel* chs, int n_ch, const 
         return CLOT_EWORKSPACE;
     }
     c->layout((char*)ws);
+    c->ws_base = (char*)ws;
+    c->ws_bytes = need;
     c->st = (hipStream_t)stream;
     hipError_t he = hipHostMalloc((void**)&c->h_nact, 64, hipHostMallocDefault);
     if (he != hipSuccess) {
@@ -1820,6 +1943,18 @@ clot_status clot_sync(clot_ctx* c) {
 clot_status clot_get_stats(const clot_ctx* c, int32_t chn, clot_stats* s) {
     if (!c || !s) return CLOT_EINVAL;
     return c->stats(chn, s);
+}
+clot_status clot_state_size(const clot_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return CLOT_EINVAL;
+    return c->state_size(bytes);
+}
+clot_status clot_save_state(clot_ctx* c, void* host, size_t bytes) {
+    if (!c) return CLOT_EINVAL;
+    return c->save_state(host, bytes);
+}
+clot_status clot_load_state(clot_ctx* c, const void* host, size_t bytes) {
+    if (!c) return CLOT_EINVAL;
+    return c->load_state(host, bytes);
 }
 clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* blob, size_t nb, double tol) {
     if (!c) return CLOT_EINVAL;

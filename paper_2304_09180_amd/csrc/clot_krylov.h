@@ -88,7 +88,21 @@ __global__ __launch_bounds__(FIN_BS) void k_finish(const ChanDev* chans, KState 
         KState SL = S;
         SL.sc = scl;
         SL.sc_ch0 = chid;
-        epi(acc, SL, chid);
+        bool finite = true;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) finite = finite && isfinite(acc[q]);
+        if (finite) {
+            epi(acc, SL, chid);
+        } else {
+            // a NaN or infinity reached the reductions: the channel's systems stop,
+            // marked failed (2), and the channel leaves the solve
+            for (int k = 0; k < MAXK; ++k) {
+                double* s = scp(SL, chid, k);
+                s[SC_FAIL] = 2.0;
+                s[SC_ACT] = 0.0;
+            }
+            S.chact[chid] = 0;
+        }
     }
     __syncthreads();
     for (int q = threadIdx.x; q < MAXK * NSC; q += FIN_BS) scg[q] = scl[q];
