@@ -137,6 +137,10 @@ typedef struct {
     int64_t steps;
     double t;                                   /* simulated time                            */
     double dt;                                  /* step the next clot_step takes             */
+    double div_rel;                             /* largest |net outflow| of a cell over the
+                                                   largest face flux (discrete continuity)   */
+    double min_species;                         /* smallest species value over its scale
+                                                   (P_max, ADP*, S1_0, S2_0): < 0 if negative */
 } clot_stats;
 
 typedef struct clot_ctx clot_ctx;

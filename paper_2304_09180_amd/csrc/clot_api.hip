@@ -24,7 +24,7 @@ constexpr int NPART = 24;            // max partial sums per tile
 constexpr int NSTAT = 40;            // per-channel statistics slots
 constexpr int MAXCORR = 8;
 enum { ST_MOM = 0, ST_ETA = 1, ST_TR = 2, ST_P = 3 /* +corr */, ST_REF = 12 /* +corr */, ST_RESM = 21, ST_RESP = 22,
-       ST_RESE = 23, ST_REST = 24, ST_FAIL = 25, ST_FALLBACK = 26 };
+       ST_RESE = 23, ST_REST = 24, ST_FAIL = 25, ST_FALLBACK = 26, ST_DIAG = 27 /* div, |phi| max, min species */ };
 
 struct Carver {
     char* base;
@@ -1709,6 +1709,11 @@ struct Ctx : clot_ctx {
     }
 
     clot_status stats(int c, clot_stats* s) const override {
+        // diagnostics of the current state, after whatever the context stream holds
+        hipLaunchKernelGGL(k_diag_tiles<T>, dim3(ntiles), dim3(NT), 0, st, grid(), F, M, S.part);
+        hipLaunchKernelGGL(k_diag_finish, dim3((int)ch.size()), dim3(256), 0, st, d_ch, (const double*)S.part, dstats,
+                           NSTAT, (int)ST_DIAG);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return CLOT_EHIP;
         std::vector<double> v(NSTAT);
         if (hipMemcpy(v.data(), dstats + (size_t)c * NSTAT, NSTAT * 8, hipMemcpyDeviceToHost) != hipSuccess) return CLOT_EHIP;
         std::memset(s, 0, sizeof(*s));
@@ -1732,6 +1737,8 @@ struct Ctx : clot_ctx {
             return CLOT_EHIP;
         s->t = sg.t;
         s->dt = cd.dt;
+        s->div_rel = v[ST_DIAG + 1] > 0.0 ? v[ST_DIAG] / v[ST_DIAG + 1] : v[ST_DIAG];
+        s->min_species = v[ST_DIAG + 2];
         return v[ST_FAIL] >= 2 ? CLOT_W_NONFINITE : v[ST_FAIL] > 0 ? CLOT_W_NOTCONV : CLOT_OK;
     }
 };

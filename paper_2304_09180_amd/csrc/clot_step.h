@@ -692,6 +692,64 @@ __global__ void k_count_active(const int32_t* chact, int32_t* nact, int nch) {
     }
 }
 
+// On-demand diagnostics of the current state, per tile: the largest |net outflow| of a
+// cell (discrete continuity, section 3.2), the largest face-flux magnitude and the
+// smallest species value over its scale (non-negativity).
+template <class T>
+__global__ __launch_bounds__(NT) void k_diag_tiles(Grid G, Fields<T> F, ModelDev M, double* part) {
+    CLOT_TILE_PROLOGUE(G)
+    const double sc[NSPC] = {M.P_max, M.P_max, M.P_max, M.P_max, M.adp_crit, M.S1_0, M.S2_0, M.S1_0, M.S2_0,
+                             M.S1_0, M.S2_0, M.S1_0, M.S2_0, M.S2_0, M.S2_0};
+    double dmax = 0.0, fmx = 0.0, smin = 1e300;
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const double fw = F.phi[0][fx_id(C, P.i, P.j, P.k)], fe = F.phi[0][fx_id(C, P.i + 1, P.j, P.k)];
+        const double fs = F.phi[1][fy_id(C, P.i, P.j, P.k)], fn = F.phi[1][fy_id(C, P.i, P.j + 1, P.k)];
+        double div = (fe - fw) + (fn - fs);
+        double m = fmax(fmax(fabs(fw), fabs(fe)), fmax(fabs(fs), fabs(fn)));
+        if (C.dim == 3) {
+            const double fb = F.phi[2][fz_id(C, P.i, P.j, P.k)], ff = F.phi[2][fz_id(C, P.i, P.j, P.k + 1)];
+            div += ff - fb;
+            m = fmax(m, fmax(fabs(fb), fabs(ff)));
+        }
+        dmax = fmax(dmax, fabs(div));
+        fmx = fmax(fmx, m);
+#pragma unroll
+        for (int q = 0; q < NSPC; ++q) smin = fmin(smin, (double)F.spc[q][P.g] / sc[q]);
+    CLOT_END_CELLS
+    __shared__ double lds[NT / 64];
+    dmax = block_max(dmax, lds);
+    fmx = block_max(fmx, lds);
+    smin = -block_max(-smin, lds);
+    if (threadIdx.x == 0) {
+        part[3 * (int64_t)tile] = dmax;
+        part[3 * (int64_t)tile + 1] = fmx;
+        part[3 * (int64_t)tile + 2] = smin;
+    }
+}
+
+// The channel's diagnostics from its tiles (one block per channel) into its statistics.
+__global__ __launch_bounds__(256) void k_diag_finish(const ChanDev* chans, const double* part, double* stats,
+                                                     int nstat, int slot) {
+    __shared__ double lds[4];
+    const int c = blockIdx.x;
+    const int32_t t0 = chans[c].t0, nt = chans[c].nt;
+    double d = 0.0, f = 0.0, s = 1e300;
+    for (int t = threadIdx.x; t < nt; t += 256) {
+        d = fmax(d, part[3 * (int64_t)(t0 + t)]);
+        f = fmax(f, part[3 * (int64_t)(t0 + t) + 1]);
+        s = fmin(s, part[3 * (int64_t)(t0 + t) + 2]);
+    }
+    d = block_max<256>(d, lds);
+    f = block_max<256>(f, lds);
+    s = -block_max<256>(-s, lds);
+    if (threadIdx.x == 0) {
+        stats[(int64_t)c * nstat + slot] = d;
+        stats[(int64_t)c * nstat + slot + 1] = f;
+        stats[(int64_t)c * nstat + slot + 2] = s;
+    }
+}
+
 // Copies Krylov outcomes of the last solve into the per-channel statistics.
 // Records one solve's iteration count, residual and failure flag per channel; with
 // `mask`, only channels whose mask entry is set took part in the solve.
