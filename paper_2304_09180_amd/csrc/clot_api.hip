@@ -66,12 +66,7 @@ struct ChanHost {
     int64_t c0, ncell, fx0, fy0, fz0, nfx, nfy, nfz, in0, inj0;
     int32_t ninj, inj_i0, inj_ni, inj_k0, inj_nk, jadh, t0, nt, ncorr;
     double dx, dy, dz;
-    double t = 0.0;
-    int64_t n = 0;
-    int64_t next_push = 0;
-    double hist_t[NHIST];
-    int head = -1;           // slot of the newest snapshot
-    int npushed = 0;
+    int64_t n = 0;           // steps taken (the clock itself lives on the device)
 };
 
 }  // namespace
@@ -489,7 +484,6 @@ struct Ctx : clot_ctx {
                                     : (Dn <= 10.0 ? 2 : Dn <= 30.0 ? 3 : Dn <= 50.0 ? 4 : Dn <= 80.0 ? 5 : Dn <= 120.0 ? 6 : 8);
             if (h.ncorr > MAXCORR) h.ncorr = MAXCORR;
             maxcorr = std::max(maxcorr, h.ncorr);
-            for (int q = 0; q < NHIST; ++q) h.hist_t[q] = -1e300;
         }
         N = c0;
         NFX = fx;
@@ -799,7 +793,6 @@ struct Ctx : clot_ctx {
         // theta_B of the "previous" step = current
         std::vector<double> thb(n, 0.0);
         if ((s = upload(F.thB_prev + h.c0, thb))) return s;
-        h.t = 0.0;
         h.n = 0;
         {   // statistics (and the failure status they carry) start afresh
             const std::vector<double> zs(NSTAT, 0.0);
@@ -1413,7 +1406,6 @@ struct Ctx : clot_ctx {
         parity ^= 1;
         for (ChanHost& h : ch) {
             h.n += 1;
-            h.t = h.n * h.d.dt;
         }
     }
 
@@ -1608,7 +1600,7 @@ struct Ctx : clot_ctx {
     };
     struct StateChan {
         int64_t n;
-        double t;
+        double t;     // the channel's simulated time (informative: the clock is in the workspace)
         int32_t dim, nx, ny, nz;
     };
     static constexpr uint64_t STATE_MAGIC = 0x54415453544f4c43ull;   // "CLOTSTAT"
@@ -1643,11 +1635,14 @@ struct Ctx : clot_ctx {
         h.surr_tol = surr_tol;
         for (int i = 0; i < 8; ++i) h.last_it[i] = last_it[i];
         h.surr_tb = surr_tb;
+        std::vector<SigState> clocks(ch.size());
+        HIPCHK(hipMemcpy(clocks.data(), sig, ch.size() * sizeof(SigState), hipMemcpyDeviceToHost));
         char* p = static_cast<char*>(host);
         std::memcpy(p, &h, sizeof(h));
         p += sizeof(h);
-        for (const ChanHost& c : ch) {
-            StateChan sc{c.n, c.t, c.d.dim, c.d.nx, c.d.ny, c.d.nz};
+        for (size_t i = 0; i < ch.size(); ++i) {
+            const ChanHost& c = ch[i];
+            StateChan sc{c.n, clocks[i].t, c.d.dim, c.d.nx, c.d.ny, c.d.nz};
             std::memcpy(p, &sc, sizeof(sc));
             p += sizeof(sc);
         }
@@ -1687,7 +1682,6 @@ struct Ctx : clot_ctx {
         HIPCHK(hipMemcpy(ws_base, p, ws_bytes, hipMemcpyHostToDevice));
         for (size_t i = 0; i < ch.size(); ++i) {
             ch[i].n = sc[i].n;
-            ch[i].t = sc[i].t;
         }
         if (parity != h.parity) {   // the buffer pair that holds the current flux and theta_B
             std::swap(F.thB, F.thB_prev);
