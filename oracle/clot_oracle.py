@@ -48,6 +48,10 @@ RXN = ["Pmu", "Pma", "Pba", "Pbse", "S1", "S2", "E1", "E2",
        "S1b", "S2b", "E1b", "E2b", "C1", "C2"]
 # The 7 transported scalars (bound species do not move).
 TRANSPORTED = ["Pmu", "Pma", "S1", "S2", "E1", "E2", "ADP"]
+# The extensibility example (section 4.3): a fluid-phase inhibitor I that binds thrombin
+# for good, I + E2 -> E2i.  Both new species are transported and react; they follow the
+# 15 species above, whose indices do not change.
+INHIBITOR_SPECIES = ["I", "E2i"]
 
 
 @dataclass
@@ -107,6 +111,11 @@ class Params:
     ddt_psi: float = 0.0
     max_co: float = 0.0
     dt_growth: float = 1.2
+    # the inhibitor variant (section 4.3 names the reaction, not its constants): an
+    # antithrombin-like inlet and initial concentration and association rate
+    inhibitor: bool = False
+    k_I: float = 7.1               # (nmol/mm^3)^-1 s^-1
+    I_0: float = 3.4e-3            # nmol/mm^3
 
 
 # --------------------------------------------------------------------------------------
@@ -333,14 +342,15 @@ def solve(M, b, spd):
 # --------------------------------------------------------------------------------------
 
 def reaction_rhs(y, adp, gam, hadh, p: Params):
-    """d/dt of the 14 reacting species (RXN order) with ADP, g(eta) and H_adh frozen.
+    """d/dt of the 14 reacting species (RXN order; 16 with the inhibitor, I and E2i last)
+    with ADP, g(eta) and H_adh frozen.
 
     Platelets (Appendix A, eqs. Pmu..Pbse): adhesion k_adh H_adh (Pmax - Pbse),
     activation A1(ADP)+A2(E2) with Hill functions, cohesion kcoh Pmax g(eta).
     Coagulation (Appendix B, reactions reactionFirst..reactionFeedback2) by mass
     action with binding-site totals N1/N_A (Pba+Pbse) and N2/N_A (Pba+Pbse).
     """
-    Pmu, Pma, Pba, Pbse, S1, S2, E1, E2, S1b, S2b, E1b, E2b, C1, C2 = y
+    Pmu, Pma, Pba, Pbse, S1, S2, E1, E2, S1b, S2b, E1b, E2b, C1, C2 = y[:14]
     adh = p.k_adh * hadh * (p.P_max - Pbse)
     act = p.k_adp * adp / (p.adp_crit + adp) + p.k_e2 * E2 / (p.e2_crit + E2)
     coh = p.kcoh_Pmax * gam
@@ -352,7 +362,8 @@ def reaction_rhs(y, adp, gam, hadh, p: Params):
     bS2 = p.kS2p * B2 * S2 - p.kS2m * S2b
     bE1 = p.kE1p * B1 * E1 - p.kE1m * E1b
     bE2 = p.kE2p * B2 * E2 - p.kE2m * E2b
-    return np.array([
+    rI = p.k_I * y[14] * E2 if p.inhibitor else 0.0      # I + E2 -> E2i, mass action
+    rows = [
         -adh * Pmu - act * Pmu,
         -adh * Pma + act * Pmu - coh * Pma,
         -adh * Pba + coh * Pma,
@@ -360,14 +371,17 @@ def reaction_rhs(y, adp, gam, hadh, p: Params):
         -bS1,
         -bS2,
         -bE1,
-        -bE2,
+        -bE2 - rI,
         bS1 - c2f + p.kC2m * C2,
         bS2 - c1f + p.kC1m * C1,
         bE1 - c1f + (p.kC1m + p.kC1cat) * C1 + p.kC2cat * C2,
         bE2 - c2f + (p.kC2m + p.kC2cat) * C2 + p.kC1cat * C1,
         c1f - (p.kC1m + p.kC1cat) * C1,
         c2f - (p.kC2m + p.kC2cat) * C2,
-    ])
+    ]
+    if p.inhibitor:
+        rows += [-rI, rI]
+    return np.array(rows)
 
 
 def rk4(f, y, h, nsub):
@@ -411,6 +425,11 @@ class Oracle:
         self.p = params or Params()
         self.m = Mesh(desc)
         self.desc = desc
+        extra = INHIBITOR_SPECIES if self.p.inhibitor else []
+        self.species = SPECIES + extra
+        self.sp = {n: i for i, n in enumerate(self.species)}
+        self.transported = TRANSPORTED + extra
+        self.rxn = RXN + extra
         self.dt = desc["dt"]
         self.dt_max = desc["dt"]
         self._init_state(xi_cell, xi_face, inlet_u)
@@ -444,11 +463,14 @@ class Oracle:
         self.phi[0][:, :, m.nx] = m.axes[0][1] * u3[:, :, -1]
         if inlet_u is not None:
             self.phi[0][:, :, 0] = m.axes[0][1] * self.u_in.reshape(m.nz, m.ny)
-        c = np.zeros((len(SPECIES), m.n))
+        c = np.zeros((len(self.species), m.n))
         c[SP["Pmu"]] = platelet_inflow(m.yc, m.zc, self.desc, p)
         c[SP["S1"]] = p.S1_0
         c[SP["S2"]] = p.S2_0
-        self.c = c * (1.0 + 0.01 * xi_cell)
+        c[:len(SPECIES)] *= 1.0 + 0.01 * xi_cell
+        if p.inhibitor:
+            c[self.sp["I"]] = p.I_0            # no noise draws for the added species
+        self.c = c
         self.E0 = p.E0_0 * (1.0 + 0.01 * xi_face[0])
         self.C0 = np.zeros(m.nface) * (1.0 + 0.01 * xi_face[1])
         self.hadh = m.adhesion_mask(p)
@@ -464,7 +486,7 @@ class Oracle:
         self.dt = self.dt_max
         # stored time derivatives of the fields with a ddt term (Crank-Nicolson history)
         self.ddt0u = np.zeros((3, m.n))
-        self.ddt0c = {name: np.zeros(m.n) for name in TRANSPORTED}
+        self.ddt0c = {name: np.zeros(m.n) for name in self.transported}
         if p.max_co > 0.0:
             # a variable step starts at the largest step the initial flux allows
             co = self.courant()
@@ -732,7 +754,7 @@ class Oracle:
         k_dt, w_dt = self.ddt_coeffs()
         platelet = name in ("Pmu", "Pma")
         D = p.D_P if platelet else (p.D_ADP if name == "ADP" else p.D_chem)
-        Cn = self.c[SP[name]]
+        Cn = self.c[self.sp[name]]
         C3 = Cn.reshape(m.shape)
         T3 = thetaT.reshape(m.shape)
         S = System(m.n)
@@ -802,7 +824,7 @@ class Oracle:
                 Wlo = hindrance(thetaT[lo]) if platelet else 1.0
                 Whi = hindrance(thetaT[hi]) if platelet else 1.0
                 phi_out_in = -self.phi[a][:, :, 0].ravel()
-                fixed = {"Pmu": self.pmu_in, "S1": p.S1_0, "S2": p.S2_0}.get(name)
+                fixed = {"Pmu": self.pmu_in, "S1": p.S1_0, "S2": p.S2_0, "I": p.I_0}.get(name)
                 if fixed is not None:
                     Cb = np.broadcast_to(fixed, lo.shape)
                     g = 2.0 * Wlo * D * A / d
@@ -829,13 +851,13 @@ class Oracle:
         transport sub-step (from C^n to the transported value; the reactions that follow
         in the fractional step are not part of it)."""
         out = {}
-        for name in TRANSPORTED:
+        for name in self.transported:
             S = self.transport_system(name, thetaT)
             out[name] = solve(S.matrix(), S.rhs, spd=False)
         k_dt, w_dt = self.ddt_coeffs()
         for name, v in out.items():
-            self.ddt0c[name] = k_dt * (v - self.c[SP[name]]) / self.dt - w_dt * self.ddt0c[name]
-            self.c[SP[name]] = v
+            self.ddt0c[name] = k_dt * (v - self.c[self.sp[name]]) / self.dt - w_dt * self.ddt0c[name]
+            self.c[self.sp[name]] = v
 
     # ---- O-6 reactions ---------------------------------------------------------------------------
     def wall_value_S1(self):
@@ -857,7 +879,7 @@ class Oracle:
         gam = binding_affinity(self.eta, p)
         adp = self.c[SP["ADP"]]
         hadh = self.hadh
-        ids = [SP[s] for s in RXN]
+        ids = [self.sp[s] for s in self.rxn]
         y = rk4(lambda v: reaction_rhs(v, adp, gam, hadh, p), self.c[ids].copy(), h, p.M_rxn)
         self.c[ids] = y
 
@@ -891,6 +913,6 @@ class Oracle:
         if self.m.dim == 3:
             out["UZ"] = self.u[2].copy()
             out["PHIZ"] = self.phi[2].ravel().copy()
-        for n in SPECIES:
-            out[n.upper()] = self.c[SP[n]].copy()
+        for n in self.species:
+            out[n.upper()] = self.c[self.sp[n]].copy()
         return out
