@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
     ap.add_argument("--train-samples", type=int, default=400_000)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-inhibitor", action="store_true",
+                    help="skip the leg of the model with the inhibitor (section 4.3)")
     ap.add_argument("--no-time-scheme", action="store_true",
                     help="skip the Crank-Nicolson / variable-step leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -214,6 +216,26 @@ def time_scheme_leg(desc, prec, args, xc, xf, tile):
             "solver": {k: st[k] for k in ("it_mom", "it_p", "it_eta", "it_tr", "refine_p")}}
 
 
+def inhibitor_leg(desc, prec, args, xc, xf):
+    """The same workload with the inhibitor of section 4.3's extensibility example
+    (I + E2 -> E2i: 17 cell species, 9 transported, 16 reacting) from its own build:
+    cost per step next to the base model's, and the kernels the two species widen."""
+    import torch
+    from paper_2304_09180_amd import clot
+    s = clot.Solver([desc], prec, clot.default_params(prec), inhibitor=True)
+    s.init_state(0, xc, xf)
+    for _ in range(max(1, args.warmup)):
+        s.step(1)
+    el, _, _ = timed_steps(s, args.steps, args.probe)
+    st = s.stats(0)
+    us = {k: kernel_us(s, k) for k in ("rxn", "tr_asm", "tr_b1")}
+    s.close()
+    torch.cuda.synchronize()
+    return {"species": 17, "transported": 9, "tile": 256, "ms_per_step": round(el * 1e3 / args.steps, 4),
+            "kernel_us": us, "status": st["status"],
+            "solver": {k: st[k] for k in ("it_mom", "it_p", "it_eta", "it_tr", "refine_p")}}
+
+
 def ensemble_leg(args):
     """The 64-member uneven ensemble of 2-D channels in one context, FP32: eager steps,
     then the same steps replayed as HIP graphs."""
@@ -280,6 +302,7 @@ def main():
     st = s.stats(0)
     print(f"# timed {args.steps} steps: {el * 1e3:.1f} ms {st}", file=sys.stderr, flush=True)
     rxn_us = kernel_us(s, "rxn")
+    base_us = {k: kernel_us(s, k) for k in ("tr_asm", "tr_b1")}
     value = ncell * args.steps / el
     bpe = 4 if prec == clot.FP32_MIXED else 8
     nbytes = ARRAYS[args.probe](desc["dim"]) * bpe * ncell
@@ -301,12 +324,15 @@ def main():
                       "reaction": "plain RK4"},
            "solver": {k: st[k] for k in ("it_mom", "it_p", "it_eta", "it_tr", "refine_p")},
            "rxn_kernel_us": rxn_us,
+           "kernel_us": dict(base_us, rxn=rxn_us),
            "roofline": roof}
     if tuned:
         out["autotune"] = {"ms_per_step": tuned["ms_per_step"], "kernel_us": tuned["kernel_us"]}
     s.close()
     if not args.no_time_scheme:
         out["time_scheme"] = time_scheme_leg(desc, prec, args, xc, xf, tile)
+    if not args.no_inhibitor:
+        out["inhibitor"] = inhibitor_leg(desc, prec, args, xc, xf)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(desc, prec, args, xc, xf, tile)
     if not args.no_ensemble:

@@ -66,6 +66,10 @@ typedef enum {
     CLOT_E0, CLOT_C0,                                            /* injury-face species     */
     CLOT_ETA, CLOT_THETAB, CLOT_SIGMA,                           /* derived, read only      */
     CLOT_HADH,                                                   /* adhesion mask, read only */
+    CLOT_I, CLOT_E2I,            /* inhibitor build only (section 4.3, I + E2 -> E2i): the
+                                    inhibitor I and the inhibited thrombin E2i, both
+                                    transported and reacting; other builds refuse them
+                                    with CLOT_EINVAL                                      */
     CLOT_NFIELDS
 } clot_field;
 
@@ -123,6 +127,10 @@ typedef struct {
                              dt (default).  The corrector count (n_corr = 0) follows the
                              channel's dt.                                               */
     double dt_growth;     /* variable step: largest growth factor per step, >= 1 (default 1.2) */
+    double k_I;           /* inhibitor variant: rate of I + E2 -> E2i, (nmol/mm^3)^-1 s^-1,
+                             >= 0 (default 7.1); other builds ignore it                   */
+    double I_0;           /* inhibitor variant: inlet and initial I, nmol/mm^3, >= 0
+                             (default 3.4e-3); other builds ignore it                     */
 } clot_params;
 
 /* Per-channel statistics of the last step. */
@@ -211,6 +219,15 @@ clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* 
  * group of cells one 256-thread block owns, with its own partial sums.  The tile
  * size is a build option; the autotuner chooses among the built libraries. */
 int32_t clot_tile_cells(void);
+
+/* Cell species this library carries: 15 (the model of section 2 and Appendix B), or
+ * 17 for the inhibitor build (section 4.3's extensibility example), which appends the
+ * inhibitor I and the inhibited thrombin E2i (fields CLOT_I, CLOT_E2I).  That build
+ * solves 9 transport equations and 16 reaction equations; I has the fixed inlet value
+ * I_0 and starts there, E2i starts at zero, neither takes an initial-noise draw; its
+ * learned reaction step, clot_rxn_rk4_batch and clot_surr_dataset return CLOT_EINVAL
+ * (the network covers the base model's 14 reacting species). */
+int32_t clot_cell_species(void);
 
 /* Graph replay of whole steps (for ensembles stepped many times).
  * on != 0: the next two clot_step steps run as usual and record, per solve, the

@@ -15,9 +15,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 TILES = (256, 512, 1024)
 
 
-def lib_path(tile: int = 256) -> str:
-    """The library built for `tile` cells per block (see build.py)."""
-    return os.path.join(_HERE, "libclot.so" if tile == 256 else f"libclot_t{tile}.so")
+def lib_path(tile: int = 256, inhibitor: bool = False) -> str:
+    """The library built for `tile` cells per block, with the inhibitor model or
+    without (see build.py)."""
+    stem = "libclot_inh" if inhibitor else "libclot"
+    return os.path.join(_HERE, f"{stem}.so" if tile == 256 else f"{stem}_t{tile}.so")
 
 
 LIB_PATH = lib_path(256)
@@ -27,9 +29,11 @@ PLAIN, SURROGATE = 0, 1
 
 FIELDS = ["UX", "UY", "UZ", "P", "PHIX", "PHIY", "PHIZ",
           "PMU", "PMA", "PBA", "PBSE", "ADP", "S1", "S2", "E1", "E2",
-          "S1B", "S2B", "E1B", "E2B", "C1", "C2", "E0", "C0", "ETA", "THETAB", "SIGMA", "HADH"]
+          "S1B", "S2B", "E1B", "E2B", "C1", "C2", "E0", "C0", "ETA", "THETAB", "SIGMA", "HADH",
+          "I", "E2I"]                # the last two: inhibitor build only
 FIELD = {n: i for i, n in enumerate(FIELDS)}
 SPECIES_FIELDS = FIELDS[7:22]
+INHIBITOR_FIELDS = ["I", "E2I"]
 
 STATUS = {0: "OK", 1: "W_NOTCONV", 2: "W_FALLBACK", 3: "W_NONFINITE", -1: "EINVAL", -2: "ENOMEM", -3: "EWORKSPACE",
           -4: "EHIP", -5: "ESTATE", -6: "ENAN"}
@@ -56,7 +60,8 @@ class Params(C.Structure):
                  ("marg_m", C.c_int32), ("marg_n", C.c_int32),
                  ("rtol_p", C.c_double), ("rtol_s", C.c_double), ("rtol_inner", C.c_double),
                  ("mg_tail", C.c_int32), ("mg_sweeps", C.c_int32),
-                 ("ddt_psi", C.c_double), ("max_co", C.c_double), ("dt_growth", C.c_double)])
+                 ("ddt_psi", C.c_double), ("max_co", C.c_double), ("dt_growth", C.c_double),
+                 ("k_I", C.c_double), ("I_0", C.c_double)])
 
 
 class Stats(C.Structure):
@@ -74,14 +79,15 @@ class ClotError(RuntimeError):
 _libs = {}
 
 
-def load(tile: int = 256):
-    """Load the library built for `tile` cells per block; raises if it has not been
-    built."""
-    if tile in _libs:
-        return _libs[tile]
-    if tile not in TILES:
-        raise ClotError(f"no library for tile {tile}: choose one of {TILES}")
-    path = lib_path(tile)
+def load(tile: int = 256, inhibitor: bool = False):
+    """Load the library built for `tile` cells per block (with the inhibitor model:
+    256 only); raises if it has not been built."""
+    key = (tile, bool(inhibitor))
+    if key in _libs:
+        return _libs[key]
+    if tile not in TILES or (inhibitor and tile != 256):
+        raise ClotError(f"no library for tile {tile}{' with the inhibitor' if inhibitor else ''}")
+    path = lib_path(tile, inhibitor)
     if not os.path.exists(path):
         raise ClotError(f"HIP library not built: {path} (run __graft_entry__.build())")
     # One HIP runtime per process: torch's bundled runtime carries the soname this
@@ -122,6 +128,7 @@ def load(tile: int = 256):
         "clot_surr_dataset": ([C.POINTER(Params), P, P, C.c_int64, P, P, P, P, P], C.c_int),
         "clot_mfma_selftest": ([P, P, P, P], C.c_int),
         "clot_tile_cells": ([], C.c_int32),
+        "clot_cell_species": ([], C.c_int32),
         "clot_destroy": ([P], None),
         "clot_last_error": ([P], C.c_char_p),
     }
@@ -131,7 +138,9 @@ def load(tile: int = 256):
         f.restype = res
     if lib.clot_tile_cells() != tile:
         raise ClotError(f"{path} was built for {lib.clot_tile_cells()} cells per tile, not {tile}")
-    _libs[tile] = lib
+    if lib.clot_cell_species() != (17 if inhibitor else 15):
+        raise ClotError(f"{path} carries {lib.clot_cell_species()} species")
+    _libs[key] = lib
     return lib
 
 
@@ -141,7 +150,9 @@ def exported_symbols():
             "clot_set_field", "clot_get_field", "clot_step", "clot_step_async", "clot_sync", "clot_get_stats",
             "clot_set_reaction_mode", "clot_probe", "clot_probe_read", "clot_destroy", "clot_last_error",
             "clot_mlp_nparam", "clot_mlp_backward_workspace", "clot_mlp_forward", "clot_mlp_backward",
-            "clot_mlp_adam", "clot_mlp_mse", "clot_rxn_rk4_batch", "clot_surr_dataset", "clot_mfma_selftest"]
+            "clot_mlp_adam", "clot_mlp_mse", "clot_rxn_rk4_batch", "clot_surr_dataset", "clot_mfma_selftest",
+            "clot_cell_species", "clot_tile_cells", "clot_set_graph_mode", "clot_graph_info", "clot_state_size",
+            "clot_save_state", "clot_load_state"]
 
 
 PROBES = {"p_cg_a": 1, "p_cg_b": 2, "tr_b1": 3, "tr_b2": 4, "tr_b3": 5, "mom_b1": 6, "mom_b2": 7, "mom_b3": 8,
@@ -191,10 +202,12 @@ class Solver:
     stream (or the one passed in).
     """
 
-    def __init__(self, descs, precision=FP64, params: Params | None = None, device="cuda", stream=None, tile=256):
+    def __init__(self, descs, precision=FP64, params: Params | None = None, device="cuda", stream=None, tile=256,
+                 inhibitor=False):
         import torch
         self.tile = tile
-        self.lib = load(tile)
+        self.inhibitor = bool(inhibitor)
+        self.lib = load(tile, inhibitor)
         if not torch.cuda.is_available():
             raise ClotError("no GPU visible: the clotting-step library runs only on the GPU")
         self.descs = list(descs)
@@ -312,6 +325,8 @@ class Solver:
 
     def fields(self, ch=0):
         names = ["UX", "UY", "P", "PHIX", "PHIY", "E0", "C0", "ETA", "SIGMA"] + SPECIES_FIELDS
+        if self.inhibitor:
+            names += INHIBITOR_FIELDS
         if self.descs[ch]["dim"] == 3:
             names += ["UZ", "PHIZ"]
         return {n: self.get(ch, n) for n in names}

@@ -19,8 +19,8 @@ using namespace clot;
 
 namespace {
 
-constexpr int NPOOL = 7 + 7 * 7;     // Krylov vector pool (CG scratch + 7 BiCGStab systems)
-constexpr int NPART = 24;            // max partial sums per tile
+constexpr int NPOOL = 7 + 7 * NTR;   // Krylov vector pool (CG scratch + one BiCGStab set per transported species)
+constexpr int NPART = 3 * MAXK;      // max partial sums per tile
 constexpr int NSTAT = 40;            // per-channel statistics slots
 constexpr int MAXCORR = 8;
 enum { ST_MOM = 0, ST_ETA = 1, ST_TR = 2, ST_P = 3 /* +corr */, ST_REF = 12 /* +corr */, ST_RESM = 21, ST_RESP = 22,
@@ -262,6 +262,10 @@ struct Ctx : clot_ctx {
             rxn_mode = mode;
             return CLOT_OK;
         }
+#ifdef CLOT_INHIBITOR
+        err = "set_reaction_mode: the learned reaction step covers the base model's 14 reacting species only";
+        return CLOT_EINVAL;
+#endif
         if (mode != CLOT_RXN_SURROGATE || !blob || nb != (MLP_NPARAM + 2 * MLP_NSP) * sizeof(float) || !(tol >= 0.0)) {
             err = "set_reaction_mode: expected a float32 blob of MLP parameters + 28 scales and tol >= 0";
             return CLOT_EINVAL;
@@ -553,6 +557,8 @@ struct Ctx : clot_ctx {
         M.psi = q.ddt_psi;
         M.max_co = q.max_co;
         M.dt_growth = q.dt_growth;
+        M.k_I = q.k_I;
+        M.I_0 = q.I_0;
         return CLOT_OK;
     }
 
@@ -731,7 +737,7 @@ struct Ctx : clot_ctx {
     clot_status init_state(int c, const double* xc, size_t nc, const double* xf, size_t nf) override {
         ChanHost& h = ch[c];
         const int64_t n = h.ncell;
-        if (nc != (size_t)(NSPC * n) || nf != (size_t)(2 * h.ninj) || (!xc && nc) || (!xf && nf)) {
+        if (nc != (size_t)(NSPC_DRAWN * n) || nf != (size_t)(2 * h.ninj) || (!xc && nc) || (!xf && nf)) {
             err = "init_state: expected 15*ncell cell draws and 2*nface face draws";
             return CLOT_EINVAL;
         }
@@ -763,9 +769,14 @@ struct Ctx : clot_ctx {
         if ((s = upload(F.phi[0] + h.fx0, fxv))) return s;
         if ((s = upload(F.phi[1] + h.fy0, fyv))) return s;
         if (h.nfz && (s = upload(F.phi[2] + h.fz0, fzv))) return s;
-        // species with 1% multiplicative noise
+        // species with 1% multiplicative noise; the inhibitor variant's I starts at its
+        // inlet value and E2i at zero, neither with a draw
         for (int sp = 0; sp < NSPC; ++sp) {
-            std::vector<double> v(n, 0.0);
+            std::vector<double> v(n, sp == INH ? prm.I_0 : 0.0);
+            if (sp >= NSPC_DRAWN) {
+                if ((s = upload(F.spc[sp] + h.c0, v))) return s;
+                continue;
+            }
             for (int k = 0; k < h.d.nz; ++k)
                 for (int j = 0; j < h.d.ny; ++j) {
                     const double y = (j + 0.5) * h.dy, z = (k + 0.5) * h.dz;
@@ -860,16 +871,23 @@ struct Ctx : clot_ctx {
             case CLOT_THETAB: return {F.thB_prev + h.c0, n, false, true};
             case CLOT_SIGMA: return {F.sigma + h.c0, n, false, true};
             case CLOT_HADH: return {nullptr, n, false, true};
+#ifdef CLOT_INHIBITOR
+            case CLOT_I: return {F.spc[INH] + h.c0, n, false, false};
+            case CLOT_E2I: return {F.spc[E2I] + h.c0, n, false, false};
+#endif
             default:
                 if (f >= CLOT_PMU && f <= CLOT_C2) return {F.spc[f - CLOT_PMU] + h.c0, n, false, false};
         }
         return {nullptr, 0, false, true};
     }
 
+    static bool unknown(const FieldRef& r, clot_field f) {
+        return !r.ptr && r.n == 0 && f != CLOT_UZ && f != CLOT_PHIZ && f != CLOT_HADH;
+    }
     clot_status count(int c, clot_field f, size_t* n) const override {
         FieldRef r = ref(c, f);
-        if (!r.ptr && r.n == 0 && f != CLOT_UZ && f != CLOT_PHIZ && f != CLOT_HADH) {
-            const_cast<Ctx*>(this)->err = "unknown field";
+        if (unknown(r, f)) {
+            const_cast<Ctx*>(this)->err = "unknown field (or one of another build)";
             return CLOT_EINVAL;
         }
         *n = (size_t)r.n;
@@ -878,6 +896,10 @@ struct Ctx : clot_ctx {
 
     clot_status set(int c, clot_field f, const double* h, size_t n) override {
         FieldRef r = ref(c, f);
+        if (unknown(r, f)) {
+            err = "unknown field (or one of another build)";
+            return CLOT_EINVAL;
+        }
         if (r.ro) {
             err = "field is read only";
             return CLOT_EINVAL;
@@ -902,6 +924,10 @@ struct Ctx : clot_ctx {
 
     clot_status get(int c, clot_field f, double* h, size_t n) override {
         FieldRef r = ref(c, f);
+        if (unknown(r, f)) {
+            err = "unknown field (or one of another build)";
+            return CLOT_EINVAL;
+        }
         if ((int64_t)n != r.n || (!h && n)) {
             err = "get_field: size mismatch";
             return CLOT_EINVAL;
@@ -1344,7 +1370,8 @@ struct Ctx : clot_ctx {
             const int sp = tr_species(k);
             top.scale[k] = T(sp == PMU || sp == PMA ? M.P_max
                              : sp == S1 || sp == E1 ? M.S1_0
-                             : sp == S2 || sp == E2 ? M.S2_0 : M.adp_crit);
+                             : sp == S2 || sp == E2 || sp == E2I ? M.S2_0
+                             : sp == INH ? M.I_0 : M.adp_crit);
             top.Dk[k] = tr_diffusivity<T>(k, M);
         }
         top.phx = F.phin[0];
@@ -1376,6 +1403,7 @@ struct Ctx : clot_ctx {
         // O-6 reactions (wall first: it reads the transported S1)
         if (NINJ > 0)
             hipLaunchKernelGGL(k_wall_rxn<T>, dim3((NINJ + NT - 1) / NT), tb, 0, st, d_ch, d_f2c, NINJ, F, M);
+#ifndef CLOT_INHIBITOR
         if (rxn_mode == CLOT_RXN_SURROGATE) {
             fill(fb_count, 0, 1);
             fill(fb_chan, 0, nch);
@@ -1387,7 +1415,9 @@ struct Ctx : clot_ctx {
                         fb_list, fb_count);
             hipLaunchKernelGGL(k_record_fallback, dim3(1), dim3(64), 0, st, fb_chan, d_ch, dstats, NSTAT, nch,
                                (int)ST_FALLBACK);
-        } else {
+        } else
+#endif
+        {
             CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn<T>, gb, tb, 0, st, G, F, M);
         }
         // the next step's ddt coefficients and variable step
@@ -1765,6 +1795,8 @@ static ModelDev model_from_params(const clot_params& q) {
     M.psi = q.ddt_psi;
     M.max_co = q.max_co;
     M.dt_growth = q.dt_growth;
+    M.k_I = q.k_I;
+    M.I_0 = q.I_0;
     return M;
 }
 
@@ -1866,6 +1898,8 @@ clot_status clot_params_default(clot_params* p) {
     p->ddt_psi = 0.0;
     p->max_co = 0.0;
     p->dt_growth = 1.2;
+    p->k_I = 7.1;
+    p->I_0 = 3.4e-3;
     return CLOT_OK;
 }
 
@@ -1894,7 +1928,7 @@ clot_status clot_create(const clot_channel* chs, int32_t n_ch, const clot_params
     *out = nullptr;
     if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1 || p->mg_tail < 0 ||
         (p->mg_sweeps != 1 && p->mg_sweeps != 2) || !(p->ddt_psi >= 0.0 && p->ddt_psi <= 1.0) ||
-        !(p->max_co >= 0.0) || !(p->dt_growth >= 1.0))
+        !(p->max_co >= 0.0) || !(p->dt_growth >= 1.0) || !(p->k_I >= 0.0) || !(p->I_0 >= 0.0))
         return CLOT_EINVAL;
     clot_ctx* c = make_ctx(prec);
     c->prec = prec;
@@ -2020,16 +2054,25 @@ clot_status clot_mlp_mse(const float* y, const float* t, int64_t n, int32_t nuse
 }
 
 clot_status clot_rxn_rk4_batch(const clot_params* p, const double* rows, int64_t n, double* inc, void* stream) {
+#ifdef CLOT_INHIBITOR
+    (void)p, (void)rows, (void)n, (void)inc, (void)stream;
+    return CLOT_EINVAL;   // rows hold the base model's 14 species
+#else
     if (!p || !rows || !inc || n < 0 || p->M_rxn < 1) return CLOT_EINVAL;
     if (n == 0) return CLOT_OK;
     hipLaunchKernelGGL(k_rxn_batch, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, (hipStream_t)stream, rows, n,
                        model_from_params(*p), inc);
     CHK_LAUNCH();
     return CLOT_OK;
+#endif
 }
 
 clot_status clot_surr_dataset(const clot_params* p, const double* rows, const double* inc, int64_t n,
                               const float* scales, uint16_t* x, float* t, double* stats, void* stream) {
+#ifdef CLOT_INHIBITOR
+    (void)p, (void)rows, (void)inc, (void)n, (void)scales, (void)x, (void)t, (void)stats, (void)stream;
+    return CLOT_EINVAL;   // the learned step covers the base model only
+#else
     if (!p || !rows || !inc || n <= 0 || (!stats && (!scales || !x || !t))) return CLOT_EINVAL;
     const ModelDev M = model_from_params(*p);
     SurrTables tb{};
@@ -2042,6 +2085,7 @@ clot_status clot_surr_dataset(const clot_params* p, const double* rows, const do
                        M, tb, x, t, stats);
     CHK_LAUNCH();
     return CLOT_OK;
+#endif
 }
 
 clot_status clot_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, void* stream) {
@@ -2059,6 +2103,8 @@ clot_status clot_probe_read(clot_ctx* c, double* ms, int64_t* n) {
     return c->probe_read(ms, n);
 }
 int32_t clot_tile_cells(void) { return TILE; }
+
+int32_t clot_cell_species(void) { return NSPC; }
 clot_status clot_set_graph_mode(clot_ctx* c, int32_t on, double budget_scale, int32_t budget_pad) {
     if (!c) return CLOT_EINVAL;
     return c->set_graph(on, budget_scale, budget_pad);

@@ -19,18 +19,29 @@ constexpr int NT = 256;           // threads per block (4 wavefronts of 64)
 constexpr int CPT = CLOT_CPT;     // cells per thread (a build option: 1, 2 or 4)
 constexpr int TILE = NT * CPT;    // cells per tile
 constexpr int NXCD = 8;
+#ifdef CLOT_INHIBITOR
+// The extensibility example (section 4.3): an inhibitor I that binds thrombin for good,
+// I + E2 -> E2i; both new species follow the 15, are transported and react.
+constexpr int NSPC = 17;          // cell species
+constexpr int NTR = 9;            // transported species
+constexpr int NRX = 16;           // reacting species
+constexpr int MAXK = 9;           // max systems in one batched Krylov solve
+#else
 constexpr int NSPC = 15;          // cell species
 constexpr int NTR = 7;            // transported species
 constexpr int NRX = 14;           // reacting species
-constexpr int NHIST = 25;         // release-history nodes (tau_f/dtau + 1)
 constexpr int MAXK = 8;           // max systems in one batched Krylov solve
+#endif
+constexpr int NSPC_DRAWN = 15;    // species with initial-noise draws (the added ones have none)
+constexpr int NHIST = 25;         // release-history nodes (tau_f/dtau + 1)
 constexpr int NSC = 64;           // per-channel scalar slots
 
 // Cell species slots (library field order).
-enum { PMU = 0, PMA, PBA, PBSE, ADP, S1, S2, E1, E2, S1B, S2B, E1B, E2B, C1, C2 };
-// Transported species, solve order.
+enum { PMU = 0, PMA, PBA, PBSE, ADP, S1, S2, E1, E2, S1B, S2B, E1B, E2B, C1, C2, INH, E2I };
+// Transported species, solve order (the inhibitor variant adds I and E2i last).
 __host__ __device__ constexpr int tr_species(int k) {
-    return k == 0 ? PMU : k == 1 ? PMA : k == 2 ? S1 : k == 3 ? S2 : k == 4 ? E1 : k == 5 ? E2 : ADP;
+    return k == 0 ? PMU : k == 1 ? PMA : k == 2 ? S1 : k == 3 ? S2 : k == 4 ? E1 : k == 5 ? E2 : k == 6 ? ADP
+         : k == 7 ? INH : E2I;
 }
 
 struct ChanDev {
@@ -73,6 +84,7 @@ struct ModelDev {
     double g0;
     int32_t M_rxn;
     double psi, max_co, dt_growth;   // time scheme: Crank-Nicolson off-centring, variable step
+    double k_I, I_0;                 // inhibitor variant: association rate, inlet value
 };
 
 // Launch-wide tables.

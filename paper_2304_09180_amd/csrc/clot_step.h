@@ -449,9 +449,10 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             const T W = plt ? Wp : T(1);
             if (P.i == 0) {
                 const T fo = -fin;       // outward flux through the inlet face
-                const bool fixed = (sp == PMU || sp == S1 || sp == S2);
+                const bool fixed = (sp == PMU || sp == S1 || sp == S2 || sp == INH);
                 if (fixed) {
-                    const T cb = sp == PMU ? F.pmu_in[C.in0 + P.j + (int64_t)C.ny * P.k] : (sp == S1 ? T(M.S1_0) : T(M.S2_0));
+                    const T cb = sp == PMU ? F.pmu_in[C.in0 + P.j + (int64_t)C.ny * P.k]
+                               : sp == S1 ? T(M.S1_0) : sp == S2 ? T(M.S2_0) : T(M.I_0);
                     const T gg = T(2) * W * D * T(C.gx);
                     d += gg;
                     b += gg * cb - W * fo * cb;
@@ -565,7 +566,14 @@ __device__ inline void rxn_rhs(const T (&y)[NRX], T adp, T gam, T hadh, const Mo
     f[4] = -bS1;
     f[5] = -bS2;
     f[6] = -bE1;
+#ifdef CLOT_INHIBITOR
+    const T rI = T(M.k_I) * y[14] * y[7];   // I + E2 -> E2i (section 4.3), mass action
+    f[7] = -bE2 - rI;
+    f[14] = -rI;
+    f[15] = rI;
+#else
     f[7] = -bE2;
+#endif
     f[8] = bS1 - c2 + T(M.kC2m) * y[13];
     f[9] = bS2 - c1 + T(M.kC1m) * y[12];
     f[10] = bE1 - c1 + T(M.kC1m + M.kC1cat) * y[12] + T(M.kC2cat) * y[13];
@@ -659,6 +667,10 @@ __global__ __launch_bounds__(NT) void k_rxn(Grid G, Fields<T> F, ModelDev M) {
         y[11] = F.spc[E2B][g];
         y[12] = F.spc[C1][g];
         y[13] = F.spc[C2][g];
+#ifdef CLOT_INHIBITOR
+        y[14] = F.xt[7][g];
+        y[15] = F.xt[8][g];
+#endif
         const T adp = F.xt[6][g];
         const T gam = binding_g<T>(F.eta[g], M);
         const bool hin = P.j < C.jadh && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
@@ -679,6 +691,10 @@ __global__ __launch_bounds__(NT) void k_rxn(Grid G, Fields<T> F, ModelDev M) {
         F.spc[E2B][g] = y[11];
         F.spc[C1][g] = y[12];
         F.spc[C2][g] = y[13];
+#ifdef CLOT_INHIBITOR
+        F.spc[INH][g] = y[14];
+        F.spc[E2I][g] = y[15];
+#endif
         F.spc[ADP][g] = adp;
     CLOT_END_CELLS
 }
@@ -699,7 +715,11 @@ template <class T>
 __global__ __launch_bounds__(NT) void k_diag_tiles(Grid G, Fields<T> F, ModelDev M, double* part) {
     CLOT_TILE_PROLOGUE(G)
     const double sc[NSPC] = {M.P_max, M.P_max, M.P_max, M.P_max, M.adp_crit, M.S1_0, M.S2_0, M.S1_0, M.S2_0,
-                             M.S1_0, M.S2_0, M.S1_0, M.S2_0, M.S2_0, M.S2_0};
+                             M.S1_0, M.S2_0, M.S1_0, M.S2_0, M.S2_0, M.S2_0
+#ifdef CLOT_INHIBITOR
+                             , M.I_0, M.S2_0
+#endif
+    };
     double dmax = 0.0, fmx = 0.0, smin = 1e300;
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);

@@ -44,6 +44,7 @@ inline void surr_tables_finish(const ModelDev& M, SurrTables& tb) {
     }
 }
 
+#ifndef CLOT_INHIBITOR   // the network covers the 14 reacting species of the base model
 // Signed logarithm of a scaled value: |v| in [1e-12, 1] maps onto [0, 1], zero below
 // 1e-12 (single precision: the feature is rounded to bf16 afterwards).
 __device__ inline float slog(float v) {
@@ -328,5 +329,7 @@ __global__ __launch_bounds__(NT) void k_surr_dataset(const double* rows, const d
             for (int i = 0; i < 42; ++i) stats[(int64_t)blockIdx.x * 42 + i] = acc[i];
     }
 }
+
+#endif  // CLOT_INHIBITOR
 
 }  // namespace clot

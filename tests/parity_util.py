@@ -10,7 +10,7 @@ import numpy as np
 SCALE = {"UX": 62.5, "UY": 62.5, "UZ": 62.5, "P": 2e4, "PMU": 2.5e5, "PMA": 2.5e5, "PBA": 6.67e7, "PBSE": 6.67e7,
          "ADP": 2e-3, "S1": 1.7e-4, "S2": 1.4e-3, "E1": 1.7e-4, "E2": 1.4e-3, "S1B": 1.7e-4, "S2B": 1.4e-3,
          "E1B": 1.7e-4, "E2B": 1.4e-3, "C1": 1.4e-3, "C2": 1.4e-3, "E0": 1.5e-7, "C0": 1.5e-7, "ETA": 1.0,
-         "SIGMA": 1.0, "PHIX": 1e-2, "PHIY": 1e-2, "PHIZ": 1e-2}
+         "SIGMA": 1.0, "PHIX": 1e-2, "PHIY": 1e-2, "PHIZ": 1e-2, "I": 3.4e-3, "E2I": 1.4e-3}
 
 
 def rel_l2(a, b, name):

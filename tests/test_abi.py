@@ -9,12 +9,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "clot.h")
 PKG = os.path.join(ROOT, "paper_2304_09180_amd")
 LIB = os.path.join(PKG, "libclot.so")
-VARIANTS = {256: LIB, 512: os.path.join(PKG, "libclot_t512.so"), 1024: os.path.join(PKG, "libclot_t1024.so")}
+# (cells per tile, cell species) of every library built
+VARIANTS = {"libclot.so": (256, 15), "libclot_t512.so": (512, 15), "libclot_t1024.so": (1024, 15),
+            "libclot_inh.so": (256, 17)}
 
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(clot_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(clot_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_abi():
@@ -23,16 +25,22 @@ def test_header_declares_the_abi():
         assert n in names
 
 
-@pytest.mark.parametrize("tile", sorted(VARIANTS))
-def test_library_exports_every_declared_symbol(tile):
-    path = VARIANTS[tile]
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_library_exports_every_declared_symbol(name):
+    path = os.path.join(PKG, name)
     if not os.path.exists(path):
-        pytest.skip(f"{os.path.basename(path)} not built")
+        pytest.skip(f"{name} not built")
     lib = ctypes.CDLL(path)
     for n in declared():
         assert hasattr(lib, n), n
     lib.clot_tile_cells.restype = ctypes.c_int32
-    assert lib.clot_tile_cells() == tile
+    lib.clot_cell_species.restype = ctypes.c_int32
+    assert (lib.clot_tile_cells(), lib.clot_cell_species()) == VARIANTS[name]
+
+
+def test_binding_knows_every_declared_symbol():
+    from paper_2304_09180_amd import clot
+    assert set(declared()) == set(clot.exported_symbols())
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libclot.so not built")
@@ -57,3 +65,36 @@ def test_params_default_and_argument_checks_without_gpu():
     assert lib.clot_query_workspace((clot.Channel * 1)(bad), 1, clot.FP64, ctypes.byref(n)) == -1
     assert lib.clot_query_workspace(arr, 0, clot.FP64, ctypes.byref(n)) == -1
     assert lib.clot_query_workspace(arr, 1, 7, ctypes.byref(n)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(PKG, "libclot_inh.so")), reason="libclot_inh.so not built")
+def test_inhibitor_build_defaults_workspace_and_refusals_without_gpu():
+    """The inhibitor build's defaults carry the inhibitor's constants, its workspace holds
+    two more cell species and two more transport systems than the base build's, and the
+    batch entry points of the base model's reaction network refuse before any GPU work."""
+    from paper_2304_09180_amd import clot
+    lib = clot.load(256, inhibitor=True)
+    p = clot.Params()
+    assert lib.clot_params_default(ctypes.byref(p)) == 0
+    assert p.k_I == 7.1 and p.I_0 == 3.4e-3
+    import clot_inputs as ci
+    d = ci.workload("channel2d_64x16")
+    arr = (clot.Channel * 1)(clot.channel_struct(d))
+    n_inh, n_base = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.clot_query_workspace(arr, 1, clot.FP64, ctypes.byref(n_inh)) == 0
+    assert clot.load().clot_query_workspace(arr, 1, clot.FP64, ctypes.byref(n_base)) == 0
+    # per cell at least: 2 species + 2 x (transport solution, diagonal, rhs, 6 couplings,
+    # history) + 2 x 7 Krylov vectors, 8 bytes each
+    assert n_inh.value - n_base.value >= 64 * 16 * 8 * (2 + 2 * 10 + 2 * 7)
+    rows = (ctypes.c_double * 64)()
+    inc = (ctypes.c_double * 64)()
+    assert lib.clot_rxn_rk4_batch(ctypes.byref(p), rows, 1, inc, None) == -1
+    assert lib.clot_surr_dataset(ctypes.byref(p), rows, inc, 1, None, None, None, rows, None) == -1
+    for bad in (dict(k_I=-1.0), dict(I_0=float("nan"))):
+        q = clot.Params()
+        lib.clot_params_default(ctypes.byref(q))
+        for k, v in bad.items():
+            setattr(q, k, v)
+        ctx = ctypes.c_void_p()
+        assert lib.clot_create(arr, 1, ctypes.byref(q), clot.FP64, ctypes.c_void_p(256), 1 << 30, None,
+                               ctypes.byref(ctx)) == -1
