@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--train-samples", type=int, default=400_000)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-inhibitor", action="store_true",
-                    help="skip the leg of the model with the inhibitor (section 4.3)")
+                    help="skip the leg of the model with the inhibitor (section 3.4)")
     ap.add_argument("--no-time-scheme", action="store_true",
                     help="skip the Crank-Nicolson / variable-step leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -217,7 +217,7 @@ def time_scheme_leg(desc, prec, args, xc, xf, tile):
 
 
 def inhibitor_leg(desc, prec, args, xc, xf):
-    """The same workload with the inhibitor of section 4.3's extensibility example
+    """The same workload with the inhibitor of section 3.4's extensibility example
     (I + E2 -> E2i: 17 cell species, 9 transported, 16 reacting) from its own build:
     cost per step next to the base model's, and the kernels the two species widen."""
     import torch

@@ -66,7 +66,7 @@ typedef enum {
     CLOT_E0, CLOT_C0,                                            /* injury-face species     */
     CLOT_ETA, CLOT_THETAB, CLOT_SIGMA,                           /* derived, read only      */
     CLOT_HADH,                                                   /* adhesion mask, read only */
-    CLOT_I, CLOT_E2I,            /* inhibitor build only (section 4.3, I + E2 -> E2i): the
+    CLOT_I, CLOT_E2I,            /* inhibitor build only (section 3.4, I + E2 -> E2i): the
                                     inhibitor I and the inhibited thrombin E2i, both
                                     transported and reacting; other builds refuse them
                                     with CLOT_EINVAL                                      */
@@ -221,7 +221,7 @@ clot_status clot_set_reaction_mode(clot_ctx* c, clot_rxn_mode mode, const void* 
 int32_t clot_tile_cells(void);
 
 /* Cell species this library carries: 15 (the model of section 2 and Appendix B), or
- * 17 for the inhibitor build (section 4.3's extensibility example), which appends the
+ * 17 for the inhibitor build (section 3.4's extensibility example), which appends the
  * inhibitor I and the inhibited thrombin E2i (fields CLOT_I, CLOT_E2I).  That build
  * solves 9 transport equations and 16 reaction equations; I has the fixed inlet value
  * I_0 and starts there, E2i starts at zero, neither takes an initial-noise draw; its

@@ -48,7 +48,7 @@ RXN = ["Pmu", "Pma", "Pba", "Pbse", "S1", "S2", "E1", "E2",
        "S1b", "S2b", "E1b", "E2b", "C1", "C2"]
 # The 7 transported scalars (bound species do not move).
 TRANSPORTED = ["Pmu", "Pma", "S1", "S2", "E1", "E2", "ADP"]
-# The extensibility example (section 4.3): a fluid-phase inhibitor I that binds thrombin
+# The extensibility example (section 3.4): a fluid-phase inhibitor I that binds thrombin
 # for good, I + E2 -> E2i.  Both new species are transported and react; they follow the
 # 15 species above, whose indices do not change.
 INHIBITOR_SPECIES = ["I", "E2i"]
@@ -111,7 +111,7 @@ class Params:
     ddt_psi: float = 0.0
     max_co: float = 0.0
     dt_growth: float = 1.2
-    # the inhibitor variant (section 4.3 names the reaction, not its constants): an
+    # the inhibitor variant (section 3.4 names the reaction, not its constants): an
     # antithrombin-like inlet and initial concentration and association rate
     inhibitor: bool = False
     k_I: float = 7.1               # (nmol/mm^3)^-1 s^-1
@@ -834,7 +834,7 @@ class Oracle:
                     np.add.at(S.diag, lo, Wlo * phi_out_in)
                 phi_out = self.phi[a][:, :, -1].ravel()
                 np.add.at(S.diag, hi, Whi * phi_out)
-        # reactive injury wall (Appendix B boundary conditions; normal into the fluid)
+        # reactive injury wall (Appendix C table; normal into the fluid)
         Ai = m.inj_area
         if name == "E1":
             np.add.at(S.rhs, m.inj_cells, Ai * p.kC0cat * self.C0)

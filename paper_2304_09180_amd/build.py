@@ -4,7 +4,7 @@ A tile is the group of cells one 256-thread block owns (its partial sums, its
 channel); the tile size is fixed at compile time, so each candidate size is its own
 library: libclot.so (256 cells, one per thread), libclot_t512.so and
 libclot_t1024.so (two and four cells per thread).  The autotuner picks among them.
-libclot_inh.so (256 cells) is the model with the inhibitor of section 4.3's
+libclot_inh.so (256 cells) is the model with the inhibitor of section 3.4's
 extensibility example (I + E2 -> E2i), built from the same sources with
 CLOT_INHIBITOR defined.
 """

@@ -20,7 +20,7 @@ constexpr int CPT = CLOT_CPT;     // cells per thread (a build option: 1, 2 or 4
 constexpr int TILE = NT * CPT;    // cells per tile
 constexpr int NXCD = 8;
 #ifdef CLOT_INHIBITOR
-// The extensibility example (section 4.3): an inhibitor I that binds thrombin for good,
+// The extensibility example (section 3.4): an inhibitor I that binds thrombin for good,
 // I + E2 -> E2i; both new species follow the 15, are transported and react.
 constexpr int NSPC = 17;          // cell species
 constexpr int NTR = 9;            // transported species

@@ -567,7 +567,7 @@ __device__ inline void rxn_rhs(const T (&y)[NRX], T adp, T gam, T hadh, const Mo
     f[5] = -bS2;
     f[6] = -bE1;
 #ifdef CLOT_INHIBITOR
-    const T rI = T(M.k_I) * y[14] * y[7];   // I + E2 -> E2i (section 4.3), mass action
+    const T rI = T(M.k_I) * y[14] * y[7];   // I + E2 -> E2i (section 3.4), mass action
     f[7] = -bE2 - rI;
     f[14] = -rI;
     f[15] = rI;

@@ -1,4 +1,4 @@
-"""The paper's 2-D thrombosis example (section 5.1): a 240 x 60 um channel on a
+"""The paper's 2-D thrombosis example (section 4.1): a 240 x 60 um channel on a
 uniform 128 x 32 mesh with a ~90 um adhesive, reactive patch centred on the bottom
 wall, wall shear 1000 1/s, Crank-Nicolson 0.9 and a variable step at Courant 0.75
 (Appendix D).  Reports over time the clot 'areas' used in the paper's quantitative

@@ -1,4 +1,4 @@
-"""GPU parity of the inhibitor build (section 4.3's extensibility example: I + E2 -> E2i,
+"""GPU parity of the inhibitor build (section 3.4's extensibility example: I + E2 -> E2i,
 two more transported and reacting species) through the C ABI against the FP64 oracle
 run with the same species added.
 

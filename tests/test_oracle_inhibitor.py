@@ -1,4 +1,4 @@
-"""CPU pins of the oracle's inhibitor variant (section 4.3: a fluid-phase inhibitor I that
+"""CPU pins of the oracle's inhibitor variant (section 3.4: a fluid-phase inhibitor I that
 binds thrombin for good, I + E2 -> E2i, rate k_I I E2; the two species are appended to
 the 15 and both are transported).
 

@@ -306,7 +306,7 @@ def test_transport_flow_balance():
 
 
 # ----------------------------------------------------------------------------------------
-# Reactive wall (Appendix B boundary conditions, eqs. seBound_E0/C0)
+# Reactive wall (Appendix C table; Appendix B eqs. seBound_E0/C0)
 # ----------------------------------------------------------------------------------------
 
 def test_robin_wall_equilibrium_and_limits():

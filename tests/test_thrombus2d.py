@@ -1,4 +1,4 @@
-"""CPU checks of the paper's 2-D thrombosis example set-up (section 5.1): geometry and
+"""CPU checks of the paper's 2-D thrombosis example set-up (section 4.1): geometry and
 the adhesion region whose cell count is the level of the temporary plateau the paper
 reports for the area above 10% of P_max."""
 import numpy as np
