@@ -151,3 +151,44 @@ def test_inhibitor_stats_minimum_covers_the_added_species():
     print(st["min_species"], min(mins.items(), key=lambda kv: kv[1]))
     assert min(mins, key=mins.get) == "I"
     assert st["min_species"] == pytest.approx(min(mins.values()), rel=1e-9)
+
+
+def test_inhibitor_batched_uneven_channels_and_graph_replay():
+    """Three uneven channels in one context of the inhibitor build: each equals the
+    oracle run alone (FP64), and whole steps replayed as HIP graphs equal the eager
+    steps bit for bit (the 9-system transport solve inside the recorded step)."""
+    from paper_2304_09180_amd import clot
+    descs = [ci.channel(2, 40, 12, shear=1000.0, dt=1e-4, seed=45),
+             ci.channel(2, 24, 8, shear=600.0, dt=1e-4, seed=46, inj_frac=0.4),
+             ci.channel(3, 12, 6, 5, shear=900.0, dt=1e-4, seed=47)]
+    extras = [seeded_extra(d, 50 + c) for c, d in enumerate(descs)]
+
+    def make(prec):
+        s = clot.Solver(descs, prec, clot.default_params(prec), inhibitor=True)
+        for c, d in enumerate(descs):
+            xc, xf = ci.noise(d)
+            s.init_state(c, xc, xf)
+            for name, v in extras[c].items():
+                s.set(c, name, v)
+        return s
+
+    s = make(clot.FP64)
+    s.step(3)
+    for c, d in enumerate(descs):
+        assert s.stats(c)["status"] == "OK"
+        compare(s.fields(c), run_oracle(d, 3, extras[c]), 1e-10)
+    s.close()
+    for prec in (clot.FP32_MIXED, clot.FP64):
+        eager, graph = make(prec), make(prec)
+        graph.set_graph_mode(True, 1.25, 2)
+        for step in range(5):
+            eager.step(1)
+            graph.step(1)
+            for c in range(len(descs)):
+                fe, fg = eager.fields(c), graph.fields(c)
+                for name in fe:
+                    assert np.array_equal(fe[name], fg[name]), (prec, step, c, name)
+        info = graph.graph_info()
+        assert info["captures"] == 2 and info["replays"] == 3 and info["overflows"] == 0, info
+        eager.close()
+        graph.close()
