@@ -98,3 +98,13 @@ def test_inhibitor_build_defaults_workspace_and_refusals_without_gpu():
         ctx = ctypes.c_void_p()
         assert lib.clot_create(arr, 1, ctypes.byref(q), clot.FP64, ctypes.c_void_p(256), 1 << 30, None,
                                ctypes.byref(ctx)) == -1
+
+
+def test_binding_refuses_libraries_that_are_not_built():
+    from paper_2304_09180_amd import clot
+    with pytest.raises(clot.ClotError):
+        clot.load(512, inhibitor=True)      # the inhibitor model is built at 256 cells per tile only
+    with pytest.raises(clot.ClotError):
+        clot.load(384)
+    assert clot.lib_path(256, True).endswith("libclot_inh.so")
+    assert clot.lib_path(1024).endswith("libclot_t1024.so")
