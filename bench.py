@@ -278,8 +278,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
-                                   "this build (see the design notes on slab decomposition)"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library solves every channel "
+                                   "on one device (a slab decomposition over several GPUs is designed, not built)"}))
         sys.exit(2)
     import torch
     import clot_inputs as ci

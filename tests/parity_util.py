@@ -2,7 +2,7 @@
 
 Fields that stay near zero make the relative l2 of the field itself 0/0 or dominated
 by round-off carried from larger fields; the denominator is floored at
-1e-12 * s * sqrt(N) with s the field's scale (the survey's AMB-29 reading), and
+1e-12 * s * sqrt(N) with s the field's scale (a field that stays at round-off is compared on its scale), and
 velocity and flux components are measured against the norm of the whole vector."""
 import numpy as np
 

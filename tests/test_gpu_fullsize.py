@@ -92,7 +92,7 @@ def test_ensemble_members_match_their_single_runs():
 
 
 def test_surrogate_step_against_plain_step_on_the_duct():
-    """The learned reaction step on the 1M-cell duct (plain RK4 as the judge)."""
+    """The learned reaction step on the 1M-cell duct (plain RK4 as the reference)."""
     from paper_2304_09180_amd import clot, surrogate
     d1 = ci.workload("channel2d_64x16")
     states = surrogate.collect_states([(d1, 100)], log=lambda *a: None)
