@@ -194,7 +194,7 @@ struct Ctx : clot_ctx {
         Grid grid() const { return Grid{d_ch, d_t2c, ntiles}; }
     };
     std::vector<Level> lev;
-    T mg_w = T(0.8);
+    T mg_w = T(0.8);         // weighted-Jacobi smoothing weight (set with the channels)
     int mg_t0 = -1;          // first level run by the fused tail launch (-1: none)
     size_t mg_tail_lds = 0;  // its dynamic LDS bytes
     T* mg_y0 = nullptr;      // level-0 smoother scratch
@@ -503,6 +503,13 @@ struct Ctx : clot_ctx {
                     err = "channel too long for the pressure multigrid hierarchy";
                     return CLOT_EINVAL;
                 }
+        // Jacobi smoothing weight of the pressure V-cycle: for the 7-point Laplacian omega =
+        // 6/7 shrinks every error mode with a component above half the grid frequency to at
+        // most 5/7 per sweep, the best a single weight does; for the 5-point one omega = 4/5
+        // (at most 3/5).  A context with a 2-D channel keeps 4/5.
+        bool all3d = true;
+        for (const ChanHost& h : ch) all3d = all3d && h.d.dim == 3;
+        mg_w = T(all3d ? 6.0 / 7.0 : 0.8);
         // fused launch for the trailing levels whose channels all fit the cell threshold
         // and, with every level's arrays, the LDS of one block
         mg_t0 = -1;
