@@ -22,18 +22,22 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 
 # Algorithmic bytes per cell for each timed phase (compulsory reads + writes of one
 # launch, stencil neighbours counted once), FP32 storage (x2 for FP64).
-#   p_cg_a : r, p_old, diag, rAU read; p_new, q written            -> 6 arrays
+#   p_cg_a : z, p_old, diag, rAU read; p_new, q written            -> 6 arrays
 #   p_cg_b : x, p_new, r, q, diag read; x, r written                -> 7 arrays
 #   tr_b1  : per system r, p_old, v_old, diag, rhat, C^n read; p, v written (8)
 #            plus the shared face fluxes (dim arrays) and W(theta_T)
 #   tr_b2  : per system r, v, diag, C^n read; t written (5) + fluxes + W
 #   tr_b3  : per system x, r, rhat, p, v, t, diag read; x, r written (9)
 #   rxn    : 14 species + ADP + eta read; 15 species written (31)
+#   mom_b1 : per velocity component r, p_old, v_old, rhat read; p, v written (6)
+#            plus the shared diagonal a_P and the face fluxes (dim arrays)
+#   mom_b2 : per component r, v read; t written (3) + a_P + fluxes
+#   mom_b3 : per component x, r, rhat, p, v, t read; x, r written (8) + a_P
 ARRAYS = {"p_cg_a": lambda dim: 6, "p_cg_b": lambda dim: 7,
           "tr_b1": lambda dim: 7 * 8 + dim + 1, "tr_b2": lambda dim: 7 * 5 + dim + 1,
           "tr_b3": lambda dim: 7 * 9, "rxn": lambda dim: 31,
-          "mom_b1": lambda dim: dim * 7 + 1 + dim, "mom_b2": lambda dim: dim * 4 + 1 + dim,
-          "mom_b3": lambda dim: dim * 9 + 1}
+          "mom_b1": lambda dim: dim * 6 + 1 + dim, "mom_b2": lambda dim: dim * 3 + 1 + dim,
+          "mom_b3": lambda dim: dim * 8 + 1}
 
 
 def parse():
@@ -45,7 +49,9 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--tile", default="auto", choices=["auto", "256", "512", "1024"],
                     help="cells per block; auto runs the tile autotuner on each workload first")
-    ap.add_argument("--probe", default="p_cg_a", help="kernel phase timed for the roofline")
+    ap.add_argument("--probe", default="mom_b2",
+                    help="kernel phase timed for the roofline (default: the momentum BiCGStab's second phase, "
+                         "the kernel with the largest share of the step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
     ap.add_argument("--train-samples", type=int, default=400_000)

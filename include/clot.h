@@ -112,7 +112,9 @@ typedef struct {
                              this many cells run as one launch (one block per channel);
                              0 = every level its own launches.  Default 4096.            */
     int32_t mg_sweeps;    /* pressure multigrid: weighted-Jacobi sweeps before and after each
-                             restriction, 1 or 2 (default 2)                               */
+                             restriction, 1 to 4, or 0 (default): 3 when every channel is
+                             3-D, else 2.  Each sweep costs one stencil pass per level;
+                             more sweeps need fewer CG iterations                       */
     double ddt_psi;       /* Crank-Nicolson off-centring of every ddt term (Appendix D
                              table), in [0,1]; 0 = implicit Euler (default).  The time
                              derivative over a step is k (f' - f)/dt - w D, D the stored

@@ -455,7 +455,7 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
         tail_copy_in(lds + tv[0].ob, tl.L[0].b + C0.c0, C0.ncell);
     }
     __syncthreads();
-    // down: two Jacobi sweeps (from zero) and the residual restriction per level
+    // down: `sweeps` Jacobi sweeps (from zero) and the residual restriction per level
     for (int l = 0; l + 1 < nl; ++l) {
         const TailLds& v = tv[l];
         const ChanDev& C = v.C;
@@ -464,17 +464,20 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
         T* x = lds + v.ox;
         T* y = lds + v.oy;
         // first sweep from zero, stored (the same value the separate kernel forms at
-        // each neighbour), then (two-sweep cycle) the second sweep
-        T* x1 = sweeps == 2 ? y : x;
-        for (int64_t g = threadIdx.x; g < C.ncell; g += MG_TAIL_BS) x1[g] = w * b[g] / op.diag(0, g);
+        // each neighbour), then the others alternating between x and y so that the last
+        // lands in x
+        T* cur = sweeps % 2 == 0 ? y : x;
+        for (int64_t g = threadIdx.x; g < C.ncell; g += MG_TAIL_BS) cur[g] = w * b[g] / op.diag(0, g);
         __syncthreads();
-        if (sweeps == 2) {
+        for (int k = 1; k < sweeps; ++k) {
+            T* nxt = cur == x ? y : x;
             for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
                 const Cell P = cell_at(C, local);
-                const T ax = op.apply(0, C, P, [&](int64_t g) { return y[g]; });
-                x[P.g] = y[P.g] + w * (b[P.g] - ax) / op.diag(0, P.g);
+                const T ac = op.apply(0, C, P, [&](int64_t g) { return cur[g]; });
+                nxt[P.g] = cur[P.g] + w * (b[P.g] - ac) / op.diag(0, P.g);
             }
             __syncthreads();
+            cur = nxt;
         }
         const ChanDev& Cc = tv[l + 1].C;
         T* bc = lds + tv[l + 1].ob;
@@ -526,34 +529,31 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
         const TailLds& v = tv[l];
         const ChanDev& C = v.C;
         const ChanDev& Cc = tv[l + 1].C;
-        // the finished correction of the level below: x after two sweeps, y after one
-        // (the coarsest level's is x, from the dense solve)
-        const T* xc = lds + ((l + 1 == nl - 1 || sweeps == 2) ? tv[l + 1].ox : tv[l + 1].oy);
+        // the finished correction of the level below: x after an even number of sweeps, y
+        // after an odd one (the coarsest level's is x, from the dense solve)
+        const T* xc = lds + ((l + 1 == nl - 1 || sweeps % 2 == 0) ? tv[l + 1].ox : tv[l + 1].oy);
         const CoefOp<T> op{lds + v.odg, lds + v.ocx, lds + v.ocy, lds + v.ocz};
         const T* b = lds + v.ob;
         T* x = lds + v.ox;
         T* y = lds + v.oy;
-        // prolongation by injection, in place, then the first sweep
+        // prolongation by injection, in place, then the sweeps alternating x -> y -> x ...
         for (int64_t g = threadIdx.x; g < C.ncell; g += MG_TAIL_BS) x[g] = x[g] + xc[coarse_of(C, Cc, g)];
         __syncthreads();
-        for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
-            const Cell P = cell_at(C, local);
-            const T ax = op.apply(0, C, P, [&](int64_t g) { return x[g]; });
-            y[P.g] = x[P.g] + w * (b[P.g] - ax) / op.diag(0, P.g);
-        }
-        __syncthreads();
-        if (sweeps == 2) {
+        T* cur = x;
+        for (int k = 0; k < sweeps; ++k) {
+            T* nxt = cur == x ? y : x;
             for (int64_t local = threadIdx.x; local < C.ncell; local += MG_TAIL_BS) {
                 const Cell P = cell_at(C, local);
-                const T ay = op.apply(0, C, P, [&](int64_t g) { return y[g]; });
-                x[P.g] = y[P.g] + w * (b[P.g] - ay) / op.diag(0, P.g);
+                const T ac = op.apply(0, C, P, [&](int64_t g) { return cur[g]; });
+                nxt[P.g] = cur[P.g] + w * (b[P.g] - ac) / op.diag(0, P.g);
             }
             __syncthreads();
+            cur = nxt;
         }
     }
     // the first tail level's correction, for the prolongation of the level above
     const ChanDev& C0 = tl.L[0].ch[chid];
-    const int32_t o0 = (nl == 1 || sweeps == 2) ? tv[0].ox : tv[0].oy;
+    const int32_t o0 = (nl == 1 || sweeps % 2 == 0) ? tv[0].ox : tv[0].oy;
     for (int64_t q = threadIdx.x; q < C0.ncell; q += MG_TAIL_BS) tl.L[0].x[C0.c0 + q] = lds[o0 + q];
 }
 

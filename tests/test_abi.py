@@ -108,3 +108,18 @@ def test_binding_refuses_libraries_that_are_not_built():
         clot.load(384)
     assert clot.lib_path(256, True).endswith("libclot_inh.so")
     assert clot.lib_path(1024).endswith("libclot_t1024.so")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libclot.so not built")
+def test_multigrid_sweep_count_is_checked_without_gpu():
+    from paper_2304_09180_amd import clot
+    import clot_inputs as ci
+    lib = clot.load()
+    arr = (clot.Channel * 1)(clot.channel_struct(ci.workload("channel2d_64x16")))
+    for bad in (5, -1):
+        q = clot.Params()
+        lib.clot_params_default(ctypes.byref(q))
+        q.mg_sweeps = bad
+        ctx = ctypes.c_void_p()
+        assert lib.clot_create(arr, 1, ctypes.byref(q), clot.FP64, ctypes.c_void_p(256), 1 << 30, None,
+                               ctypes.byref(ctx)) == -1

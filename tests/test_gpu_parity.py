@@ -127,18 +127,24 @@ def test_release_history_length_is_checked():
         clot.Solver([d], clot.FP64, clot.default_params(clot.FP64, dtau=0.5))
 
 
-@pytest.mark.parametrize("prec_name,descs", [
-    ("FP32_MIXED", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5)]),
-    ("FP32_MIXED", [ci.channel(3, 48, 16, 16, shear=800.0, dt=5e-5, seed=6)]),
-    ("FP64", [ci.channel(2, 40, 12, seed=7), ci.channel(2, 128, 32, shear=400.0, seed=8)]),
+@pytest.mark.parametrize("prec_name,descs,sweeps", [
+    ("FP32_MIXED", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5)], None),
+    ("FP32_MIXED", [ci.channel(3, 48, 16, 16, shear=800.0, dt=5e-5, seed=6)], None),
+    ("FP64", [ci.channel(2, 40, 12, seed=7), ci.channel(2, 128, 32, shear=400.0, seed=8)], None),
+    ("FP32_MIXED", [ci.channel(3, 48, 16, 16, shear=800.0, dt=5e-5, seed=6)], 2),
+    ("FP64", [ci.channel(2, 40, 12, seed=7), ci.channel(2, 128, 32, shear=400.0, seed=8)], 3),
+    ("FP32_MIXED", [ci.channel(3, 48, 16, 16, shear=800.0, dt=5e-5, seed=6)], 4),
+    ("FP64", [ci.channel(2, 40, 12, seed=7), ci.channel(2, 128, 32, shear=400.0, seed=8)], 1),
 ])
-def test_fused_multigrid_tail_is_bitwise_equal_to_separate_launches(prec_name, descs):
+def test_fused_multigrid_tail_is_bitwise_equal_to_separate_launches(prec_name, descs, sweeps):
     """The small levels of the pressure V-cycle in one launch (default) against one
-    launch per level and pass (mg_tail = 0)."""
+    launch per level and pass (mg_tail = 0), with the automatic sweep count (3 on 3-D
+    channels, 2 on 2-D ones) and the others."""
     from paper_2304_09180_amd import clot
     prec = getattr(clot, prec_name)
-    fused, _ = run_gpu(descs, prec, 6)
-    sep, _ = run_gpu(descs, prec, 6, clot.default_params(prec, mg_tail=0))
+    over = {} if sweeps is None else {"mg_sweeps": sweeps}
+    fused, _ = run_gpu(descs, prec, 6, clot.default_params(prec, **over))
+    sep, _ = run_gpu(descs, prec, 6, clot.default_params(prec, mg_tail=0, **over))
     for c in range(len(descs)):
         for name in fused[c]:
             assert np.array_equal(fused[c][name], sep[c][name]), (c, name)
@@ -148,10 +154,12 @@ def test_fused_multigrid_tail_is_bitwise_equal_to_separate_launches(prec_name, d
     ([ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=11)], 5),
     ([ci.channel(3, 24, 10, 9, shear=1000.0, dt=1e-4, seed=12), ci.channel(2, 128, 32, shear=400.0, seed=13)], 4),
 ])
-def test_fp64_single_sweep_multigrid_matches_oracle(descs, steps):
-    """The pressure preconditioner with one Jacobi sweep each way changes only the
-    iteration count: the converged step still matches the oracle."""
+@pytest.mark.parametrize("sweeps", [1, 3, 4])
+def test_fp64_multigrid_sweep_counts_match_oracle(descs, steps, sweeps):
+    """The pressure preconditioner with 1, 3 or 4 Jacobi sweeps each way changes only
+    the iteration count: the converged step still matches the oracle."""
     from paper_2304_09180_amd import clot
-    gpu, st = run_gpu(descs, clot.FP64, steps, clot.default_params(clot.FP64, mg_sweeps=1))
+    gpu, st = run_gpu(descs, clot.FP64, steps, clot.default_params(clot.FP64, mg_sweeps=sweeps))
     for c, d in enumerate(descs):
+        print(sweeps, c, st[c]["it_p"], flush=True)
         compare(gpu[c], run_oracle(d, steps), 1e-10)
