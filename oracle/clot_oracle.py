@@ -20,10 +20,13 @@ Model (paper section 2, Appendices A-E):
     convection, downwind/localMax interpolation of theta_T (Appendix D table),
     the reactive injury-wall conditions (Appendix B, Appendix C table);
   * the reactions by M_rxn sub-steps of classical RK4 (section 3.2 fractional
-    step; Appendix A and B right-hand sides; eqs. seBound_E0/C0 on the wall).
+    step; Appendix A and B right-hand sides; eqs. seBound_E0/C0 on the wall);
+  * optionally Crank-Nicolson off-centring of every ddt term and a variable step
+    at a Courant limit (Appendix D), and the inhibitor of the extensibility
+    example, I + E2 -> E2i (section 3.4).
 
-Readings where the paper is silent or ambiguous are listed in the design notes of
-the repository; the ones that change arithmetic are repeated next to the code.
+Where the paper is silent or ambiguous, the reading taken is stated next to the
+code that depends on it.
 
 Parity status: every function here is pinned by a CPU test against a closed form,
 an invariant, a special case or a printed value of the paper (tests/test_oracle_*).
