@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg may import this module.  It shares no code with the GPU library:
 it assembles every finite-volume system explicitly as a scipy sparse matrix (one
 row per cell, one entry per face coupling) and solves it with a sparse direct
-factorisation (or, above DIRECT_MAX unknowns, a Jacobi-preconditioned Krylov
-solve to a relative residual of 1e-13).  Everything is float64.
+factorisation (the momentum and pressure systems up to FLOW_DIRECT_MAX unknowns,
+the others up to DIRECT_MAX) or else a Jacobi-preconditioned Krylov solve to a
+relative residual of 1e-13.  Everything is float64.
 
 Model (paper section 2, Appendices A-E):
   * Navier-Stokes-Brinkman flow (eq. NSB) with the Carman-Kozeny permeability,
@@ -40,7 +41,13 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-DIRECT_MAX = 400_000
+# Sparse LU limits: the momentum and pressure matrices are factorised up to FLOW_DIRECT_MAX
+# unknowns (once per step: the velocity components share the momentum matrix and every
+# corrector of the step the pressure matrix), the eta and transport systems, which the
+# time derivative makes strongly diagonally dominant, up to DIRECT_MAX; larger systems
+# take a Jacobi-preconditioned Krylov solve to a relative residual of 1e-13.
+FLOW_DIRECT_MAX = 400_000
+DIRECT_MAX = 20_000
 
 # Cell species in library field order.
 SPECIES = ["Pmu", "Pma", "Pba", "Pbse", "ADP", "S1", "S2", "E1", "E2",
@@ -207,7 +214,8 @@ def duct_wall_slope(a, b, nterms=200):
     s = 0.5 * a
     for k in range(nterms):
         n = 2 * k + 1
-        s -= (4.0 * a / (math.pi ** 2 * n ** 2)) / math.cosh(n * math.pi * b / (2.0 * a))
+        x = n * math.pi * b / (2.0 * a)
+        s -= (4.0 * a / (math.pi ** 2 * n ** 2)) * 2.0 * math.exp(-x) / (1.0 + math.exp(-2.0 * x))  # 1/cosh x
     return s
 
 
@@ -323,21 +331,40 @@ class System:
         return (sp.diags(self.diag) + self.offdiag()).tocsr()
 
 
-def solve(M, b, spd):
-    """Solve M x = b: sparse direct factorisation, or a tight Krylov solve for big systems."""
-    if not np.any(b):
-        return np.zeros_like(b)
-    if M.shape[0] <= DIRECT_MAX:
-        return spla.spsolve(M.tocsc(), b)
+def linear_solver(M, spd, direct_max=DIRECT_MAX):
+    """A solve function x = f(b, x0) for M x = b: sparse LU (factorised here, once, for
+    any number of right-hand sides) up to direct_max unknowns, else a Jacobi-preconditioned
+    CG (spd) or BiCGStab solve to a relative residual of 1e-13, started from x0."""
+    n = M.shape[0]
+    if n <= direct_max:
+        lu = spla.splu(M.tocsc(), permc_spec="MMD_AT_PLUS_A")     # structurally symmetric
+
+        def run(b, x0=None):
+            if not np.any(b):
+                return np.zeros_like(b)
+            return lu.solve(b)
+        return run
     d = M.diagonal()
     pre = spla.LinearOperator(M.shape, matvec=lambda v: v / d)
-    if spd:
-        x, info = spla.cg(M, b, rtol=1e-13, atol=0.0, maxiter=100000, M=pre)
-    else:
-        x, info = spla.bicgstab(M, b, rtol=1e-13, atol=0.0, maxiter=100000, M=pre)
-    if info != 0:
-        raise RuntimeError(f"oracle Krylov solve did not converge (info={info})")
-    return x
+    method = spla.cg if spd else spla.bicgstab
+
+    def run(b, x0=None):
+        if not np.any(b):
+            return np.zeros_like(b)
+        # solved for b/||b||: scipy's breakdown tests are absolute, and a right-hand side
+        # as small as a species not yet produced (~1e-20) would trip them at once
+        s = float(np.linalg.norm(b))
+        x, info = method(M, b / s, x0=None if x0 is None else x0 / s, rtol=1e-13, atol=0.0,
+                         maxiter=100000, M=pre)
+        if info != 0:
+            raise RuntimeError(f"oracle Krylov solve did not converge (info={info})")
+        return x * s
+    return run
+
+
+def solve(M, b, spd, x0=None):
+    """Solve M x = b once (see linear_solver)."""
+    return linear_solver(M, spd)(b, x0)
 
 
 # --------------------------------------------------------------------------------------
@@ -631,11 +658,31 @@ class Oracle:
         M = S.matrix()
         Noff = S.offdiag()
         gp = self.grad_p(self.p_)
+        mom = linear_solver(M, spd=False, direct_max=FLOW_DIRECT_MAX)   # the components share M
         for c in range(ncomp):
-            self.u[c] = solve(M, src[c] - m.V * gp[c], spd=False)
+            self.u[c] = mom(src[c] - m.V * gp[c], self.u[c])
         aP = S.diag
         rAU = m.V / aP
         ids = m.idx
+        # pressure matrix: sum_f c_f (p_P - p_N) + c_out p_P, c_f = rAU_f A/d; rAU is fixed
+        # by the predictor, so every corrector of the step solves with the same matrix
+        K = System(m.n)
+        r3 = rAU.reshape(m.shape)
+        coefs = []
+        for a, (ax, A, d) in enumerate(m.axes):
+            L, R = _pair_slices(ax)
+            cf = 0.5 * (r3[L] + r3[R]) * A / d
+            coefs.append(cf)
+            iL, iR = ids[L], ids[R]
+            np.add.at(K.diag, iL.ravel(), cf.ravel())
+            np.add.at(K.diag, iR.ravel(), cf.ravel())
+            K.couple(iL, iR, -cf)
+            K.couple(iR, iL, -cf)
+        Ax, dx = m.axes[0][1], m.axes[0][2]
+        out = ids[:, :, -1].ravel()
+        c_out = r3[:, :, -1].ravel() * 2.0 * Ax / dx
+        np.add.at(K.diag, out, c_out)
+        pres = linear_solver(K.matrix(), spd=True, direct_max=FLOW_DIRECT_MAX)
         for _ in range(self.n_correctors()):
             HbyA = np.zeros((3, m.n))
             for c in range(ncomp):
@@ -651,32 +698,17 @@ class Oracle:
                     f[_face_at(ax, 0)] = A * self.u_in.reshape(m.nz, m.ny)
                     f[_face_at(ax, -1)] = A * h3[_cell_at(ax, -1)]
                 phiH.append(f)
-            # pressure system: sum_f c_f (p_P - p_N) + c_out p_P = -div(phiH) + c_out p_out
-            K = System(m.n)
+            # pressure equation: K p = -div(phiH) + c_out p_out, warm-started from p
             div = np.zeros(m.shape)
-            r3 = rAU.reshape(m.shape)
-            coefs = []
             for a, (ax, A, d) in enumerate(m.axes):
                 hi = [slice(None)] * 3
                 lo = [slice(None)] * 3
                 hi[ax] = slice(1, None)
                 lo[ax] = slice(0, -1)
                 div += phiH[a][tuple(hi)] - phiH[a][tuple(lo)]
-                L, R = _pair_slices(ax)
-                cf = 0.5 * (r3[L] + r3[R]) * A / d
-                coefs.append(cf)
-                iL, iR = ids[L], ids[R]
-                np.add.at(K.diag, iL.ravel(), cf.ravel())
-                np.add.at(K.diag, iR.ravel(), cf.ravel())
-                K.couple(iL, iR, -cf)
-                K.couple(iR, iL, -cf)
-            Ax, dx = m.axes[0][1], m.axes[0][2]
-            out = ids[:, :, -1].ravel()
-            c_out = r3[:, :, -1].ravel() * 2.0 * Ax / dx
-            np.add.at(K.diag, out, c_out)
-            K.rhs = -div.ravel()
-            K.rhs[out] += c_out * p.p_out
-            self.p_ = solve(K.matrix(), K.rhs, spd=True)
+            rhs = -div.ravel()
+            rhs[out] += c_out * p.p_out
+            self.p_ = pres(rhs, self.p_)
             p3 = self.p_.reshape(m.shape)
             for a, (ax, A, d) in enumerate(m.axes):
                 L, R = _pair_slices(ax)
@@ -718,7 +750,7 @@ class Oracle:
             np.add.at(S.diag, iR.ravel(), c)
             S.couple(iL, iR, -c)
             S.couple(iR, iL, -c)
-        return solve(S.matrix(), m.V * thetaB, spd=True)
+        return solve(S.matrix(), m.V * thetaB, spd=True, x0=self.eta)
 
     # ---- O-4 sigma ---------------------------------------------------------------------------
     def sigma_update(self, thetaB):
@@ -856,7 +888,7 @@ class Oracle:
         out = {}
         for name in self.transported:
             S = self.transport_system(name, thetaT)
-            out[name] = solve(S.matrix(), S.rhs, spd=False)
+            out[name] = solve(S.matrix(), S.rhs, spd=False, x0=self.c[self.sp[name]])
         k_dt, w_dt = self.ddt_coeffs()
         for name, v in out.items():
             self.ddt0c[name] = k_dt * (v - self.c[self.sp[name]]) / self.dt - w_dt * self.ddt0c[name]
