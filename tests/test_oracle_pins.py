@@ -529,3 +529,180 @@ def test_limiter_linear_profile_is_central():
     D = oc.Params().D_chem
     for i in range(1, 6):       # faces i|i+1 with a far-upwind cell i-1
         assert M[i, i + 1] == pytest.approx(1e-6 * 0.5 - D * A / d, rel=1e-12)
+
+
+# ----------------------------------------------------------------------------------------
+# Momentum convection (section 2, eq. NSB; Appendix D table: Gauss linear div(phi,U))
+# ----------------------------------------------------------------------------------------
+
+def _stream_field(Lx, Ly, amp):
+    """A divergence-free velocity u = d(psi)/dy, v = -d(psi)/dx from psi = amp sin(ax + .3) sin(by + .2),
+    with its closed-form first derivatives; both components satisfy lap f = -(a^2 + b^2) f."""
+    a, b = math.pi / Lx, 2.0 * math.pi / Ly
+
+    def psi(x, y):
+        return amp * np.sin(a * x + 0.3) * np.sin(b * y + 0.2)
+
+    def fields(x, y):
+        sx, cx = np.sin(a * x + 0.3), np.cos(a * x + 0.3)
+        sy, cy = np.sin(b * y + 0.2), np.cos(b * y + 0.2)
+        u, v = amp * b * sx * cy, -amp * a * cx * sy
+        ux, uy = amp * a * b * cx * cy, -amp * b * b * sx * sy
+        vx, vy = amp * a * a * sx * sy, -amp * a * b * cx * cy
+        return u, v, ux, uy, vx, vy
+    return psi, fields, a * a + b * b
+
+
+def test_momentum_convection_is_central_second_order():
+    """The momentum operator applied to a smooth divergence-free field, with face fluxes
+    integrated exactly from its stream function, approximates (u.grad)u - nu lap u at
+    second order in interior cells (Gauss linear convection of eq. NSB).  Dropping the
+    convection leaves an O(1) error; upwind convection an O(h) one; either fails."""
+    Lx, Ly = 1.0, 0.5
+    psi, fields, k2 = _stream_field(Lx, Ly, 40.0)
+    errs = []
+    conv_share = []
+    for n in (16, 32, 64):
+        desc = ci.channel(2, 2 * n, n, dt=1e-3, Lx=Lx, Ly=Ly)
+        o = quiet_oracle(desc)
+        m = o.m
+        xf = np.arange(m.nx + 1) * m.dx
+        yf = np.arange(m.ny + 1) * m.dy
+        X, Yt = np.meshgrid(xf, yf[1:])
+        _, Yb = np.meshgrid(xf, yf[:-1])
+        o.phi[0][0] = m.dz * (psi(X, Yt) - psi(X, Yb))          # exact flux through each x face
+        Xr, Y = np.meshgrid(xf[1:], yf)
+        Xl, _ = np.meshgrid(xf[:-1], yf)
+        o.phi[1][0] = -m.dz * (psi(Xr, Y) - psi(Xl, Y))         # and each y face
+        u, v, ux, uy, vx, vy = fields(m.xc, m.yc)
+        o.u[0], o.u[1] = u, v
+        S, src = o.momentum_system(np.zeros(m.n))
+        M = S.matrix()
+        nu = o.p.nu
+        want = (u * ux + v * uy + nu * k2 * u, u * vx + v * vy + nu * k2 * v)
+        inner = m.idx[0][1:-1, 1:-1].ravel()
+        e = 0.0
+        for c in range(2):
+            got = (M @ o.u[c] - src[c]) / m.V        # the time terms cancel: u^n is the field itself
+            e = max(e, np.abs(got[inner] - want[c][inner]).max() / np.abs(want[c][inner]).max())
+        errs.append(e)
+        conv_share.append(np.abs(u * ux + v * uy).max() / np.abs(want[0]).max())
+    assert min(conv_share) > 0.3          # convection is a large part of what is checked
+    orders = observed_orders(errs)
+    assert errs[-1] < 6e-3 and min(orders) > 1.8, (errs, orders)
+
+
+def test_developing_flow_closes_the_momentum_balance():
+    """Plug inflow into a 2-D channel at Re = 100, marched to steady state: the x-momentum of
+    eq. NSB integrated over the channel balances, to round-off, the momentum carried in and
+    out, the pressure force on the inlet and outlet, the viscous force on the inlet face and
+    the wall shear.  The profile develops, so the outflow carries 18% more momentum than
+    the inflow: without convection the balance would miss by that much."""
+    nx, ny, U = 48, 12, 40.0
+    p = oc.Params(nu=0.1)
+    desc = ci.channel(2, nx, ny, dt=2e-3, Lx=1.0, Ly=0.25)
+    o = quiet_oracle(desc, p, inlet_u=np.full(ny, U))
+    o.u[0][:] = U
+    o.phi[0][:] = o.m.axes[0][1] * U
+    for _ in range(80):
+        u0 = o.u.copy()
+        o.flow_step(np.zeros(o.m.n))
+    assert np.abs(o.u - u0).max() < 1e-12 * U            # steady
+    m = o.m
+    A, d = m.axes[0][1], m.axes[0][2]
+    Ay, dy = m.axes[1][1], m.axes[1][2]
+    ux = o.u[0].reshape(m.shape)
+    P = o.p_.reshape(m.shape)
+    flux_in = float(np.sum(o.phi[0][:, :, 0] * U))
+    flux_out = float(np.sum(o.phi[0][:, :, -1] * ux[:, :, -1]))     # zero-gradient outlet value
+    pressure = float(np.sum(P[:, :, 0]) * A - np.sum(np.full(ny, p.p_out)) * A)
+    visc_in = float(np.sum(2.0 * p.nu * A / d * (U - ux[:, :, 0])))  # half-cell gradient at the inlet
+    shear = float(np.sum(2.0 * p.nu * Ay / dy * (ux[:, 0, :] + ux[:, -1, :])))
+    assert flux_out / flux_in > 1.1
+    assert abs(flux_in - flux_out + pressure + visc_in - shear) < 1e-10 * flux_in
+
+
+# ----------------------------------------------------------------------------------------
+# The limiter and hindrance on reversed flow (Appendix D: van Leer, downwind, localMax)
+# ----------------------------------------------------------------------------------------
+
+def _mirror(o, axis):
+    """Mirror a copy of the oracle's state along a mesh axis ('x', 'y' or 'z'): cell values
+    and tangential fluxes move to the image cell/face, normal fluxes also change sign.
+    Returns the permutation q with (mirrored field)[q] = field."""
+    m = o.m
+    nax = {"x": 2, "y": 1, "z": 0}[axis]
+    q = np.flip(m.idx, axis=nax).ravel()
+    q_inv = np.empty_like(q)
+    q_inv[q] = np.arange(q.size)
+    flip = lambda a3: np.flip(a3, axis=nax)
+    o.c = o.c[:, q]
+    for a, (ax, A, d) in enumerate(m.axes):
+        f = flip(o.phi[a])
+        o.phi[a] = -f if ax == nax else f.copy()
+    return q
+
+
+def _mirrored_system_check(desc, name, axis, rng):
+    o = quiet_oracle(desc)
+    m = o.m
+    p = o.p
+    scale = p.P_max if name in ("Pmu", "Pma") else 1e-6
+    # C^n with both signs of the slopes, a few platelet values outside [0, P_max]
+    c = scale * rng.uniform(0.0, 1.0, m.n)
+    if name in ("Pmu", "Pma"):
+        c[rng.integers(0, m.n, 3)] = 1.2 * p.P_max
+    o.c[o.sp[name]] = c
+    for a in range(len(m.axes)):
+        o.phi[a] = 1e-5 * rng.standard_normal(o.phi[a].shape)     # fluxes of both signs
+    thT = rng.uniform(0.0, 1.1, m.n)
+    M = o.transport_system(name, thT).matrix().toarray()
+    rhs = o.transport_system(name, thT).rhs
+    o2 = quiet_oracle(desc)
+    o2.c = o.c.copy()
+    o2.phi = [f.copy() for f in o.phi]
+    q = _mirror(o2, axis)
+    # mirrored state: cell a of the original sits at q_inv[a]; the system must be the image
+    q_inv = np.empty_like(q)
+    q_inv[q] = np.arange(q.size)
+    S2 = o2.transport_system(name, thT[q])
+    M2 = S2.matrix().toarray()
+    assert np.allclose(M2[np.ix_(q_inv, q_inv)], M, rtol=1e-12, atol=1e-12 * np.abs(M).max())
+    assert np.allclose(S2.rhs[q_inv], rhs, rtol=1e-12, atol=0.0)
+
+
+@pytest.mark.parametrize("name", ["E2", "Pma"])
+def test_transport_system_is_mirror_symmetric_along_x(name):
+    """Reversing the flow along x and mirroring C^n, theta_T and the fluxes gives the mirrored
+    matrix (species with zero-gradient inlet and outlet, so the ends swap roles): the
+    negative-flux faces take their far-upwind cell at R + 1 as the positive ones take L - 1."""
+    rng = np.random.default_rng(11)
+    desc = ci.channel(2, 9, 5, dt=1e-3, Lx=9e-3, Ly=5e-3)
+    _mirrored_system_check(desc, name, "x", rng)
+
+
+@pytest.mark.parametrize("name", ["E2", "Pmu", "S2"])
+def test_transport_system_is_mirror_symmetric_along_y_and_z(name):
+    """The same symmetry across the channel (both walls alike for species without an injury
+    term; the inlet profiles are symmetric about the centre line) and, in 3-D, along z."""
+    rng = np.random.default_rng(12)
+    _mirrored_system_check(ci.channel(2, 6, 9, dt=1e-3, Lx=6e-3, Ly=9e-3, inj_frac=0.0), name, "y", rng)
+    d3 = ci.channel(3, 5, 6, 7, dt=1e-3, Lx=5e-3, Ly=6e-3, Lz=7e-3, inj_frac=0.0)
+    _mirrored_system_check(d3, name, "y", rng)
+    _mirrored_system_check(d3, name, "z", rng)
+
+
+def test_limiter_linear_profile_is_central_on_reversed_flow():
+    """On a linear C^n profile with negative flux, r = 1 again (far-upwind cell R + 1), so the
+    faces with a far-upwind cell use the central average."""
+    desc = ci.channel(2, 8, 1, dt=1e-3, Lx=8e-3, Ly=1e-3)
+    o = quiet_oracle(desc)
+    o.phi[0][:] = -1e-6
+    o.phi[1][:] = 0.0
+    o.c[oc.SP["E2"]] = 1e-6 * (1.0 + np.arange(8))
+    M = o.transport_system("E2", np.zeros(8)).matrix().toarray()
+    A, d = o.m.axes[0][1], o.m.axes[0][2]
+    D = oc.Params().D_chem
+    for i in range(0, 6):       # faces i|i+1 with a far-upwind cell i+2
+        assert M[i, i + 1] == pytest.approx(-1e-6 * 0.5 - D * A / d, rel=1e-12)
+        assert M[i + 1, i] == pytest.approx(1e-6 * 0.5 - D * A / d, rel=1e-12)
