@@ -20,7 +20,8 @@
  *
  * Conventions
  *   - Every call returns clot_status: 0 success, >0 warning (state valid),
- *     <0 error (state unchanged; clot_last_error() says why).
+ *     <0 error (state unchanged; clot_last_error() says why).  A channel index
+ *     outside [0, n_ch) is an error (CLOT_EINVAL).
  *   - Units: mm, s, nmol, platelets/mm^3 (Appendix E tables).
  *   - Cell fields cross the ABI as float64 in x-fastest order, cell id
  *     i + nx*(j + ny*k).  Face fluxes (mm^3/s, positive along +axis) are x-faces
@@ -46,14 +47,17 @@ typedef enum {
     CLOT_OK = 0,
     CLOT_W_NOTCONV = 1,     /* a linear solve stopped at max_iter; the step completed        */
     CLOT_W_FALLBACK = 2,    /* surrogate step: some cells fell back to the plain integrator  */
-    CLOT_W_NONFINITE = 3,   /* a linear solve met a NaN or infinity (in the fields or its
-                               system) and stopped; the fields are not valid                 */
+    CLOT_W_NONFINITE = 3,   /* reported by clot_get_stats: a linear solve met a NaN or
+                               infinity (in the fields or its system) and stopped; the call
+                               that ran it returned CLOT_ENAN and rolled the state back      */
     CLOT_EINVAL = -1,       /* bad argument                                                  */
     CLOT_ENOMEM = -2,       /* workspace too small                                           */
     CLOT_EWORKSPACE = -3,   /* workspace pointer misaligned                                  */
     CLOT_EHIP = -4,         /* a HIP runtime call failed                                     */
     CLOT_ESTATE = -5,       /* call not valid in the current state                           */
-    CLOT_ENAN = -6          /* a non-finite value appeared                                   */
+    CLOT_ENAN = -6          /* a non-finite value appeared: clot_set_field refuses it; a
+                               step call (or the clot_sync that closes asynchronous steps)
+                               restores the state of the call's start                         */
 } clot_status;
 
 typedef enum { CLOT_FP64 = 0, CLOT_FP32_MIXED = 1 } clot_precision;
@@ -187,11 +191,22 @@ clot_status clot_field_count(const clot_ctx* c, int32_t ch, clot_field f, size_t
 clot_status clot_set_field(clot_ctx* c, int32_t ch, clot_field f, const double* host, size_t n);
 clot_status clot_get_field(clot_ctx* c, int32_t ch, clot_field f, double* host, size_t n);
 
-/* Advances every channel by nsteps time steps; blocks until done. */
+/* Advances every channel by nsteps time steps; blocks until done.  Before the first
+ * step the call copies the context's persistent state (fields, fluxes, clocks, release
+ * and time-derivative histories) aside in its workspace, on the context stream; after
+ * the last it scans the velocity, pressure and species for NaN or infinity.  If the scan
+ * or any linear-solve reduction of the call met one, the state of the call's start is
+ * restored (every channel) and CLOT_ENAN is returned; clot_get_stats then reports the
+ * failed step's statistics and CLOT_W_NONFINITE. */
 clot_status clot_step(clot_ctx* c, int32_t nsteps);
 
 /* Enqueues nsteps steps on the context stream without waiting; returns a warning
- * only through clot_get_stats after a later synchronising call. */
+ * only through clot_get_stats after a later synchronising call.  The first
+ * asynchronous call after a synchronisation opens a window (the state is copied aside
+ * as by clot_step); clot_sync closes it with the same scan and, on a non-finite value,
+ * restores the window's start and returns CLOT_ENAN.  clot_set_field, clot_init_state
+ * and clot_load_state end an open window without a check (the state they set is the
+ * next window's start). */
 clot_status clot_step_async(clot_ctx* c, int32_t nsteps);
 clot_status clot_sync(clot_ctx* c);
 
@@ -203,8 +218,10 @@ clot_status clot_get_stats(const clot_ctx* c, int32_t ch, clot_stats* s);
  * (channel clocks and step counts, buffer parity, solver budgets, reaction mode); it
  * goes to and from a host blob of clot_state_size bytes, owned by the caller.
  * clot_load_state accepts a blob saved from a context created with the same channels
- * (dimensions and grids), precision and workspace size, else CLOT_EINVAL and the
- * context is unchanged; the model parameters remain the loading context's.  Both calls
+ * (every field of every clot_channel equal: the blob holds channel tables and clocks
+ * built from them), precision and workspace size, else CLOT_EINVAL and the context is
+ * unchanged; the model parameters remain the loading context's (its inflow profiles are
+ * rebuilt from them after the load).  Both calls
  * wait for the context's streams; recorded graphs are dropped on load (graph mode
  * calibrates again).  Steps after a load continue bit for bit as from the saved one. */
 clot_status clot_state_size(const clot_ctx* c, size_t* bytes);

@@ -73,6 +73,7 @@ struct ChanHost {
 
 struct clot_ctx {
     clot_precision prec;
+    int32_t nchan = 0;
     std::string err;
     virtual ~clot_ctx() {}
     virtual clot_status init_state(int ch, const double* xc, size_t nc, const double* xf, size_t nf) = 0;
@@ -215,6 +216,14 @@ struct Ctx : clot_ctx {
     double probe_ms = 0.0;
     int64_t probe_n = 0;
     bool nonconv = false;
+    // rollback: a step call that meets a non-finite value restores the state of its start
+    char* snap = nullptr;             // device copy of the persistent state
+    size_t state_bytes = 0;           // the persistent state: the workspace's first bytes
+    int32_t* nanflag = nullptr;       // device: [0] a reduction met a NaN or infinity, [1] the state scan did
+    bool snap_valid = false;          // a copy of the current call window's start exists
+    int snap_parity = 0;
+    Fields<T> snap_F{};
+    std::vector<int64_t> snap_n;
     Grid grid() const { return Grid{d_ch, d_t2c, ntiles}; }
     ~Ctx() override {
         drop_graphs();
@@ -309,6 +318,9 @@ struct Ctx : clot_ctx {
     size_t layout(char* base) {
         Carver cv{base};
         const int nch = (int)ch.size();
+        // the persistent state first (what a step reads from the previous one: fields,
+        // clocks, histories, and the constant tables), one contiguous range that a step
+        // call copies aside and restores if it meets a non-finite value
         d_ch = cv.take<ChanDev>(nch);
         d_t2c = cv.take<int32_t>(ntiles);
         d_f2c = cv.take<int32_t>(std::max<int64_t>(NINJ, 1));
@@ -321,7 +333,6 @@ struct Ctx : clot_ctx {
         F.phin[1] = cv.take<T>(NFY);
         F.phin[2] = cv.take<T>(std::max<int64_t>(NFZ, 1));
         for (int s = 0; s < NSPC; ++s) F.spc[s] = cv.take<T>(N);
-        for (int k = 0; k < NTR; ++k) F.xt[k] = cv.take<T>(N);
         const int64_t ni = std::max<int64_t>(NINJ, 1);
         F.E0 = cv.take<T>(ni);
         F.C0 = cv.take<T>(ni);
@@ -329,13 +340,21 @@ struct Ctx : clot_ctx {
         F.eta = cv.take<T>(N);
         F.thB = cv.take<T>(N);
         F.thB_prev = cv.take<T>(N);
-        F.Wc = cv.take<T>(N);
         F.sigma = cv.take<T>(N);
         F.hist = cv.take<T>((size_t)N * NHIST);
         u_in = cv.take<T>(NIN);
         pmu_in = cv.take<T>(NIN);
         F.u_in = u_in;
         F.pmu_in = pmu_in;
+        for (int c = 0; c < 3; ++c) F.ddt0u[c] = cv.take<T>(N);
+        for (int k = 0; k < NTR; ++k) F.ddt0c[k] = cv.take<T>(N);
+        allmask = cv.take<int32_t>(nch);
+        corrmask = cv.take<int32_t>((size_t)MAXCORR * nch);
+        sig = cv.take<SigState>(nch);
+        state_bytes = (cv.off + 255) & ~size_t(255);
+        // per-step scratch
+        for (int k = 0; k < NTR; ++k) F.xt[k] = cv.take<T>(N);
+        F.Wc = cv.take<T>(N);
         F.aP = cv.take<T>(N);
         for (int c = 0; c < 3; ++c) F.src[c] = cv.take<T>(N);
         for (int c = 0; c < 3; ++c) F.bm[c] = cv.take<T>(N);
@@ -347,8 +366,6 @@ struct Ctx : clot_ctx {
         for (int k = 0; k < NTR; ++k) F.trd[k] = cv.take<T>(N);
         for (int k = 0; k < NTR; ++k) F.trb[k] = cv.take<T>(N);
         for (int k = 0; k < NTR; ++k) F.trc[k] = cv.take<T>((size_t)6 * N);
-        for (int c = 0; c < 3; ++c) F.ddt0u[c] = cv.take<T>(N);
-        for (int k = 0; k < NTR; ++k) F.ddt0c[k] = cv.take<T>(N);
         F.co_part = cv.take<double>(ntiles);
         for (int q = 0; q < NPOOL; ++q) pool[q] = cv.take<T>(N);
         F.ncell = N;
@@ -359,18 +376,18 @@ struct Ctx : clot_ctx {
         S.part = cv.take<double>((size_t)ntiles * NPART);
         S.tick = cv.take<uint32_t>(nch);
         refmask = cv.take<int32_t>(nch);
-        allmask = cv.take<int32_t>(nch);
-        corrmask = cv.take<int32_t>((size_t)MAXCORR * nch);
         sigw = cv.take<double>((size_t)nch * NHIST);
         push = cv.take<int32_t>((size_t)nch * 2);
         dstats = cv.take<double>((size_t)nch * NSTAT);
-        sig = cv.take<SigState>(nch);
         gflag = cv.take<int32_t>(1);
+        nanflag = cv.take<int32_t>(2);
+        S.nanflag = nanflag;
         Se.maxit = prm.max_iter;
         Se.sc = cv.take<double>((size_t)nch * MAXK * NSC);
         Se.chact = cv.take<int32_t>(nch);
         Se.nact = cv.take<int32_t>(1);
         Se.part = cv.take<double>((size_t)ntiles * NPART);
+        Se.nanflag = nanflag;
         for (int q = 0; q < 5; ++q) eta_v[q] = cv.take<T>(N);
         eta_info = cv.take<int32_t>(2);
         mg_y0 = cv.take<T>(N);
@@ -393,6 +410,7 @@ struct Ctx : clot_ctx {
             L.cy = cv.take<T>(L.NFY);
             L.cz = cv.take<T>(L.NFZ);
         }
+        snap = cv.take<char>(state_bytes);
         return cv.off + 256;
     }
 
@@ -685,7 +703,19 @@ struct Ctx : clot_ctx {
         std::vector<SigState> sv(nch, fresh_sig());
         HIPCHK(hipMemcpyAsync(sig, sv.data(), nch * sizeof(SigState), hipMemcpyHostToDevice, st));
         fill(gflag, 0, 1);
-        // inflow profiles (Appendix C.1 / C.2)
+        clot_status r = upload_inflow();
+        if (r) return r;
+        std::vector<uint32_t> z(nch, 0);
+        HIPCHK(hipMemcpy(S.tick, z.data(), nch * 4, hipMemcpyHostToDevice));
+        std::vector<double> zs((size_t)nch * NSTAT, 0.0);
+        HIPCHK(hipMemcpy(dstats, zs.data(), zs.size() * 8, hipMemcpyHostToDevice));
+        return CLOT_OK;
+    }
+
+    // inflow profiles of every channel (Appendix C.1 / C.2), from the host descriptors
+    // and this context's parameters
+    clot_status upload_inflow() {
+        const int nch = (int)ch.size();
         std::vector<T> ui(NIN), pi(NIN);
         for (int i = 0; i < nch; ++i) {
             const ChanHost& h = ch[i];
@@ -699,10 +729,6 @@ struct Ctx : clot_ctx {
         HIPCHK(hipMemcpyAsync(u_in, ui.data(), NIN * sizeof(T), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(pmu_in, pi.data(), NIN * sizeof(T), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
-        std::vector<uint32_t> z(nch, 0);
-        HIPCHK(hipMemcpy(S.tick, z.data(), nch * 4, hipMemcpyHostToDevice));
-        std::vector<double> zs((size_t)nch * NSTAT, 0.0);
-        HIPCHK(hipMemcpy(dstats, zs.data(), zs.size() * 8, hipMemcpyHostToDevice));
         return CLOT_OK;
     }
 
@@ -746,6 +772,7 @@ struct Ctx : clot_ctx {
     }
 
     clot_status init_state(int c, const double* xc, size_t nc, const double* xf, size_t nf) override {
+        snap_valid = false;
         ChanHost& h = ch[c];
         const int64_t n = h.ncell;
         if (nc != (size_t)(NSPC_DRAWN * n) || nf != (size_t)(2 * h.ninj) || (!xc && nc) || (!xf && nf)) {
@@ -924,6 +951,7 @@ struct Ctx : clot_ctx {
                 err = "set_field: non-finite value";
                 return CLOT_ENAN;
             }
+        snap_valid = false;   // a state changed between steps starts a new call window
         if (r.dbl) {
             HIPCHK(hipMemcpyAsync(r.ptr, h, n * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -1595,7 +1623,44 @@ struct Ctx : clot_ctx {
         return CLOT_OK;
     }
 
+    // ---- rollback of a call window that meets a non-finite value ------------------
+    // The persistent state (the workspace's first state_bytes) is copied aside on the
+    // stream when a window opens: at a blocking clot_step, or at the first
+    // clot_step_async after a synchronisation.  The synchronisation that closes it scans
+    // the fields; if they or any reduction of the window met a NaN or infinity, the copy
+    // is put back with the host side of the window's start (buffer parity, step counts).
+    clot_status snapshot() {
+        HIPCHK(hipMemcpyAsync(snap, ws_base, state_bytes, hipMemcpyDeviceToDevice, st));
+        fill(nanflag, 0, 2);
+        snap_parity = parity;
+        snap_F = F;
+        snap_n.resize(ch.size());
+        for (size_t i = 0; i < ch.size(); ++i) snap_n[i] = ch[i].n;
+        snap_valid = true;
+        return CLOT_OK;
+    }
+    clot_status close_window() {
+        snap_valid = false;
+        hipLaunchKernelGGL(k_nonfinite_scan<T>, dim3(ntiles), dim3(NT), 0, st, grid(), F, NINJ, nanflag + 1);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h_nact + 8, nanflag, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!h_nact[8] && !h_nact[9]) return CLOT_OK;
+        HIPCHK(hipMemcpyAsync(ws_base, snap, state_bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        F = snap_F;
+        parity = snap_parity;
+        for (size_t i = 0; i < ch.size(); ++i) ch[i].n = snap_n[i];
+        err = std::string("a non-finite value appeared (") + (h_nact[8] ? "in a linear solve" : "in the fields") +
+              "); the state is rolled back to the start of the call";
+        return CLOT_ENAN;
+    }
+
     clot_status step(int nsteps, bool wait) override {
+        if (!snap_valid) {
+            const clot_status r = snapshot();
+            if (r < 0) return r;
+        }
         for (int s = 0; s < nsteps; ++s) {
             if (graph_on && calib_left == 0) {
                 if (gseg[parity].empty()) {
@@ -1629,6 +1694,7 @@ struct Ctx : clot_ctx {
                 drop_graphs();
             }
         }
+        if (snap_valid) return close_window();
         return CLOT_OK;
     }
 
@@ -1673,8 +1739,8 @@ struct Ctx : clot_ctx {
     };
     struct StateChan {
         int64_t n;
-        double t;     // the channel's simulated time (informative: the clock is in the workspace)
-        int32_t dim, nx, ny, nz;
+        double t;          // the channel's simulated time (informative: the clock is in the workspace)
+        clot_channel d;    // the descriptor: the workspace's channel tables derive from it
     };
     static constexpr uint64_t STATE_MAGIC = 0x54415453544f4c43ull;   // "CLOTSTAT"
     clot_status state_size(size_t* bytes) const override {
@@ -1692,7 +1758,7 @@ struct Ctx : clot_ctx {
         if (st2) HIPCHK(hipStreamSynchronize(st2));
         StateHead h{};
         h.magic = STATE_MAGIC;
-        h.version = 1;
+        h.version = 2;
         h.prec = (int32_t)prec;
         h.nch = (int32_t)ch.size();
         h.parity = parity;
@@ -1715,7 +1781,10 @@ struct Ctx : clot_ctx {
         p += sizeof(h);
         for (size_t i = 0; i < ch.size(); ++i) {
             const ChanHost& c = ch[i];
-            StateChan sc{c.n, clocks[i].t, c.d.dim, c.d.nx, c.d.ny, c.d.nz};
+            StateChan sc{};
+            sc.n = c.n;
+            sc.t = clocks[i].t;
+            sc.d = c.d;
             std::memcpy(p, &sc, sizeof(sc));
             p += sizeof(sc);
         }
@@ -1733,7 +1802,7 @@ struct Ctx : clot_ctx {
         const char* p = static_cast<const char*>(host);
         std::memcpy(&h, p, sizeof(h));
         p += sizeof(h);
-        if (h.magic != STATE_MAGIC || h.version != 1 || h.prec != (int32_t)prec || h.nch != (int32_t)ch.size() ||
+        if (h.magic != STATE_MAGIC || h.version != 2 || h.prec != (int32_t)prec || h.nch != (int32_t)ch.size() ||
             h.N != N || h.NFX != NFX || h.NFY != NFY || h.NFZ != NFZ || h.NINJ != NINJ || h.ntiles != ntiles ||
             h.ws != (int64_t)ws_bytes || (h.parity != 0 && h.parity != 1)) {
             err = "load_state: the blob was saved from a context of another layout";
@@ -1743,8 +1812,9 @@ struct Ctx : clot_ctx {
         for (size_t i = 0; i < ch.size(); ++i) {
             std::memcpy(&sc[i], p, sizeof(StateChan));
             p += sizeof(StateChan);
-            const clot_channel& d = ch[i].d;
-            if (sc[i].dim != d.dim || sc[i].nx != d.nx || sc[i].ny != d.ny || sc[i].nz != d.nz) {
+            // every field of the descriptor (extents, injury patch, shear, margination, step)
+            // must match: the blob carries the channel tables and clocks built from it
+            if (std::memcmp(&sc[i].d, &ch[i].d, sizeof(clot_channel)) != 0) {
                 err = "load_state: channel " + std::to_string(i) + " differs from the saved one";
                 return CLOT_EINVAL;
             }
@@ -1752,7 +1822,12 @@ struct Ctx : clot_ctx {
         HIPCHK(hipStreamSynchronize(st));
         if (st2) HIPCHK(hipStreamSynchronize(st2));
         drop_graphs();
+        snap_valid = false;
         HIPCHK(hipMemcpy(ws_base, p, ws_bytes, hipMemcpyHostToDevice));
+        {   // the inflow profiles follow this context's parameters
+            const clot_status r = upload_inflow();
+            if (r) return r;
+        }
         for (size_t i = 0; i < ch.size(); ++i) {
             ch[i].n = sc[i].n;
         }
@@ -1858,6 +1933,7 @@ static clot_status create_t(Ctx<T>* c, const clot_channel* chs, int n_ch, const 
         return CLOT_EWORKSPACE;
     }
     c->layout((char*)ws);
+    c->nchan = n_ch;
     c->ws_base = (char*)ws;
     c->ws_bytes = need;
     c->st = (hipStream_t)stream;
@@ -1987,23 +2063,28 @@ clot_status clot_create(const clot_channel* chs, int32_t n_ch, const clot_params
     return CLOT_OK;
 }
 
-#define CTXCHK(c, chn)                                        \
-    if (!(c)) return CLOT_EINVAL;
+// A channel index outside [0, n_ch) is refused before anything is touched.
+static bool bad_channel(const clot_ctx* c, int32_t chn) {
+    if (chn >= 0 && chn < c->nchan) return false;
+    const_cast<clot_ctx*>(c)->err =
+        "channel index " + std::to_string(chn) + " outside [0, " + std::to_string(c->nchan) + ")";
+    return true;
+}
 
 clot_status clot_init_state(clot_ctx* c, int32_t chn, const double* xc, size_t nc, const double* xf, size_t nf) {
-    if (!c) return CLOT_EINVAL;
+    if (!c || bad_channel(c, chn)) return CLOT_EINVAL;
     return c->init_state(chn, xc, nc, xf, nf);
 }
 clot_status clot_field_count(const clot_ctx* c, int32_t chn, clot_field f, size_t* n) {
-    if (!c || !n) return CLOT_EINVAL;
+    if (!c || !n || bad_channel(c, chn)) return CLOT_EINVAL;
     return c->count(chn, f, n);
 }
 clot_status clot_set_field(clot_ctx* c, int32_t chn, clot_field f, const double* h, size_t n) {
-    if (!c) return CLOT_EINVAL;
+    if (!c || bad_channel(c, chn)) return CLOT_EINVAL;
     return c->set(chn, f, h, n);
 }
 clot_status clot_get_field(clot_ctx* c, int32_t chn, clot_field f, double* h, size_t n) {
-    if (!c) return CLOT_EINVAL;
+    if (!c || bad_channel(c, chn)) return CLOT_EINVAL;
     return c->get(chn, f, h, n);
 }
 clot_status clot_step(clot_ctx* c, int32_t nsteps) {
@@ -2019,7 +2100,7 @@ clot_status clot_sync(clot_ctx* c) {
     return c->sync();
 }
 clot_status clot_get_stats(const clot_ctx* c, int32_t chn, clot_stats* s) {
-    if (!c || !s) return CLOT_EINVAL;
+    if (!c || !s || bad_channel(c, chn)) return CLOT_EINVAL;
     return c->stats(chn, s);
 }
 clot_status clot_state_size(const clot_ctx* c, size_t* bytes) {

@@ -14,6 +14,9 @@
 #pragma once
 #include "clot_ops.h"
 
+#include <type_traits>
+#include <utility>
+
 namespace clot {
 
 // Per (channel, system) scalar slots.
@@ -30,6 +33,7 @@ struct KState {
     int32_t* nact;       // global count of active channels
     double* part;        // [ntiles][NV]
     uint32_t* tick;      // unused (kept for layout stability)
+    int32_t* nanflag;    // set to 1 when a NaN or infinity reaches any reduction
     int32_t maxit;
     int32_t sc_ch0;      // channel whose slots sc starts at (0: the whole table)
 };
@@ -61,6 +65,19 @@ struct KVec {
         if (local >= C.ncell) break;
 
 #define CLOT_END_CELLS }
+
+// Epilogue traits.  An initialising epilogue (static member kInit) admits a channel to
+// the solve and adds it to the active count; in every later phase the channel is
+// already counted.  An epilogue with a refmask member also keeps the channel in a
+// further refinement pass.
+template <class E, class = void>
+struct epi_is_init : std::false_type {};
+template <class E>
+struct epi_is_init<E, std::void_t<decltype(E::kInit)>> : std::true_type {};
+template <class E, class = void>
+struct epi_has_refmask : std::false_type {};
+template <class E>
+struct epi_has_refmask<E, std::void_t<decltype(std::declval<E>().refmask)>> : std::true_type {};
 
 // Sums the tile partials of each active channel (fixed order) and runs the phase
 // epilogue in thread 0.  One 1024-thread block per channel.
@@ -95,13 +112,18 @@ __global__ __launch_bounds__(FIN_BS) void k_finish(const ChanDev* chans, KState 
             epi(acc, SL, chid);
         } else {
             // a NaN or infinity reached the reductions: the channel's systems stop,
-            // marked failed (2), and the channel leaves the solve
+            // marked failed (2), and the channel leaves the solve (and the active
+            // count, unless this phase would have admitted it) and any further
+            // refinement pass
             for (int k = 0; k < MAXK; ++k) {
                 double* s = scp(SL, chid, k);
                 s[SC_FAIL] = 2.0;
                 s[SC_ACT] = 0.0;
             }
             S.chact[chid] = 0;
+            if (!epi_is_init<Epi>::value) atomicSub(S.nact, 1);
+            if constexpr (epi_has_refmask<Epi>::value) epi.refmask[chid] = 0;
+            if (S.nanflag) S.nanflag[0] = 1;
         }
     }
     __syncthreads();
@@ -112,6 +134,7 @@ __global__ __launch_bounds__(FIN_BS) void k_finish(const ChanDev* chans, KState 
 // tol_mode 0: tolerance rtol^2 ||b||^2; 1: tolerance already in SC_TOL2.
 template <int K>
 struct EpiCgInit {
+    static constexpr bool kInit = true;
     double rtol;
     int tol_mode;
     __device__ void operator()(const double* sums, const KState& S, int ch) const {
@@ -189,6 +212,7 @@ struct EpiCgB {   // beta, convergence
 // (an enzyme at 1e-8 of its scale) lie far above it.  FP64 has no floor.
 template <int K>
 struct EpiBicgInit {
+    static constexpr bool kInit = true;
     double rtol;
     __device__ void operator()(const double* sums, const KState& S, int ch) const {
         int any = 0;

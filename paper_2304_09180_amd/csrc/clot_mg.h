@@ -583,6 +583,7 @@ __global__ __launch_bounds__(NT) void k_mgcg_init(Grid G, Op op, KVec<T, 1> V, K
 }
 
 struct EpiMgcgInit {
+    static constexpr bool kInit = true;
     double rtol;
     int tol_mode;
     __device__ void operator()(const double* sums, const KState& S, int ch) const {

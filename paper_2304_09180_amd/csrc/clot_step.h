@@ -699,6 +699,24 @@ __global__ __launch_bounds__(NT) void k_rxn(Grid G, Fields<T> F, ModelDev M) {
     CLOT_END_CELLS
 }
 
+// Non-finite scan of the persistent fields after a step call: velocity, pressure,
+// every cell species and the injury-face species.  flag = 1 if any value is a NaN or
+// an infinity (every writer stores the same value).
+template <class T>
+__global__ __launch_bounds__(NT) void k_nonfinite_scan(Grid G, Fields<T> F, int64_t ninj, int32_t* flag) {
+    CLOT_TILE_PROLOGUE(G)
+    bool bad = false;
+    CLOT_FOR_CELLS(local)
+        const int64_t g = C.c0 + local;
+        for (int c = 0; c < 3; ++c) bad = bad || !isfinite((double)F.u[c][g]);
+        bad = bad || !isfinite(F.p[g]);
+        for (int q = 0; q < NSPC; ++q) bad = bad || !isfinite((double)F.spc[q][g]);
+    CLOT_END_CELLS
+    for (int64_t f = (int64_t)blockIdx.x * NT + threadIdx.x; f < ninj; f += (int64_t)gridDim.x * NT)
+        bad = bad || !isfinite((double)F.E0[f]) || !isfinite((double)F.C0[f]);
+    if (bad) flag[0] = 1;
+}
+
 // Driver bookkeeping kernels (graph-safe replacements for memset and host reads).
 __global__ void k_count_active(const int32_t* chact, int32_t* nact, int nch) {
     if (threadIdx.x == 0) {

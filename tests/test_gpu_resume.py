@@ -4,7 +4,8 @@ A state saved after k steps and loaded (into the same context or a fresh one) mu
 continue bit for bit as the saved context does; the state exercised here carries the
 Crank-Nicolson history, the variable step, a release history with several snapshots and
 the buffer parity.  Failures: non-finite values refused by clot_set_field, a solve that
-overflows FP32, and a solve allowed a single iteration."""
+overflows FP32 (the call rolled back), and a solve allowed a single iteration; channel
+indices outside the context and blobs of channels with other physics are refused."""
 import numpy as np
 import pytest
 
@@ -97,29 +98,103 @@ def test_non_finite_values_are_refused_at_the_boundary():
     s.close()
 
 
-def test_overflow_in_a_solve_is_reported_and_cleared_by_reinitialisation():
+def test_overflow_in_a_solve_rolls_the_call_back():
     """A finite velocity near the FP32 limit passes the boundary; the FP32 pressure
-    solve it drives (p ~ 1e40) overflows, and the step must say so rather than OK (the
-    solve stops at the first non-finite sum, so its vector can still read finite)."""
+    solve it drives (p ~ 1e40) overflows.  The step call returns CLOT_ENAN and every
+    channel is back at the state of the call's start (the planted velocity included);
+    the statistics report the failed step.  Re-initialised, the channel steps with its
+    usual iteration counts: the failed solve left no inflated counts behind."""
     from paper_2304_09180_amd import clot
     d = DESCS[0]
     s = clot.Solver([d], clot.FP32_MIXED)
     xc, xf = ci.noise(d)
     s.init_state(0, xc, xf)
     s.step(1)
-    assert s.stats(0)["status"] == "OK"
+    normal = s.stats(0)
+    assert normal["status"] == "OK"
     u = s.get(0, "UX")
     u[len(u) // 2] = 3e38
     s.set(0, "UX", u)
-    s.step(1)
-    f = s.fields(0)
-    nonfinite = [n for n, v in f.items() if not np.isfinite(v).all()]
-    print("non-finite fields", nonfinite, s.stats(0)["status"])
-    assert s.stats(0)["status"] == "W_NONFINITE"
+    before = s.fields(0)
+    with pytest.raises(clot.ClotError, match="ENAN"):
+        s.step(2)
+    after = s.fields(0)
+    for n, v in before.items():
+        assert np.array_equal(after[n], v), n
+    st = s.stats(0)
+    assert st["status"] == "W_NONFINITE" and st["steps"] == 1
     s.init_state(0, xc, xf)
     s.step(1)
-    assert s.stats(0)["status"] == "OK"
+    again = s.stats(0)
+    print(normal["it_mom"], normal["it_p"][:2], again["it_mom"], again["it_p"][:2], flush=True)
+    assert again["status"] == "OK"
+    assert again["it_mom"] <= normal["it_mom"] + 2 and max(again["it_p"]) <= max(normal["it_p"]) + 2
     s.close()
+
+
+def test_asynchronous_window_rolls_back_at_sync():
+    """Asynchronous steps share one window: clot_sync finds the non-finite value and
+    restores the state of the first asynchronous call; a clean window passes."""
+    from paper_2304_09180_amd import clot
+    d = DESCS[1]
+    s = clot.Solver([d], clot.FP32_MIXED)
+    xc, xf = ci.noise(d)
+    s.init_state(0, xc, xf)
+    s.step_async(2)
+    s.step_async(1)
+    assert s.sync() == 0
+    u = s.get(0, "UX")
+    u[5] = 3e38
+    s.set(0, "UX", u)
+    before = s.fields(0)
+    s.step_async(1)
+    s.step_async(1)
+    with pytest.raises(clot.ClotError, match="ENAN"):
+        s.sync()
+    after = s.fields(0)
+    for n, v in before.items():
+        assert np.array_equal(after[n], v), n
+    assert s.stats(0)["steps"] == 3
+    s.close()
+
+
+def test_channel_index_outside_the_context_is_refused():
+    import ctypes
+    from paper_2304_09180_amd import clot
+    s = make("FP64")
+    lib, ctx = s.lib, s.ctx
+    buf = np.zeros(10)
+    n = ctypes.c_size_t(0)
+    st = clot.Stats()
+    xc, xf = ci.noise(DESCS[0])
+    for bad in (-1, len(DESCS), 1 << 30):
+        assert lib.clot_field_count(ctx, bad, clot.FIELD["UX"], ctypes.byref(n)) == -1
+        assert lib.clot_get_field(ctx, bad, clot.FIELD["UX"], buf.ctypes.data, buf.size) == -1
+        assert lib.clot_set_field(ctx, bad, clot.FIELD["UX"], buf.ctypes.data, buf.size) == -1
+        assert lib.clot_get_stats(ctx, bad, ctypes.byref(st)) == -1
+        assert lib.clot_init_state(ctx, bad, xc.ctypes.data, xc.size, xf.ctypes.data, xf.size) == -1
+        assert b"outside" in lib.clot_last_error(ctx)
+    s.step(1)                       # the context is untouched
+    assert s.stats(len(DESCS) - 1)["status"] == "OK"
+    s.close()
+
+
+def test_load_state_refuses_a_channel_with_other_physics():
+    """Same grids, but another shear rate or injury patch: the blob's channel tables and
+    clocks do not belong to this context."""
+    from paper_2304_09180_amd import clot
+    a = make("FP64")
+    a.step(1)
+    blob = a.save_state()
+    for change in (dict(shear=700.0), dict(inj_frac=0.2)):
+        d0 = dict(DESCS[0])
+        d1 = ci.channel(2, d0["nx"], d0["ny"], shear=change.get("shear", d0["shear"]), dt=d0["dt"], seed=21,
+                        inj_frac=change.get("inj_frac", 0.3))
+        other = clot.Solver([d1, DESCS[1]], clot.FP64, clot.default_params(clot.FP64, **OVER))
+        with pytest.raises(clot.ClotError, match="EINVAL"):
+            other.load_state(blob)
+        other.close()
+    a.close()
 
 
 def test_single_iteration_solves_report_not_converged():
