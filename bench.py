@@ -24,9 +24,9 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 # launch, stencil neighbours counted once), FP32 storage (x2 for FP64).
 #   p_cg_a : z, p_old, diag, rAU read; p_new, q written            -> 6 arrays
 #   p_cg_b : x, p_new, r, q, diag read; x, r written                -> 7 arrays
-#   tr_b1  : per system r, p_old, v_old, diag, rhat, C^n read; p, v written (8)
-#            plus the shared face fluxes (dim arrays) and W(theta_T)
-#   tr_b2  : per system r, v, diag, C^n read; t written (5) + fluxes + W
+#   tr_b1  : per system r, p_old, v_old, diag, rhat read and the six stored couplings;
+#            p, v written (13)
+#   tr_b2  : per system r, v, diag and the six couplings read; t written (10)
 #   tr_b3  : per system x, r, rhat, p, v, t, diag read; x, r written (9)
 #   rxn    : 14 species + ADP + eta read; 15 species written (31)
 #   mom_b1 : per velocity component r, p_old, v_old, rhat read; p, v written (6)
@@ -34,10 +34,42 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 #   mom_b2 : per component r, v read; t written (3) + a_P + fluxes
 #   mom_b3 : per component x, r, rhat, p, v, t read; x, r written (8) + a_P
 ARRAYS = {"p_cg_a": lambda dim: 6, "p_cg_b": lambda dim: 7,
-          "tr_b1": lambda dim: 7 * 8 + dim + 1, "tr_b2": lambda dim: 7 * 5 + dim + 1,
+          "tr_b1": lambda dim: 7 * 13, "tr_b2": lambda dim: 7 * 10,
           "tr_b3": lambda dim: 7 * 9, "rxn": lambda dim: 31,
           "mom_b1": lambda dim: dim * 6 + 1 + dim, "mom_b2": lambda dim: dim * 3 + 1 + dim,
           "mom_b3": lambda dim: dim * 8 + 1}
+
+
+
+def step_arrays(dim, st, ns):
+    """Algorithmic traffic of one whole step, in cell-sized FP32 arrays per cell (an FP64
+    array counts 2), from the solver's iteration counts of that step: every pass over the
+    mesh counted once with its compulsory reads and writes (stencil neighbours once; the
+    multigrid levels below the mesh at their own sizes).  ns: multigrid sweeps each way."""
+    c = dim                                           # velocity components
+    fixed = (6                                        # k_derive: 4 platelet fields -> theta_B, W
+             + (2 * c + 2 + dim + 1) + (1 + 2 * c)    # k_mom_assemble: u, p, fluxes, theta_B -> a_P, src, b
+             + (2 * c + 1 + dim) + 4 * c)             # momentum BiCGStab start: x, b, a_P, fluxes -> r, rh, p, v
+    mom_it = (c * 6 + 1 + dim) + (c * 3 + 1 + dim) + (c * 8 + 1)
+    corr = (2 * c + 1 + dim) + c                      # k_hbya: u, src, a_P, fluxes -> HbyA
+    corr += (c + 1) + 2 + 1                           # k_prhs: HbyA, rAU -> rhs (FP64), diagonal
+    corr += (2 + c + 1) + (c + dim)                   # k_correct: p, HbyA, rAU -> u, flux
+    per_pass = 8 + 6 + 5                              # FP64 residual, MG-CG start, p += e
+    cg_it = 6 + 6                                     # k_mgcg_a, k_mgcg_b
+    fine = 4 + 5 * (ns - 2) + 4.125 + 5.125 + 5 * (ns - 1)   # V-cycle on the mesh (pre, sweeps, restrict, up)
+    lvl = (7 + 8 * (ns - 2) + 7.125 + 8.125 + 8 * (ns - 1)) / 8.0   # coefficient levels, 1/8 the cells each
+    vcyc = fine + lvl * 8.0 / 7.0                     # geometric sum over the coarser levels
+    eta = 3 + 5 + st["it_eta"] * 12                   # prep, CG start, per iteration cg_a + cg_b
+    ntr = 7
+    tr = (7 + 1 + dim + 7 + 7 + 6 * 7 + 7) + ntr * 13 + st["it_tr"] * ntr * (13 + 10 + 9)
+    rxn = 31
+    total = fixed + st["it_mom"] * mom_it + eta + tr + rxn
+    for k, passes in enumerate(st["refine_p"]):
+        if passes <= 0:
+            continue
+        its = st["it_p"][k]
+        total += corr + passes * (per_pass + vcyc) + its * (cg_it + vcyc)
+    return total
 
 
 def parse():
@@ -93,33 +125,41 @@ def copy_calibration(mib):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
 
 
-def cpu_baseline(desc):
-    """FP64 oracle on a bounded sample: the same channel geometry, shear and seed on a
-    grid 4x coarser per axis, 5 timed steps (about 10 s of one core); reported as
-    cell-timesteps/s."""
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(desc, steps=2):
+    """FP64 oracle on a bounded sample of the workload: a slice of the same channel, 16
+    cells long (its full cross-section at the same cell size, time step, shear, seed and
+    injury patch proportions), `steps` timed steps (about 20-25 s of one core).  The
+    oracle's sparse LU and Krylov solves run on one thread.  Reported in cell-timesteps/s."""
     import clot_inputs as ci
     from oracle import clot_oracle as oc
     d = dict(desc)
-    fac = 4
-    d["nx"] = max(8, desc["nx"] // fac)
-    d["ny"] = max(4, desc["ny"] // fac)
-    if desc["dim"] == 3:
-        d["nz"] = max(4, desc["nz"] // fac)
-    d["dt"] = desc["dt"]
+    nx = min(16, desc["nx"])
+    d["nx"] = nx
+    d["Lx"] = desc["Lx"] * nx / desc["nx"]
+    d["inj_x0"], d["inj_x1"] = 0.25 * d["Lx"], 0.75 * d["Lx"]
     xc, xf = ci.noise(d)
     o = oc.Oracle(d, xc, xf)
-    o.step()                        # first step outside the timing (imports, caches)
-    n = 5
     t0 = time.perf_counter()
-    for _ in range(n):
+    for _ in range(steps):
         o.step()
     el = time.perf_counter() - t0
     cells = d["nx"] * d["ny"] * d["nz"]
-    return {"value": cells * n / el, "unit": "cell-timesteps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} steps of the same channel at {d['nx']}x{d['ny']}x{d['nz']} cells "
-                      f"(4x coarser per axis), FP64 scipy sparse direct solves, single thread",
-            "seconds": el}
+    return {"value": cells * steps / el, "unit": "cell-timesteps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of a {d['nx']}x{d['ny']}x{d['nz']} slice of the same channel (the "
+                      f"full {desc['ny']}x{desc['nz']} cross-section, same cell size, time step, shear and "
+                      f"seed), FP64, sparse LU for momentum and pressure, Krylov for eta and transport",
+            "grid": [d["nx"], d["ny"], d["nz"]], "steps": steps, "seconds": round(el, 3),
+            "threads": 1, "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def timed_steps(s, steps, probe):
@@ -320,6 +360,13 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": recorded_traffic(args.workload, args.probe),
                 "bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 3), "launches": probe_n}
+    if roof is not None:
+        ns = 3 if desc["dim"] == 3 else 2
+        per_cell = step_arrays(desc["dim"], st, ns) * bpe
+        ach = per_cell * ncell / (el / args.steps) / 1e9
+        roof["step"] = {"achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_cell_step": round(per_cell, 1),
+                        "model": "sum over the step's passes of compulsory bytes x this run's iteration counts"}
     out = {"metric": "cell-timesteps/s", "value": value, "unit": "cell-timesteps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
