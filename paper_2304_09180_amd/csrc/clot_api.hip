@@ -364,7 +364,8 @@ struct Ctx : clot_ctx {
         F.dE = cv.take<T>(N);
         F.rhs_p = cv.take<double>(N);
         for (int k = 0; k < NTR; ++k) F.trd[k] = cv.take<T>(N);
-        for (int k = 0; k < NTR; ++k) F.trb[k] = cv.take<T>(N);
+        for (int k = 0; k < NTR; ++k) F.trd64[k] = cv.take<double>(N);
+        for (int k = 0; k < NTR; ++k) F.trb[k] = cv.take<double>(N);
         for (int k = 0; k < NTR; ++k) F.trc[k] = cv.take<T>((size_t)6 * N);
         F.co_part = cv.take<double>(ntiles);
         for (int q = 0; q < NPOOL; ++q) pool[q] = cv.take<T>(N);
@@ -1437,6 +1438,8 @@ struct Ctx : clot_ctx {
         for (int k = 0; k < NTR; ++k) {
             top.Cn[k] = F.spc[tr_species(k)];
             top.dg[k] = F.trd[k];
+            top.dg64[k] = F.trd64[k];
+            top.b64[k] = F.trb[k];
             top.cf[k] = F.trc[k];
             const int sp = tr_species(k);
             top.scale[k] = T(sp == PMU || sp == PMA ? M.P_max
@@ -1460,7 +1463,7 @@ struct Ctx : clot_ctx {
             KVec<T, NTR> V = bicg_vecs<NTR>(0);
             for (int k = 0; k < NTR; ++k) {
                 V.x[k] = F.xt[k];
-                V.b[k] = F.trb[k];
+                V.b[k] = nullptr;   // TrOp forms the starting residual from its FP64 right-hand side
             }
             run_bicg<TrOp<T>, NTR>(top, V, prm.rtol_s, allmask, 5, CLOT_PROBE_TR_B1);
             record(ST_TR, ST_REST, NTR, false);

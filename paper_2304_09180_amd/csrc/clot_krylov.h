@@ -74,6 +74,11 @@ template <class E, class = void>
 struct epi_is_init : std::false_type {};
 template <class E>
 struct epi_is_init<E, std::void_t<decltype(E::kInit)>> : std::true_type {};
+// An operator with kExactResidual forms the starting residual itself, in FP64.
+template <class O, class = void>
+struct op_exact_residual : std::false_type {};
+template <class O>
+struct op_exact_residual<O, std::void_t<decltype(O::kExactResidual)>> : std::true_type {};
 template <class E, class = void>
 struct epi_has_refmask : std::false_type {};
 template <class E>
@@ -409,14 +414,21 @@ __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, K
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const T* x = V.x[k];
-            const T ax = op.apply(k, C, P, [&](int64_t g) { return x[g]; });
-            const T b = V.b[k][P.g];
-            const T r = b - ax;
+            double bd;
+            T r;
+            if constexpr (op_exact_residual<Op>::value) {
+                r = T(op.residual64(k, C, P, [&](int64_t g) { return x[g]; }, bd));
+            } else {
+                const T ax = op.apply(k, C, P, [&](int64_t g) { return x[g]; });
+                const T b = V.b[k][P.g];
+                bd = (double)b;
+                r = b - ax;
+            }
             V.r[k][P.g] = r;
             V.rh[k][P.g] = r;
             V.p[0][k][P.g] = T(0);
             V.v[0][k][P.g] = T(0);
-            acc[3 * k] += (double)b * (double)b;
+            acc[3 * k] += bd * bd;
             acc[3 * k + 1] += (double)r * (double)r;
             // FP32: 1e-30 of the scale, and no residual below 1e-34 (the normal range
             // ends at 1.2e-38); FP64: no floor

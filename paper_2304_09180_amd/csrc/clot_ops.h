@@ -38,8 +38,9 @@ struct Fields {
     T* dP;                // pressure diagonal
     T* dE;                // eta diagonal
     double* rhs_p;        // pressure right-hand side
-    T* trd[NTR];          // transport diagonals
-    T* trb[NTR];          // transport right-hand sides
+    T* trd[NTR];          // transport diagonals (the solver's Jacobi scaling and stencil)
+    double* trd64[NTR];   // the same diagonals in FP64, consistent with the stored couplings
+    double* trb[NTR];     // transport right-hand sides (FP64)
     T* trc[NTR];      // transport off-diagonal couplings, 6 slots x ncell per species
     T* ddt0u[3];          // Crank-Nicolson history: stored time derivative of u
     T* ddt0c[NTR];        // ... and of each transported species (its transport sub-step)
@@ -208,6 +209,7 @@ __device__ inline void tvd_weights(const T* Cn, int64_t gL, int64_t s, int iL, i
 template <class T>
 struct FaceCoef {
     T dL, oLR, dR, oRL;
+    T conv;               // the face's convective coefficient W phi (phi positive from L to R)
 };
 
 template <class T>
@@ -227,6 +229,7 @@ __device__ inline FaceCoef<T> tr_face(const T* Cn, const T* Wc, bool platelet, T
     f.oLR = conv * wR - dif;
     f.dR = -conv * wR + dif;
     f.oRL = -conv * wL - dif;
+    f.conv = conv;
     return f;
 }
 
@@ -248,6 +251,30 @@ struct TrOp {
     const T* Wc;
     T Dk[NTR];
     T Pmax;
+    // The start of each solve takes its residual b - A x in FP64 from an FP64 right-hand
+    // side and an FP64 diagonal that the assembly made consistent with the stored
+    // couplings (row sum = k V/dt + net outflow coefficient, exactly): a field the step
+    // leaves unchanged then starts with a zero residual instead of the FP32 rounding of
+    // k V/dt + (face terms), which would otherwise drift it by that rounding every step.
+    static constexpr bool kExactResidual = true;
+    const double* b64[NTR];
+    const double* dg64[NTR];
+    template <class XV>
+    __device__ double residual64(int k, const ChanDev& C, const Cell& P, XV xv, double& b) const {
+        const T* c = cf[k] + P.g;
+        double y = dg64[k][P.g] * (double)xv(P.g);
+        if (P.i < C.nx - 1) y += (double)c[0] * (double)xv(P.g + 1);
+        if (P.i > 0) y += (double)c[n] * (double)xv(P.g - 1);
+        if (P.j < C.ny - 1) y += (double)c[2 * n] * (double)xv(P.g + C.nx);
+        if (P.j > 0) y += (double)c[3 * n] * (double)xv(P.g - C.nx);
+        if (C.dim == 3) {
+            const int64_t sz = (int64_t)C.nx * C.ny;
+            if (P.k < C.nz - 1) y += (double)c[4 * n] * (double)xv(P.g + sz);
+            if (P.k > 0) y += (double)c[5 * n] * (double)xv(P.g - sz);
+        }
+        b = b64[k][P.g];
+        return b - y;
+    }
     __device__ T diag(int k, int64_t g) const { return dg[k][g]; }
     __device__ T floor_scale(int k) const { return scale[k]; }
     // The couplings are frozen over the step (TVD weights and hindrance from C^n):

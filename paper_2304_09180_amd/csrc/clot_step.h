@@ -379,8 +379,8 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
         const int64_t g = P.g;
-        const T V = T(C.V), rdt = T(C.rdt);
-        const T kd = T(C.ddtk), kvr = kd * V * rdt;
+        const T rdt = T(C.rdt);
+        const T kd = T(C.ddtk);
         const T Wp = F.Wc[g];
         const bool inj = P.j == 0 && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
                          P.k < C.inj_k0 + C.inj_nk;
@@ -393,41 +393,45 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             const T* c = op.Cn[k];
             const T D = op.Dk[k];
             const T cn = c[g];
-            T d = kvr;
-            T b = kvr * cn;
-            if (sp == ADP) b += V * F.sigma[g];
+            // diagonal and right-hand side in FP64: each face adds to the diagonal its
+            // convective coefficient minus the coupling as stored, so that the row sum is
+            // k V/dt + the net outflow coefficient exactly and the starting residual of a
+            // field the step leaves unchanged is zero (see TrOp::residual64)
+            const double kvr = C.ddtk * C.V * C.rdt;
+            double d = kvr;
+            double b = kvr * (double)cn;
+            if (sp == ADP) b += C.V * (double)F.sigma[g];
             if (M.psi > 0.0) {
                 const T w = T(C.ddtw), kr = kd * rdt;
                 T* hq = F.ddt0c[k] + g;
                 const T q = *hq;
-                b += w * V * q;
+                b += (double)w * C.V * (double)q;
                 *hq = -(kr * cn + w * q);
             }
-            // couplings of this row, stored for the solver's stencil products, and the
-            // diagonal (same faces, same order as the products)
+            // couplings of this row, stored for the solver's stencil products
             T* cf = F.trc[k] + g;
             const int64_t n = F.ncell;
             T o[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
             T ad = T(C.gx);
             if (P.i < C.nx - 1) {
                 const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, 1, P.i, C.nx, F.phin[0][fx_id(C, P.i + 1, P.j, P.k)], op.Pmax);
-                d += f.dL;
+                d += (double)f.conv - (double)f.oLR;
                 o[0] = f.oLR;
             }
             if (P.i > 0) {
                 const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g - 1, 1, P.i - 1, C.nx, F.phin[0][fx_id(C, P.i, P.j, P.k)], op.Pmax);
-                d += f.dR;
+                d += -(double)f.conv - (double)f.oRL;
                 o[1] = f.oRL;
             }
             ad = T(C.gy);
             if (P.j < C.ny - 1) {
                 const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, C.nx, P.j, C.ny, F.phin[1][fy_id(C, P.i, P.j + 1, P.k)], op.Pmax);
-                d += f.dL;
+                d += (double)f.conv - (double)f.oLR;
                 o[2] = f.oLR;
             }
             if (P.j > 0) {
                 const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g - C.nx, C.nx, P.j - 1, C.ny, F.phin[1][fy_id(C, P.i, P.j, P.k)], op.Pmax);
-                d += f.dR;
+                d += -(double)f.conv - (double)f.oRL;
                 o[3] = f.oRL;
             }
             if (C.dim == 3) {
@@ -435,43 +439,44 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
                 ad = T(C.gz);
                 if (P.k < C.nz - 1) {
                     const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g, sz, P.k, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k + 1)], op.Pmax);
-                    d += f.dL;
+                    d += (double)f.conv - (double)f.oLR;
                     o[4] = f.oLR;
                 }
                 if (P.k > 0) {
                     const FaceCoef<T> f = tr_face(c, F.Wc, plt, D, ad, g - sz, sz, P.k - 1, C.nz, F.phin[2][fz_id(C, P.i, P.j, P.k)], op.Pmax);
-                    d += f.dR;
+                    d += -(double)f.conv - (double)f.oRL;
                     o[5] = f.oRL;
                 }
             }
 #pragma unroll
             for (int q = 0; q < 6; ++q) cf[q * n] = o[q];
-            const T W = plt ? Wp : T(1);
+            const double W = plt ? (double)Wp : 1.0;
             if (P.i == 0) {
-                const T fo = -fin;       // outward flux through the inlet face
+                const double fo = -(double)fin;       // outward flux through the inlet face
                 const bool fixed = (sp == PMU || sp == S1 || sp == S2 || sp == INH);
                 if (fixed) {
-                    const T cb = sp == PMU ? F.pmu_in[C.in0 + P.j + (int64_t)C.ny * P.k]
-                               : sp == S1 ? T(M.S1_0) : sp == S2 ? T(M.S2_0) : T(M.I_0);
-                    const T gg = T(2) * W * D * T(C.gx);
+                    const double cb = sp == PMU ? (double)F.pmu_in[C.in0 + P.j + (int64_t)C.ny * P.k]
+                                    : sp == S1 ? (double)T(M.S1_0) : sp == S2 ? (double)T(M.S2_0) : (double)T(M.I_0);
+                    const double gg = 2.0 * W * (double)D * C.gx;
                     d += gg;
                     b += gg * cb - W * fo * cb;
                 } else {
                     d += W * fo;
                 }
             }
-            if (P.i == C.nx - 1) d += W * fout;
+            if (P.i == C.nx - 1) d += W * (double)fout;
             if (inj) {
-                const T A = T(C.dx * C.dz);
-                if (sp == E1) b += A * T(M.kC0cat) * F.C0[fi];
+                const double A = C.dx * C.dz;
+                if (sp == E1) b += A * M.kC0cat * (double)F.C0[fi];
                 if (sp == S1) {
-                    const T kk = T(M.kC0p) * F.E0[fi], qq = T(M.kC0m) * F.C0[fi];
-                    const T gg = T(M.D_chem) / (T(0.5) * T(C.dy));
+                    const double kk = M.kC0p * (double)F.E0[fi], qq = M.kC0m * (double)F.C0[fi];
+                    const double gg = M.D_chem / (0.5 * C.dy);
                     d += A * kk * gg / (gg + kk);
                     b += A * qq * gg / (gg + kk);
                 }
             }
-            F.trd[k][g] = d;
+            F.trd[k][g] = T(d);
+            F.trd64[k][g] = d;
             F.trb[k][g] = b;
             F.xt[k][g] = cn;
         }

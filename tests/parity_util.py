@@ -41,3 +41,49 @@ def compare(gpu, ref, tol, names=None):
     assert not bad, bad
 
 
+
+
+# ---- comparison with the oracle goldens of the full-size workloads ---------------------
+GOLDEN_SPECIES = ["PMU", "PMA", "PBA", "PBSE", "ADP", "S1", "S2", "E1", "E2", "S1B", "S2B", "E1B", "E2B", "C1", "C2"]
+
+
+def load_golden(path):
+    """A golden written by tests/golden/make_workload_goldens.py: (meta, arrays)."""
+    import json
+    z = np.load(path, allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    return meta, {k: z[k] for k in z.files if k != "meta"}
+
+
+def compare_golden(fields, meta, g, tol, names=None, report=("P", "ETA")):
+    """Relative l2 of a GPU run's fields against the oracle golden of the same workload
+    and step count: on the golden's cell sample (velocity as one vector; each species
+    with the near-zero floor, on the sample's size), on the full-field norms, and on the
+    injury-face species in full.  Pressure and eta are reported, not checked."""
+    idx = g["idx"]
+    dim = meta["desc"]["dim"]
+    vel = ["UX", "UY"] + (["UZ"] if dim == 3 else [])
+    errs = {}
+    den = np.sqrt(sum(np.linalg.norm(g["s_" + c]) ** 2 for c in vel))
+    errs["U(sample)"] = np.sqrt(sum(np.linalg.norm(fields[c][idx] - g["s_" + c]) ** 2 for c in vel)) / den
+    nfull = np.sqrt(sum(float(g["n_" + c]) ** 2 for c in vel))
+    ngot = np.sqrt(sum(np.linalg.norm(fields[c]) ** 2 for c in vel))
+    errs["U(norm)"] = abs(ngot - nfull) / nfull
+    for n in (names or GOLDEN_SPECIES):
+        b = g["s_" + n]
+        floor = 1e-12 * SCALE[n] * np.sqrt(max(b.size, 1))
+        errs[n + "(sample)"] = np.linalg.norm(fields[n][idx] - b) / max(np.linalg.norm(b), floor)
+        nb = float(g["n_" + n])
+        ffloor = 1e-12 * SCALE[n] * np.sqrt(max(fields[n].size, 1))
+        errs[n + "(norm)"] = abs(np.linalg.norm(fields[n]) - nb) / max(nb, ffloor)
+    for n in ("E0", "C0"):
+        b = g["f_" + n]
+        if b.size:
+            errs[n] = rel_l2(fields[n], b, n)
+    rep = {}
+    for n in report:
+        b = g["s_" + n]
+        rep[n] = np.linalg.norm(fields[n][idx] - b) / max(np.linalg.norm(b), 1e-300)
+    print({k: f"{v:.2e}" for k, v in errs.items()}, {k: f"{v:.2e}" for k, v in rep.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    return errs, bad
