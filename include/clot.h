@@ -322,6 +322,18 @@ clot_status clot_mlp_forward(const float* w_f32, const uint16_t* w_bf16, const u
 clot_status clot_mlp_backward(const float* w_f32, const uint16_t* w_bf16, const uint16_t* x_bf16,
                               const uint16_t* cache_bf16, const float* dy_f32, int64_t n, float* part, float* dw_f32,
                               void* hip_stream);
+/* The same gradient as clot_mlp_backward, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving or training loops, harnesses
+ * that forbid hipMalloc): the per-block partials live in a static device array inside
+ * the library (7.5 MB, one copy per GPU, held until the process ends), so the call
+ * allocates nothing and needs no workspace.  n <= 16384 samples, else CLOT_EINVAL
+ * (message through clot_last_error(NULL)).  All
+ * calls on one GPU share that array: calls that overlap on one GPU (concurrent
+ * streams or threads) race and must be serialised by the caller; the first call on
+ * each device looks the array up (hipGetSymbolAddress) with that device current. */
+clot_status clot_mlp_backward_noalloc(const float* w_f32, const uint16_t* w_bf16, const uint16_t* x_bf16,
+                                      const uint16_t* cache_bf16, const float* dy_f32, int64_t n, float* dw_f32,
+                                      void* hip_stream);
 /* Adam step t (>= 1) on the float32 master parameters; refreshes the bf16 copy */
 clot_status clot_mlp_adam(float* w_f32, uint16_t* w_bf16, const float* grad, float* m, float* v, int64_t t,
                           double lr, double beta1, double beta2, double eps, void* hip_stream);
@@ -340,7 +352,7 @@ clot_status clot_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, v
 
 void clot_destroy(clot_ctx* c);
 /* the context's last error message; with c == NULL, that of the last failed clot_create
- * on the calling thread */
+ * or context-free call that sets one (clot_mlp_backward_noalloc) on the calling thread */
 const char* clot_last_error(const clot_ctx* c);
 
 #ifdef __cplusplus

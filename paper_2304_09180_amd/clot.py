@@ -122,6 +122,7 @@ def load(tile: int = 256, inhibitor: bool = False):
         "clot_mlp_backward_workspace": ([C.c_int64], C.c_size_t),
         "clot_mlp_forward": ([P, P, P, C.c_int64, P, P, P], C.c_int),
         "clot_mlp_backward": ([P, P, P, P, P, C.c_int64, P, P, P], C.c_int),
+        "clot_mlp_backward_noalloc": ([P, P, P, P, P, C.c_int64, P, P], C.c_int),
         "clot_mlp_adam": ([P, P, P, P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, P], C.c_int),
         "clot_mlp_mse": ([P, P, C.c_int64, C.c_int32, P, P, P], C.c_int),
         "clot_rxn_rk4_batch": ([C.POINTER(Params), P, C.c_int64, P, P], C.c_int),
@@ -152,7 +153,7 @@ def exported_symbols():
             "clot_mlp_nparam", "clot_mlp_backward_workspace", "clot_mlp_forward", "clot_mlp_backward",
             "clot_mlp_adam", "clot_mlp_mse", "clot_rxn_rk4_batch", "clot_surr_dataset", "clot_mfma_selftest",
             "clot_cell_species", "clot_tile_cells", "clot_set_graph_mode", "clot_graph_info", "clot_state_size",
-            "clot_save_state", "clot_load_state"]
+            "clot_save_state", "clot_load_state", "clot_mlp_backward_noalloc"]
 
 
 PROBES = {"p_cg_a": 1, "p_cg_b": 2, "tr_b1": 3, "tr_b2": 4, "tr_b3": 5, "mom_b1": 6, "mom_b2": 7, "mom_b3": 8,

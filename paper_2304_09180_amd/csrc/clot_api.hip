@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1955,8 +1956,43 @@ static clot_status create_t(Ctx<T>* c, const clot_channel* chs, int n_ch, const 
     return c->upload_tables();
 }
 
-// Message of the last failed clot_create on this thread (its context no longer exists).
+// Message of the last failed clot_create (its context no longer exists) or failed
+// context-free call on this thread.
 static thread_local std::string g_create_err;
+
+// ---- the MLP backward without allocation --------------------------------------------
+// Per-block gradient partials of clot_mlp_backward_noalloc: one MLP_NPARAM slice per
+// block of 64 samples, for at most NOALLOC_MAX samples (7.5 MB).  Each device holds its
+// own copy for the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the name is a host-side stand-in).
+constexpr int64_t NOALLOC_MAX = 16384;
+constexpr int64_t NOALLOC_BLOCKS = NOALLOC_MAX / 64;
+static __device__ __align__(256) float scratch[NOALLOC_BLOCKS * MLP_NPARAM];
+
+static std::mutex g_scratch_mu;
+static std::array<float*, 64> g_scratch_ptr{};   // per device id
+
+// The current device's copy of `scratch`, looked up once per device.
+static clot_status noalloc_scratch(float** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= (int)g_scratch_ptr.size()) {
+        g_create_err = std::string("mlp_backward_noalloc: no usable current device: ") + hipGetErrorString(e);
+        return CLOT_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_create_err = std::string("mlp_backward_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+            return CLOT_EHIP;
+        }
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return CLOT_OK;
+}
 
 extern "C" {
 
@@ -2153,6 +2189,27 @@ clot_status clot_mlp_forward(const float* wf, const uint16_t* wb, const uint16_t
 clot_status clot_mlp_backward(const float* wf, const uint16_t* wb, const uint16_t* x, const uint16_t* cache,
                               const float* dy, int64_t n, float* part, float* dw, void* stream) {
     if (!wf || !wb || !x || !cache || !dy || !part || !dw || n <= 0) return CLOT_EINVAL;
+    const int nblk = (int)((n + 63) / 64);
+    hipLaunchKernelGGL(k_mlp_backward, dim3(nblk), dim3(256), 0, (hipStream_t)stream, mlp_ptrs(wf, wb), x, cache, dy, n,
+                       part);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)stream, part, nblk, dw);
+    CHK_LAUNCH();
+    return CLOT_OK;
+}
+
+clot_status clot_mlp_backward_noalloc(const float* wf, const uint16_t* wb, const uint16_t* x, const uint16_t* cache,
+                                      const float* dy, int64_t n, float* dw, void* stream) {
+    if (!wf || !wb || !x || !cache || !dy || !dw || n <= 0) return CLOT_EINVAL;
+    if (n > NOALLOC_MAX) {
+        g_create_err = "mlp_backward_noalloc: n = " + std::to_string(n) + " exceeds the limit of " +
+                       std::to_string(NOALLOC_MAX) + " samples";
+        return CLOT_EINVAL;
+    }
+    float* part = nullptr;
+    const clot_status r = noalloc_scratch(&part);
+    if (r) return r;
+    // the same kernels as clot_mlp_backward: every block writes its whole slice, the
+    // reduction reads exactly nblk slices, so nothing needs clearing between calls
     const int nblk = (int)((n + 63) / 64);
     hipLaunchKernelGGL(k_mlp_backward, dim3(nblk), dim3(256), 0, (hipStream_t)stream, mlp_ptrs(wf, wb), x, cache, dy, n,
                        part);
