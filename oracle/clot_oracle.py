@@ -356,6 +356,9 @@ def linear_solver(M, spd, direct_max=DIRECT_MAX):
         s = float(np.linalg.norm(b))
         x, info = method(M, b / s, x0=None if x0 is None else x0 / s, rtol=1e-13, atol=0.0,
                          maxiter=100000, M=pre)
+        if info != 0 and not spd:
+            # a BiCGStab breakdown: restarted GMRES, which cannot break down, from where it stopped
+            x, info = spla.gmres(M, b / s, x0=x, rtol=1e-13, atol=0.0, restart=100, maxiter=1000, M=pre)
         if info != 0:
             raise RuntimeError(f"oracle Krylov solve did not converge (info={info})")
         return x * s
