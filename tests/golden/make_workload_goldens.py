@@ -14,13 +14,16 @@ oracle cell by cell on the sample and field by field on the norms.
 
 Usage (each run is hours of one core for the big workloads):
   python tests/golden/make_workload_goldens.py channel2d_1024x256 1000
-  python tests/golden/make_workload_goldens.py channel3d_256x64x64 20,50,100,200
+  python tests/golden/make_workload_goldens.py channel3d_256x64x64 20,50,100,200 [--state DIR]
   python tests/golden/make_workload_goldens.py ensemble:0,3,10 500
+With --state DIR the oracle's state is also saved at every checkpoint (DIR/<tag>.pkl, a
+file this script writes itself) and a run resumes from it when it is there.
 """
 from __future__ import annotations
 
 import json
 import os
+import pickle
 import sys
 import time
 
@@ -80,30 +83,46 @@ def write(path: str, d: dict, o: oc.Oracle, idx: np.ndarray, steps: int, wall: f
     print(f"wrote {path} ({os.path.getsize(path) / 1e6:.2f} MB) after {steps} steps, {wall:.0f} s", flush=True)
 
 
-def run(tag: str, d: dict, checkpoints: list[int]) -> None:
+def run(tag: str, d: dict, checkpoints: list[int], state_dir: str | None = None) -> None:
     xc, xf = ci.noise(d)
     t0 = time.time()
-    o = oc.Oracle(d, xc, xf)
+    spath = os.path.join(state_dir, f"{tag}.pkl") if state_dir else None
+    if spath and os.path.exists(spath):
+        with open(spath, "rb") as fh:
+            o = pickle.load(fh)          # the oracle's own state, written below by this script
+        print(f"{tag}: resumed at step {o.n}", flush=True)
+    else:
+        o = oc.Oracle(d, xc, xf)
     idx = sample_cells(d)
     last = max(checkpoints)
-    for s in range(1, last + 1):
+    for s in range(o.n + 1, last + 1):
         o.step()
         if s % 10 == 0:
             print(f"{tag}: step {s}/{last}, {time.time() - t0:.0f} s", flush=True)
         if s in checkpoints:
             write(os.path.join(HERE, f"{tag}_step{s}.npz"), d, o, idx, s, time.time() - t0)
+            if spath:
+                with open(spath + ".tmp", "wb") as fh:
+                    pickle.dump(o, fh)
+                os.replace(spath + ".tmp", spath)
 
 
 def main(argv: list[str]) -> None:
+    state_dir = None
+    if "--state" in argv:
+        i = argv.index("--state")
+        state_dir = argv[i + 1]
+        os.makedirs(state_dir, exist_ok=True)
+        argv = argv[:i] + argv[i + 2:]
     what, cps = argv[1], sorted(int(c) for c in argv[2].split(","))
     if what.startswith("ensemble:"):
         members = [int(m) for m in what.split(":")[1].split(",")]
         descs = ci.ensemble(64)
         for m in members:
             d = descs[m]
-            run(f"ensemble64_member{m}_{d['nx']}x{d['ny']}", d, cps)
+            run(f"ensemble64_member{m}_{d['nx']}x{d['ny']}", d, cps, state_dir)
     else:
-        run(what, ci.workload(what), cps)
+        run(what, ci.workload(what), cps, state_dir)
 
 
 if __name__ == "__main__":
