@@ -28,14 +28,15 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 #            p, v written (13)
 #   tr_b2  : per system r, v, diag and the six couplings read; t written (10)
 #   tr_b3  : per system x, r, rhat, p, v, t, diag read; x, r written (9)
-#   rxn    : 14 species + ADP + eta read; 15 species written (31)
+#   rxn    : 14 species and their low parts + ADP + eta read; 14 species and their low
+#            parts written (58)
 #   mom_b1 : per velocity component r, p_old, v_old, rhat read; p, v written (6)
 #            plus the shared diagonal a_P and the face fluxes (dim arrays)
 #   mom_b2 : per component r, v read; t written (3) + a_P + fluxes
 #   mom_b3 : per component x, r, rhat, p, v, t read; x, r written (8) + a_P
 ARRAYS = {"p_cg_a": lambda dim: 6, "p_cg_b": lambda dim: 7,
           "tr_b1": lambda dim: 7 * 13, "tr_b2": lambda dim: 7 * 10,
-          "tr_b3": lambda dim: 7 * 9, "rxn": lambda dim: 31,
+          "tr_b3": lambda dim: 7 * 9, "rxn": lambda dim: 58,
           "mom_b1": lambda dim: dim * 6 + 1 + dim, "mom_b2": lambda dim: dim * 3 + 1 + dim,
           "mom_b3": lambda dim: dim * 8 + 1}
 
@@ -61,8 +62,13 @@ def step_arrays(dim, st, ns):
     vcyc = fine + lvl * 8.0 / 7.0                     # geometric sum over the coarser levels
     eta = 3 + 5 + st["it_eta"] * 12                   # prep, CG start, per iteration cg_a + cg_b
     ntr = 7
-    tr = (7 + 1 + dim + 7 + 7 + 6 * 7 + 7) + ntr * 13 + st["it_tr"] * ntr * (13 + 10 + 9)
-    rxn = 31
+    tr = ((7 + 7 + 1 + dim) + (7 + 14 + 14 + 6 * 7)   # assembly: C^n and low parts, W, fluxes -> diagonals
+                                                      # (FP32 and FP64), FP64 right-hand sides, couplings
+          + ntr * 17                                  # delta-form start: C^n, low part, FP64 diagonal and
+                                                      # right-hand side, couplings -> r, rh, p, v, change
+          + st["it_tr"] * ntr * (13 + 10 + 9)         # BiCGStab phases
+          + ntr * 5)                                  # species + low part + change -> species, low part
+    rxn = 58                                          # reactions on value + low part of 14 species
     total = fixed + st["it_mom"] * mom_it + eta + tr + rxn
     for k, passes in enumerate(st["refine_p"]):
         if passes <= 0:

@@ -110,7 +110,7 @@ typedef struct {
     int32_t max_iter;     /* per linear solve                                              */
     int32_t marg_m, marg_n;
     double rtol_p;        /* pressure: ||b - A p|| <= rtol_p ||b|| (FP64 residual)           */
-    double rtol_s;        /* momentum, eta, transport                                      */
+    double rtol_s;        /* momentum, eta (and transport when rtol_tr is 0)               */
     double rtol_inner;    /* FP32 inner pressure solve of each refinement pass             */
     int32_t mg_tail;      /* pressure multigrid: the levels whose channels all have at most
                              this many cells run as one launch (one block per channel);
@@ -137,6 +137,8 @@ typedef struct {
                              >= 0 (default 7.1); other builds ignore it                   */
     double I_0;           /* inhibitor variant: inlet and initial I, nmol/mm^3, >= 0
                              (default 3.4e-3); other builds ignore it                     */
+    double rtol_tr;       /* the 7 transport solves (each solves for the step's change,
+                             from an FP64 residual); 0 = rtol_s                          */
 } clot_params;
 
 /* Per-channel statistics of the last step. */
@@ -160,9 +162,9 @@ typedef struct {
 typedef struct clot_ctx clot_ctx;
 
 /* Fills the Appendix E constants; M_rxn = 2, n_corr = 0 (automatic), max_iter 5000,
- * rtol_p = rtol_s = 1e-13, rtol_inner = 1e-4 (FP64 settings; the FP32 path is run
- * with rtol_s 1e-7, rtol_p 1e-10, rtol_inner 1e-3).  Never fails for a non-NULL
- * pointer. */
+ * rtol_p = rtol_s = rtol_tr = 1e-13, rtol_inner = 1e-4 (FP64 settings; the FP32 path
+ * is run with rtol_s 1e-7, rtol_tr 1e-8, rtol_p 1e-10, rtol_inner 1e-4).  Never fails
+ * for a non-NULL pointer. */
 clot_status clot_params_default(clot_params* p);
 
 /* Bytes of device workspace clot_create needs for these channels and precision. */

@@ -61,7 +61,7 @@ class Params(C.Structure):
                  ("rtol_p", C.c_double), ("rtol_s", C.c_double), ("rtol_inner", C.c_double),
                  ("mg_tail", C.c_int32), ("mg_sweeps", C.c_int32),
                  ("ddt_psi", C.c_double), ("max_co", C.c_double), ("dt_growth", C.c_double),
-                 ("k_I", C.c_double), ("I_0", C.c_double)])
+                 ("k_I", C.c_double), ("I_0", C.c_double), ("rtol_tr", C.c_double)])
 
 
 class Stats(C.Structure):
@@ -166,6 +166,7 @@ def default_params(precision=FP64, **over) -> Params:
     load().clot_params_default(C.byref(p))
     if precision == FP32_MIXED:
         p.rtol_s = 1e-7
+        p.rtol_tr = 1e-8
         p.rtol_p = 1e-10
         p.rtol_inner = 1e-4
         p.max_iter = 400

@@ -334,10 +334,11 @@ struct Ctx : clot_ctx {
         F.phin[1] = cv.take<T>(NFY);
         F.phin[2] = cv.take<T>(std::max<int64_t>(NFZ, 1));
         for (int s = 0; s < NSPC; ++s) F.spc[s] = cv.take<T>(N);
+        for (int q = 0; q < NSPC; ++q) F.lo[q] = cv.take<T>(N);
         const int64_t ni = std::max<int64_t>(NINJ, 1);
-        F.E0 = cv.take<T>(ni);
-        F.C0 = cv.take<T>(ni);
-        F.s1w = cv.take<T>(ni);
+        F.E0 = cv.take<double>(ni);
+        F.C0 = cv.take<double>(ni);
+        F.s1w = cv.take<double>(ni);
         F.eta = cv.take<T>(N);
         F.thB = cv.take<T>(N);
         F.thB_prev = cv.take<T>(N);
@@ -354,7 +355,7 @@ struct Ctx : clot_ctx {
         sig = cv.take<SigState>(nch);
         state_bytes = (cv.off + 255) & ~size_t(255);
         // per-step scratch
-        for (int k = 0; k < NTR; ++k) F.xt[k] = cv.take<T>(N);
+        for (int k = 0; k < NTR; ++k) F.dlt[k] = cv.take<T>(N);
         F.Wc = cv.take<T>(N);
         F.aP = cv.take<T>(N);
         for (int c = 0; c < 3; ++c) F.src[c] = cv.take<T>(N);
@@ -834,9 +835,11 @@ struct Ctx : clot_ctx {
             c0[f] = 0.0 * (1.0 + 0.01 * xf[h.ninj + f]);
         }
         if (h.ninj) {
-            if ((s = upload(F.E0 + h.inj0, e0))) return s;
-            if ((s = upload(F.C0 + h.inj0, c0))) return s;
+            HIPCHK(hipMemcpy(F.E0 + h.inj0, e0.data(), h.ninj * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(F.C0 + h.inj0, c0.data(), h.ninj * sizeof(double), hipMemcpyHostToDevice));
         }
+        for (int q = 0; q < NSPC; ++q)
+            if ((s = upload(F.lo[q] + h.c0, zero))) return s;
         if ((s = upload(F.eta + h.c0, zero))) return s;
         if ((s = upload(F.sigma + h.c0, zero))) return s;
         for (int q = 0; q < NHIST; ++q)
@@ -905,8 +908,8 @@ struct Ctx : clot_ctx {
             case CLOT_PHIX: return {F.phi[0] + h.fx0, h.nfx, false, false};
             case CLOT_PHIY: return {F.phi[1] + h.fy0, h.nfy, false, false};
             case CLOT_PHIZ: return {F.phi[2] + h.fz0, h.nfz, false, false};
-            case CLOT_E0: return {F.E0 + h.inj0, h.ninj, false, false};
-            case CLOT_C0: return {F.C0 + h.inj0, h.ninj, false, false};
+            case CLOT_E0: return {F.E0 + h.inj0, h.ninj, true, false};
+            case CLOT_C0: return {F.C0 + h.inj0, h.ninj, true, false};
             case CLOT_ETA: return {F.eta + h.c0, n, false, true};
             case CLOT_THETAB: return {F.thB_prev + h.c0, n, false, true};
             case CLOT_SIGMA: return {F.sigma + h.c0, n, false, true};
@@ -921,6 +924,15 @@ struct Ctx : clot_ctx {
         return {nullptr, 0, false, true};
     }
 
+    // The species index of a cell-species field, or -1.
+    static int species_of(clot_field f) {
+        if (f >= CLOT_PMU && f <= CLOT_C2) return (int)f - (int)CLOT_PMU;
+#ifdef CLOT_INHIBITOR
+        if (f == CLOT_I) return INH;
+        if (f == CLOT_E2I) return E2I;
+#endif
+        return -1;
+    }
     static bool unknown(const FieldRef& r, clot_field f) {
         return !r.ptr && r.n == 0 && f != CLOT_UZ && f != CLOT_PHIZ && f != CLOT_HADH;
     }
@@ -960,6 +972,20 @@ struct Ctx : clot_ctx {
             return CLOT_OK;
         }
         std::vector<double> v(h, h + n);
+        const int bq = species_of(f);
+        if (bq >= 0) {   // stored value + low part, so the field is set to full precision
+            std::vector<T> hi(n);
+            std::vector<double> rem(n);
+            for (size_t i = 0; i < n; ++i) {
+                hi[i] = T(h[i]);
+                rem[i] = h[i] - (double)hi[i];
+            }
+            HIPCHK(hipMemcpyAsync(r.ptr, hi.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
+            clot_status rs = upload(F.lo[bq] + ch[c].c0, rem);
+            if (rs) return rs;
+            HIPCHK(hipStreamSynchronize(st));
+            return CLOT_OK;
+        }
         return upload((T*)r.ptr, v);
     }
 
@@ -991,6 +1017,11 @@ struct Ctx : clot_ctx {
         std::vector<T> tmp(n);
         HIPCHK(hipMemcpy(tmp.data(), r.ptr, n * sizeof(T), hipMemcpyDeviceToHost));
         for (size_t i = 0; i < n; ++i) h[i] = (double)tmp[i];
+        const int bq = species_of(f);
+        if (bq >= 0) {   // stored value + low part
+            HIPCHK(hipMemcpy(tmp.data(), F.lo[bq] + ch[c].c0, n * sizeof(T), hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < n; ++i) h[i] += (double)tmp[i];
+        }
         return CLOT_OK;
     }
 
@@ -1441,6 +1472,7 @@ struct Ctx : clot_ctx {
             top.dg[k] = F.trd[k];
             top.dg64[k] = F.trd64[k];
             top.b64[k] = F.trb[k];
+            top.Cl[k] = F.lo[tr_species(k)];
             top.cf[k] = F.trc[k];
             const int sp = tr_species(k);
             top.scale[k] = T(sp == PMU || sp == PMA ? M.P_max
@@ -1463,10 +1495,12 @@ struct Ctx : clot_ctx {
         {
             KVec<T, NTR> V = bicg_vecs<NTR>(0);
             for (int k = 0; k < NTR; ++k) {
-                V.x[k] = F.xt[k];
+                V.x[k] = F.dlt[k];  // delta form: each species' change, from zero
                 V.b[k] = nullptr;   // TrOp forms the starting residual from its FP64 right-hand side
             }
-            run_bicg<TrOp<T>, NTR>(top, V, prm.rtol_s, allmask, 5, CLOT_PROBE_TR_B1);
+            run_bicg<TrOp<T>, NTR>(top, V, prm.rtol_tr > 0.0 ? prm.rtol_tr : prm.rtol_s, allmask, 5,
+                                   CLOT_PROBE_TR_B1);
+            hipLaunchKernelGGL(k_add_change<T>, gb, tb, 0, st, G, F);
             record(ST_TR, ST_REST, NTR, false);
         }
         if (eta_side) {   // the transport solve's polls have synchronised the main stream
@@ -2058,6 +2092,7 @@ clot_status clot_params_default(clot_params* p) {
     p->dt_growth = 1.2;
     p->k_I = 7.1;
     p->I_0 = 3.4e-3;
+    p->rtol_tr = 1e-13;
     return CLOT_OK;
 }
 

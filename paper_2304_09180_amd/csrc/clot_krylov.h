@@ -417,7 +417,9 @@ __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, K
             double bd;
             T r;
             if constexpr (op_exact_residual<Op>::value) {
-                r = T(op.residual64(k, C, P, [&](int64_t g) { return x[g]; }, bd));
+                // delta form: the unknown is the change, starting at zero
+                r = T(op.residual64(k, C, P, bd));
+                V.x[k][P.g] = T(0);
             } else {
                 const T ax = op.apply(k, C, P, [&](int64_t g) { return x[g]; });
                 const T b = V.b[k][P.g];

@@ -17,11 +17,12 @@ struct Fields {
     double* p;            // kinematic pressure (FP64 in both precisions)
     T* phi[3];            // flux of the previous step (convects the momentum)
     T* phin[3];           // flux written by the PISO correctors
-    T* spc[NSPC];
-    T* xt[NTR];           // transport solutions
-    T* E0;
-    T* C0;
-    T* s1w;
+    T* spc[NSPC];         // species (the stored value) ...
+    T* lo[NSPC];          // ... and its low part: a species is spc + lo (see the transport and reaction updates)
+    T* dlt[NTR];          // the transport solves' unknowns: each species' change over the step
+    double* E0;           // injury-face species: FP64 in every precision (each step adds a
+    double* C0;           // nearly constant increment, which FP32 rounding would bias)
+    double* s1w;
     T* eta;
     T* thB;
     T* thB_prev;
@@ -251,7 +252,8 @@ struct TrOp {
     const T* Wc;
     T Dk[NTR];
     T Pmax;
-    // The start of each solve takes its residual b - A x in FP64 from an FP64 right-hand
+    // Delta form: each solve's unknown is the species' change over the transport step,
+    // started at zero from the residual b - A C^n taken in FP64 from an FP64 right-hand
     // side and an FP64 diagonal that the assembly made consistent with the stored
     // couplings (row sum = k V/dt + net outflow coefficient, exactly): a field the step
     // leaves unchanged then starts with a zero residual instead of the FP32 rounding of
@@ -259,18 +261,21 @@ struct TrOp {
     static constexpr bool kExactResidual = true;
     const double* b64[NTR];
     const double* dg64[NTR];
-    template <class XV>
-    __device__ double residual64(int k, const ChanDev& C, const Cell& P, XV xv, double& b) const {
+    const T* Cl[NTR];     // low parts of the start-of-step species
+    __device__ double residual64(int k, const ChanDev& C, const Cell& P, double& b) const {
+        const T* x = Cn[k];
+        const T* xl = Cl[k];
+        auto xv = [&](int64_t g) { return (double)x[g] + (double)xl[g]; };
         const T* c = cf[k] + P.g;
-        double y = dg64[k][P.g] * (double)xv(P.g);
-        if (P.i < C.nx - 1) y += (double)c[0] * (double)xv(P.g + 1);
-        if (P.i > 0) y += (double)c[n] * (double)xv(P.g - 1);
-        if (P.j < C.ny - 1) y += (double)c[2 * n] * (double)xv(P.g + C.nx);
-        if (P.j > 0) y += (double)c[3 * n] * (double)xv(P.g - C.nx);
+        double y = dg64[k][P.g] * xv(P.g);
+        if (P.i < C.nx - 1) y += (double)c[0] * xv(P.g + 1);
+        if (P.i > 0) y += (double)c[n] * xv(P.g - 1);
+        if (P.j < C.ny - 1) y += (double)c[2 * n] * xv(P.g + C.nx);
+        if (P.j > 0) y += (double)c[3 * n] * xv(P.g - C.nx);
         if (C.dim == 3) {
             const int64_t sz = (int64_t)C.nx * C.ny;
-            if (P.k < C.nz - 1) y += (double)c[4 * n] * (double)xv(P.g + sz);
-            if (P.k > 0) y += (double)c[5 * n] * (double)xv(P.g - sz);
+            if (P.k < C.nz - 1) y += (double)c[4 * n] * xv(P.g + sz);
+            if (P.k > 0) y += (double)c[5 * n] * xv(P.g - sz);
         }
         b = b64[k][P.g];
         return b - y;

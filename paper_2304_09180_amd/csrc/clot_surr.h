@@ -91,41 +91,20 @@ __device__ inline float surr_defect(const T (&y)[NRX], const T (&inc)[NRX], T ad
     return worst;
 }
 
+// The learned step works on the stored values (FP32 in the mixed path) and leaves no low parts.
 template <class T>
 __device__ inline void load_rxn_state(const Fields<T>& F, int64_t g, T (&y)[NRX]) {
-    y[0] = F.xt[0][g];
-    y[1] = F.xt[1][g];
-    y[2] = F.spc[PBA][g];
-    y[3] = F.spc[PBSE][g];
-    y[4] = F.xt[2][g];
-    y[5] = F.xt[3][g];
-    y[6] = F.xt[4][g];
-    y[7] = F.xt[5][g];
-    y[8] = F.spc[S1B][g];
-    y[9] = F.spc[S2B][g];
-    y[10] = F.spc[E1B][g];
-    y[11] = F.spc[E2B][g];
-    y[12] = F.spc[C1][g];
-    y[13] = F.spc[C2][g];
+#pragma unroll
+    for (int q = 0; q < NRX; ++q) y[q] = F.spc[rxn_species(q)][g];
 }
 
 template <class T>
-__device__ inline void store_rxn_state(const Fields<T>& F, int64_t g, const T (&y)[NRX], T adp) {
-    F.spc[PMU][g] = y[0];
-    F.spc[PMA][g] = y[1];
-    F.spc[PBA][g] = y[2];
-    F.spc[PBSE][g] = y[3];
-    F.spc[S1][g] = y[4];
-    F.spc[S2][g] = y[5];
-    F.spc[E1][g] = y[6];
-    F.spc[E2][g] = y[7];
-    F.spc[S1B][g] = y[8];
-    F.spc[S2B][g] = y[9];
-    F.spc[E1B][g] = y[10];
-    F.spc[E2B][g] = y[11];
-    F.spc[C1][g] = y[12];
-    F.spc[C2][g] = y[13];
-    F.spc[ADP][g] = adp;
+__device__ inline void store_rxn_state(const Fields<T>& F, int64_t g, const T (&y)[NRX]) {
+#pragma unroll
+    for (int q = 0; q < NRX; ++q) {
+        F.spc[rxn_species(q)][g] = y[q];
+        F.lo[rxn_species(q)][g] = T(0);
+    }
 }
 
 template <class T>
@@ -166,7 +145,7 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
                 const Cell P = cell_at(C, local);
                 g = P.g;
                 load_rxn_state(F, g, y);
-                adp = F.xt[6][g];
+                adp = F.spc[ADP][g];
                 gam = binding_g<T>(F.eta[g], M);
                 hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
                 surr_features(y, adp, gam, hadh, dt, M, tb, x, f);
@@ -208,7 +187,7 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
             if (d < tol) {
 #pragma unroll
                 for (int i = 0; i < NRX; ++i) y[i] += inc[i];
-                store_rxn_state(F, g, y, adp);
+                store_rxn_state(F, g, y);
             } else {
                 const int32_t slot = atomicAdd(fb_count, 1);
                 fb_list[slot] = (int32_t)g;
@@ -235,13 +214,12 @@ __global__ __launch_bounds__(NT) void k_rxn_list(const ChanDev* chans, int nch, 
     }
     const ChanDev C = chans[lo];
     const Cell P = cell_at(C, g - C.c0);
-    T y[NRX];
-    load_rxn_state(F, g, y);
-    const T adp = F.xt[6][g];
-    const T gam = binding_g<T>(F.eta[g], M);
-    const T hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
-    rk4_cell(y, adp, gam, hadh, T(C.dt / M.M_rxn), M);
-    store_rxn_state(F, g, y, adp);
+    double y[NRX];
+    load_rxn_state64(F, g, y);     // as the plain step: FP64 sub-steps, low parts kept
+    const double adp = F.spc[ADP][g];
+    const double gam = binding_g<double>((double)F.eta[g], M);
+    rk4_cell<double>(y, adp, gam, adhesion_cell<T>(C, P) ? 1.0 : 0.0, C.dt / M.M_rxn, M);
+    store_rxn_state64(F, g, y);
     }
 }
 
