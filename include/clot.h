@@ -163,7 +163,7 @@ typedef struct clot_ctx clot_ctx;
 
 /* Fills the Appendix E constants; M_rxn = 2, n_corr = 0 (automatic), max_iter 5000,
  * rtol_p = rtol_s = rtol_tr = 1e-13, rtol_inner = 1e-4 (FP64 settings; the FP32 path
- * is run with rtol_s 1e-7, rtol_tr 1e-8, rtol_p 1e-10, rtol_inner 1e-4).  Never fails
+ * is run with rtol_s 1e-7, rtol_tr 1e-8, rtol_p 1e-8, rtol_inner 1e-4).  Never fails
  * for a non-NULL pointer. */
 clot_status clot_params_default(clot_params* p);
 

@@ -167,7 +167,7 @@ def default_params(precision=FP64, **over) -> Params:
     if precision == FP32_MIXED:
         p.rtol_s = 1e-7
         p.rtol_tr = 1e-8
-        p.rtol_p = 1e-10
+        p.rtol_p = 1e-8
         p.rtol_inner = 1e-4
         p.max_iter = 400
     for k, v in over.items():
