@@ -139,6 +139,11 @@ typedef struct {
                              (default 3.4e-3); other builds ignore it                     */
     double rtol_tr;       /* the 7 transport solves (each solves for the step's change,
                              from an FP64 residual); 0 = rtol_s                          */
+    int32_t mom_mg;       /* momentum predictor (eq. NSB, section 3.2): 1 (default) =
+                             BiCGStab with one multigrid V-cycle per direction (the
+                             aggregation levels of the pressure solver carrying the mass
+                             and viscous parts of the momentum matrix); 0 = BiCGStab with
+                             the Jacobi preconditioner.  Both stop at rtol_s.             */
 } clot_params;
 
 /* Per-channel statistics of the last step. */
@@ -299,6 +304,9 @@ typedef enum {
     CLOT_PROBE_MOM_ASM = 17,
     CLOT_PROBE_P_MG_POST = 18,  /* pressure multigrid: finest-level smoothing sweep + r.z  */
     CLOT_PROBE_RXN_FALLBACK = 19, /* plain RK4 on the cells the surrogate rejected          */
+    CLOT_PROBE_MOM_MG_R = 20,   /* momentum V-cycle: finest-level sweep + restriction      */
+    CLOT_PROBE_MOM_MG_P1 = 21,  /* momentum V-cycle: prolongation + finest-level sweep     */
+    CLOT_PROBE_MOM_MG_P2 = 22,  /* momentum V-cycle: last finest-level sweep               */
     CLOT_PROBE_NKERNELS
 } clot_probe_kernel;
 clot_status clot_probe(clot_ctx* c, int32_t kernel);

@@ -3,6 +3,7 @@
 #include "../../include/clot.h"
 #include "clot_step.h"
 #include "clot_mg.h"
+#include "clot_mgm.h"
 #include "clot_surr.h"
 
 #include <hip/hip_ext.h>
@@ -193,7 +194,12 @@ struct Ctx : clot_ctx {
         int64_t N = 0, NFX = 0, NFY = 0, NFZ = 0;
         T *x = nullptr, *y = nullptr, *b = nullptr, *dg = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr,
           *cout = nullptr;
+        // the momentum preconditioner's operator on this level (boundary face slots hold
+        // the Dirichlet terms) and its V-cycle vectors, one per velocity component
+        T *mmass = nullptr, *mdg = nullptr, *mcx = nullptr, *mcy = nullptr, *mcz = nullptr;
+        T *mb[MGM_K] = {}, *mx[MGM_K] = {}, *my[MGM_K] = {};
         Grid grid() const { return Grid{d_ch, d_t2c, ntiles}; }
+        CoefOp<T> mom_op() const { return CoefOp<T>{mdg, mcx, mcy, mcz}; }
     };
     std::vector<Level> lev;
     T mg_w = T(0.8);         // weighted-Jacobi smoothing weight (set with the channels)
@@ -202,6 +208,7 @@ struct Ctx : clot_ctx {
     T* mg_y0 = nullptr;      // level-0 smoother scratch
     T* mg_z0 = nullptr;      // preconditioned residual z = M r
     double* mg_inv = nullptr;  // per-channel inverse of the coarsest-level matrix
+    int mgm_nc = 0;          // coarse levels of the momentum preconditioner (0: Jacobi BiCGStab)
     // reaction surrogate
     clot_rxn_mode rxn_mode = CLOT_RXN_PLAIN;
     float surr_tol = 1e-3f;
@@ -413,6 +420,19 @@ struct Ctx : clot_ctx {
             L.cy = cv.take<T>(L.NFY);
             L.cz = cv.take<T>(L.NFZ);
         }
+        for (int l = 0; l < mgm_nc; ++l) {
+            Level& L = lev[l];
+            L.mmass = cv.take<T>(L.N);
+            L.mdg = cv.take<T>(L.N);
+            L.mcx = cv.take<T>(L.NFX);
+            L.mcy = cv.take<T>(L.NFY);
+            L.mcz = cv.take<T>(L.NFZ);
+            for (int k = 0; k < MGM_K; ++k) {
+                L.mb[k] = cv.take<T>(L.N);
+                L.mx[k] = cv.take<T>(L.N);
+                L.my[k] = cv.take<T>(L.N);
+            }
+        }
         snap = cv.take<char>(state_bytes);
         return cv.off + 256;
     }
@@ -531,6 +551,25 @@ struct Ctx : clot_ctx {
         bool all3d = true;
         for (const ChanHost& h : ch) all3d = all3d && h.d.dim == 3;
         mg_w = T(all3d ? 6.0 / 7.0 : 0.8);
+        // momentum preconditioner: coarse levels until, in every channel, the viscous part
+        // of the diagonal (nu dt sum_ax 2/h_ax^2 of the mass V/dt; Darcy and Crank-Nicolson
+        // only add mass) is below half the mass
+        mgm_nc = 0;
+        if (p->mom_mg && !lev.empty()) {
+            for (int l = 0; l < (int)lev.size(); ++l) {
+                ++mgm_nc;
+                double worst = 0.0;
+                for (int i = 0; i < nch; ++i) {
+                    const ChanDev& c = lev[l].ch[i];
+                    const clot_channel& d = ch[i].d;
+                    const double hx = d.Lx / c.nx, hy = d.Ly / c.ny, hz = d.Lz / c.nz;
+                    double v = 2.0 / (hx * hx) + 2.0 / (hy * hy);
+                    if (c.dim == 3) v += 2.0 / (hz * hz);
+                    worst = std::max(worst, p->nu * d.dt * v);
+                }
+                if (worst < 0.5) break;
+            }
+        }
         // sweeps each way, automatic: a third sweep saves a third of the CG iterations on
         // 3-D channels (13 -> 9 per corrector on the 1M-cell duct, 7% of the step), while on
         // 2-D channels the iterations it saves cost about what the sweep adds
@@ -1348,6 +1387,108 @@ struct Ctx : clot_ctx {
         return it;
     }
 
+    // ---- momentum predictor: BiCGStab preconditioned by a V-cycle (clot_mgm.h) ----
+    // Coarse operators of the momentum preconditioner: from the mesh's mass (theta_B,
+    // the channel's dt) and viscous couplings, then level by level.
+    void mgm_setup() {
+        for (int l = 0; l < mgm_nc; ++l) {
+            Level& L = lev[l];
+            if (l == 0)
+                hipLaunchKernelGGL((k_mgm_setup<T, true>), dim3(L.ntiles), dim3(NT), 0, st, MGPair{grid(), L.grid()}, M,
+                                   (const T*)F.thB, (const T*)nullptr, (const T*)nullptr, (const T*)nullptr,
+                                   (const T*)nullptr, L.mmass, L.mdg, L.mcx, L.mcy, L.mcz);
+            else {
+                const Level& Fl = lev[l - 1];
+                hipLaunchKernelGGL((k_mgm_setup<T, false>), dim3(L.ntiles), dim3(NT), 0, st,
+                                   MGPair{Fl.grid(), L.grid()}, M, (const T*)nullptr, (const T*)Fl.mmass,
+                                   (const T*)Fl.mcx, (const T*)Fl.mcy, (const T*)Fl.mcz, L.mmass, L.mdg, L.mcx, L.mcy,
+                                   L.mcz);
+            }
+        }
+    }
+    static MGCVec<T> cv3(T* const (&v)[MGM_K]) { return MGCVec<T>{{v[0], v[1], v[2]}}; }
+    static MGVec<T> mv3(T* const (&v)[MGM_K]) { return MGVec<T>{{v[0], v[1], v[2]}}; }
+    // scratch vectors of the momentum solve (the transport solve's, unused until then):
+    // 0..2 y = M^-1 p, 3..5 z = M^-1 s, 6..8 s, 9..11 and 12..14 finest-level sweeps
+    T* const (&mgm_vec(int q) const)[MGM_K] { return *reinterpret_cast<T* const(*)[MGM_K]>(pool + 7 + 7 * 3 + 3 * q); }
+
+    // out = M^-1 b (one V(1,2) cycle) for the active components; FORM (clot_mgm.h) says
+    // how the finest right-hand side is formed; a formed one is written to bout.
+    template <int FORM>
+    void vcycle_mom(const MomOp<T>& mop, const MGSrc<T>& src, T* const (&bout)[MGM_K], T* const (&out)[MGM_K]) {
+        const int nc = mgm_nc;
+        const unsigned rb = TILE / (NT / 8);   // restriction blocks per coarse tile
+        const MGCVec<T> none{};
+        CLOT_LAUNCH(CLOT_PROBE_MOM_MG_R, (k_mgm_restrict<T, MomOp<T>, FORM, true>), dim3(lev[0].ntiles * rb), dim3(NT),
+                    0, st, MGPair{grid(), lev[0].grid()}, mop, src, mv3(bout), none, mv3(lev[0].mb), S, mg_w);
+        for (int l = 0; l + 1 < nc; ++l) {
+            Level& L = lev[l];
+            MGSrc<T> sl{};
+            for (int k = 0; k < MGM_K; ++k) sl.b[k] = L.mb[k];
+            hipLaunchKernelGGL((k_mgm_restrict<T, CoefOp<T>, 0, true>), dim3(lev[l + 1].ntiles * rb), dim3(NT), 0, st,
+                               MGPair{L.grid(), lev[l + 1].grid()}, L.mom_op(), sl, MGVec<T>{}, none,
+                               mv3(lev[l + 1].mb), S, mg_w);
+        }
+        {   // coarsest: three Jacobi sweeps from zero (the mass dominates there)
+            Level& L = lev[nc - 1];
+            hipLaunchKernelGGL((k_mgm_pre<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), L.mom_op(),
+                               cv3(L.mb), mv3(L.my), mg_w, S);
+            hipLaunchKernelGGL((k_mgm_post2<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), L.mom_op(),
+                               cv3(L.mb), cv3(L.my), mv3(L.mx), mg_w, S);
+        }
+        for (int l = nc - 2; l >= 0; --l) {
+            Level& L = lev[l];
+            hipLaunchKernelGGL((k_mgm_post1<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st,
+                               MGPair{L.grid(), lev[l + 1].grid()}, L.mom_op(), cv3(L.mb), cv3(lev[l + 1].mx),
+                               mv3(L.my), mg_w, S);
+            hipLaunchKernelGGL((k_mgm_post2<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), L.mom_op(),
+                               cv3(L.mb), cv3(L.my), mv3(L.mx), mg_w, S);
+        }
+        const MGCVec<T> bf = FORM == 0 ? MGCVec<T>{{src.b[0], src.b[1], src.b[2]}} : cv3(bout);
+        CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P1, (k_mgm_post1<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st,
+                    MGPair{grid(), lev[0].grid()}, mop, bf, cv3(lev[0].mx), mv3(mgm_vec(3)), mg_w, S);
+        CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P2, (k_mgm_post2<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, bf,
+                    cv3(mgm_vec(3)), mv3(out), mg_w, S);
+    }
+
+    // BiCGStab on the momentum system with one V-cycle per direction (right
+    // preconditioning): y = M^-1 p, v = A y, s = r - alpha v, z = M^-1 s, t = A z,
+    // x += alpha y + omega z, r = s - omega t; the recurrence scalars are those of the
+    // Jacobi-preconditioned solve.
+    int run_mom_mg(const MomOp<T>& mop, KVec<T, 3> V, double rtol) {
+        set_active(allmask);
+        hipLaunchKernelGGL((k_bicg_init<T, 3, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, V, S);
+        finish<9>(EpiBicgInit<3>{rtol});
+        T* const (&Y)[MGM_K] = mgm_vec(0);
+        T* const (&Z)[MGM_K] = mgm_vec(1);
+        T* const (&Sv)[MGM_K] = mgm_vec(2);
+        return iterate<3>(0, 1, 2, budget[0], [&](int par) {
+            MGSrc<T> s1{};
+            for (int k = 0; k < MGM_K; ++k) {
+                s1.r[k] = V.r[k];
+                s1.p[k] = V.p[par][k];
+                s1.v[k] = V.v[par][k];
+            }
+            T* pn[MGM_K] = {V.p[par ^ 1][0], V.p[par ^ 1][1], V.p[par ^ 1][2]};
+            vcycle_mom<1>(mop, s1, pn, Y);
+            CLOT_LAUNCH(CLOT_PROBE_MOM_B1, (k_pbicg_1<T, 3, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, V,
+                        cv3(Y), S, par);
+            finish<3>(EpiBicg1<3>{});
+            MGSrc<T> s2{};
+            for (int k = 0; k < MGM_K; ++k) {
+                s2.r[k] = V.r[k];
+                s2.v[k] = V.v[par ^ 1][k];
+            }
+            vcycle_mom<2>(mop, s2, Sv, Z);
+            CLOT_LAUNCH(CLOT_PROBE_MOM_B2, (k_pbicg_2<T, 3, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, V,
+                        cv3(Z), cv3(Sv), S);
+            finish<6>(EpiBicg2<3>{});
+            CLOT_LAUNCH(CLOT_PROBE_MOM_B3, (k_pbicg_3<T, 3>), dim3(ntiles), dim3(NT), 0, st, grid(), V, cv3(Y), cv3(Z),
+                        cv3(Sv), S);
+            finish<6>(EpiBicg3<3>{});
+        });
+    }
+
     template <int K>
     KVec<T, K> bicg_vecs(int first) {
         KVec<T, K> V{};
@@ -1397,6 +1538,7 @@ struct Ctx : clot_ctx {
         }
         // O-1 momentum predictor
         CLOT_LAUNCH(CLOT_PROBE_MOM_ASM, k_mom_assemble<T>, gb, tb, 0, st, G, F, M);
+        mgm_setup();
         // the pressure preconditioner depends only on rAU: built once per step, on the
         // side stream (behind eta) while the momentum predictor is solved
         if (eta_side) {
@@ -1416,7 +1558,8 @@ struct Ctx : clot_ctx {
                 V.x[c] = F.u[c];
                 V.b[c] = F.bm[c];
             }
-            run_bicg<MomOp<T>, 3>(mop, V, prm.rtol_s, allmask, 0, CLOT_PROBE_MOM_B1);
+            if (mgm_nc > 0) run_mom_mg(mop, V, prm.rtol_s);
+            else run_bicg<MomOp<T>, 3>(mop, V, prm.rtol_s, allmask, 0, CLOT_PROBE_MOM_B1);
             record(ST_MOM, ST_RESM, 3, false);
         }
         // O-2 PISO correctors
@@ -2093,6 +2236,7 @@ clot_status clot_params_default(clot_params* p) {
     p->k_I = 7.1;
     p->I_0 = 3.4e-3;
     p->rtol_tr = 1e-13;
+    p->mom_mg = 1;
     return CLOT_OK;
 }
 
@@ -2121,7 +2265,8 @@ clot_status clot_create(const clot_channel* chs, int32_t n_ch, const clot_params
     *out = nullptr;
     if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1 || p->mg_tail < 0 ||
         p->mg_sweeps < 0 || p->mg_sweeps > 4 || !(p->ddt_psi >= 0.0 && p->ddt_psi <= 1.0) ||
-        !(p->max_co >= 0.0) || !(p->dt_growth >= 1.0) || !(p->k_I >= 0.0) || !(p->I_0 >= 0.0))
+        !(p->max_co >= 0.0) || !(p->dt_growth >= 1.0) || !(p->k_I >= 0.0) || !(p->I_0 >= 0.0) ||
+        (p->mom_mg != 0 && p->mom_mg != 1))
         return CLOT_EINVAL;
     clot_ctx* c = make_ctx(prec);
     c->prec = prec;

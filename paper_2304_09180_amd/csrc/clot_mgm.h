@@ -1,0 +1,367 @@
+// Multigrid preconditioner of the momentum predictor (gfx950).
+//
+// The predictor's matrix (time derivative, Gauss-linear convection with the old flux,
+// nu-Laplacian, Darcy term nu*alpha*V on the diagonal; eq. NSB, section 3.2) is a
+// Helmholtz operator with a small skew part: at cell Peclet numbers below one the
+// convective couplings are a few per cent of the viscous ones.  Jacobi-preconditioned
+// Krylov methods need O(sqrt(1 + 12 D)) iterations for the viscous diffusion number
+// D = nu dt / h^2 (33 BiCGStab iterations on a 256x64x64 duct at D = 5.6, about 100 on
+// a 512x128 channel at D = 69); one V-cycle of this preconditioner per BiCGStab
+// direction brings that to a handful.
+//
+// Hierarchy: the aggregation levels of the pressure multigrid (each level halves
+// every axis with >= 3 cells).  The finest level smooths with the full operator
+// (weighted Jacobi on the stored diagonal aP); a coarse level carries the symmetric
+// part re-discretised by aggregation: the cell mass k V/dt + nu alpha V summed over
+// the aggregate, and the viscous face couplings and Dirichlet (inlet, wall) terms
+// summed across each coarse face and halved along a coarsened normal direction (as
+// for the pressure operator, this equals the re-discretisation on uniform cells).
+// A boundary face coefficient lives in the face array at the boundary position
+// (outlet: zero-gradient, no viscous term), so the diagonal of a coarse cell is its
+// mass plus its six face coefficients.  Levels are used until the viscous part of
+// the diagonal falls below half the mass everywhere; there three Jacobi sweeps from
+// zero stand in for the coarsest solve.
+//
+// Cycle: V(1,2) — one weighted-Jacobi sweep from zero, formed inside the residual
+// restriction, and two sweeps after the prolongation.  All velocity components of a
+// channel share every coefficient read; a component (or channel) that has left the
+// Krylov solve is skipped.
+#pragma once
+#include "clot_mg.h"
+
+namespace clot {
+
+constexpr int MGM_K = 3;   // velocity components
+
+template <class T>
+struct MGVec {
+    T* v[MGM_K];
+};
+template <class T>
+struct MGCVec {
+    const T* v[MGM_K];
+};
+
+// Right-hand side of a V-cycle at the finest level.  FORM 0: the vector b; FORM 1:
+// the new BiCGStab direction p = r + beta (p_old - omega v_old); FORM 2: s = r - alpha v
+// (alpha, beta, omega: the channel's solve scalars).  A formed right-hand side is also
+// written out, for the rest of the cycle and the outer iteration.
+template <class T>
+struct MGSrc {
+    const T* b[MGM_K];
+    const T* r[MGM_K];
+    const T* p[MGM_K];
+    const T* v[MGM_K];
+};
+
+template <class T>
+__device__ inline T mom_mass(const ChanDev& C, const ModelDev& M, T thB) {
+    const T V = T(C.V);
+    const T s = T(0.6) * thB;
+    const T om = T(1) - s;
+    const T alpha = T(M.C_CK) * s * s / (om * om * om);
+    return T(C.ddtk) * V * T(C.rdt) + T(M.nu) * alpha * V;
+}
+
+// Face coefficient of the finest level along axis ax at face index f (0..n): the
+// viscous coupling nu A/d inside, 2 nu A/d on the inlet and the walls, 0 on the outlet.
+template <class T>
+__device__ inline T mom_face0(const ChanDev& C, T nu, int ax, int f) {
+    const int n = ax == 0 ? C.nx : ax == 1 ? C.ny : C.nz;
+    const T g = T(ax == 0 ? C.gx : ax == 1 ? C.gy : C.gz);
+    if (f > 0 && f < n) return nu * g;
+    if (ax == 0 && f == n) return T(0);
+    return T(2) * nu * g;
+}
+
+// Builds one coarse momentum level from its fine level (FROM0: the mesh itself).
+template <class T, bool FROM0>
+__global__ __launch_bounds__(NT) void k_mgm_setup(MGPair L, ModelDev M, const T* thB, const T* fmass, const T* fcx,
+                                                  const T* fcy, const T* fcz, T* mass, T* dg, T* cx, T* cy, T* cz) {
+    CLOT_TILE_PROLOGUE(L.coarse)
+    const ChanDev Fc = L.fine.ch[chid];
+    const bool ax0 = Fc.nx != C.nx, ax1 = Fc.ny != C.ny, ax2 = Fc.nz != C.nz;
+    const T s0 = ax0 ? T(0.5) : T(1), s1 = ax1 ? T(0.5) : T(1), s2 = ax2 ? T(0.5) : T(1);
+    const T nu = T(M.nu);
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const int i0 = ax0 ? 2 * P.i : P.i, i1 = ax0 ? min(2 * P.i + 1, Fc.nx - 1) : P.i;
+        const int j0 = ax1 ? 2 * P.j : P.j, j1 = ax1 ? min(2 * P.j + 1, Fc.ny - 1) : P.j;
+        const int k0 = ax2 ? 2 * P.k : P.k, k1 = ax2 ? min(2 * P.k + 1, Fc.nz - 1) : P.k;
+        auto fg = [&](int i, int j, int k) { return Fc.c0 + i + (int64_t)Fc.nx * (j + (int64_t)Fc.ny * k); };
+        T m = T(0);
+        for (int k = k0; k <= k1; ++k)
+            for (int j = j0; j <= j1; ++j)
+                for (int i = i0; i <= i1; ++i)
+                    m += FROM0 ? mom_mass<T>(Fc, M, thB[fg(i, j, k)]) : fmass[fg(i, j, k)];
+        // fine coefficients summed across the coarse face at fine face index f of axis ax
+        auto across = [&](int ax, int f) -> T {
+            T s = T(0);
+            if (ax == 0) {
+                for (int k = k0; k <= k1; ++k)
+                    for (int j = j0; j <= j1; ++j) s += FROM0 ? mom_face0<T>(Fc, nu, 0, f) : fcx[fx_id(Fc, f, j, k)];
+            } else if (ax == 1) {
+                for (int k = k0; k <= k1; ++k)
+                    for (int i = i0; i <= i1; ++i) s += FROM0 ? mom_face0<T>(Fc, nu, 1, f) : fcy[fy_id(Fc, i, f, k)];
+            } else {
+                for (int j = j0; j <= j1; ++j)
+                    for (int i = i0; i <= i1; ++i) s += FROM0 ? mom_face0<T>(Fc, nu, 2, f) : fcz[fz_id(Fc, i, j, f)];
+            }
+            return s;
+        };
+        const T xl = s0 * across(0, i0), xh = s0 * across(0, i1 + 1);
+        const T yl = s1 * across(1, j0), yh = s1 * across(1, j1 + 1);
+        T zl = T(0), zh = T(0);
+        if (C.dim == 3) {
+            zl = s2 * across(2, k0);
+            zh = s2 * across(2, k1 + 1);
+        }
+        cx[fx_id(C, P.i, P.j, P.k)] = xl;
+        if (P.i == C.nx - 1) cx[fx_id(C, C.nx, P.j, P.k)] = xh;
+        cy[fy_id(C, P.i, P.j, P.k)] = yl;
+        if (P.j == C.ny - 1) cy[fy_id(C, P.i, C.ny, P.k)] = yh;
+        if (C.dim == 3) {
+            cz[fz_id(C, P.i, P.j, P.k)] = zl;
+            if (P.k == C.nz - 1) cz[fz_id(C, P.i, P.j, C.nz)] = zh;
+        }
+        mass[P.g] = m;
+        dg[P.g] = m + xl + xh + yl + yh + zl + zh;
+    CLOT_END_CELLS
+}
+
+// Active components of a channel (k < dim and still iterating).
+__device__ inline void mgm_active(const KState& S, int chid, int dim, bool (&act)[MGM_K]) {
+#pragma unroll
+    for (int k = 0; k < MGM_K; ++k) act[k] = k < dim && scp(S, chid, k)[SC_ACT] != 0.0;
+}
+
+// Restriction of the residual of one Jacobi sweep from zero (x = w D^-1 b, ONFLY) or
+// of a given x, summed over each aggregate: eight lanes per coarse cell, one per fine
+// cell, added by lane shuffles.  FORM 1/2 form the finest right-hand side on the fly
+// and write it to bout.  Launch: 8 blocks per coarse tile.
+template <class T, class Op, int FORM, bool ONFLY>
+__global__ __launch_bounds__(NT) void k_mgm_restrict(MGPair L, Op op, MGSrc<T> src, MGVec<T> bout, MGCVec<T> x,
+                                                     MGVec<T> bc, KState S, T w) {
+    constexpr int CPB = NT / 8;
+    constexpr int BPT = TILE / CPB;
+    const int32_t tile = xcd_tile((int32_t)blockIdx.x / BPT, L.coarse.ntiles);
+    const int32_t sub = (int32_t)blockIdx.x % BPT;
+    const int32_t chid = L.coarse.t2c[tile];
+    if (!S.chact[chid]) return;
+    const ChanDev C = L.coarse.ch[chid];
+    const ChanDev Fc = L.fine.ch[chid];
+    bool act[MGM_K];
+    mgm_active(S, chid, Fc.dim, act);
+    double sa[MGM_K] = {}, sb[MGM_K] = {};
+#pragma unroll
+    for (int k = 0; k < MGM_K; ++k) {
+        const double* s = scp(S, chid, k);
+        sa[k] = FORM == 1 ? s[SC_BETA] : s[SC_ALPHA];
+        sb[k] = s[SC_OMEGA];
+    }
+    const int64_t local = (int64_t)(tile - C.t0) * TILE + (int64_t)sub * CPB + threadIdx.x / 8;
+    const int f = threadIdx.x & 7;
+    const bool ax0 = Fc.nx != C.nx, ax1 = Fc.ny != C.ny, ax2 = Fc.nz != C.nz;
+    const bool valid = local < C.ncell;
+    Cell P{}, Q{};
+    bool in = false;
+    if (valid) {
+        P = cell_at(C, local);
+        const int di = f & 1, dj = (f >> 1) & 1, dk = f >> 2;
+        const int i = ax0 ? 2 * P.i + di : P.i + 8 * di;
+        const int j = ax1 ? 2 * P.j + dj : P.j + 8 * dj;
+        const int k = ax2 ? 2 * P.k + dk : P.k + 8 * dk;
+        in = (ax0 || di == 0) && (ax1 || dj == 0) && (ax2 || dk == 0) && i < Fc.nx && j < Fc.ny && k < Fc.nz;
+        Q.i = i;
+        Q.j = j;
+        Q.k = k;
+        Q.g = Fc.c0 + i + (int64_t)Fc.nx * (j + (int64_t)Fc.ny * k);
+    }
+#pragma unroll
+    for (int k = 0; k < MGM_K; ++k) {
+        if (!act[k]) continue;
+        const T a = T(sa[k]), om = T(sb[k]);
+        const T* b0 = src.b[k];
+        const T* r = src.r[k];
+        const T* pp = src.p[k];
+        const T* vv = src.v[k];
+        auto bf = [&](int64_t g) -> T {
+            if (FORM == 0) return b0[g];
+            if (FORM == 1) return r[g] + a * (pp[g] - om * vv[g]);
+            return r[g] - a * vv[g];
+        };
+        T v = T(0);
+        if (in) {
+            const T* xk = x.v[k];
+            const T bq = bf(Q.g);
+            v = bq - op.apply(k, Fc, Q, [&](int64_t g) { return ONFLY ? w * bf(g) / op.diag(k, g) : xk[g]; });
+            if (FORM != 0) bout.v[k][Q.g] = bq;
+        }
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        if (valid && f == 0) bc.v[k][P.g] = v;
+    }
+}
+
+// After the prolongation: x1 = w D^-1 b + P xc (the one pre-sweep from zero and the
+// injected coarse correction, both formed on the fly), y = x1 + w D^-1 (b - A x1).
+template <class T, class Op>
+__global__ __launch_bounds__(NT) void k_mgm_post1(MGPair L, Op op, MGCVec<T> b, MGCVec<T> xc, MGVec<T> y, T w,
+                                                  KState S) {
+    CLOT_TILE_PROLOGUE(L.fine)
+    if (!S.chact[chid]) return;
+    const ChanDev Cc = L.coarse.ch[chid];
+    bool act[MGM_K];
+    mgm_active(S, chid, C.dim, act);
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        const int64_t gc = coarse_of(C, Cc, P.g);
+#pragma unroll
+        for (int k = 0; k < MGM_K; ++k) {
+            if (!act[k]) continue;
+            const T* bk = b.v[k];
+            const T* xk = xc.v[k];
+            auto x1 = [&](int64_t g) { return w * bk[g] / op.diag(k, g) + xk[coarse_of(C, Cc, g)]; };
+            const T ax = op.apply(k, C, P, x1);
+            y.v[k][P.g] = w * bk[P.g] / op.diag(k, P.g) + xk[gc] + w * (bk[P.g] - ax) / op.diag(k, P.g);
+        }
+    CLOT_END_CELLS
+}
+
+// One weighted-Jacobi sweep: out = y + w D^-1 (b - A y).
+template <class T, class Op>
+__global__ __launch_bounds__(NT) void k_mgm_post2(Grid G, Op op, MGCVec<T> b, MGCVec<T> y, MGVec<T> out, T w,
+                                                  KState S) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    bool act[MGM_K];
+    mgm_active(S, chid, C.dim, act);
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < MGM_K; ++k) {
+            if (!act[k]) continue;
+            const T* yk = y.v[k];
+            const T ay = op.apply(k, C, P, [&](int64_t g) { return yk[g]; });
+            out.v[k][P.g] = yk[P.g] + w * (b.v[k][P.g] - ay) / op.diag(k, P.g);
+        }
+    CLOT_END_CELLS
+}
+
+// Two weighted-Jacobi sweeps from zero (the coarsest level): x1 = w D^-1 b,
+// x = x1 + w D^-1 (b - A x1).
+template <class T, class Op>
+__global__ __launch_bounds__(NT) void k_mgm_pre(Grid G, Op op, MGCVec<T> b, MGVec<T> x, T w, KState S) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    bool act[MGM_K];
+    mgm_active(S, chid, C.dim, act);
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < MGM_K; ++k) {
+            if (!act[k]) continue;
+            const T* bk = b.v[k];
+            auto x1 = [&](int64_t g) { return w * bk[g] / op.diag(k, g); };
+            const T ax = op.apply(k, C, P, x1);
+            x.v[k][P.g] = x1(P.g) + w * (bk[P.g] - ax) / op.diag(k, P.g);
+        }
+    CLOT_END_CELLS
+}
+
+// ---- BiCGStab with the V-cycle as right preconditioner ------------------------------
+// y = M^-1 p and z = M^-1 s come from the V-cycles; the phases apply A to them.
+
+// v = A y; rhat . v
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_pbicg_1(Grid G, Op op, KVec<T, K> V, MGCVec<T> y, KState S, int par) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * K];
+    double acc[K];
+    bool act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[k] = 0.0;
+        act[k] = scp(S, chid, k)[SC_ACT] != 0.0;
+    }
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            const T* yk = y.v[k];
+            const T vn = op.apply(k, C, P, [&](int64_t g) { return yk[g]; });
+            V.v[par ^ 1][k][P.g] = vn;
+            acc[k] += (double)V.rh[k][P.g] * (double)vn;
+        }
+    CLOT_END_CELLS
+    store_partials<K>(acc, S.part, tile, lds);
+}
+
+// t = A z; t.s, t.t
+template <class T, int K, class Op>
+__global__ __launch_bounds__(NT) void k_pbicg_2(Grid G, Op op, KVec<T, K> V, MGCVec<T> z, MGCVec<T> s, KState S) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * 2 * K];
+    double acc[2 * K];
+    bool act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[2 * k] = acc[2 * k + 1] = 0.0;
+        act[k] = scp(S, chid, k)[SC_ACT] != 0.0;
+    }
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            const T* zk = z.v[k];
+            const T t = op.apply(k, C, P, [&](int64_t g) { return zk[g]; });
+            V.t[k][P.g] = t;
+            const T sv = s.v[k][P.g];
+            acc[2 * k] += (double)t * (double)sv;
+            acc[2 * k + 1] += (double)t * (double)t;
+        }
+    CLOT_END_CELLS
+    store_partials<2 * K>(acc, S.part, tile, lds);
+}
+
+// x += alpha y + omega z; r = s - omega t; rhat.r, r.r
+template <class T, int K>
+__global__ __launch_bounds__(NT) void k_pbicg_3(Grid G, KVec<T, K> V, MGCVec<T> y, MGCVec<T> z, MGCVec<T> s,
+                                                KState S) {
+    CLOT_TILE_PROLOGUE(G)
+    if (!S.chact[chid]) return;
+    __shared__ double lds[5 * 2 * K];
+    double acc[2 * K];
+    double alpha[K], omega[K];
+    bool act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[2 * k] = acc[2 * k + 1] = 0.0;
+        const double* sc = scp(S, chid, k);
+        alpha[k] = sc[SC_ALPHA];
+        omega[k] = sc[SC_OMEGA];
+        act[k] = sc[SC_ACT] != 0.0;
+    }
+    CLOT_FOR_CELLS(local)
+        const int64_t g = C.c0 + local;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            const T a = (T)alpha[k], om = (T)omega[k];
+            const T sv = s.v[k][g];
+            V.x[k][g] += a * y.v[k][g] + om * z.v[k][g];
+            const T r = sv - om * V.t[k][g];
+            V.r[k][g] = r;
+            acc[2 * k] += (double)V.rh[k][g] * (double)r;
+            acc[2 * k + 1] += (double)r * (double)r;
+        }
+    CLOT_END_CELLS
+    store_partials<2 * K>(acc, S.part, tile, lds);
+}
+
+}  // namespace clot

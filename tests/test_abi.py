@@ -50,7 +50,7 @@ def test_params_default_and_argument_checks_without_gpu():
     p = clot.Params()
     assert lib.clot_params_default(ctypes.byref(p)) == 0
     assert p.nu == 2.62507 and p.M_rxn == 2 and p.P_max == 6.67e7
-    assert p.rtol_s == 1e-13 and p.rtol_tr == 1e-13 and p.I_0 == 3.4e-3   # the struct's last fields
+    assert p.rtol_s == 1e-13 and p.rtol_tr == 1e-13 and p.I_0 == 3.4e-3 and p.mom_mg == 1   # the last fields
     assert lib.clot_params_default(None) == -1
     # workspace query is host-only arithmetic
     import clot_inputs as ci
