@@ -209,6 +209,13 @@ struct Ctx : clot_ctx {
     T* mg_z0 = nullptr;      // preconditioned residual z = M r
     double* mg_inv = nullptr;  // per-channel inverse of the coarsest-level matrix
     int mgm_nc = 0;          // coarse levels of the momentum preconditioner (0: Jacobi BiCGStab)
+    // LDS-staged finest-level momentum kernels: bricks of every channel (when every
+    // channel is coarsened along every axis)
+    std::vector<BrickChan> h_brick;
+    std::vector<int32_t> h_b2c;
+    BrickChan* d_brick = nullptr;
+    int32_t* d_b2c = nullptr;
+    BrickGrid bricks() const { return BrickGrid{d_brick, d_b2c, (int32_t)h_b2c.size()}; }
     // reaction surrogate
     clot_rxn_mode rxn_mode = CLOT_RXN_PLAIN;
     float surr_tol = 1e-3f;
@@ -420,6 +427,8 @@ struct Ctx : clot_ctx {
             L.cy = cv.take<T>(L.NFY);
             L.cz = cv.take<T>(L.NFZ);
         }
+        d_brick = cv.take<BrickChan>(std::max<size_t>(h_brick.size(), 1));
+        d_b2c = cv.take<int32_t>(std::max<size_t>(h_b2c.size(), 1));
         for (int l = 0; l < mgm_nc; ++l) {
             Level& L = lev[l];
             L.mmass = cv.take<T>(L.N);
@@ -568,6 +577,25 @@ struct Ctx : clot_ctx {
                     worst = std::max(worst, p->nu * d.dt * v);
                 }
                 if (worst < 0.5) break;
+            }
+        }
+        h_brick.clear();
+        h_b2c.clear();
+        if (mgm_nc > 0) {
+            bool ok = true;
+            for (const ChanHost& h : ch) ok = ok && h.d.nx >= 3 && h.d.ny >= 3 && (h.d.dim == 2 || h.d.nz >= 3);
+            for (int i = 0; ok && i < nch; ++i) {
+                const clot_channel& d = ch[i].d;
+                const int bx = d.dim == 3 ? BrickDims<3>::BX : BrickDims<2>::BX;
+                const int by = d.dim == 3 ? BrickDims<3>::BY : BrickDims<2>::BY;
+                const int bz = d.dim == 3 ? BrickDims<3>::BZ : 1;
+                BrickChan b{(int32_t)h_b2c.size(), (d.nx + bx - 1) / bx, (d.ny + by - 1) / by, (d.nz + bz - 1) / bz};
+                for (int q = 0; q < b.nbx * b.nby * b.nbz; ++q) h_b2c.push_back(i);
+                h_brick.push_back(b);
+            }
+            if (!ok) {
+                h_brick.clear();
+                h_b2c.clear();
             }
         }
         // sweeps each way, automatic: a third sweep saves a third of the CG iterations on
@@ -736,6 +764,11 @@ struct Ctx : clot_ctx {
             HIPCHK(hipMemcpyAsync(L.d_t2c, L.t2c.data(), L.t2c.size() * 4, hipMemcpyHostToDevice, st));
         }
         HIPCHK(hipMemcpyAsync(d_t2c, t2c.data(), t2c.size() * 4, hipMemcpyHostToDevice, st));
+        if (!h_b2c.empty()) {
+            HIPCHK(hipMemcpyAsync(d_brick, h_brick.data(), h_brick.size() * sizeof(BrickChan), hipMemcpyHostToDevice,
+                                  st));
+            HIPCHK(hipMemcpyAsync(d_b2c, h_b2c.data(), h_b2c.size() * 4, hipMemcpyHostToDevice, st));
+        }
         HIPCHK(hipMemcpyAsync(d_f2c, f2c.data(), f2c.size() * 4, hipMemcpyHostToDevice, st));
         std::vector<int32_t> ones(nch, 1), cm((size_t)MAXCORR * nch, 0);
         for (int k = 0; k < MAXCORR; ++k)
@@ -1419,8 +1452,15 @@ struct Ctx : clot_ctx {
         const int nc = mgm_nc;
         const unsigned rb = TILE / (NT / 8);   // restriction blocks per coarse tile
         const MGCVec<T> none{};
-        CLOT_LAUNCH(CLOT_PROBE_MOM_MG_R, (k_mgm_restrict<T, MomOp<T>, FORM, true>), dim3(lev[0].ntiles * rb), dim3(NT),
-                    0, st, MGPair{grid(), lev[0].grid()}, mop, src, mv3(bout), none, mv3(lev[0].mb), S, mg_w);
+        const bool brick = !h_b2c.empty();
+        if (brick)
+            CLOT_LAUNCH(CLOT_PROBE_MOM_MG_R, (k_mgm_brick<T, MGM_MODE_R, FORM>), dim3((unsigned)h_b2c.size()), dim3(NT),
+                        0, st, bricks(), MGPair{grid(), lev[0].grid()}, mop, src, mv3(bout), none, mv3(lev[0].mb), S,
+                        mg_w);
+        else
+            CLOT_LAUNCH(CLOT_PROBE_MOM_MG_R, (k_mgm_restrict<T, MomOp<T>, FORM, true>), dim3(lev[0].ntiles * rb),
+                        dim3(NT), 0, st, MGPair{grid(), lev[0].grid()}, mop, src, mv3(bout), none, mv3(lev[0].mb), S,
+                        mg_w);
         for (int l = 0; l + 1 < nc; ++l) {
             Level& L = lev[l];
             MGSrc<T> sl{};
@@ -1445,8 +1485,15 @@ struct Ctx : clot_ctx {
                                cv3(L.mb), cv3(L.my), mv3(L.mx), mg_w, S);
         }
         const MGCVec<T> bf = FORM == 0 ? MGCVec<T>{{src.b[0], src.b[1], src.b[2]}} : cv3(bout);
-        CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P1, (k_mgm_post1<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st,
-                    MGPair{grid(), lev[0].grid()}, mop, bf, cv3(lev[0].mx), mv3(mgm_vec(3)), mg_w, S);
+        if (brick) {
+            MGSrc<T> sb{};
+            for (int k = 0; k < MGM_K; ++k) sb.b[k] = bf.v[k];
+            CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P1, (k_mgm_brick<T, MGM_MODE_P, 0>), dim3((unsigned)h_b2c.size()), dim3(NT),
+                        0, st, bricks(), MGPair{grid(), lev[0].grid()}, mop, sb, MGVec<T>{}, cv3(lev[0].mx),
+                        mv3(mgm_vec(3)), S, mg_w);
+        } else
+            CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P1, (k_mgm_post1<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st,
+                        MGPair{grid(), lev[0].grid()}, mop, bf, cv3(lev[0].mx), mv3(mgm_vec(3)), mg_w, S);
         CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P2, (k_mgm_post2<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, bf,
                     cv3(mgm_vec(3)), mv3(out), mg_w, S);
     }

@@ -270,6 +270,185 @@ __global__ __launch_bounds__(NT) void k_mgm_pre(Grid G, Op op, MGCVec<T> b, MGVe
     CLOT_END_CELLS
 }
 
+// ---- LDS-staged finest-level kernels ------------------------------------------------
+// A block owns a brick of fine cells (3-D: 32 x 8 x 4, 2-D: 64 x 16; 4 per thread).
+// It first forms the smoothed value x1 at every cell of the brick and its one-cell halo
+// exactly once, into LDS (the halo from neighbouring bricks' cells, read through L2),
+// then applies the 7-point stencil to its own cells from LDS.  A bricked launch needs
+// every channel coarsened along every axis (aggregates then never straddle bricks).
+//
+// MODE_R: residual restriction.  x1 = w D^-1 b with b formed per FORM (written to bout);
+//   the residuals b - A x1 of each 2x2(x2) aggregate are added in registers and by lane
+//   shuffles (brick columns are laid out so that an aggregate's cells sit in one thread
+//   and its x- and y-neighbour lanes) and written to the coarse right-hand side.
+// MODE_P: prolongation + sweep.  x1 = w D^-1 b + P xc, out = x1 + w D^-1 (b - A x1).
+enum { MGM_MODE_R = 0, MGM_MODE_P = 1 };
+
+struct BrickChan {
+    int32_t b0;              // first brick of the channel
+    int32_t nbx, nby, nbz;   // bricks along each axis
+};
+struct BrickGrid {
+    const BrickChan* bc;
+    const int32_t* b2c;      // brick -> channel
+    int32_t nb;              // bricks over all channels
+};
+template <int DIM>
+struct BrickDims {
+    static constexpr int BX = DIM == 3 ? 32 : 64, BY = DIM == 3 ? 8 : 16, BZ = DIM == 3 ? 4 : 1;
+    static constexpr int EX = BX + 2, EY = BY + 2, EZ = DIM == 3 ? BZ + 2 : 1;
+    static constexpr int NE = EX * EY * EZ;
+    static constexpr int NOWN = BX * BY * BZ;
+};
+constexpr int MGM_BRICK_NE = BrickDims<3>::NE > BrickDims<2>::NE ? BrickDims<3>::NE : BrickDims<2>::NE;
+constexpr int MGM_BRICK_OWN = 1024;
+static_assert(BrickDims<3>::NOWN == MGM_BRICK_OWN && BrickDims<2>::NOWN == MGM_BRICK_OWN, "4 cells per thread");
+
+template <class T, int DIM, int MODE, int FORM>
+__device__ inline void mgm_brick_body(const ChanDev& C, const ChanDev& Cc, int bx, int by, int bz,
+                                      const MomOp<T>& op, const MGSrc<T>& src, const MGVec<T>& bout,
+                                      const MGCVec<T>& xc, const MGVec<T>& out, const bool (&act)[MGM_K],
+                                      const double (&sa)[MGM_K], const double (&sb)[MGM_K], T w,
+                                      T (*xs)[MGM_BRICK_NE], T (*bs)[MGM_BRICK_OWN]) {
+    using D = BrickDims<DIM>;
+    const int x0 = bx * D::BX, y0 = by * D::BY, z0 = bz * D::BZ;
+    const int64_t sxy = (int64_t)C.nx * C.ny;
+    // 1. smoothed value at every cell of the brick and its halo (zero outside the channel)
+    for (int e = threadIdx.x; e < D::NE; e += NT) {
+        const int ex = e % D::EX - 1;
+        const int ey = (e / D::EX) % D::EY - 1;
+        const int ez = DIM == 3 ? e / (D::EX * D::EY) - 1 : 0;
+        const int gi = x0 + ex, gj = y0 + ey, gk = z0 + ez;
+        const bool inside = gi >= 0 && gi < C.nx && gj >= 0 && gj < C.ny && gk >= 0 && gk < C.nz;
+        const bool own = ex >= 0 && ex < D::BX && ey >= 0 && ey < D::BY && ez >= 0 && ez < D::BZ;
+        const int oq = ex + D::BX * (ey + D::BY * ez);
+        int64_t g = 0, gc = 0;
+        T rd = T(0);
+        if (inside) {
+            g = C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk);
+            rd = w / op.aP[g];
+            if (MODE == MGM_MODE_P) gc = Cc.c0 + (gi >> 1) + (int64_t)Cc.nx * ((gj >> 1) + (int64_t)Cc.ny * (gk >> 1));
+        }
+#pragma unroll
+        for (int k = 0; k < MGM_K; ++k) {
+            if (!act[k]) continue;
+            T b = T(0), x1 = T(0);
+            if (inside) {
+                if (MODE == MGM_MODE_P || FORM == 0) b = src.b[k][g];
+                else if (FORM == 1) b = src.r[k][g] + T(sa[k]) * (src.p[k][g] - T(sb[k]) * src.v[k][g]);
+                else b = src.r[k][g] - T(sa[k]) * src.v[k][g];
+                x1 = rd * b;
+                if (MODE == MGM_MODE_P) x1 += xc.v[k][gc];
+                if (own) {
+                    bs[k][oq] = b;
+                    if (MODE == MGM_MODE_R && FORM != 0) bout.v[k][g] = b;
+                }
+            }
+            xs[k][e] = x1;
+        }
+    }
+    __syncthreads();
+    // 2. stencil on the own cells; thread t holds four cells of one (x, y) column pair
+    //    (3-D: z = 0..3; 2-D: y = 2w, 2w+1, 2w+8, 2w+9 for wave w)
+    const int t = threadIdx.x;
+    const int lx = DIM == 3 ? t % 32 : t % 64;
+    T res[4][MGM_K];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int ly = DIM == 3 ? (t / 32) % 8 : 2 * (t / 64) + (m & 1) + 8 * (m >> 1);
+        const int lz = DIM == 3 ? m : 0;
+        const int gi = x0 + lx, gj = y0 + ly, gk = z0 + lz;
+        const bool inside = gi < C.nx && gj < C.ny && gk < C.nz;
+#pragma unroll
+        for (int k = 0; k < MGM_K; ++k) res[m][k] = T(0);
+        if (!inside) continue;
+        const int64_t g = C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk);
+        const int e = (lx + 1) + D::EX * ((ly + 1) + D::EY * (DIM == 3 ? lz + 1 : 0));
+        const int oq = lx + D::BX * (ly + D::BY * lz);
+        // the momentum operator's coefficients (MomOp), in its order: x-, x+, y-, y+, z-, z+
+        const T nu = op.nu;
+        T cxm = T(0), cxp = T(0), cym = T(0), cyp = T(0), czm = T(0), czp = T(0);
+        T d = nu * T(C.gx);
+        if (gi > 0) cxm = T(-0.5) * op.phx[fx_id(C, gi, gj, gk)] - d;
+        if (gi < C.nx - 1) cxp = T(0.5) * op.phx[fx_id(C, gi + 1, gj, gk)] - d;
+        d = nu * T(C.gy);
+        if (gj > 0) cym = T(-0.5) * op.phy[fy_id(C, gi, gj, gk)] - d;
+        if (gj < C.ny - 1) cyp = T(0.5) * op.phy[fy_id(C, gi, gj + 1, gk)] - d;
+        if (DIM == 3) {
+            d = nu * T(C.gz);
+            if (gk > 0) czm = T(-0.5) * op.phz[fz_id(C, gi, gj, gk)] - d;
+            if (gk < C.nz - 1) czp = T(0.5) * op.phz[fz_id(C, gi, gj, gk + 1)] - d;
+        }
+        const T aP = op.aP[g];
+        constexpr int SY = D::EX, SZ = D::EX * D::EY;
+#pragma unroll
+        for (int k = 0; k < MGM_K; ++k) {
+            if (!act[k]) continue;
+            const T* x = xs[k];
+            T s = T(0);
+            if (gi > 0) s += cxm * x[e - 1];
+            if (gi < C.nx - 1) s += cxp * x[e + 1];
+            if (gj > 0) s += cym * x[e - SY];
+            if (gj < C.ny - 1) s += cyp * x[e + SY];
+            if (DIM == 3) {
+                if (gk > 0) s += czm * x[e - SZ];
+                if (gk < C.nz - 1) s += czp * x[e + SZ];
+            }
+            const T r = bs[k][oq] - (aP * x[e] + s);
+            if (MODE == MGM_MODE_P) out.v[k][g] = x[e] + w * r / aP;
+            else res[m][k] = r;
+        }
+    }
+    if (MODE == MGM_MODE_R) {
+        // aggregates: cells m = 0,1 and 2,3 of a thread, then the x pair (lane ^ 1) and,
+        // in 3-D, the y pair (lane ^ 32)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int k = 0; k < MGM_K; ++k) {
+                if (!act[k]) continue;
+                T v = res[2 * h][k] + res[2 * h + 1][k];
+                v += __shfl_xor(v, 1, 64);
+                if (DIM == 3) v += __shfl_xor(v, 32, 64);
+                const int ly = DIM == 3 ? (t / 32) % 8 : 2 * (t / 64) + 8 * h;
+                const int lz = DIM == 3 ? 2 * h : 0;
+                const int ci = (x0 + lx) >> 1, cj = (y0 + ly) >> 1, ck = (z0 + lz) >> 1;
+                const bool lead = (lx & 1) == 0 && (DIM == 2 || (ly & 1) == 0);
+                if (lead && ci < Cc.nx && cj < Cc.ny && ck < Cc.nz)
+                    out.v[k][Cc.c0 + ci + (int64_t)Cc.nx * (cj + (int64_t)Cc.ny * ck)] = v;
+            }
+        }
+    }
+}
+
+template <class T, int MODE, int FORM>
+__global__ __launch_bounds__(NT) void k_mgm_brick(BrickGrid BG, MGPair L, MomOp<T> op, MGSrc<T> src, MGVec<T> bout,
+                                                  MGCVec<T> xc, MGVec<T> out, KState S, T w) {
+    const int32_t b = xcd_tile((int32_t)blockIdx.x, BG.nb);
+    const int32_t chid = BG.b2c[b];
+    if (!S.chact[chid]) return;
+    const ChanDev C = L.fine.ch[chid];
+    const ChanDev Cc = L.coarse.ch[chid];
+    const BrickChan B = BG.bc[chid];
+    const int lb = b - B.b0;
+    const int bx = lb % B.nbx, by = (lb / B.nbx) % B.nby, bz = lb / (B.nbx * B.nby);
+    bool act[MGM_K];
+    mgm_active(S, chid, C.dim, act);
+    double sa[MGM_K], sb[MGM_K];
+#pragma unroll
+    for (int k = 0; k < MGM_K; ++k) {
+        const double* s = scp(S, chid, k);
+        sa[k] = FORM == 1 ? s[SC_BETA] : s[SC_ALPHA];
+        sb[k] = s[SC_OMEGA];
+    }
+    __shared__ T xs[MGM_K][MGM_BRICK_NE];
+    __shared__ T bs[MGM_K][MGM_BRICK_OWN];
+    if (C.dim == 3)
+        mgm_brick_body<T, 3, MODE, FORM>(C, Cc, bx, by, bz, op, src, bout, xc, out, act, sa, sb, w, xs, bs);
+    else
+        mgm_brick_body<T, 2, MODE, FORM>(C, Cc, bx, by, bz, op, src, bout, xc, out, act, sa, sb, w, xs, bs);
+}
+
 // ---- BiCGStab with the V-cycle as right preconditioner ------------------------------
 // y = M^-1 p and z = M^-1 s come from the V-cycles; the phases apply A to them.
 
