@@ -391,6 +391,7 @@ struct Ctx : clot_ctx {
         S.chact = cv.take<int32_t>(nch);
         S.nact = cv.take<int32_t>(1);
         S.part = cv.take<double>((size_t)ntiles * NPART);
+        S.pstride = ntiles;
         S.tick = cv.take<uint32_t>(nch);
         refmask = cv.take<int32_t>(nch);
         sigw = cv.take<double>((size_t)nch * NHIST);
@@ -404,6 +405,7 @@ struct Ctx : clot_ctx {
         Se.chact = cv.take<int32_t>(nch);
         Se.nact = cv.take<int32_t>(1);
         Se.part = cv.take<double>((size_t)ntiles * NPART);
+        Se.pstride = ntiles;
         Se.nanflag = nanflag;
         for (int q = 0; q < 5; ++q) eta_v[q] = cv.take<T>(N);
         eta_info = cv.take<int32_t>(2);
@@ -562,7 +564,10 @@ struct Ctx : clot_ctx {
         mg_w = T(all3d ? 6.0 / 7.0 : 0.8);
         // momentum preconditioner: coarse levels until, in every channel, the viscous part
         // of the diagonal (nu dt sum_ax 2/h_ax^2 of the mass V/dt; Darcy and Crank-Nicolson
-        // only add mass) is below half the mass
+        // only add mass) is below MGM_RATIO times the mass (a CPU model of the cycle: 4
+        // BiCGStab iterations on the duct and 2 on a 512x128 channel at D = 69 whether the
+        // coarsest level's ratio is 0.5 or 8; each level dropped saves three launches per
+        // cycle)
         mgm_nc = 0;
         if (p->mom_mg && !lev.empty()) {
             for (int l = 0; l < (int)lev.size(); ++l) {
@@ -576,7 +581,7 @@ struct Ctx : clot_ctx {
                     if (c.dim == 3) v += 2.0 / (hz * hz);
                     worst = std::max(worst, p->nu * d.dt * v);
                 }
-                if (worst < 0.5) break;
+                if (worst < MGM_RATIO) break;
             }
         }
         h_brick.clear();
@@ -1469,12 +1474,10 @@ struct Ctx : clot_ctx {
                                MGPair{L.grid(), lev[l + 1].grid()}, L.mom_op(), sl, MGVec<T>{}, none,
                                mv3(lev[l + 1].mb), S, mg_w);
         }
-        {   // coarsest: three Jacobi sweeps from zero (the mass dominates there)
+        {   // coarsest: two Jacobi sweeps from zero (the mass dominates there)
             Level& L = lev[nc - 1];
             hipLaunchKernelGGL((k_mgm_pre<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), L.mom_op(),
-                               cv3(L.mb), mv3(L.my), mg_w, S);
-            hipLaunchKernelGGL((k_mgm_post2<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), L.mom_op(),
-                               cv3(L.mb), cv3(L.my), mv3(L.mx), mg_w, S);
+                               cv3(L.mb), mv3(L.mx), mg_w, S);
         }
         for (int l = nc - 2; l >= 0; --l) {
             Level& L = lev[l];

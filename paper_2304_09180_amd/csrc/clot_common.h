@@ -173,17 +173,17 @@ __device__ inline double block_max(double v, double* lds) {
     return m;
 }
 
-// Writes the block's totals of v[] as the tile partials part[tile*NV + q].  The
-// per-channel totals are finished by k_finish (clot_krylov.h): a separate small
-// launch, so no block needs a device-wide fence (on a multi-XCD part each such
-// fence writes back the whole L2) and the summation order is fixed.
+// Writes the block's totals of v[] as the tile partials part[q*stride + tile]
+// (component-major, so the finishing launch reads each component's partials as one
+// contiguous run).  The per-channel totals are finished by k_finish (clot_krylov.h):
+// a separate small launch, so no block needs a device-wide fence (on a multi-XCD part
+// each such fence writes back the whole L2) and the summation order is fixed.
 template <int NV>
-__device__ inline void store_partials(double (&v)[NV], double* part, int32_t tile, double* lds) {
+__device__ inline void store_partials(double (&v)[NV], double* part, int32_t stride, int32_t tile, double* lds) {
     block_sum<NV>(v, lds);
-    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) part[(int64_t)tile * NV + q] = v[q];
-    }
+    for (int q = 0; q < NV; ++q)
+        if (threadIdx.x == q) part[(int64_t)q * stride + tile] = v[q];
 }
 
 }  // namespace clot

@@ -36,6 +36,7 @@ struct KState {
     int32_t* nanflag;    // set to 1 when a NaN or infinity reaches any reduction
     int32_t maxit;
     int32_t sc_ch0;      // channel whose slots sc starts at (0: the whole table)
+    int32_t pstride;     // partials: part[q*pstride + tile]
 };
 
 __device__ inline double* scp(const KState& S, int ch, int k) {
@@ -101,9 +102,20 @@ __global__ __launch_bounds__(FIN_BS) void k_finish(const ChanDev* chans, KState 
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    for (int t = threadIdx.x; t < nt; t += FIN_BS) {
+    // U tiles per thread in flight at once (fewer for wide reductions, to bound registers)
+    constexpr int U = NV <= 8 ? 4 : NV <= 16 ? 2 : 1;
+    for (int tb = threadIdx.x; tb < nt; tb += U * FIN_BS) {
+        double v[U][NV];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) acc[q] += S.part[(int64_t)(t0 + t) * NV + q];
+        for (int u = 0; u < U; ++u) {
+            const int t = tb + u * FIN_BS;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[u][q] = t < nt ? S.part[(int64_t)q * S.pstride + t0 + t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) acc[q] += v[u][q];
     }
     block_sum<NV, FIN_BS>(acc, lds);   // its barriers also publish scl
     if (threadIdx.x == 0) {
@@ -330,7 +342,7 @@ __global__ __launch_bounds__(NT) void k_cg_init(Grid G, Op op, KVec<T, K> V, KSt
             acc[3 * k + 2] += (double)r * (double)r;
         }
     CLOT_END_CELLS
-    store_partials<3 * K>(acc, S.part, tile, lds);
+    store_partials<3 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
 // q = A p_new with p_new = z + beta p_old formed on the fly.
@@ -364,7 +376,7 @@ __global__ __launch_bounds__(NT) void k_cg_a(Grid G, Op op, KVec<T, K> V, KState
             acc[k] += (double)pn * (double)q;
         }
     CLOT_END_CELLS
-    store_partials<K>(acc, S.part, tile, lds);
+    store_partials<K>(acc, S.part, S.pstride, tile, lds);
 }
 
 // x += alpha p; r -= alpha q; r.z and r.r.
@@ -397,7 +409,7 @@ __global__ __launch_bounds__(NT) void k_cg_b(Grid G, Op op, KVec<T, K> V, KState
             acc[2 * k + 1] += (double)r * (double)r;
         }
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, tile, lds);
+    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
 // ---- BiCGStab ----------------------------------------------------------------------
@@ -442,7 +454,7 @@ __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, K
             acc[3 * k + 2] += f * f;
         }
     CLOT_END_CELLS
-    store_partials<3 * K>(acc, S.part, tile, lds);
+    store_partials<3 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
 // p_new = r + beta (p_old - omega v_old); v_new = A (p_new/diag); rhat.v_new
@@ -478,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_bicg_1(Grid G, Op op, KVec<T, K> V, KSta
             acc[k] += (double)V.rh[k][P.g] * (double)vn;
         }
     CLOT_END_CELLS
-    store_partials<K>(acc, S.part, tile, lds);
+    store_partials<K>(acc, S.part, S.pstride, tile, lds);
 }
 
 // s = r - alpha v; t = A (s/diag); t.s, t.t
@@ -512,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_bicg_2(Grid G, Op op, KVec<T, K> V, KSta
             acc[2 * k + 1] += (double)t * (double)t;
         }
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, tile, lds);
+    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
 // x += alpha p/diag + omega s/diag; r = s - omega t; rhat.r, r.r
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(NT) void k_bicg_3(Grid G, Op op, KVec<T, K> V, KSta
             acc[2 * k + 1] += (double)r * (double)r;
         }
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, tile, lds);
+    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
 }  // namespace clot

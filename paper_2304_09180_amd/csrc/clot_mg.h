@@ -237,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_mg_post2(Grid G, Op op, const T* b, cons
         x[P.g] = z;
         if (DOT) acc[0] += (double)b[P.g] * (double)z;
     CLOT_END_CELLS
-    if (DOT) store_partials<1>(acc, S.part, tile, lds);
+    if (DOT) store_partials<1>(acc, S.part, S.pstride, tile, lds);
 }
 
 // One post-smoothing sweep with the prolonged correction (the single-sweep cycle):
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(NT) void k_mg_post_one(MGPair L, Op op, const T* b,
         z[P.g] = zz;
         if (DOT) acc[0] += (double)b[P.g] * (double)zz;
     CLOT_END_CELLS
-    if (DOT) store_partials<1>(acc, S.part, tile, lds);
+    if (DOT) store_partials<1>(acc, S.part, S.pstride, tile, lds);
 }
 
 struct EpiMgDot {   // r.z of the new preconditioned residual -> beta
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(NT) void k_mgcg_init(Grid G, Op op, KVec<T, 1> V, K
         acc[0] += (double)b * (double)b;
         acc[1] += (double)r * (double)r;
     CLOT_END_CELLS
-    store_partials<2>(acc, S.part, tile, lds);
+    store_partials<2>(acc, S.part, S.pstride, tile, lds);
 }
 
 struct EpiMgcgInit {
@@ -622,7 +622,7 @@ __global__ __launch_bounds__(NT) void k_mgcg_a(Grid G, Op op, KVec<T, 1> V, cons
         V.t[0][P.g] = q;
         acc[0] += (double)pn * (double)q;
     CLOT_END_CELLS
-    store_partials<1>(acc, S.part, tile, lds);
+    store_partials<1>(acc, S.part, S.pstride, tile, lds);
 }
 
 // x += alpha p; r -= alpha q; rr; convergence (the next z comes from the V-cycle).
@@ -640,7 +640,7 @@ __global__ __launch_bounds__(NT) void k_mgcg_b(Grid G, Op op, KVec<T, 1> V, KSta
         V.r[0][g] = r;
         acc[0] += (double)r * (double)r;
     CLOT_END_CELLS
-    store_partials<1>(acc, S.part, tile, lds);
+    store_partials<1>(acc, S.part, S.pstride, tile, lds);
 }
 
 struct EpiMgcgB {   // convergence of the MG-preconditioned CG

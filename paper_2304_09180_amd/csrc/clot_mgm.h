@@ -19,8 +19,8 @@
 // A boundary face coefficient lives in the face array at the boundary position
 // (outlet: zero-gradient, no viscous term), so the diagonal of a coarse cell is its
 // mass plus its six face coefficients.  Levels are used until the viscous part of
-// the diagonal falls below half the mass everywhere; there three Jacobi sweeps from
-// zero stand in for the coarsest solve.
+// the diagonal falls below MGM_RATIO times the mass everywhere; there two Jacobi
+// sweeps from zero stand in for the coarsest solve.
 //
 // Cycle: V(1,2) — one weighted-Jacobi sweep from zero, formed inside the residual
 // restriction, and two sweeps after the prolongation.  All velocity components of a
@@ -31,7 +31,8 @@
 
 namespace clot {
 
-constexpr int MGM_K = 3;   // velocity components
+constexpr int MGM_K = 3;            // velocity components
+constexpr double MGM_RATIO = 2.5;   // coarsest level: viscous part of the diagonal < this x the mass
 
 template <class T>
 struct MGVec {
@@ -476,7 +477,7 @@ __global__ __launch_bounds__(NT) void k_pbicg_1(Grid G, Op op, KVec<T, K> V, MGC
             acc[k] += (double)V.rh[k][P.g] * (double)vn;
         }
     CLOT_END_CELLS
-    store_partials<K>(acc, S.part, tile, lds);
+    store_partials<K>(acc, S.part, S.pstride, tile, lds);
 }
 
 // t = A z; t.s, t.t
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(NT) void k_pbicg_2(Grid G, Op op, KVec<T, K> V, MGC
             acc[2 * k + 1] += (double)t * (double)t;
         }
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, tile, lds);
+    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
 // x += alpha y + omega z; r = s - omega t; rhat.r, r.r
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(NT) void k_pbicg_3(Grid G, KVec<T, K> V, MGCVec<T> 
             acc[2 * k + 1] += (double)r * (double)r;
         }
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, tile, lds);
+    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
 }  // namespace clot

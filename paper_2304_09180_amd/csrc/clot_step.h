@@ -181,7 +181,7 @@ __global__ __launch_bounds__(NT) void k_pres_resid(Grid G, Fields<T> F, T* rin, 
         acc[0] += r * r;
         acc[1] += b * b;
     CLOT_END_CELLS
-    store_partials<2>(acc, S.part, tile, lds);
+    store_partials<2>(acc, S.part, S.pstride, tile, lds);
 }
 
 // Decides on the device whether a channel needs another refinement pass, and the
