@@ -21,25 +21,34 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 
 # Algorithmic bytes per cell for each timed phase (compulsory reads + writes of one
-# launch, stencil neighbours counted once), FP32 storage (x2 for FP64).
-#   p_cg_a : z, p_old, diag, rAU read; p_new, q written            -> 6 arrays
-#   p_cg_b : x, p_new, r, q, diag read; x, r written                -> 7 arrays
-#   tr_b1  : per system r, p_old, v_old, diag, rhat read and the six stored couplings;
-#            p, v written (13)
-#   tr_b2  : per system r, v, diag and the six couplings read; t written (10)
-#   tr_b3  : per system x, r, rhat, p, v, t, diag read; x, r written (9)
-#   rxn    : 14 species and their low parts + ADP + eta read; 14 species and their low
-#            parts written (58)
-#   mom_b1 : per velocity component r, p_old, v_old, rhat read; p, v written (6)
-#            plus the shared diagonal a_P and the face fluxes (dim arrays)
-#   mom_b2 : per component r, v read; t written (3) + a_P + fluxes
-#   mom_b3 : per component x, r, rhat, p, v, t read; x, r written (8) + a_P
-ARRAYS = {"p_cg_a": lambda dim: 6, "p_cg_b": lambda dim: 7,
-          "tr_b1": lambda dim: 7 * 13, "tr_b2": lambda dim: 7 * 10,
-          "tr_b3": lambda dim: 7 * 9, "rxn": lambda dim: 58,
-          "mom_b1": lambda dim: dim * 6 + 1 + dim, "mom_b2": lambda dim: dim * 3 + 1 + dim,
-          "mom_b3": lambda dim: dim * 8 + 1}
-
+# launch, stencil neighbours counted once), in cell-sized FP32 arrays (x2 for FP64).
+# c = velocity components (= dim), a = transport systems still iterating (the last
+# step's sysit_tr / it_tr: a system leaves the batched solve once it converges).
+#   p_cg_a   : z, p_old, diag, rAU read; p_new, q written                       -> 6
+#   p_cg_b   : x, p_new, r, q, diag read; x, r written                          -> 7
+#   tr_b1    : per system r, p_old, v_old, diag, rhat and the six stored couplings
+#              read; p, v written                                              -> 13 a
+#   tr_b2    : per system r, v, diag and the six couplings read; t written       -> 10 a
+#   tr_b3    : per system x, r, rhat, p, v, t, diag read; x, r written          -> 9 a
+#   rxn      : 14 species and their low parts + ADP + eta read; 14 species and
+#              their low parts written                                          -> 58
+#   momentum BiCGStab with the multigrid V-cycle (the default):
+#   mom_b1   : y, rhat per component + a_P + dim face fluxes read; v written   -> 3c + 1 + dim
+#   mom_b2   : z, s per component + a_P + fluxes read; t written               -> 3c + 1 + dim
+#   mom_b3   : x, y, z, s, t, rhat read; x, r written per component             -> 8c
+#   mom_mg_r : finest restriction, averaged over its two forms (r, p, v or r, v
+#              read; the formed right-hand side and the coarse one (1/8) written)
+#              + a_P + fluxes                                                   -> 3.5c + 1 + dim + c/8
+#   mom_mg_p1: b, coarse x (1/8), a_P, fluxes read; y written                  -> 2c + 1 + dim + c/8
+#   mom_mg_p2: b, y, a_P, fluxes read; x written                                -> 3c + 1 + dim
+def probe_arrays(probe, dim, st):
+    c = dim
+    a = st["sysit_tr"] / st["it_tr"] if st.get("it_tr") else 7.0
+    table = {"p_cg_a": 6, "p_cg_b": 7, "tr_b1": 13 * a, "tr_b2": 10 * a, "tr_b3": 9 * a, "rxn": 58,
+             "mom_b1": 3 * c + 1 + dim, "mom_b2": 3 * c + 1 + dim, "mom_b3": 8 * c,
+             "mom_mg_r": 3.5 * c + 1 + dim + c / 8, "mom_mg_p1": 2 * c + 1 + dim + c / 8,
+             "mom_mg_p2": 3 * c + 1 + dim}
+    return table[probe]
 
 
 def step_arrays(dim, st, ns):
@@ -50,8 +59,14 @@ def step_arrays(dim, st, ns):
     c = dim                                           # velocity components
     fixed = (6                                        # k_derive: 4 platelet fields -> theta_B, W
              + (2 * c + 2 + dim + 1) + (1 + 2 * c)    # k_mom_assemble: u, p, fluxes, theta_B -> a_P, src, b
+             + 1 + 5 / 8.0                            # momentum levels: theta_B -> coarse mass, coefficients
              + (2 * c + 1 + dim) + 4 * c)             # momentum BiCGStab start: x, b, a_P, fluxes -> r, rh, p, v
-    mom_it = (c * 6 + 1 + dim) + (c * 3 + 1 + dim) + (c * 8 + 1)
+    # momentum iteration: two V-cycles (finest: restriction, prolongation sweep, sweep; the
+    # coarse levels at 1/8 the cells each, three passes over b, x, y and four coefficient
+    # arrays) and the three BiCGStab phases
+    fine = ((3.5 * c + 1 + dim + c / 8) + (2 * c + 1 + dim + c / 8) + (3 * c + 1 + dim))
+    coarse = ((c + 4 + c / 8) + (2 * c + 4 + c / 8) + (3 * c + 4)) / 8.0 * 8.0 / 7.0
+    mom_it = 2 * (fine + coarse) + (3 * c + 1 + dim) + (3 * c + 1 + dim) + 8 * c
     corr = (2 * c + 1 + dim) + c                      # k_hbya: u, src, a_P, fluxes -> HbyA
     corr += (c + 1) + 2 + 1                           # k_prhs: HbyA, rAU -> rhs (FP64), diagonal
     corr += (2 + c + 1) + (c + dim)                   # k_correct: p, HbyA, rAU -> u, flux
@@ -66,7 +81,7 @@ def step_arrays(dim, st, ns):
                                                       # (FP32 and FP64), FP64 right-hand sides, couplings
           + ntr * 17                                  # delta-form start: C^n, low part, FP64 diagonal and
                                                       # right-hand side, couplings -> r, rh, p, v, change
-          + st["it_tr"] * ntr * (13 + 10 + 9)         # BiCGStab phases
+          + st["sysit_tr"] * (13 + 10 + 9)            # BiCGStab phases of the systems still iterating
           + ntr * 5)                                  # species + low part + change -> species, low part
     rxn = 58                                          # reactions on value + low part of 14 species
     total = fixed + st["it_mom"] * mom_it + eta + tr + rxn
@@ -87,9 +102,9 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--tile", default="auto", choices=["auto", "256", "512", "1024"],
                     help="cells per block; auto runs the tile autotuner on each workload first")
-    ap.add_argument("--probe", default="mom_b2",
-                    help="kernel phase timed for the roofline (default: the momentum BiCGStab's second phase, "
-                         "the kernel with the largest share of the step)")
+    ap.add_argument("--probe", default="tr_b1",
+                    help="kernel phase timed for the roofline (default: the transport BiCGStab's first phase, "
+                         "the mesh-streaming kernel with the largest share of the step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
     ap.add_argument("--train-samples", type=int, default=400_000)
@@ -357,7 +372,7 @@ def main():
     base_us = {k: kernel_us(s, k) for k in ("tr_asm", "tr_b1")}
     value = ncell * args.steps / el
     bpe = 4 if prec == clot.FP32_MIXED else 8
-    nbytes = ARRAYS[args.probe](desc["dim"]) * bpe * ncell
+    nbytes = int(probe_arrays(args.probe, desc["dim"], st) * bpe * ncell)
     roof = None
     if probe_n:
         avg_s = probe_ms / 1e3 / probe_n

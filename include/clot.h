@@ -162,6 +162,10 @@ typedef struct {
                                                    largest face flux (discrete continuity)   */
     double min_species;                         /* smallest species value over its scale
                                                    (P_max, ADP*, S1_0, S2_0): < 0 if negative */
+    int32_t sysit_tr;                           /* transport: iterations summed over the
+                                                   systems (a system leaves the batched solve
+                                                   when it converges, so sysit_tr / it_tr
+                                                   systems work per iteration on average)     */
 } clot_stats;
 
 typedef struct clot_ctx clot_ctx;

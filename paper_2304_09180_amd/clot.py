@@ -70,7 +70,7 @@ class Stats(C.Structure):
                 ("refine_p", C.c_int32 * 8),
                 ("res_mom", C.c_double), ("res_p", C.c_double), ("res_eta", C.c_double), ("res_tr", C.c_double),
                 ("fallback_frac", C.c_double), ("steps", C.c_int64), ("t", C.c_double), ("dt", C.c_double),
-                ("div_rel", C.c_double), ("min_species", C.c_double)]
+                ("div_rel", C.c_double), ("min_species", C.c_double), ("sysit_tr", C.c_int32)]
 
 
 class ClotError(RuntimeError):
@@ -279,7 +279,7 @@ class Solver:
         return {"status": STATUS.get(st, st), "it_mom": s.it_mom, "it_p": list(s.it_p), "it_eta": s.it_eta,
                 "it_tr": s.it_tr, "refine_p": list(s.refine_p), "res_mom": s.res_mom, "res_p": s.res_p,
                 "res_eta": s.res_eta, "res_tr": s.res_tr, "fallback_frac": s.fallback_frac, "steps": s.steps,
-                "t": s.t, "dt": s.dt, "div_rel": s.div_rel, "min_species": s.min_species}
+                "t": s.t, "dt": s.dt, "div_rel": s.div_rel, "min_species": s.min_species, "sysit_tr": s.sysit_tr}
 
     def save_state(self) -> np.ndarray:
         """The context's state (device workspace and host side) as a uint8 host array."""

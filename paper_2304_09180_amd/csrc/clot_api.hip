@@ -26,7 +26,8 @@ constexpr int NPART = 3 * MAXK;      // max partial sums per tile
 constexpr int NSTAT = 40;            // per-channel statistics slots
 constexpr int MAXCORR = 8;
 enum { ST_MOM = 0, ST_ETA = 1, ST_TR = 2, ST_P = 3 /* +corr */, ST_REF = 12 /* +corr */, ST_RESM = 21, ST_RESP = 22,
-       ST_RESE = 23, ST_REST = 24, ST_FAIL = 25, ST_FALLBACK = 26, ST_DIAG = 27 /* div, |phi| max, min species */ };
+       ST_RESE = 23, ST_REST = 24, ST_FAIL = 25, ST_FALLBACK = 26, ST_DIAG = 27 /* div, |phi| max, min species */,
+       ST_SYSIT_TR = 30 };
 
 struct Carver {
     char* base;
@@ -209,6 +210,8 @@ struct Ctx : clot_ctx {
     T* mg_z0 = nullptr;      // preconditioned residual z = M r
     double* mg_inv = nullptr;  // per-channel inverse of the coarsest-level matrix
     int mgm_nc = 0;          // coarse levels of the momentum preconditioner (0: Jacobi BiCGStab)
+    std::vector<int32_t> h_mgm_last;   // per channel: its coarsest momentum level
+    int32_t* d_mgm_last = nullptr;
     // LDS-staged finest-level momentum kernels: bricks of every channel (when every
     // channel is coarsened along every axis)
     std::vector<BrickChan> h_brick;
@@ -429,6 +432,7 @@ struct Ctx : clot_ctx {
             L.cy = cv.take<T>(L.NFY);
             L.cz = cv.take<T>(L.NFZ);
         }
+        d_mgm_last = cv.take<int32_t>(nch);
         d_brick = cv.take<BrickChan>(std::max<size_t>(h_brick.size(), 1));
         d_b2c = cv.take<int32_t>(std::max<size_t>(h_b2c.size(), 1));
         for (int l = 0; l < mgm_nc; ++l) {
@@ -562,26 +566,27 @@ struct Ctx : clot_ctx {
         bool all3d = true;
         for (const ChanHost& h : ch) all3d = all3d && h.d.dim == 3;
         mg_w = T(all3d ? 6.0 / 7.0 : 0.8);
-        // momentum preconditioner: coarse levels until, in every channel, the viscous part
-        // of the diagonal (nu dt sum_ax 2/h_ax^2 of the mass V/dt; Darcy and Crank-Nicolson
+        // momentum preconditioner: each channel's coarse levels run until the viscous part
+        // of its diagonal (nu dt sum_ax 2/h_ax^2 of the mass V/dt; Darcy and Crank-Nicolson
         // only add mass) is below MGM_RATIO times the mass (a CPU model of the cycle: 4
         // BiCGStab iterations on the duct and 2 on a 512x128 channel at D = 69 whether the
         // coarsest level's ratio is 0.5 or 8; each level dropped saves three launches per
-        // cycle)
+        // cycle).  The context keeps as many levels as its deepest channel needs.
         mgm_nc = 0;
+        h_mgm_last.assign(nch, 0);
         if (p->mom_mg && !lev.empty()) {
-            for (int l = 0; l < (int)lev.size(); ++l) {
-                ++mgm_nc;
-                double worst = 0.0;
-                for (int i = 0; i < nch; ++i) {
+            for (int i = 0; i < nch; ++i) {
+                const clot_channel& d = ch[i].d;
+                int l = 0;
+                for (; l + 1 < (int)lev.size(); ++l) {
                     const ChanDev& c = lev[l].ch[i];
-                    const clot_channel& d = ch[i].d;
                     const double hx = d.Lx / c.nx, hy = d.Ly / c.ny, hz = d.Lz / c.nz;
                     double v = 2.0 / (hx * hx) + 2.0 / (hy * hy);
                     if (c.dim == 3) v += 2.0 / (hz * hz);
-                    worst = std::max(worst, p->nu * d.dt * v);
+                    if (p->nu * d.dt * v < MGM_RATIO) break;
                 }
-                if (worst < MGM_RATIO) break;
+                h_mgm_last[i] = l;
+                mgm_nc = std::max(mgm_nc, l + 1);
             }
         }
         h_brick.clear();
@@ -769,6 +774,7 @@ struct Ctx : clot_ctx {
             HIPCHK(hipMemcpyAsync(L.d_t2c, L.t2c.data(), L.t2c.size() * 4, hipMemcpyHostToDevice, st));
         }
         HIPCHK(hipMemcpyAsync(d_t2c, t2c.data(), t2c.size() * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_mgm_last, h_mgm_last.data(), nch * 4, hipMemcpyHostToDevice, st));
         if (!h_b2c.empty()) {
             HIPCHK(hipMemcpyAsync(d_brick, h_brick.data(), h_brick.size() * sizeof(BrickChan), hipMemcpyHostToDevice,
                                   st));
@@ -1243,7 +1249,7 @@ struct Ctx : clot_ctx {
         }
         it_max[4] = std::max(it_max[4], total);   // for graph budgets
         hipLaunchKernelGGL(k_record, dim3(1), dim3(64), 0, st, Se.sc, dstats, NSTAT, (int)ch.size(), 1, (int)ST_ETA,
-                           (int)ST_RESE, (int)ST_FAIL, 0, (const int32_t*)nullptr);
+                           (int)ST_RESE, (int)ST_FAIL, 0, (const int32_t*)nullptr, -1);
         return CLOT_OK;
     }
 
@@ -1465,27 +1471,34 @@ struct Ctx : clot_ctx {
         else
             CLOT_LAUNCH(CLOT_PROBE_MOM_MG_R, (k_mgm_restrict<T, MomOp<T>, FORM, true>), dim3(lev[0].ntiles * rb),
                         dim3(NT), 0, st, MGPair{grid(), lev[0].grid()}, mop, src, mv3(bout), none, mv3(lev[0].mb), S,
-                        mg_w);
+                        mg_w, MGGate{});
+        // a channel's coarsest level: two Jacobi sweeps from zero (the mass dominates there)
+        auto coarsest = [&](int l) {
+            bool any = false;
+            for (int32_t q : h_mgm_last) any = any || q == l;
+            if (!any) return;
+            Level& L = lev[l];
+            hipLaunchKernelGGL((k_mgm_pre<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), L.mom_op(),
+                               cv3(L.mb), mv3(L.mx), mg_w, S, MGGate{d_mgm_last, l, 1});
+        };
         for (int l = 0; l + 1 < nc; ++l) {
             Level& L = lev[l];
+            coarsest(l);
             MGSrc<T> sl{};
             for (int k = 0; k < MGM_K; ++k) sl.b[k] = L.mb[k];
             hipLaunchKernelGGL((k_mgm_restrict<T, CoefOp<T>, 0, true>), dim3(lev[l + 1].ntiles * rb), dim3(NT), 0, st,
                                MGPair{L.grid(), lev[l + 1].grid()}, L.mom_op(), sl, MGVec<T>{}, none,
-                               mv3(lev[l + 1].mb), S, mg_w);
+                               mv3(lev[l + 1].mb), S, mg_w, MGGate{d_mgm_last, l, 0});
         }
-        {   // coarsest: two Jacobi sweeps from zero (the mass dominates there)
-            Level& L = lev[nc - 1];
-            hipLaunchKernelGGL((k_mgm_pre<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), L.mom_op(),
-                               cv3(L.mb), mv3(L.mx), mg_w, S);
-        }
+        coarsest(nc - 1);
         for (int l = nc - 2; l >= 0; --l) {
             Level& L = lev[l];
+            const MGGate up{d_mgm_last, l, 0};
             hipLaunchKernelGGL((k_mgm_post1<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st,
                                MGPair{L.grid(), lev[l + 1].grid()}, L.mom_op(), cv3(L.mb), cv3(lev[l + 1].mx),
-                               mv3(L.my), mg_w, S);
+                               mv3(L.my), mg_w, S, up);
             hipLaunchKernelGGL((k_mgm_post2<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, L.grid(), L.mom_op(),
-                               cv3(L.mb), cv3(L.my), mv3(L.mx), mg_w, S);
+                               cv3(L.mb), cv3(L.my), mv3(L.mx), mg_w, S, up);
         }
         const MGCVec<T> bf = FORM == 0 ? MGCVec<T>{{src.b[0], src.b[1], src.b[2]}} : cv3(bout);
         if (brick) {
@@ -1496,9 +1509,9 @@ struct Ctx : clot_ctx {
                         mv3(mgm_vec(3)), S, mg_w);
         } else
             CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P1, (k_mgm_post1<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st,
-                        MGPair{grid(), lev[0].grid()}, mop, bf, cv3(lev[0].mx), mv3(mgm_vec(3)), mg_w, S);
+                        MGPair{grid(), lev[0].grid()}, mop, bf, cv3(lev[0].mx), mv3(mgm_vec(3)), mg_w, S, MGGate{});
         CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P2, (k_mgm_post2<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, bf,
-                    cv3(mgm_vec(3)), mv3(out), mg_w, S);
+                    cv3(mgm_vec(3)), mv3(out), mg_w, S, MGGate{});
     }
 
     // BiCGStab on the momentum system with one V-cycle per direction (right
@@ -1568,9 +1581,9 @@ struct Ctx : clot_ctx {
         return V;
     }
 
-    void record(int slot_it, int slot_res, int K, bool add, const int32_t* mask = nullptr) {
+    void record(int slot_it, int slot_res, int K, bool add, const int32_t* mask = nullptr, int slot_sum = -1) {
         hipLaunchKernelGGL(k_record, dim3(1), dim3(64), 0, st, S.sc, dstats, NSTAT, (int)ch.size(), K, slot_it, slot_res,
-                           (int)ST_FAIL, add ? 1 : 0, mask);
+                           (int)ST_FAIL, add ? 1 : 0, mask, slot_sum);
     }
 
     // ---------------------------------------------------------------------------
@@ -1694,7 +1707,7 @@ struct Ctx : clot_ctx {
             run_bicg<TrOp<T>, NTR>(top, V, prm.rtol_tr > 0.0 ? prm.rtol_tr : prm.rtol_s, allmask, 5,
                                    CLOT_PROBE_TR_B1);
             hipLaunchKernelGGL(k_add_change<T>, gb, tb, 0, st, G, F);
-            record(ST_TR, ST_REST, NTR, false);
+            record(ST_TR, ST_REST, NTR, false, nullptr, ST_SYSIT_TR);
         }
         if (eta_side) {   // the transport solve's polls have synchronised the main stream
             const clot_status r = eta_side_finish();
@@ -2112,6 +2125,7 @@ struct Ctx : clot_ctx {
         s->dt = cd.dt;
         s->div_rel = v[ST_DIAG + 1] > 0.0 ? v[ST_DIAG] / v[ST_DIAG + 1] : v[ST_DIAG];
         s->min_species = v[ST_DIAG + 2];
+        s->sysit_tr = (int32_t)v[ST_SYSIT_TR];
         return v[ST_FAIL] >= 2 ? CLOT_W_NONFINITE : v[ST_FAIL] > 0 ? CLOT_W_NOTCONV : CLOT_OK;
     }
 };

@@ -18,9 +18,9 @@
 // for the pressure operator, this equals the re-discretisation on uniform cells).
 // A boundary face coefficient lives in the face array at the boundary position
 // (outlet: zero-gradient, no viscous term), so the diagonal of a coarse cell is its
-// mass plus its six face coefficients.  Levels are used until the viscous part of
-// the diagonal falls below MGM_RATIO times the mass everywhere; there two Jacobi
-// sweeps from zero stand in for the coarsest solve.
+// mass plus its six face coefficients.  A channel's levels are used until the viscous
+// part of its diagonal falls below MGM_RATIO times the mass; there two Jacobi sweeps
+// from zero stand in for the coarsest solve.
 //
 // Cycle: V(1,2) — one weighted-Jacobi sweep from zero, formed inside the residual
 // restriction, and two sweeps after the prolongation.  All velocity components of a
@@ -136,19 +136,31 @@ __device__ inline void mgm_active(const KState& S, int chid, int dim, bool (&act
     for (int k = 0; k < MGM_K; ++k) act[k] = k < dim && scp(S, chid, k)[SC_ACT] != 0.0;
 }
 
+// Each channel has its own coarsest momentum level (last[ch], an index of the coarse
+// levels), so its cycle does not depend on the other channels of the context.  A
+// coarse-level launch of level `level` works for the channels with last > level
+// (restriction to the next level, sweeps after its correction) or, with eq, for those
+// whose coarsest level it is.  No gate (last = nullptr): every channel.
+struct MGGate {
+    const int32_t* last;
+    int32_t level;
+    int32_t eq;
+    __device__ bool open(int ch) const { return !last || (eq ? last[ch] == level : last[ch] > level); }
+};
+
 // Restriction of the residual of one Jacobi sweep from zero (x = w D^-1 b, ONFLY) or
 // of a given x, summed over each aggregate: eight lanes per coarse cell, one per fine
 // cell, added by lane shuffles.  FORM 1/2 form the finest right-hand side on the fly
 // and write it to bout.  Launch: 8 blocks per coarse tile.
 template <class T, class Op, int FORM, bool ONFLY>
 __global__ __launch_bounds__(NT) void k_mgm_restrict(MGPair L, Op op, MGSrc<T> src, MGVec<T> bout, MGCVec<T> x,
-                                                     MGVec<T> bc, KState S, T w) {
+                                                     MGVec<T> bc, KState S, T w, MGGate gate) {
     constexpr int CPB = NT / 8;
     constexpr int BPT = TILE / CPB;
     const int32_t tile = xcd_tile((int32_t)blockIdx.x / BPT, L.coarse.ntiles);
     const int32_t sub = (int32_t)blockIdx.x % BPT;
     const int32_t chid = L.coarse.t2c[tile];
-    if (!S.chact[chid]) return;
+    if (!S.chact[chid] || !gate.open(chid)) return;
     const ChanDev C = L.coarse.ch[chid];
     const ChanDev Fc = L.fine.ch[chid];
     bool act[MGM_K];
@@ -209,9 +221,9 @@ __global__ __launch_bounds__(NT) void k_mgm_restrict(MGPair L, Op op, MGSrc<T> s
 // injected coarse correction, both formed on the fly), y = x1 + w D^-1 (b - A x1).
 template <class T, class Op>
 __global__ __launch_bounds__(NT) void k_mgm_post1(MGPair L, Op op, MGCVec<T> b, MGCVec<T> xc, MGVec<T> y, T w,
-                                                  KState S) {
+                                                  KState S, MGGate gate) {
     CLOT_TILE_PROLOGUE(L.fine)
-    if (!S.chact[chid]) return;
+    if (!S.chact[chid] || !gate.open(chid)) return;
     const ChanDev Cc = L.coarse.ch[chid];
     bool act[MGM_K];
     mgm_active(S, chid, C.dim, act);
@@ -233,9 +245,9 @@ __global__ __launch_bounds__(NT) void k_mgm_post1(MGPair L, Op op, MGCVec<T> b, 
 // One weighted-Jacobi sweep: out = y + w D^-1 (b - A y).
 template <class T, class Op>
 __global__ __launch_bounds__(NT) void k_mgm_post2(Grid G, Op op, MGCVec<T> b, MGCVec<T> y, MGVec<T> out, T w,
-                                                  KState S) {
+                                                  KState S, MGGate gate) {
     CLOT_TILE_PROLOGUE(G)
-    if (!S.chact[chid]) return;
+    if (!S.chact[chid] || !gate.open(chid)) return;
     bool act[MGM_K];
     mgm_active(S, chid, C.dim, act);
     CLOT_FOR_CELLS(local)
@@ -253,9 +265,9 @@ __global__ __launch_bounds__(NT) void k_mgm_post2(Grid G, Op op, MGCVec<T> b, MG
 // Two weighted-Jacobi sweeps from zero (the coarsest level): x1 = w D^-1 b,
 // x = x1 + w D^-1 (b - A x1).
 template <class T, class Op>
-__global__ __launch_bounds__(NT) void k_mgm_pre(Grid G, Op op, MGCVec<T> b, MGVec<T> x, T w, KState S) {
+__global__ __launch_bounds__(NT) void k_mgm_pre(Grid G, Op op, MGCVec<T> b, MGVec<T> x, T w, KState S, MGGate gate) {
     CLOT_TILE_PROLOGUE(G)
-    if (!S.chact[chid]) return;
+    if (!S.chact[chid] || !gate.open(chid)) return;
     bool act[MGM_K];
     mgm_active(S, chid, C.dim, act);
     CLOT_FOR_CELLS(local)

@@ -805,18 +805,20 @@ __global__ __launch_bounds__(256) void k_diag_finish(const ChanDev* chans, const
 // Records one solve's iteration count, residual and failure flag per channel; with
 // `mask`, only channels whose mask entry is set took part in the solve.
 __global__ void k_record(const double* sc, double* stats, int nstat, int nch, int K, int slot_it, int slot_res,
-                         int slot_fail, int add, const int32_t* mask) {
+                         int slot_fail, int add, const int32_t* mask, int slot_sum) {
     for (int c = threadIdx.x; c < nch; c += blockDim.x) {
         if (mask && !mask[c]) continue;
-        double it = 0.0, res = 0.0, fail = 0.0;
+        double it = 0.0, res = 0.0, fail = 0.0, sum = 0.0;
         for (int k = 0; k < K; ++k) {
             const double* s = sc + ((int64_t)c * MAXK + k) * NSC;
             it = fmax(it, s[SC_IT]);
+            sum += s[SC_IT];
             if (s[SC_BBS] > 0.0) res = fmax(res, sqrt(s[SC_RR] / s[SC_BBS]));
             fail = fmax(fail, s[SC_FAIL]);
         }
         double* st = stats + (int64_t)c * nstat;
         st[slot_it] = add ? st[slot_it] + it : it;
+        if (slot_sum >= 0) st[slot_sum] = add ? st[slot_sum] + sum : sum;   // system-iterations
         if (slot_res >= 0) st[slot_res] = res;
         st[slot_fail] = fmax(st[slot_fail], fail);
     }
