@@ -1724,16 +1724,16 @@ struct Ctx : clot_ctx {
             fill(fb_chan, 0, nch);
             MLPWeights w{mlp_wb + MLP_OFF_W1, mlp_wb + MLP_OFF_W2, mlp_wb + MLP_OFF_W3,
                          mlp_wf + MLP_OFF_B1, mlp_wf + MLP_OFF_B2, mlp_wf + MLP_OFF_B3};
-            CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn_surr<T>, gb, dim3(256), 0, st, G, F, M, w, surr_tb, surr_tol, fb_list,
+            CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn_surr<T>, gb, dim3(256), 0, st, G, F, rxn_consts<T>(M), w, surr_tb, surr_tol, fb_list,
                         fb_count, fb_chan);
-            CLOT_LAUNCH(CLOT_PROBE_RXN_FALLBACK, k_rxn_list<T>, dim3((unsigned)std::min<int64_t>((N + NT - 1) / NT, 1024)), tb, 0, st, d_ch, nch, F, M,
+            CLOT_LAUNCH(CLOT_PROBE_RXN_FALLBACK, k_rxn_list<T>, dim3((unsigned)std::min<int64_t>((N + NT - 1) / NT, 1024)), tb, 0, st, d_ch, nch, F, (int)M.M_rxn, rxn_consts<T>(M),
                         fb_list, fb_count);
             hipLaunchKernelGGL(k_record_fallback, dim3(1), dim3(64), 0, st, fb_chan, d_ch, dstats, NSTAT, nch,
                                (int)ST_FALLBACK);
         } else
 #endif
         {
-            CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn<T>, gb, tb, 0, st, G, F, M);
+            CLOT_LAUNCH(CLOT_PROBE_RXN, k_rxn<T>, gb, tb, 0, st, G, F, (int)M.M_rxn, rxn_consts<T>(M));
         }
         // the next step's ddt coefficients and variable step
         if (M.psi > 0.0 || M.max_co > 0.0)
@@ -2488,8 +2488,9 @@ clot_status clot_rxn_rk4_batch(const clot_params* p, const double* rows, int64_t
 #else
     if (!p || !rows || !inc || n < 0 || p->M_rxn < 1) return CLOT_EINVAL;
     if (n == 0) return CLOT_OK;
+    const ModelDev M = model_from_params(*p);
     hipLaunchKernelGGL(k_rxn_batch, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, (hipStream_t)stream, rows, n,
-                       model_from_params(*p), inc);
+                       (int)M.M_rxn, rxn_consts<double>(M), inc);
     CHK_LAUNCH();
     return CLOT_OK;
 #endif
@@ -2510,7 +2511,7 @@ clot_status clot_surr_dataset(const clot_params* p, const double* rows, const do
     }
     surr_tables_finish(M, tb);
     hipLaunchKernelGGL(k_surr_dataset, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, (hipStream_t)stream, rows, inc, n,
-                       M, tb, x, t, stats);
+                       rxn_consts<double>(M), tb, x, t, stats);
     CHK_LAUNCH();
     return CLOT_OK;
 #endif

@@ -548,21 +548,65 @@ __global__ __launch_bounds__(256) void k_time_end(ChanDev* chans, const double* 
 
 // Reaction right-hand side (Appendix A platelet equations, Appendix B coagulation
 // equations), y in the order Pmu Pma Pba Pbse S1 S2 E1 E2 S1b S2b E1b E2b C1 C2.
+// The reaction constants in the arithmetic type, formed once on the host and passed
+// as a kernel argument (uniform, so they stay in scalar registers instead of being
+// converted from the FP64 model table into vector registers in every thread).
 template <class T>
-__device__ inline void rxn_rhs(const T (&y)[NRX], T adp, T gam, T hadh, const ModelDev& M, T (&f)[NRX]) {
-    const T pmax = T(M.P_max);
-    const T adh = T(M.k_adh) * hadh * (pmax - y[3]);
-    const T act = T(M.k_adp) * adp / (T(M.adp_crit) + adp) + T(M.k_e2) * y[7] / (T(M.e2_crit) + y[7]);
-    const T coh = T(M.kcoh_Pmax) * gam;
+struct RxnK {
+    T P_max, k_adh, k_adp, adp_crit, k_e2, e2_crit, kcoh_Pmax, n1, n2;
+    T kC1p, kC2p, kS1p, kS1m, kS2p, kS2m, kE1p, kE1m, kE2p, kE2m;
+    T kC1m, kC2m, kC1cat, kC2cat, kC1mc, kC2mc, k_I;
+    T eta_t, eta_star3, g0;
+};
+template <class T>
+__host__ __device__ inline RxnK<T> rxn_consts(const ModelDev& M) {
+    RxnK<T> K;
+    K.P_max = T(M.P_max);
+    K.k_adh = T(M.k_adh);
+    K.k_adp = T(M.k_adp);
+    K.adp_crit = T(M.adp_crit);
+    K.k_e2 = T(M.k_e2);
+    K.e2_crit = T(M.e2_crit);
+    K.kcoh_Pmax = T(M.kcoh_Pmax);
+    K.n1 = T(M.N1 / M.N_A);
+    K.n2 = T(M.N2 / M.N_A);
+    K.kC1p = T(M.kC1p);
+    K.kC2p = T(M.kC2p);
+    K.kS1p = T(M.kS1p);
+    K.kS1m = T(M.kS1m);
+    K.kS2p = T(M.kS2p);
+    K.kS2m = T(M.kS2m);
+    K.kE1p = T(M.kE1p);
+    K.kE1m = T(M.kE1m);
+    K.kE2p = T(M.kE2p);
+    K.kE2m = T(M.kE2m);
+    K.kC1m = T(M.kC1m);
+    K.kC2m = T(M.kC2m);
+    K.kC1cat = T(M.kC1cat);
+    K.kC2cat = T(M.kC2cat);
+    K.kC1mc = T(M.kC1m + M.kC1cat);
+    K.kC2mc = T(M.kC2m + M.kC2cat);
+    K.k_I = T(M.k_I);
+    K.eta_t = T(M.eta_t);
+    K.eta_star3 = T(M.eta_star * M.eta_star * M.eta_star);
+    K.g0 = T(M.g0);
+    return K;
+}
+
+template <class T>
+__device__ inline void rxn_rhs(const T (&y)[NRX], T adp, T gam, T hadh, const RxnK<T>& K, T (&f)[NRX]) {
+    const T adh = K.k_adh * hadh * (K.P_max - y[3]);
+    const T act = K.k_adp * adp / (K.adp_crit + adp) + K.k_e2 * y[7] / (K.e2_crit + y[7]);
+    const T coh = K.kcoh_Pmax * gam;
     const T bound = y[2] + y[3];
-    const T B1 = T(M.N1 / M.N_A) * bound - (y[8] + y[10] + y[12] + y[13]);
-    const T B2 = T(M.N2 / M.N_A) * bound - (y[9] + y[11] + y[12] + y[13]);
-    const T c1 = T(M.kC1p) * y[9] * y[10];
-    const T c2 = T(M.kC2p) * y[8] * y[11];
-    const T bS1 = T(M.kS1p) * B1 * y[4] - T(M.kS1m) * y[8];
-    const T bS2 = T(M.kS2p) * B2 * y[5] - T(M.kS2m) * y[9];
-    const T bE1 = T(M.kE1p) * B1 * y[6] - T(M.kE1m) * y[10];
-    const T bE2 = T(M.kE2p) * B2 * y[7] - T(M.kE2m) * y[11];
+    const T B1 = K.n1 * bound - (y[8] + y[10] + y[12] + y[13]);
+    const T B2 = K.n2 * bound - (y[9] + y[11] + y[12] + y[13]);
+    const T c1 = K.kC1p * y[9] * y[10];
+    const T c2 = K.kC2p * y[8] * y[11];
+    const T bS1 = K.kS1p * B1 * y[4] - K.kS1m * y[8];
+    const T bS2 = K.kS2p * B2 * y[5] - K.kS2m * y[9];
+    const T bE1 = K.kE1p * B1 * y[6] - K.kE1m * y[10];
+    const T bE2 = K.kE2p * B2 * y[7] - K.kE2m * y[11];
     f[0] = -(adh + act) * y[0];
     f[1] = -adh * y[1] + act * y[0] - coh * y[1];
     f[2] = -adh * y[2] + coh * y[1];
@@ -571,47 +615,27 @@ __device__ inline void rxn_rhs(const T (&y)[NRX], T adp, T gam, T hadh, const Mo
     f[5] = -bS2;
     f[6] = -bE1;
 #ifdef CLOT_INHIBITOR
-    const T rI = T(M.k_I) * y[14] * y[7];   // I + E2 -> E2i (section 3.4), mass action
+    const T rI = K.k_I * y[14] * y[7];   // I + E2 -> E2i (section 3.4), mass action
     f[7] = -bE2 - rI;
     f[14] = -rI;
     f[15] = rI;
 #else
     f[7] = -bE2;
 #endif
-    f[8] = bS1 - c2 + T(M.kC2m) * y[13];
-    f[9] = bS2 - c1 + T(M.kC1m) * y[12];
-    f[10] = bE1 - c1 + T(M.kC1m + M.kC1cat) * y[12] + T(M.kC2cat) * y[13];
-    f[11] = bE2 - c2 + T(M.kC2m + M.kC2cat) * y[13] + T(M.kC1cat) * y[12];
-    f[12] = c1 - T(M.kC1m + M.kC1cat) * y[12];
-    f[13] = c2 - T(M.kC2m + M.kC2cat) * y[13];
+    f[8] = bS1 - c2 + K.kC2m * y[13];
+    f[9] = bS2 - c1 + K.kC1m * y[12];
+    f[10] = bE1 - c1 + K.kC1mc * y[12] + K.kC2cat * y[13];
+    f[11] = bE2 - c2 + K.kC2mc * y[13] + K.kC1cat * y[12];
+    f[12] = c1 - K.kC1mc * y[12];
+    f[13] = c2 - K.kC2mc * y[13];
 }
 
 template <class T>
-__device__ inline T binding_g(T eta, const ModelDev& M) {
-    const T e = eta - T(M.eta_t);
+__device__ inline T binding_g(T eta, const RxnK<T>& K) {
+    const T e = eta - K.eta_t;
     if (!(e > T(0))) return T(0);
-    const T e3 = e * e * e, s3 = T(M.eta_star * M.eta_star * M.eta_star);
-    return T(M.g0) * e3 / (s3 + e3);
-}
-
-// M_rxn classical RK4 sub-steps of size h on one cell's 14 reacting species.
-template <class T>
-__device__ inline void rk4_cell(T (&y)[NRX], T adp, T gam, T hadh, T h, const ModelDev& M) {
-    for (int m = 0; m < M.M_rxn; ++m) {
-        T k1[NRX], k2[NRX], k3[NRX], k4[NRX], w[NRX];
-        rxn_rhs(y, adp, gam, hadh, M, k1);
-#pragma unroll
-        for (int q = 0; q < NRX; ++q) w[q] = y[q] + T(0.5) * h * k1[q];
-        rxn_rhs(w, adp, gam, hadh, M, k2);
-#pragma unroll
-        for (int q = 0; q < NRX; ++q) w[q] = y[q] + T(0.5) * h * k2[q];
-        rxn_rhs(w, adp, gam, hadh, M, k3);
-#pragma unroll
-        for (int q = 0; q < NRX; ++q) w[q] = y[q] + h * k3[q];
-        rxn_rhs(w, adp, gam, hadh, M, k4);
-#pragma unroll
-        for (int q = 0; q < NRX; ++q) y[q] += h / T(6) * (k1[q] + T(2) * k2[q] + T(2) * k3[q] + k4[q]);
-    }
+    const T e3 = e * e * e;
+    return K.g0 * e3 / (K.eta_star3 + e3);
 }
 
 // Reactive wall: S1 wall value from the Robin balance with the transported S1,
@@ -653,44 +677,79 @@ __host__ __device__ constexpr int rxn_species(int q) {
     return q < 4 ? q : q < 8 ? q + 1 : q < 14 ? q + 1 : q == 14 ? INH : E2I;
 }
 
-// Reaction state of a cell in FP64, each species as stored value + low part.
+// M_rxn classical RK4 sub-steps (section 3.2) in increment form: the stages are
+// evaluated in T at (state + increment so far), and the increment d is accumulated
+// apart from the state, so it keeps its own relative precision however small it is
+// next to the state.
+// The four stage slopes are summed as they come (k1 + 2 k2 + 2 k3 + k4), so a cell
+// holds the state, the increment, one slope, the sum and the stage point.
 template <class T>
-__device__ inline void load_rxn_state64(const Fields<T>& F, int64_t g, double (&y)[NRX]) {
+__device__ inline void rk4_increment(const T (&y)[NRX], T (&d)[NRX], T adp, T gam, T hadh, T h, int nsub,
+                                     const RxnK<T>& K) {
 #pragma unroll
-    for (int q = 0; q < NRX; ++q) y[q] = (double)F.spc[rxn_species(q)][g] + (double)F.lo[rxn_species(q)][g];
-}
-
-// Stores a cell's reaction state: each species as its rounded value and the rounding remainder.
-template <class T>
-__device__ inline void store_rxn_state64(const Fields<T>& F, int64_t g, const double (&y)[NRX]) {
+    for (int q = 0; q < NRX; ++q) d[q] = T(0);
+    for (int m = 0; m < nsub; ++m) {
+        T k[NRX], acc[NRX], w[NRX];
 #pragma unroll
-    for (int q = 0; q < NRX; ++q) {
-        const T hi = T(y[q]);
-        F.spc[rxn_species(q)][g] = hi;
-        F.lo[rxn_species(q)][g] = T(y[q] - (double)hi);
+        for (int q = 0; q < NRX; ++q) w[q] = y[q] + d[q];
+        rxn_rhs(w, adp, gam, hadh, K, k);
+#pragma unroll
+        for (int q = 0; q < NRX; ++q) {
+            acc[q] = k[q];
+            w[q] = (y[q] + d[q]) + T(0.5) * h * k[q];
+        }
+        rxn_rhs(w, adp, gam, hadh, K, k);
+#pragma unroll
+        for (int q = 0; q < NRX; ++q) {
+            acc[q] += T(2) * k[q];
+            w[q] = (y[q] + d[q]) + T(0.5) * h * k[q];
+        }
+        rxn_rhs(w, adp, gam, hadh, K, k);
+#pragma unroll
+        for (int q = 0; q < NRX; ++q) {
+            acc[q] += T(2) * k[q];
+            w[q] = (y[q] + d[q]) + h * k[q];
+        }
+        rxn_rhs(w, adp, gam, hadh, K, k);
+#pragma unroll
+        for (int q = 0; q < NRX; ++q) d[q] += h / T(6) * (acc[q] + k[q]);
     }
 }
 
-// Cell reactions: M_rxn classical RK4 sub-steps (section 3.2) with ADP (post
-// transport), g(eta) and H_adh frozen, on the species after transport, in place.
-// The sub-steps run in FP64 in either precision and the state keeps its low parts: a
-// species near the injury grows by nearly the same increment step after step, and an
-// FP32 state would round each of them the same way (a bias of up to half an ulp per
-// step, 1e-5 of the value after a thousand steps).
+// One cell's reaction step in the field precision: the stages see the stored value plus
+// its low part (rounded to T); the new state is (value + low part) + increment, formed
+// in FP64 and stored again as value and low part.  A species near the injury grows by
+// nearly the same increment step after step, and a state stored in T alone would round
+// each of them the same way (a bias of up to half an ulp per step, 1e-5 of the value
+// after a thousand FP32 steps); the low part carries that remainder instead.
 template <class T>
-__global__ __launch_bounds__(NT) void k_rxn(Grid G, Fields<T> F, ModelDev M) {
+__device__ inline void rxn_cell(const Fields<T>& F, const ChanDev& C, const Cell& P, int nsub, const RxnK<T>& K) {
+    const int64_t g = P.g;
+    T y[NRX], d[NRX];
+#pragma unroll
+    for (int q = 0; q < NRX; ++q) y[q] = T((double)F.spc[rxn_species(q)][g] + (double)F.lo[rxn_species(q)][g]);
+    const T adp = F.spc[ADP][g];
+    const T gam = binding_g<T>(F.eta[g], K);
+    const bool hin = P.j < C.jadh && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
+                     P.k < C.inj_k0 + C.inj_nk;
+    rk4_increment<T>(y, d, adp, gam, hin ? T(1) : T(0), T(C.dt / nsub), nsub, K);
+#pragma unroll
+    for (int q = 0; q < NRX; ++q) {
+        const int sp = rxn_species(q);
+        const double v = (double)F.spc[sp][g] + (double)F.lo[sp][g] + (double)d[q];
+        const T hi = T(v);
+        F.spc[sp][g] = hi;
+        F.lo[sp][g] = T(v - (double)hi);
+    }
+}
+
+// Cell reactions: M_rxn RK4 sub-steps with ADP (post transport), g(eta) and H_adh
+// frozen, on the species after transport, in place.
+template <class T>
+__global__ __launch_bounds__(NT) void k_rxn(Grid G, Fields<T> F, int nsub, RxnK<T> K) {
     CLOT_TILE_PROLOGUE(G)
     CLOT_FOR_CELLS(local)
-        const Cell P = cell_at(C, local);
-        const int64_t g = P.g;
-        double y[NRX];
-        load_rxn_state64(F, g, y);
-        const double adp = F.spc[ADP][g];
-        const double gam = binding_g<double>((double)F.eta[g], M);
-        const bool hin = P.j < C.jadh && P.i >= C.inj_i0 && P.i < C.inj_i0 + C.inj_ni && P.k >= C.inj_k0 &&
-                         P.k < C.inj_k0 + C.inj_nk;
-        rk4_cell<double>(y, adp, gam, hin ? 1.0 : 0.0, C.dt / M.M_rxn, M);
-        store_rxn_state64(F, g, y);
+        rxn_cell<T>(F, C, cell_at(C, local), nsub, K);
     CLOT_END_CELLS
 }
 

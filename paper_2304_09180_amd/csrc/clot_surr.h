@@ -55,20 +55,20 @@ __device__ inline float slog(float v) {
 }
 
 template <class T>
-__device__ inline void surr_features(const T (&y)[NRX], T adp, T gam, T hadh, T dt, const ModelDev& M,
+__device__ inline void surr_features(const T (&y)[NRX], T adp, T gam, T hadh, T dt, const RxnK<T>& K,
                                      const SurrTables& tb, float (&x)[MLP_IN], T (&f)[NRX]) {
     T k1[NRX], ym[NRX];
-    rxn_rhs(y, adp, gam, hadh, M, k1);
+    rxn_rhs(y, adp, gam, hadh, K, k1);
 #pragma unroll
     for (int i = 0; i < NRX; ++i) ym[i] = y[i] + T(0.5) * dt * k1[i];
-    rxn_rhs(ym, adp, gam, hadh, M, f);
+    rxn_rhs(ym, adp, gam, hadh, K, f);
 #pragma unroll
     for (int i = 0; i < NRX; ++i) {
         f[i] *= dt;
         x[i] = slog((float)y[i] * tb.inv_s[i]);
         x[NRX + i] = slog((float)f[i] * tb.inv_f[i]);
     }
-    x[28] = (float)(adp / T(M.adp_crit));
+    x[28] = (float)(adp / K.adp_crit);
     x[29] = (float)gam;
     x[30] = (float)hadh;
     x[31] = fmaf(__log2f((float)dt), 0.30102999566f, 5.f);   // log10(Dt) + 5
@@ -77,11 +77,11 @@ __device__ inline void surr_features(const T (&y)[NRX], T adp, T gam, T hadh, T 
 // Midpoint defect of an increment in species scales (one right-hand-side evaluation).
 template <class T>
 __device__ inline float surr_defect(const T (&y)[NRX], const T (&inc)[NRX], T adp, T gam, T hadh, T dt,
-                                    const ModelDev& M, const SurrTables& tb) {
+                                    const RxnK<T>& K, const SurrTables& tb) {
     T ym[NRX], fm[NRX];
 #pragma unroll
     for (int i = 0; i < NRX; ++i) ym[i] = y[i] + T(0.5) * inc[i];
-    rxn_rhs(ym, adp, gam, hadh, M, fm);
+    rxn_rhs(ym, adp, gam, hadh, K, fm);
     float worst = 0.f;
 #pragma unroll
     for (int i = 0; i < NRX; ++i) {
@@ -122,7 +122,7 @@ constexpr int SURR_WAVE_BYTES = 64 * SURR_XLD * 2;
 static_assert(64 * SURR_OLD * 4 <= SURR_WAVE_BYTES, "output tile fits the input tile");
 
 template <class T>
-__global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev M, MLPWeights w, SurrTables tb,
+__global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, RxnK<T> K, MLPWeights w, SurrTables tb,
                                                   float tol, int32_t* fb_list, int32_t* fb_count, int32_t* fb_chan) {
     CLOT_TILE_PROLOGUE(G)
     __shared__ __align__(16) unsigned char tileb[4][SURR_WAVE_BYTES];
@@ -146,9 +146,9 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
                 g = P.g;
                 load_rxn_state(F, g, y);
                 adp = F.spc[ADP][g];
-                gam = binding_g<T>(F.eta[g], M);
+                gam = binding_g<T>(F.eta[g], K);
                 hadh = adhesion_cell<T>(C, P) ? T(1) : T(0);
-                surr_features(y, adp, gam, hadh, dt, M, tb, x, f);
+                surr_features(y, adp, gam, hadh, dt, K, tb, x, f);
             } else {
 #pragma unroll
                 for (int i = 0; i < MLP_IN; ++i) x[i] = 0.f;
@@ -157,13 +157,13 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
             for (int i = 0; i < MLP_IN; i += 4)
                 *reinterpret_cast<bf16x4*>(sX + l * SURR_XLD + i) = pack4_bf16(x[i], x[i + 1], x[i + 2], x[i + 3]);
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();   // the tile is the wave's own: its lanes' LDS ops stay in order
         bf16x4 xb[4][2];
 #pragma unroll
         for (int grp = 0; grp < 4; ++grp)
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb) xb[grp][kb] = load_b_cm(sX, SURR_XLD, 16 * kb, 16 * grp);
-        __syncthreads();   // the output tile overwrites the input tile
+        __builtin_amdgcn_wave_barrier();   // the output tile overwrites the input tile
 #pragma unroll
         for (int grp = 0; grp < 4; ++grp) {
             bf16x4 h1[4], h2[4];
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
             q[2] = o[2];
             q[3] = o[3];
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         if (own) {
             T inc[NRX];
 #pragma unroll
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
                 r = r > 0.5f ? 0.5f : (r < -0.5f ? -0.5f : r);
                 inc[i] = f[i] * (T(1) + T(r));
             }
-            const float d = surr_defect(y, inc, adp, gam, hadh, dt, M, tb);
+            const float d = surr_defect(y, inc, adp, gam, hadh, dt, K, tb);
             if (d < tol) {
 #pragma unroll
                 for (int i = 0; i < NRX; ++i) y[i] += inc[i];
@@ -194,13 +194,13 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, ModelDev 
                 atomicAdd(&fb_chan[chid], 1);
             }
         }
-        __syncthreads();   // the next pass rewrites the tile
+        __builtin_amdgcn_wave_barrier();   // the next pass rewrites the tile
     }
 }
 
 // Plain RK4 reaction step (as k_rxn) for the listed cells.
 template <class T>
-__global__ __launch_bounds__(NT) void k_rxn_list(const ChanDev* chans, int nch, Fields<T> F, ModelDev M,
+__global__ __launch_bounds__(NT) void k_rxn_list(const ChanDev* chans, int nch, Fields<T> F, int nsub, RxnK<T> K,
                                                  const int32_t* fb_list, const int32_t* fb_count) {
     const int32_t nfb = *fb_count;
     for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < nfb; q += (int64_t)gridDim.x * NT) {
@@ -213,13 +213,7 @@ __global__ __launch_bounds__(NT) void k_rxn_list(const ChanDev* chans, int nch, 
         else hi = mid - 1;
     }
     const ChanDev C = chans[lo];
-    const Cell P = cell_at(C, g - C.c0);
-    double y[NRX];
-    load_rxn_state64(F, g, y);     // as the plain step: FP64 sub-steps, low parts kept
-    const double adp = F.spc[ADP][g];
-    const double gam = binding_g<double>((double)F.eta[g], M);
-    rk4_cell<double>(y, adp, gam, adhesion_cell<T>(C, P) ? 1.0 : 0.0, C.dt / M.M_rxn, M);
-    store_rxn_state64(F, g, y);
+    rxn_cell<T>(F, C, cell_at(C, g - C.c0), nsub, K);   // exactly the plain step's cell update
     }
 }
 
@@ -229,35 +223,35 @@ __global__ __launch_bounds__(NT) void k_rxn_list(const ChanDev* chans, int nch, 
 // ---------------------------------------------------------------------------------
 constexpr int SURR_ROW = 18;
 
-__device__ inline void unpack_row(const double* r, const ModelDev& M, double (&y)[NRX], double& adp, double& gam,
+__device__ inline void unpack_row(const double* r, const RxnK<double>& K, double (&y)[NRX], double& adp, double& gam,
                                   double& hadh, double& dt) {
 #pragma unroll
     for (int i = 0; i < NRX; ++i) y[i] = r[i];
     adp = r[14];
-    gam = binding_g<double>(r[15], M);
+    gam = binding_g<double>(r[15], K);
     hadh = r[16];
     dt = r[17];
 }
 
 // Plain RK4 increments (M_rxn sub-steps, FP64) of each state.
-__global__ __launch_bounds__(NT) void k_rxn_batch(const double* rows, int64_t n, ModelDev M, double* inc) {
+__global__ __launch_bounds__(NT) void k_rxn_batch(const double* rows, int64_t n, int nsub, RxnK<double> K, double* inc) {
     const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (q >= n) return;
     double y[NRX], adp, gam, hadh, dt;
-    unpack_row(rows + q * SURR_ROW, M, y, adp, gam, hadh, dt);
+    unpack_row(rows + q * SURR_ROW, K, y, adp, gam, hadh, dt);
     double y0[NRX];
 #pragma unroll
     for (int i = 0; i < NRX; ++i) y0[i] = y[i];
-    const double h = dt / M.M_rxn;
-    for (int m = 0; m < M.M_rxn; ++m) {
+    const double h = dt / nsub;
+    for (int m = 0; m < nsub; ++m) {
         double k1[NRX], k2[NRX], k3[NRX], k4[NRX], w[NRX];
-        rxn_rhs(y, adp, gam, hadh, M, k1);
+        rxn_rhs(y, adp, gam, hadh, K, k1);
         for (int i = 0; i < NRX; ++i) w[i] = y[i] + 0.5 * h * k1[i];
-        rxn_rhs(w, adp, gam, hadh, M, k2);
+        rxn_rhs(w, adp, gam, hadh, K, k2);
         for (int i = 0; i < NRX; ++i) w[i] = y[i] + 0.5 * h * k2[i];
-        rxn_rhs(w, adp, gam, hadh, M, k3);
+        rxn_rhs(w, adp, gam, hadh, K, k3);
         for (int i = 0; i < NRX; ++i) w[i] = y[i] + h * k3[i];
-        rxn_rhs(w, adp, gam, hadh, M, k4);
+        rxn_rhs(w, adp, gam, hadh, K, k4);
         for (int i = 0; i < NRX; ++i) y[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
     }
     for (int i = 0; i < NRX; ++i) inc[q * NRX + i] = y[i] - y0[i];
@@ -269,7 +263,7 @@ __global__ __launch_bounds__(NT) void k_rxn_batch(const double* rows, int64_t n,
 // correction is noise); outputs 14..15 zero.  With stats != NULL it instead
 // accumulates per-block sums (42 per block): the squares of f/s, the squares of the
 // clamped relative corrections, and the count of rows with non-negligible f.
-__global__ __launch_bounds__(NT) void k_surr_dataset(const double* rows, const double* inc, int64_t n, ModelDev M,
+__global__ __launch_bounds__(NT) void k_surr_dataset(const double* rows, const double* inc, int64_t n, RxnK<double> K,
                                                      SurrTables tb, uint16_t* x, float* t, double* stats) {
     const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
     __shared__ double lds[42 * (NT / 64 + 1)];
@@ -278,9 +272,9 @@ __global__ __launch_bounds__(NT) void k_surr_dataset(const double* rows, const d
     for (int i = 0; i < 42; ++i) acc[i] = 0.0;
     if (q < n) {
         double y[NRX], adp, gam, hadh, dt, f[NRX];
-        unpack_row(rows + q * SURR_ROW, M, y, adp, gam, hadh, dt);
+        unpack_row(rows + q * SURR_ROW, K, y, adp, gam, hadh, dt);
         float xf[MLP_IN];
-        surr_features<double>(y, adp, gam, hadh, dt, M, tb, xf, f);
+        surr_features<double>(y, adp, gam, hadh, dt, K, tb, xf, f);
         for (int i = 0; i < NRX; ++i) {
             const bool live = fabs(f[i]) > 1e-12 * tb.s[i];
             double rel = live ? (inc[q * NRX + i] - f[i]) / fabs(f[i]) : 0.0;
