@@ -106,6 +106,8 @@ def parse():
                     help="kernel phase timed for the roofline (default: the transport BiCGStab's first phase, "
                          "the mesh-streaming kernel with the largest share of the step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-brick-tune", action="store_true",
+                    help="keep the default brick shape of the LDS-staged momentum kernels")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
     ap.add_argument("--train-samples", type=int, default=400_000)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
@@ -219,6 +221,15 @@ def pick_tile(descs, prec, args):
     return e["tile"], e
 
 
+def pick_bricks(descs, prec, tile, args):
+    """Brick shape of each LDS-staged momentum kernel: tuned (per-kernel launch times in
+    each shape) unless --no-brick-tune."""
+    if args.no_brick_tune:
+        return None
+    from paper_2304_09180_amd import autotune
+    return autotune.tune_bricks(descs, prec, tile=tile, log=lambda m: print(m, file=sys.stderr, flush=True))
+
+
 def surrogate_leg(desc, prec, args, xc, xf, tile):
     """Trains the reaction surrogate on the GPU (2-D channel states), then times the
     same workload with the learned reaction step."""
@@ -307,17 +318,22 @@ def ensemble_leg(args):
     """The 64-member uneven ensemble of 2-D channels in one context, FP32: eager steps,
     then the same steps replayed as HIP graphs."""
     import clot_inputs as ci
-    from paper_2304_09180_amd import clot
+    from paper_2304_09180_amd import autotune, clot
     descs = ci.ensemble(64)
     ncell = sum(ci.ncell(d) for d in descs)
     tile, tuned = pick_tile(descs, clot.FP32_MIXED, args)
+    bricks = pick_bricks(descs, clot.FP32_MIXED, tile, args)
     out = {"members": len(descs), "cells": ncell,
            "sizes": sorted({f"{d['nx']}x{d['ny']}" for d in descs}),
            "dt_range": [min(d["dt"] for d in descs), max(d["dt"] for d in descs)], "tile": tile}
     if tuned:
         out["autotune"] = {"ms_per_step": tuned["ms_per_step"], "kernel_us": tuned["kernel_us"]}
+    if bricks:
+        out.setdefault("autotune", {})["bricks"] = {k: bricks[k] for k in ("restrict", "prolong", "sweep", "us")}
     for mode in ("eager", "graph"):
         s = clot.Solver(descs, clot.FP32_MIXED, tile=tile)
+        if bricks:
+            autotune.apply_bricks(s, bricks)
         for c, d in enumerate(descs):
             xc, xf = ci.noise(d)
             s.init_state(c, xc, xf)
@@ -350,12 +366,15 @@ def main():
         sys.exit(2)
     import torch
     import clot_inputs as ci
-    from paper_2304_09180_amd import clot
+    from paper_2304_09180_amd import autotune, clot
 
     desc = ci.workload(args.workload)
     prec = clot.FP32_MIXED if args.precision == "fp32" else clot.FP64
     tile, tuned = pick_tile([desc], prec, args)
+    bricks = pick_bricks([desc], prec, tile, args)
     s = clot.Solver([desc], prec, tile=tile)
+    if bricks:
+        autotune.apply_bricks(s, bricks)
     xc, xf = ci.noise(desc)
     s.init_state(0, xc, xf)
     ncell = desc["nx"] * desc["ny"] * desc["nz"]
@@ -402,6 +421,8 @@ def main():
            "roofline": roof}
     if tuned:
         out["autotune"] = {"ms_per_step": tuned["ms_per_step"], "kernel_us": tuned["kernel_us"]}
+    if bricks:
+        out.setdefault("autotune", {})["bricks"] = {k: bricks[k] for k in ("restrict", "prolong", "sweep", "us")}
     s.close()
     if not args.no_time_scheme:
         out["time_scheme"] = time_scheme_leg(desc, prec, args, xc, xf, tile)

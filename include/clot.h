@@ -283,6 +283,25 @@ clot_status clot_set_graph_mode(clot_ctx* c, int32_t on, double budget_scale, in
  * of graphs of about 1500 nodes each).  info: 20 entries. */
 clot_status clot_graph_info(clot_ctx* c, int64_t* info);
 
+/* Tile shapes of the LDS-staged finest-level kernels of the momentum preconditioner
+ * (a block owns a brick of 1024 cells and stages it with a one-cell halo in LDS).  The
+ * tile autotuner times each kernel in each shape and sets its choice; shape 0 is the
+ * default of every kernel.  Shapes (BX x BY x BZ cells): 3-D 32x8x4, 16x16x4, 32x4x8,
+ * 16x8x8; 2-D 64x16, 128x8, 32x32, 256x4 (one shape index names one of each).
+ * Contexts with a channel that has fewer than three cells on an axis do not use the
+ * bricked kernels; the call still records the choice. */
+typedef enum {
+    CLOT_BRICK_RESTRICT = 0,   /* residual restriction with the formed right-hand side */
+    CLOT_BRICK_PROLONG = 1,    /* prolongation + smoothing sweep                        */
+    CLOT_BRICK_SWEEP = 2,      /* the last smoothing sweep                              */
+    CLOT_NBRICK_KERNELS = 3
+} clot_brick_kernel;
+/* kernel in [0, CLOT_NBRICK_KERNELS), shape in [0, 4), else CLOT_EINVAL.  Recorded
+ * graphs are dropped (re-recorded at the next step in graph mode). */
+clot_status clot_set_brick_shape(clot_ctx* c, int32_t kernel, int32_t shape);
+/* dims[0..2] = BX, BY, BZ of shape for channels of dimension dim (2 or 3). */
+clot_status clot_brick_dims(int32_t dim, int32_t shape, int32_t* dims);
+
 /* Kernel-phase timing probe.  While a phase is selected, every launch of it is
  * bracketed by HIP events on the context stream; clot_probe_read synchronises,
  * returns the summed event time (ms) and the launch count since the selection,

@@ -14,6 +14,14 @@ dimension, the channel shapes and the precision, so it is measured:
 
 Results are cached as JSON keyed by the GPU architecture, the precision and the
 multiset of channel shapes.
+
+The LDS-staged finest-level kernels of the momentum preconditioner (a block stages a
+brick of 1024 cells and a one-cell halo) take their brick shape per kernel:
+`tune_bricks` times each of the three kernels (restriction, prolongation sweep,
+sweep) in each of the four shapes on one context (probe average over a few steps),
+keeps the fastest per kernel (shape 0 unless another beats it by more than 1%) and
+caches the choice under the same key with a "bricks" suffix; `apply_bricks` sets it on
+a solver.
 """
 from __future__ import annotations
 
@@ -131,3 +139,51 @@ def tune(descs, precision, candidates=clot.TILES, steps=5, warmup=3, repeats=3, 
              "kernel_us": {str(t): v for t, v in kernels.items()}, "steps": steps, "repeats": repeats}
     store_cache(path, key, entry)
     return entry
+
+
+BRICK_PROBES = {"restrict": "mom_mg_r", "prolong": "mom_mg_p1", "sweep": "mom_mg_p2"}
+
+
+def tune_bricks(descs, precision, tile=clot.TILES[0], steps=4, warmup=3, cache=None, force=False, log=None):
+    """Brick shape of each LDS-staged momentum kernel for this workload: from the cache,
+    or measured (average launch time of the kernel in each shape) and stored."""
+    path = cache or default_cache_path()
+    key = cache_key(descs, precision, arch_name()) + f"|tile{tile}|bricks"
+    if not force:
+        hit = load_cache(path).get(key)
+        if hit and all(hit.get(k) in range(clot.N_BRICK_SHAPES) for k in BRICK_PROBES):
+            return hit
+    s = clot.Solver(descs, precision, tile=tile)
+    us = {k: {} for k in BRICK_PROBES}
+    try:
+        for c, d in enumerate(descs):
+            n = d["nx"] * d["ny"] * d["nz"]
+            s.init_state(c, np.zeros((15, n)), np.zeros((2, s.count(c, "E0"))))
+        for _ in range(warmup):
+            s.step(1)
+        for kernel, probe in BRICK_PROBES.items():
+            for shape in range(clot.N_BRICK_SHAPES):
+                s.set_brick_shape(kernel, shape)
+                s.step(1)
+                s.probe(probe)
+                s.step(steps)
+                ms, nl = s.probe_read()
+                s.probe(None)
+                us[kernel][shape] = 1e3 * ms / nl if nl else float("inf")
+                if log:
+                    log(f"# autotune {key} {kernel} shape {shape} {clot.brick_dims(descs[0]['dim'], shape)}: "
+                        f"{us[kernel][shape]:.2f} us over {nl} launches")
+            s.set_brick_shape(kernel, 0)
+    finally:
+        s.close()
+    entry = {k: choose(us[k]) for k in BRICK_PROBES}
+    entry["us"] = {k: {str(q): round(v, 3) for q, v in us[k].items()} for k in BRICK_PROBES}
+    entry["steps"] = steps
+    store_cache(path, key, entry)
+    return entry
+
+
+def apply_bricks(solver, entry) -> None:
+    """Sets the tuned brick shape of every LDS-staged kernel on a solver."""
+    for kernel in BRICK_PROBES:
+        solver.set_brick_shape(kernel, int(entry[kernel]))

@@ -119,6 +119,8 @@ def load(tile: int = 256, inhibitor: bool = False):
         "clot_probe_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
         "clot_set_graph_mode": ([P, C.c_int32, C.c_double, C.c_int32], C.c_int),
         "clot_graph_info": ([P, C.POINTER(C.c_int64)], C.c_int),
+        "clot_set_brick_shape": ([P, C.c_int32, C.c_int32], C.c_int),
+        "clot_brick_dims": ([C.c_int32, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "clot_mlp_nparam": ([], C.c_int64),
         "clot_mlp_backward_workspace": ([C.c_int64], C.c_size_t),
         "clot_mlp_forward": ([P, P, P, C.c_int64, P, P, P], C.c_int),
@@ -154,7 +156,21 @@ def exported_symbols():
             "clot_mlp_nparam", "clot_mlp_backward_workspace", "clot_mlp_forward", "clot_mlp_backward",
             "clot_mlp_adam", "clot_mlp_mse", "clot_rxn_rk4_batch", "clot_surr_dataset", "clot_mfma_selftest",
             "clot_cell_species", "clot_tile_cells", "clot_set_graph_mode", "clot_graph_info", "clot_state_size",
-            "clot_save_state", "clot_load_state", "clot_mlp_backward_noalloc"]
+            "clot_save_state", "clot_load_state", "clot_mlp_backward_noalloc", "clot_set_brick_shape",
+            "clot_brick_dims"]
+
+
+BRICK_KERNELS = {"restrict": 0, "prolong": 1, "sweep": 2}
+N_BRICK_SHAPES = 4
+
+
+def brick_dims(dim, shape):
+    """(BX, BY, BZ) of a brick shape for channels of dimension dim."""
+    v = (C.c_int32 * 3)()
+    st = load().clot_brick_dims(int(dim), int(shape), v)
+    if st != 0:
+        raise ClotError(f"brick_dims({dim}, {shape}): status {st}")
+    return tuple(v)
 
 
 PROBES = {"p_cg_a": 1, "p_cg_b": 2, "tr_b1": 3, "tr_b2": 4, "tr_b3": 5, "mom_b1": 6, "mom_b2": 7, "mom_b3": 8,
@@ -318,6 +334,11 @@ class Solver:
         Krylov solve then runs a fixed iteration budget; see clot_set_graph_mode)."""
         return _check(self.lib, self.ctx, self.lib.clot_set_graph_mode(self.ctx, 1 if on else 0, float(budget_scale),
                                                                       int(budget_pad)), "graph mode")
+
+    def set_brick_shape(self, kernel, shape):
+        """Tile shape (0..3) of one LDS-staged momentum kernel: 'restrict', 'prolong' or 'sweep'."""
+        k = BRICK_KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        return _check(self.lib, self.ctx, self.lib.clot_set_brick_shape(self.ctx, k, int(shape)), "brick shape")
 
     def graph_info(self):
         v = (C.c_int64 * 20)()

@@ -90,6 +90,7 @@ struct clot_ctx {
     virtual clot_status set_rxn(clot_rxn_mode mode, const void* blob, size_t nb, double tol) = 0;
     virtual clot_status probe_read(double* ms, int64_t* n) = 0;
     virtual clot_status set_graph(int on, double scale, int pad) = 0;
+    virtual clot_status set_brick(int kernel, int shape) = 0;
     virtual clot_status graph_info(int64_t* info) = 0;
     virtual clot_status state_size(size_t* bytes) const = 0;
     virtual clot_status save_state(void* host, size_t bytes) = 0;
@@ -214,11 +215,15 @@ struct Ctx : clot_ctx {
     int32_t* d_mgm_last = nullptr;
     // LDS-staged finest-level momentum kernels: bricks of every channel (when every
     // channel is coarsened along every axis)
-    std::vector<BrickChan> h_brick;
-    std::vector<int32_t> h_b2c;
-    BrickChan* d_brick = nullptr;
-    int32_t* d_b2c = nullptr;
-    BrickGrid bricks() const { return BrickGrid{d_brick, d_b2c, (int32_t)h_b2c.size()}; }
+    // channel), one table per brick shape; each bricked kernel has its own shape (the
+    // tile autotuner's choice, clot_set_brick_shape)
+    std::vector<BrickChan> h_brick[MGM_NSHAPE];
+    std::vector<int32_t> h_b2c[MGM_NSHAPE];
+    BrickChan* d_brick[MGM_NSHAPE] = {};
+    int32_t* d_b2c[MGM_NSHAPE] = {};
+    int brick_shape[CLOT_NBRICK_KERNELS] = {};   // per bricked kernel: restriction, prolongation sweep, sweep
+    BrickGrid bricks(int s) const { return BrickGrid{d_brick[s], d_b2c[s], (int32_t)h_b2c[s].size()}; }
+    bool bricked() const { return !h_b2c[0].empty(); }
     // reaction surrogate
     clot_rxn_mode rxn_mode = CLOT_RXN_PLAIN;
     float surr_tol = 1e-3f;
@@ -433,8 +438,10 @@ struct Ctx : clot_ctx {
             L.cz = cv.take<T>(L.NFZ);
         }
         d_mgm_last = cv.take<int32_t>(nch);
-        d_brick = cv.take<BrickChan>(std::max<size_t>(h_brick.size(), 1));
-        d_b2c = cv.take<int32_t>(std::max<size_t>(h_b2c.size(), 1));
+        for (int q = 0; q < MGM_NSHAPE; ++q) {
+            d_brick[q] = cv.take<BrickChan>(std::max<size_t>(h_brick[q].size(), 1));
+            d_b2c[q] = cv.take<int32_t>(std::max<size_t>(h_b2c[q].size(), 1));
+        }
         for (int l = 0; l < mgm_nc; ++l) {
             Level& L = lev[l];
             L.mmass = cv.take<T>(L.N);
@@ -589,24 +596,23 @@ struct Ctx : clot_ctx {
                 mgm_nc = std::max(mgm_nc, l + 1);
             }
         }
-        h_brick.clear();
-        h_b2c.clear();
+        for (int q = 0; q < MGM_NSHAPE; ++q) {
+            h_brick[q].clear();
+            h_b2c[q].clear();
+        }
         if (mgm_nc > 0) {
             bool ok = true;
             for (const ChanHost& h : ch) ok = ok && h.d.nx >= 3 && h.d.ny >= 3 && (h.d.dim == 2 || h.d.nz >= 3);
-            for (int i = 0; ok && i < nch; ++i) {
-                const clot_channel& d = ch[i].d;
-                const int bx = d.dim == 3 ? BrickDims<3>::BX : BrickDims<2>::BX;
-                const int by = d.dim == 3 ? BrickDims<3>::BY : BrickDims<2>::BY;
-                const int bz = d.dim == 3 ? BrickDims<3>::BZ : 1;
-                BrickChan b{(int32_t)h_b2c.size(), (d.nx + bx - 1) / bx, (d.ny + by - 1) / by, (d.nz + bz - 1) / bz};
-                for (int q = 0; q < b.nbx * b.nby * b.nbz; ++q) h_b2c.push_back(i);
-                h_brick.push_back(b);
-            }
-            if (!ok) {
-                h_brick.clear();
-                h_b2c.clear();
-            }
+            for (int q = 0; ok && q < MGM_NSHAPE; ++q)
+                for (int i = 0; i < nch; ++i) {
+                    const clot_channel& d = ch[i].d;
+                    int bx, by, bz;
+                    brick_dims(d.dim, q, bx, by, bz);
+                    BrickChan b{(int32_t)h_b2c[q].size(), (d.nx + bx - 1) / bx, (d.ny + by - 1) / by,
+                                (d.nz + bz - 1) / bz};
+                    for (int t = 0; t < b.nbx * b.nby * b.nbz; ++t) h_b2c[q].push_back(i);
+                    h_brick[q].push_back(b);
+                }
         }
         // sweeps each way, automatic: a third sweep saves a third of the CG iterations on
         // 3-D channels (13 -> 9 per corrector on the 1M-cell duct, 7% of the step), while on
@@ -775,11 +781,12 @@ struct Ctx : clot_ctx {
         }
         HIPCHK(hipMemcpyAsync(d_t2c, t2c.data(), t2c.size() * 4, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(d_mgm_last, h_mgm_last.data(), nch * 4, hipMemcpyHostToDevice, st));
-        if (!h_b2c.empty()) {
-            HIPCHK(hipMemcpyAsync(d_brick, h_brick.data(), h_brick.size() * sizeof(BrickChan), hipMemcpyHostToDevice,
-                                  st));
-            HIPCHK(hipMemcpyAsync(d_b2c, h_b2c.data(), h_b2c.size() * 4, hipMemcpyHostToDevice, st));
-        }
+        for (int q = 0; q < MGM_NSHAPE; ++q)
+            if (!h_b2c[q].empty()) {
+                HIPCHK(hipMemcpyAsync(d_brick[q], h_brick[q].data(), h_brick[q].size() * sizeof(BrickChan),
+                                      hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(d_b2c[q], h_b2c[q].data(), h_b2c[q].size() * 4, hipMemcpyHostToDevice, st));
+            }
         HIPCHK(hipMemcpyAsync(d_f2c, f2c.data(), f2c.size() * 4, hipMemcpyHostToDevice, st));
         std::vector<int32_t> ones(nch, 1), cm((size_t)MAXCORR * nch, 0);
         for (int k = 0; k < MAXCORR; ++k)
@@ -1456,6 +1463,34 @@ struct Ctx : clot_ctx {
     // 0..2 y = M^-1 p, 3..5 z = M^-1 s, 6..8 s, 9..11 and 12..14 finest-level sweeps
     T* const (&mgm_vec(int q) const)[MGM_K] { return *reinterpret_cast<T* const(*)[MGM_K]>(pool + 7 + 7 * 3 + 3 * q); }
 
+    // A bricked finest-level momentum kernel in the shape chosen for it.
+    template <int MODE, int FORM>
+    void brick_launch(int probe, const MomOp<T>& mop, const MGSrc<T>& src, const MGVec<T>& bout, const MGCVec<T>& xc,
+                      const MGVec<T>& out) {
+        const int kid = MODE == MGM_MODE_R ? 0 : MODE == MGM_MODE_P ? 1 : 2;
+        const int q = brick_shape[kid];
+        const MGPair pr{grid(), lev[0].grid()};
+        const dim3 gd((unsigned)h_b2c[q].size());
+        switch (q) {
+            case 0:
+                CLOT_LAUNCH(probe, (k_mgm_brick<T, MODE, FORM, 0>), gd, dim3(NT), 0, st, bricks(0), pr, mop, src, bout,
+                            xc, out, S, mg_w);
+                break;
+            case 1:
+                CLOT_LAUNCH(probe, (k_mgm_brick<T, MODE, FORM, 1>), gd, dim3(NT), 0, st, bricks(1), pr, mop, src, bout,
+                            xc, out, S, mg_w);
+                break;
+            case 2:
+                CLOT_LAUNCH(probe, (k_mgm_brick<T, MODE, FORM, 2>), gd, dim3(NT), 0, st, bricks(2), pr, mop, src, bout,
+                            xc, out, S, mg_w);
+                break;
+            default:
+                CLOT_LAUNCH(probe, (k_mgm_brick<T, MODE, FORM, 3>), gd, dim3(NT), 0, st, bricks(3), pr, mop, src, bout,
+                            xc, out, S, mg_w);
+                break;
+        }
+    }
+
     // out = M^-1 b (one V(1,2) cycle) for the active components; FORM (clot_mgm.h) says
     // how the finest right-hand side is formed; a formed one is written to bout.
     template <int FORM>
@@ -1463,11 +1498,9 @@ struct Ctx : clot_ctx {
         const int nc = mgm_nc;
         const unsigned rb = TILE / (NT / 8);   // restriction blocks per coarse tile
         const MGCVec<T> none{};
-        const bool brick = !h_b2c.empty();
+        const bool brick = bricked();
         if (brick)
-            CLOT_LAUNCH(CLOT_PROBE_MOM_MG_R, (k_mgm_brick<T, MGM_MODE_R, FORM>), dim3((unsigned)h_b2c.size()), dim3(NT),
-                        0, st, bricks(), MGPair{grid(), lev[0].grid()}, mop, src, mv3(bout), none, mv3(lev[0].mb), S,
-                        mg_w);
+            brick_launch<MGM_MODE_R, FORM>(CLOT_PROBE_MOM_MG_R, mop, src, mv3(bout), none, mv3(lev[0].mb));
         else
             CLOT_LAUNCH(CLOT_PROBE_MOM_MG_R, (k_mgm_restrict<T, MomOp<T>, FORM, true>), dim3(lev[0].ntiles * rb),
                         dim3(NT), 0, st, MGPair{grid(), lev[0].grid()}, mop, src, mv3(bout), none, mv3(lev[0].mb), S,
@@ -1504,14 +1537,14 @@ struct Ctx : clot_ctx {
         if (brick) {
             MGSrc<T> sb{};
             for (int k = 0; k < MGM_K; ++k) sb.b[k] = bf.v[k];
-            CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P1, (k_mgm_brick<T, MGM_MODE_P, 0>), dim3((unsigned)h_b2c.size()), dim3(NT),
-                        0, st, bricks(), MGPair{grid(), lev[0].grid()}, mop, sb, MGVec<T>{}, cv3(lev[0].mx),
-                        mv3(mgm_vec(3)), S, mg_w);
-        } else
+            brick_launch<MGM_MODE_P, 0>(CLOT_PROBE_MOM_MG_P1, mop, sb, MGVec<T>{}, cv3(lev[0].mx), mv3(mgm_vec(3)));
+            brick_launch<MGM_MODE_S, 0>(CLOT_PROBE_MOM_MG_P2, mop, sb, MGVec<T>{}, cv3(mgm_vec(3)), mv3(out));
+        } else {
             CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P1, (k_mgm_post1<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st,
                         MGPair{grid(), lev[0].grid()}, mop, bf, cv3(lev[0].mx), mv3(mgm_vec(3)), mg_w, S, MGGate{});
-        CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P2, (k_mgm_post2<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, bf,
-                    cv3(mgm_vec(3)), mv3(out), mg_w, S, MGGate{});
+            CLOT_LAUNCH(CLOT_PROBE_MOM_MG_P2, (k_mgm_post2<T, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop,
+                        bf, cv3(mgm_vec(3)), mv3(out), mg_w, S, MGGate{});
+        }
     }
 
     // BiCGStab on the momentum system with one V-cycle per direction (right
@@ -1942,6 +1975,16 @@ struct Ctx : clot_ctx {
         return CLOT_OK;
     }
 
+    clot_status set_brick(int kernel, int shape) override {
+        if (kernel < 0 || kernel >= CLOT_NBRICK_KERNELS || shape < 0 || shape >= MGM_NSHAPE) {
+            err = "set_brick_shape: kernel in [0, 3), shape in [0, 4)";
+            return CLOT_EINVAL;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        drop_graphs();   // recorded steps hold the old launches
+        brick_shape[kernel] = shape;
+        return CLOT_OK;
+    }
     clot_status set_graph(int on, double scale, int pad) override {
         HIPCHK(hipStreamSynchronize(st));
         drop_graphs();
@@ -2541,6 +2584,19 @@ clot_status clot_set_graph_mode(clot_ctx* c, int32_t on, double budget_scale, in
 clot_status clot_graph_info(clot_ctx* c, int64_t* info) {
     if (!c || !info) return CLOT_EINVAL;
     return c->graph_info(info);
+}
+clot_status clot_set_brick_shape(clot_ctx* c, int32_t kernel, int32_t shape) {
+    if (!c) return CLOT_EINVAL;
+    return c->set_brick(kernel, shape);
+}
+clot_status clot_brick_dims(int32_t dim, int32_t shape, int32_t* dims) {
+    if (!dims || (dim != 2 && dim != 3) || shape < 0 || shape >= MGM_NSHAPE) return CLOT_EINVAL;
+    int bx, by, bz;
+    brick_dims(dim, shape, bx, by, bz);
+    dims[0] = bx;
+    dims[1] = by;
+    dims[2] = bz;
+    return CLOT_OK;
 }
 void clot_destroy(clot_ctx* c) { delete c; }
 const char* clot_last_error(const clot_ctx* c) {

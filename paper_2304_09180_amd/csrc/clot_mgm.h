@@ -284,18 +284,26 @@ __global__ __launch_bounds__(NT) void k_mgm_pre(Grid G, Op op, MGCVec<T> b, MGVe
 }
 
 // ---- LDS-staged finest-level kernels ------------------------------------------------
-// A block owns a brick of fine cells (3-D: 32 x 8 x 4, 2-D: 64 x 16; 4 per thread).
-// It first forms the smoothed value x1 at every cell of the brick and its one-cell halo
-// exactly once, into LDS (the halo from neighbouring bricks' cells, read through L2),
-// then applies the 7-point stencil to its own cells from LDS.  A bricked launch needs
-// every channel coarsened along every axis (aggregates then never straddle bricks).
+// A block owns a brick of 1024 fine cells, four per thread.  It first forms the value
+// its stencil reads (MODE_R, MODE_P: the smoothed x1; MODE_S: the given iterate) at
+// every cell of the brick and its one-cell halo exactly once, into LDS (the halo from
+// neighbouring bricks' cells, read through L2), then applies the momentum stencil to
+// its own cells from LDS.  A bricked launch needs every channel coarsened along every
+// axis (aggregates then never straddle bricks).
 //
 // MODE_R: residual restriction.  x1 = w D^-1 b with b formed per FORM (written to bout);
 //   the residuals b - A x1 of each 2x2(x2) aggregate are added in registers and by lane
-//   shuffles (brick columns are laid out so that an aggregate's cells sit in one thread
-//   and its x- and y-neighbour lanes) and written to the coarse right-hand side.
+//   shuffles (a thread's four cells are two aggregate pairs along the slow axis, and the
+//   x and (3-D) y partners are lanes l^1 and l^BX) and written to the coarse
+//   right-hand side.
 // MODE_P: prolongation + sweep.  x1 = w D^-1 b + P xc, out = x1 + w D^-1 (b - A x1).
-enum { MGM_MODE_R = 0, MGM_MODE_P = 1 };
+// MODE_S: one sweep.  out = y + w D^-1 (b - A y).
+//
+// Brick shapes, chosen per kernel by the tile autotuner (one shape index covers a 3-D
+// and a 2-D shape): 3-D BX x BY x BZ with BX <= 32 (the y partner lane stays in the
+// wave) and BZ a multiple of 4; 2-D BX x BY.
+enum { MGM_MODE_R = 0, MGM_MODE_P = 1, MGM_MODE_S = 2 };
+constexpr int MGM_NSHAPE = 4;
 
 struct BrickChan {
     int32_t b0;              // first brick of the channel
@@ -306,27 +314,59 @@ struct BrickGrid {
     const int32_t* b2c;      // brick -> channel
     int32_t nb;              // bricks over all channels
 };
-template <int DIM>
-struct BrickDims {
-    static constexpr int BX = DIM == 3 ? 32 : 64, BY = DIM == 3 ? 8 : 16, BZ = DIM == 3 ? 4 : 1;
+template <int DIM, int SHAPE>
+struct Brick {
+    static constexpr int BX = DIM == 3 ? (SHAPE == 0 ? 32 : SHAPE == 1 ? 16 : SHAPE == 2 ? 32 : 16)
+                                       : (SHAPE == 0 ? 64 : SHAPE == 1 ? 128 : SHAPE == 2 ? 32 : 256);
+    static constexpr int BY = DIM == 3 ? (SHAPE == 0 ? 8 : SHAPE == 1 ? 16 : SHAPE == 2 ? 4 : 8) : 1024 / BX;
+    static constexpr int BZ = DIM == 3 ? 1024 / (BX * BY) : 1;
     static constexpr int EX = BX + 2, EY = BY + 2, EZ = DIM == 3 ? BZ + 2 : 1;
     static constexpr int NE = EX * EY * EZ;
-    static constexpr int NOWN = BX * BY * BZ;
+    static_assert(BX * BY * BZ == 1024, "four cells per thread");
+    static_assert(DIM == 2 || (BX <= 32 && BZ % 4 == 0), "3-D: y partner in the wave, z pairs in a thread");
+    // cell m (0..3) of thread t
+    __device__ static void cell(int t, int m, int& lx, int& ly, int& lz) {
+        lx = t % BX;
+        if (DIM == 3) {
+            ly = (t / BX) % BY;
+            lz = 4 * (t / (BX * BY)) + m;
+        } else {
+            constexpr int R = 256 / BX;   // rows a pass of the block covers
+            ly = 2 * (t / BX) + (m & 1) + 2 * R * (m >> 1);
+            lz = 0;
+        }
+    }
 };
-constexpr int MGM_BRICK_NE = BrickDims<3>::NE > BrickDims<2>::NE ? BrickDims<3>::NE : BrickDims<2>::NE;
+// The brick shape of a channel's dimension, on the host.
+inline void brick_dims(int dim, int shape, int& bx, int& by, int& bz) {
+    static const int d3[MGM_NSHAPE][3] = {{32, 8, 4}, {16, 16, 4}, {32, 4, 8}, {16, 8, 8}};
+    static const int d2[MGM_NSHAPE][2] = {{64, 16}, {128, 8}, {32, 32}, {256, 4}};
+    if (dim == 3) {
+        bx = d3[shape][0];
+        by = d3[shape][1];
+        bz = d3[shape][2];
+    } else {
+        bx = d2[shape][0];
+        by = d2[shape][1];
+        bz = 1;
+    }
+}
+template <int SHAPE>
+struct BrickLds {
+    static constexpr int NE = Brick<3, SHAPE>::NE > Brick<2, SHAPE>::NE ? Brick<3, SHAPE>::NE : Brick<2, SHAPE>::NE;
+};
 constexpr int MGM_BRICK_OWN = 1024;
-static_assert(BrickDims<3>::NOWN == MGM_BRICK_OWN && BrickDims<2>::NOWN == MGM_BRICK_OWN, "4 cells per thread");
 
-template <class T, int DIM, int MODE, int FORM>
+template <class T, int DIM, int SHAPE, int MODE, int FORM>
 __device__ inline void mgm_brick_body(const ChanDev& C, const ChanDev& Cc, int bx, int by, int bz,
                                       const MomOp<T>& op, const MGSrc<T>& src, const MGVec<T>& bout,
                                       const MGCVec<T>& xc, const MGVec<T>& out, const bool (&act)[MGM_K],
                                       const double (&sa)[MGM_K], const double (&sb)[MGM_K], T w,
-                                      T (*xs)[MGM_BRICK_NE], T (*bs)[MGM_BRICK_OWN]) {
-    using D = BrickDims<DIM>;
+                                      T (*xs)[BrickLds<SHAPE>::NE], T (*bs)[MGM_BRICK_OWN]) {
+    using D = Brick<DIM, SHAPE>;
     const int x0 = bx * D::BX, y0 = by * D::BY, z0 = bz * D::BZ;
-    const int64_t sxy = (int64_t)C.nx * C.ny;
-    // 1. smoothed value at every cell of the brick and its halo (zero outside the channel)
+    // 1. the stencil's input at every cell of the brick and its halo (zero outside the
+    //    channel), and the right-hand side at the own cells
     for (int e = threadIdx.x; e < D::NE; e += NT) {
         const int ex = e % D::EX - 1;
         const int ey = (e / D::EX) % D::EY - 1;
@@ -347,11 +387,16 @@ __device__ inline void mgm_brick_body(const ChanDev& C, const ChanDev& Cc, int b
             if (!act[k]) continue;
             T b = T(0), x1 = T(0);
             if (inside) {
-                if (MODE == MGM_MODE_P || FORM == 0) b = src.b[k][g];
-                else if (FORM == 1) b = src.r[k][g] + T(sa[k]) * (src.p[k][g] - T(sb[k]) * src.v[k][g]);
-                else b = src.r[k][g] - T(sa[k]) * src.v[k][g];
-                x1 = rd * b;
-                if (MODE == MGM_MODE_P) x1 += xc.v[k][gc];
+                if (MODE == MGM_MODE_S) {
+                    x1 = xc.v[k][g];                       // the iterate the sweep starts from
+                    if (own) b = src.b[k][g];
+                } else {
+                    if (MODE == MGM_MODE_P || FORM == 0) b = src.b[k][g];
+                    else if (FORM == 1) b = src.r[k][g] + T(sa[k]) * (src.p[k][g] - T(sb[k]) * src.v[k][g]);
+                    else b = src.r[k][g] - T(sa[k]) * src.v[k][g];
+                    x1 = rd * b;
+                    if (MODE == MGM_MODE_P) x1 += xc.v[k][gc];
+                }
                 if (own) {
                     bs[k][oq] = b;
                     if (MODE == MGM_MODE_R && FORM != 0) bout.v[k][g] = b;
@@ -361,15 +406,13 @@ __device__ inline void mgm_brick_body(const ChanDev& C, const ChanDev& Cc, int b
         }
     }
     __syncthreads();
-    // 2. stencil on the own cells; thread t holds four cells of one (x, y) column pair
-    //    (3-D: z = 0..3; 2-D: y = 2w, 2w+1, 2w+8, 2w+9 for wave w)
+    // 2. stencil on the own cells
     const int t = threadIdx.x;
-    const int lx = DIM == 3 ? t % 32 : t % 64;
     T res[4][MGM_K];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const int ly = DIM == 3 ? (t / 32) % 8 : 2 * (t / 64) + (m & 1) + 8 * (m >> 1);
-        const int lz = DIM == 3 ? m : 0;
+        int lx, ly, lz;
+        D::cell(t, m, lx, ly, lz);
         const int gi = x0 + lx, gj = y0 + ly, gk = z0 + lz;
         const bool inside = gi < C.nx && gj < C.ny && gk < C.nz;
 #pragma unroll
@@ -408,23 +451,23 @@ __device__ inline void mgm_brick_body(const ChanDev& C, const ChanDev& Cc, int b
                 if (gk < C.nz - 1) s += czp * x[e + SZ];
             }
             const T r = bs[k][oq] - (aP * x[e] + s);
-            if (MODE == MGM_MODE_P) out.v[k][g] = x[e] + w * r / aP;
-            else res[m][k] = r;
+            if (MODE == MGM_MODE_R) res[m][k] = r;
+            else out.v[k][g] = x[e] + w * r / aP;
         }
     }
     if (MODE == MGM_MODE_R) {
         // aggregates: cells m = 0,1 and 2,3 of a thread, then the x pair (lane ^ 1) and,
-        // in 3-D, the y pair (lane ^ 32)
+        // in 3-D, the y pair (lane ^ BX)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
+            int lx, ly, lz;
+            D::cell(t, 2 * h, lx, ly, lz);
 #pragma unroll
             for (int k = 0; k < MGM_K; ++k) {
                 if (!act[k]) continue;
                 T v = res[2 * h][k] + res[2 * h + 1][k];
                 v += __shfl_xor(v, 1, 64);
-                if (DIM == 3) v += __shfl_xor(v, 32, 64);
-                const int ly = DIM == 3 ? (t / 32) % 8 : 2 * (t / 64) + 8 * h;
-                const int lz = DIM == 3 ? 2 * h : 0;
+                if (DIM == 3) v += __shfl_xor(v, D::BX, 64);
                 const int ci = (x0 + lx) >> 1, cj = (y0 + ly) >> 1, ck = (z0 + lz) >> 1;
                 const bool lead = (lx & 1) == 0 && (DIM == 2 || (ly & 1) == 0);
                 if (lead && ci < Cc.nx && cj < Cc.ny && ck < Cc.nz)
@@ -434,7 +477,7 @@ __device__ inline void mgm_brick_body(const ChanDev& C, const ChanDev& Cc, int b
     }
 }
 
-template <class T, int MODE, int FORM>
+template <class T, int MODE, int FORM, int SHAPE>
 __global__ __launch_bounds__(NT) void k_mgm_brick(BrickGrid BG, MGPair L, MomOp<T> op, MGSrc<T> src, MGVec<T> bout,
                                                   MGCVec<T> xc, MGVec<T> out, KState S, T w) {
     const int32_t b = xcd_tile((int32_t)blockIdx.x, BG.nb);
@@ -454,12 +497,12 @@ __global__ __launch_bounds__(NT) void k_mgm_brick(BrickGrid BG, MGPair L, MomOp<
         sa[k] = FORM == 1 ? s[SC_BETA] : s[SC_ALPHA];
         sb[k] = s[SC_OMEGA];
     }
-    __shared__ T xs[MGM_K][MGM_BRICK_NE];
+    __shared__ T xs[MGM_K][BrickLds<SHAPE>::NE];
     __shared__ T bs[MGM_K][MGM_BRICK_OWN];
     if (C.dim == 3)
-        mgm_brick_body<T, 3, MODE, FORM>(C, Cc, bx, by, bz, op, src, bout, xc, out, act, sa, sb, w, xs, bs);
+        mgm_brick_body<T, 3, SHAPE, MODE, FORM>(C, Cc, bx, by, bz, op, src, bout, xc, out, act, sa, sb, w, xs, bs);
     else
-        mgm_brick_body<T, 2, MODE, FORM>(C, Cc, bx, by, bz, op, src, bout, xc, out, act, sa, sb, w, xs, bs);
+        mgm_brick_body<T, 2, SHAPE, MODE, FORM>(C, Cc, bx, by, bz, op, src, bout, xc, out, act, sa, sb, w, xs, bs);
 }
 
 // ---- BiCGStab with the V-cycle as right preconditioner ------------------------------

@@ -124,3 +124,16 @@ def test_multigrid_sweep_count_is_checked_without_gpu():
         ctx = ctypes.c_void_p()
         assert lib.clot_create(arr, 1, ctypes.byref(q), clot.FP64, ctypes.c_void_p(256), 1 << 30, None,
                                ctypes.byref(ctx)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libclot.so not built")
+def test_brick_shapes_without_gpu():
+    from paper_2304_09180_amd import clot
+    for dim in (2, 3):
+        for q in range(clot.N_BRICK_SHAPES):
+            bx, by, bz = clot.brick_dims(dim, q)
+            assert bx * by * bz == 1024 and (dim == 3 or bz == 1)
+    lib = clot.load()
+    v = (ctypes.c_int32 * 3)()
+    assert lib.clot_brick_dims(3, 4, v) == -1 and lib.clot_brick_dims(1, 0, v) == -1
+    assert lib.clot_set_brick_shape(None, 0, 0) == -1

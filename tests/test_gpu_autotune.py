@@ -50,3 +50,50 @@ def test_autotune_stores_and_reuses_its_choice(tmp_path):
     data[key]["tile"] = other
     autotune.store_cache(path, key, data[key])
     assert autotune.tune(descs, clot.FP32_MIXED, cache=path)["tile"] == other
+
+
+@pytest.mark.parametrize("precision", ["FP32_MIXED", "FP64"])
+def test_brick_shapes_give_bit_identical_steps(precision):
+    """Every brick shape of the LDS-staged momentum kernels computes each cell with the
+    same expression and adds each aggregate in the same order, so a step is the same
+    bit for bit in every shape.  Odd extents: partial bricks on every axis and
+    single-cell aggregates at the far faces."""
+    from paper_2304_09180_amd import clot
+    prec = getattr(clot, precision)
+    descs = [ci.channel(2, 201, 73, shear=400.0, seed=7), ci.channel(3, 41, 21, 19, shear=900.0, seed=8)]
+    runs = []
+    for shape in range(clot.N_BRICK_SHAPES):
+        s = clot.Solver(descs, prec)
+        for kernel in clot.BRICK_KERNELS:
+            s.set_brick_shape(kernel, shape)
+        for c, d in enumerate(descs):
+            xc, xf = ci.noise(d)
+            s.init_state(c, xc, xf)
+        s.step(4)
+        st = [s.stats(c) for c in range(len(descs))]
+        assert all(x["status"] == "OK" for x in st), st
+        runs.append([s.fields(c) for c in range(len(descs))])
+        s.close()
+    for shape in range(1, clot.N_BRICK_SHAPES):
+        for c in range(len(descs)):
+            for name, v in runs[0][c].items():
+                assert np.array_equal(runs[shape][c][name], v), (shape, c, name)
+
+
+def test_brick_tuner_stores_and_applies_its_choice(tmp_path):
+    from paper_2304_09180_amd import autotune, clot
+    descs = [ci.channel(3, 64, 16, 16, shear=900.0, seed=2)]
+    path = str(tmp_path / "tune.json")
+    e = autotune.tune_bricks(descs, clot.FP32_MIXED, steps=2, warmup=2, cache=path, log=print)
+    for k in autotune.BRICK_PROBES:
+        assert e[k] in range(clot.N_BRICK_SHAPES)
+        assert set(e["us"][k]) == {str(q) for q in range(clot.N_BRICK_SHAPES)}
+        assert all(0 < v < 1e5 for v in e["us"][k].values())
+    s = clot.Solver(descs, clot.FP32_MIXED)
+    autotune.apply_bricks(s, e)
+    s.close()
+    data = autotune.load_cache(path)
+    key = [k for k in data if k.endswith("|bricks")][0]
+    data[key]["sweep"] = 3 if e["sweep"] != 3 else 1
+    autotune.store_cache(path, key, data[key])
+    assert autotune.tune_bricks(descs, clot.FP32_MIXED, cache=path)["sweep"] == data[key]["sweep"]
