@@ -144,6 +144,11 @@ typedef struct {
                              aggregation levels of the pressure solver carrying the mass
                              and viscous parts of the momentum matrix); 0 = BiCGStab with
                              the Jacobi preconditioner.  Both stop at rtol_s.             */
+    int32_t mg_brick;     /* pressure multigrid, FP32 contexts with 2 or 3 sweeps: 1 (default)
+                             = each leg of every coarse level above the fused tail as one
+                             launch over LDS-staged 1024-cell bricks with a halo of one
+                             cell per sweep, where every channel is coarsened along every
+                             axis; 0 = the separate launches.  Bit for bit the same.     */
 } clot_params;
 
 /* Per-channel statistics of the last step. */
@@ -330,6 +335,7 @@ typedef enum {
     CLOT_PROBE_MOM_MG_R = 20,   /* momentum V-cycle: finest-level sweep + restriction      */
     CLOT_PROBE_MOM_MG_P1 = 21,  /* momentum V-cycle: prolongation + finest-level sweep     */
     CLOT_PROBE_MOM_MG_P2 = 22,  /* momentum V-cycle: last finest-level sweep               */
+    CLOT_PROBE_P_MG_DOWN = 23,  /* pressure multigrid, bricked: a coarse level's down leg   */
     CLOT_PROBE_NKERNELS
 } clot_probe_kernel;
 clot_status clot_probe(clot_ctx* c, int32_t kernel);

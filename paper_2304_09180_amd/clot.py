@@ -62,7 +62,7 @@ class Params(C.Structure):
                  ("mg_tail", C.c_int32), ("mg_sweeps", C.c_int32),
                  ("ddt_psi", C.c_double), ("max_co", C.c_double), ("dt_growth", C.c_double),
                  ("k_I", C.c_double), ("I_0", C.c_double), ("rtol_tr", C.c_double),
-                 ("mom_mg", C.c_int32)])
+                 ("mom_mg", C.c_int32), ("mg_brick", C.c_int32)])
 
 
 class Stats(C.Structure):
@@ -176,7 +176,7 @@ def brick_dims(dim, shape):
 PROBES = {"p_cg_a": 1, "p_cg_b": 2, "tr_b1": 3, "tr_b2": 4, "tr_b3": 5, "mom_b1": 6, "mom_b2": 7, "mom_b3": 8,
           "rxn": 9, "tr_asm": 10, "eta_cg_a": 11, "eta_cg_b": 12, "p_resid": 13, "correct": 14, "hbya": 15,
           "prhs": 16, "mom_asm": 17, "p_mg_post": 18, "rxn_fallback": 19, "mom_mg_r": 20, "mom_mg_p1": 21,
-          "mom_mg_p2": 22}
+          "mom_mg_p2": 22, "p_mg_down": 23}
 
 
 def default_params(precision=FP64, **over) -> Params:

@@ -4,6 +4,7 @@
 #include "clot_step.h"
 #include "clot_mg.h"
 #include "clot_mgm.h"
+#include "clot_mgb.h"
 #include "clot_surr.h"
 
 #include <hip/hip_ext.h>
@@ -213,10 +214,9 @@ struct Ctx : clot_ctx {
     int mgm_nc = 0;          // coarse levels of the momentum preconditioner (0: Jacobi BiCGStab)
     std::vector<int32_t> h_mgm_last;   // per channel: its coarsest momentum level
     int32_t* d_mgm_last = nullptr;
-    // LDS-staged finest-level momentum kernels: bricks of every channel (when every
-    // channel is coarsened along every axis)
-    // channel), one table per brick shape; each bricked kernel has its own shape (the
-    // tile autotuner's choice, clot_set_brick_shape)
+    // LDS-staged finest-level momentum kernels: the bricks of every channel (when every
+    // channel is coarsened along every axis), one table per brick shape; each bricked
+    // kernel has its own shape (the tile autotuner's choice, clot_set_brick_shape)
     std::vector<BrickChan> h_brick[MGM_NSHAPE];
     std::vector<int32_t> h_b2c[MGM_NSHAPE];
     BrickChan* d_brick[MGM_NSHAPE] = {};
@@ -224,6 +224,18 @@ struct Ctx : clot_ctx {
     int brick_shape[CLOT_NBRICK_KERNELS] = {};   // per bricked kernel: restriction, prolongation sweep, sweep
     BrickGrid bricks(int s) const { return BrickGrid{d_brick[s], d_b2c[s], (int32_t)h_b2c[s].size()}; }
     bool bricked() const { return !h_b2c[0].empty(); }
+    // LDS-staged legs of the pressure V-cycle's coarse levels (clot_mgb.h).  Table j >= 1:
+    // lev[j - 1], whose restriction reaches lev[j]; empty where some channel is not
+    // coarsened along every axis there (table 0, the mesh, stays empty).  The tables
+    // depend on the geometry only; mgb_use (mg_brick, FP32, 2 or 3 sweeps) decides
+    // whether they are used.
+    std::vector<BrickChan> h_pbr[MG_MAXLEV];
+    std::vector<int32_t> h_pb2c[MG_MAXLEV];
+    BrickChan* d_pbr[MG_MAXLEV] = {};
+    int32_t* d_pb2c[MG_MAXLEV] = {};
+    bool mgb_use = false;
+    BrickGrid pbricks(int j) const { return BrickGrid{d_pbr[j], d_pb2c[j], (int32_t)h_pb2c[j].size()}; }
+    bool pbricked(int j) const { return mgb_use && !h_pb2c[j].empty(); }
     // reaction surrogate
     clot_rxn_mode rxn_mode = CLOT_RXN_PLAIN;
     float surr_tol = 1e-3f;
@@ -438,6 +450,10 @@ struct Ctx : clot_ctx {
             L.cz = cv.take<T>(L.NFZ);
         }
         d_mgm_last = cv.take<int32_t>(nch);
+        for (int j = 0; j < MG_MAXLEV; ++j) {
+            d_pbr[j] = cv.take<BrickChan>(std::max<size_t>(h_pbr[j].size(), 1));
+            d_pb2c[j] = cv.take<int32_t>(std::max<size_t>(h_pb2c[j].size(), 1));
+        }
         for (int q = 0; q < MGM_NSHAPE; ++q) {
             d_brick[q] = cv.take<BrickChan>(std::max<size_t>(h_brick[q].size(), 1));
             d_b2c[q] = cv.take<int32_t>(std::max<size_t>(h_b2c[q].size(), 1));
@@ -651,13 +667,35 @@ struct Ctx : clot_ctx {
             if (t < nl) {
                 mg_t0 = t;
                 mg_tail_lds = (size_t)bytes_from(t);
-                if (mg_tail_lds > 65536 &&
-                    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail<T>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mg_tail_lds) != hipSuccess) {
-                    err = "multigrid tail: cannot raise the dynamic LDS limit";
-                    return CLOT_EHIP;
+            }
+        }
+        // LDS-staged legs of the coarse levels: a table per level that every channel
+        // coarsens along every axis
+        {
+            const int nl = (int)lev.size();
+            for (int j = 0; j < MG_MAXLEV; ++j) {
+                h_pbr[j].clear();
+                h_pb2c[j].clear();
+            }
+            for (int j = 1; j < nl && j < MG_MAXLEV; ++j) {
+                bool ok = true;
+                for (int i = 0; ok && i < nch; ++i) {
+                    const ChanDev& c = lev[j].ch[i];
+                    const ChanDev& f = lev[j - 1].ch[i];
+                    ok = c.nx != f.nx && c.ny != f.ny && (c.dim == 2 || c.nz != f.nz);
+                }
+                if (!ok) continue;
+                for (int i = 0; i < nch; ++i) {
+                    const int dim = lev[j].ch[i].dim;
+                    const int fx = lev[j - 1].ch[i].nx, fy = lev[j - 1].ch[i].ny, fz = lev[j - 1].ch[i].nz;
+                    int bx, by, bz;
+                    pbrick_dims(dim, bx, by, bz);
+                    BrickChan b{(int32_t)h_pb2c[j].size(), (fx + bx - 1) / bx, (fy + by - 1) / by, (fz + bz - 1) / bz};
+                    for (int t = 0; t < b.nbx * b.nby * b.nbz; ++t) h_pb2c[j].push_back(i);
+                    h_pbr[j].push_back(b);
                 }
             }
+            mgb_use = p->mg_brick != 0 && sizeof(T) == 4 && (prm.mg_sweeps == 2 || prm.mg_sweeps == 3);
         }
         const clot_params& q = *p;
         M = ModelDev{q.nu, q.C_CK, q.D_P, q.D_ADP, q.D_chem, q.P_diam, q.P_max, q.P_0, q.k_adh, q.kcoh_Pmax,
@@ -674,6 +712,32 @@ struct Ctx : clot_ctx {
         M.dt_growth = q.dt_growth;
         M.k_I = q.k_I;
         M.I_0 = q.I_0;
+        return CLOT_OK;
+    }
+
+    // Dynamic LDS limits of the kernels that use more than the default: a device call,
+    // so it runs at clot_create, not in setup (which the workspace query runs without one).
+    clot_status lds_limits() {
+        bool set = true;
+        auto attr = [&](const void* f, size_t bytes) {
+            if (bytes > 65536)
+                set = set && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+        };
+        if (mg_t0 >= 0) attr(reinterpret_cast<const void*>(&k_mg_tail<T>), mg_tail_lds);
+        if (mgb_use) {
+            const size_t by = mgb_lds_bytes(prm.mg_sweeps, sizeof(T));
+            if (prm.mg_sweeps == 3) {
+                attr(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_DOWN, 3>), by);
+                attr(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_UP, 3>), by);
+            } else {
+                attr(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_DOWN, 2>), by);
+                attr(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_UP, 2>), by);
+            }
+        }
+        if (!set) {
+            err = "cannot raise the dynamic LDS limit of the multigrid kernels";
+            return CLOT_EHIP;
+        }
         return CLOT_OK;
     }
 
@@ -781,6 +845,12 @@ struct Ctx : clot_ctx {
         }
         HIPCHK(hipMemcpyAsync(d_t2c, t2c.data(), t2c.size() * 4, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(d_mgm_last, h_mgm_last.data(), nch * 4, hipMemcpyHostToDevice, st));
+        for (int j = 0; j < MG_MAXLEV; ++j)
+            if (!h_pb2c[j].empty()) {
+                HIPCHK(hipMemcpyAsync(d_pbr[j], h_pbr[j].data(), h_pbr[j].size() * sizeof(BrickChan),
+                                      hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(d_pb2c[j], h_pb2c[j].data(), h_pb2c[j].size() * 4, hipMemcpyHostToDevice, st));
+            }
         for (int q = 0; q < MGM_NSHAPE; ++q)
             if (!h_b2c[q].empty()) {
                 HIPCHK(hipMemcpyAsync(d_brick[q], h_brick[q].data(), h_brick[q].size() * sizeof(BrickChan),
@@ -1387,7 +1457,7 @@ struct Ctx : clot_ctx {
                 cur = nxt;
             }
         };
-        // down
+        // down (a bricked level leaves its smoothed iterate in Y for its up leg)
         T* s0 = down(p0, r, mg_z0, mg_y0, grid(), (int)ntiles);
         hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>, false>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT), 0,
                            st, MGPair{grid(), lev[0].grid()}, p0, r, (const T*)s0, lev[0].b, act, mg_w);
@@ -1395,6 +1465,12 @@ struct Ctx : clot_ctx {
         for (int l = 0; l < t0; ++l) {
             Level& L = lev[l];
             CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
+            if (pbricked(l + 1)) {
+                mgb_launch<MGB_DOWN>(l + 1, CLOT_PROBE_P_MG_DOWN, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, nullptr,
+                                     nullptr, L.y, lev[l + 1].b);
+                pre_end[l] = L.y;
+                continue;
+            }
             pre_end[l] = down(op, (const T*)L.b, L.x, L.y, L.grid(), (int)L.ntiles);
             hipLaunchKernelGGL((k_mg_restrict<T, CoefOp<T>, false>), dim3(lev[l + 1].ntiles * (TILE / (NT / 8))), dim3(NT),
                                0, st, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, (const T*)pre_end[l], lev[l + 1].b,
@@ -1405,6 +1481,11 @@ struct Ctx : clot_ctx {
         for (int l = t0 - 1; l >= 0; --l) {
             Level& L = lev[l];
             CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
+            if (pbricked(l + 1)) {
+                mgb_launch<MGB_UP>(l + 1, CLOT_PROBE_OFF, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, pre_end[l],
+                                   lev[l + 1].x, L.x, nullptr);
+                continue;
+            }
             T* o1 = pre_end[l] == L.x ? L.y : L.x;
             hipLaunchKernelGGL((k_mg_post1<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, MGPair{L.grid(), lev[l + 1].grid()},
                                op, L.b, (const T*)pre_end[l], lev[l + 1].x, o1, mg_w, act);
@@ -1415,6 +1496,20 @@ struct Ctx : clot_ctx {
                            r, (const T*)s0, lev[0].x, o1, mg_w, act);
         up_rest(p0, r, mg_z0, mg_y0, o1, grid(), (int)ntiles, true);
         finish<1>(EpiMgDot{});
+    }
+
+    // One LDS-staged leg of the pressure V-cycle on the coarse level of brick table j.
+    template <int MODE>
+    void mgb_launch(int j, int probe, const MGPair& pr, const CoefOp<T>& op, const T* b, const T* xin, const T* xc,
+                    T* xout, T* bc) {
+        const dim3 gd((unsigned)h_pb2c[j].size());
+        const size_t lds = mgb_lds_bytes(prm.mg_sweeps, sizeof(T));
+        if (prm.mg_sweeps == 3)
+            CLOT_LAUNCH(probe, (k_mg_brick<T, MODE, 3>), gd, dim3(MGB_BS), lds, st, pbricks(j), pr, op, b, xin, xc, xout,
+                        bc, mg_w, (const int32_t*)S.chact);
+        else
+            CLOT_LAUNCH(probe, (k_mg_brick<T, MODE, 2>), gd, dim3(MGB_BS), lds, st, pbricks(j), pr, op, b, xin, xc, xout,
+                        bc, mg_w, (const int32_t*)S.chact);
     }
 
     // Multigrid-preconditioned CG on the pressure correction.
@@ -2211,6 +2306,8 @@ static clot_status create_t(Ctx<T>* c, const clot_channel* chs, int n_ch, const 
                             void* stream) {
     clot_status s = c->setup(chs, n_ch, p);
     if (s) return s;
+    s = c->lds_limits();
+    if (s) return s;
     const size_t need = c->layout(nullptr);
     if (wsb < need) {
         c->err = "workspace too small: need " + std::to_string(need) + " bytes";
@@ -2344,6 +2441,7 @@ clot_status clot_params_default(clot_params* p) {
     p->I_0 = 3.4e-3;
     p->rtol_tr = 1e-13;
     p->mom_mg = 1;
+    p->mg_brick = 1;
     return CLOT_OK;
 }
 
@@ -2373,7 +2471,7 @@ clot_status clot_create(const clot_channel* chs, int32_t n_ch, const clot_params
     if (p->M_rxn < 1 || p->n_corr < 0 || p->n_corr > MAXCORR || p->max_iter < 1 || p->mg_tail < 0 ||
         p->mg_sweeps < 0 || p->mg_sweeps > 4 || !(p->ddt_psi >= 0.0 && p->ddt_psi <= 1.0) ||
         !(p->max_co >= 0.0) || !(p->dt_growth >= 1.0) || !(p->k_I >= 0.0) || !(p->I_0 >= 0.0) ||
-        (p->mom_mg != 0 && p->mom_mg != 1))
+        (p->mom_mg != 0 && p->mom_mg != 1) || (p->mg_brick != 0 && p->mg_brick != 1))
         return CLOT_EINVAL;
     clot_ctx* c = make_ctx(prec);
     c->prec = prec;

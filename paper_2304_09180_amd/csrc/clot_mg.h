@@ -379,22 +379,40 @@ struct TailLds {
     int32_t nfx, nfy, nfz;
 };
 
-// dst[q] = src[q] for q < n, the block's threads each issuing U loads before storing.
+// One array copied into the tail's LDS: n elements from src to lds[dst].
 template <class T>
-__device__ inline void tail_copy_in(T* dst, const T* __restrict__ src, int64_t n) {
-    constexpr int U = 4;
-    for (int64_t q0 = threadIdx.x; q0 < n; q0 += U * MG_TAIL_BS) {
+struct TailSeg {
+    const T* src;
+    int32_t dst, n;
+};
+constexpr int MG_TAIL_SEGS = 4 * MG_MAXLEV + 1;
+
+// All the segments in one pass over their concatenation: each thread issues the loads
+// of up to U elements, whatever arrays they fall in, before it stores any of them, so
+// that the latencies of the arrays overlap instead of adding up array by array.
+template <class T>
+__device__ inline void tail_copy_in(T* lds, const TailSeg<T>* seg, const int32_t* start, int nseg) {
+    constexpr int U = 16;
+    const int32_t tot = start[nseg];
+    for (int32_t e0 = threadIdx.x; e0 < tot; e0 += U * MG_TAIL_BS) {
         T v[U];
+        int32_t d[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t q = q0 + (int64_t)u * MG_TAIL_BS;
-            v[u] = q < n ? src[q] : T(0);
+            const int32_t e = e0 + u * MG_TAIL_BS;
+            d[u] = -1;
+            v[u] = T(0);
+            if (e < tot) {
+                int s = 0;
+                while (e >= start[s + 1]) ++s;
+                const int32_t q = e - start[s];
+                v[u] = seg[s].src[q];
+                d[u] = seg[s].dst + q;
+            }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t q = q0 + (int64_t)u * MG_TAIL_BS;
-            if (q < n) dst[q] = v[u];
-        }
+        for (int u = 0; u < U; ++u)
+            if (d[u] >= 0) lds[d[u]] = v[u];
     }
 }
 
@@ -440,20 +458,35 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
             o += tail_align(v.nfz, bytes);
         }
     }
-    __syncthreads();
-    for (int l = 0; l + 1 < nl; ++l) {
-        const MGTailLevel<T>& Lv = tl.L[l];
-        const ChanDev& C = tl.L[l].ch[chid];
-        const TailLds& v = tv[l];
-        tail_copy_in(lds + v.odg, Lv.dg + C.c0, C.ncell);
-        tail_copy_in(lds + v.ocx, Lv.cx + C.fx0, v.nfx);
-        tail_copy_in(lds + v.ocy, Lv.cy + C.fy0, v.nfy);
-        tail_copy_in(lds + v.ocz, Lv.cz + C.fz0, v.nfz);
-    }
-    {
+    __shared__ TailSeg<T> seg[MG_TAIL_SEGS];
+    __shared__ int32_t sstart[MG_TAIL_SEGS + 1];
+    __shared__ int nseg;
+    if (threadIdx.x == 0) {
+        int ns = 0;
+        int32_t e = 0;
+        auto add = [&](const T* src, int32_t dst, int32_t n) {
+            if (n <= 0) return;
+            seg[ns] = TailSeg<T>{src, dst, n};
+            sstart[ns] = e;
+            e += n;
+            ++ns;
+        };
+        for (int l = 0; l + 1 < nl; ++l) {
+            const MGTailLevel<T>& Lv = tl.L[l];
+            const ChanDev& C = Lv.ch[chid];
+            const TailLds& v = tv[l];
+            add(Lv.dg + C.c0, v.odg, (int32_t)C.ncell);
+            add(Lv.cx + C.fx0, v.ocx, v.nfx);
+            add(Lv.cy + C.fy0, v.ocy, v.nfy);
+            add(Lv.cz + C.fz0, v.ocz, v.nfz);
+        }
         const ChanDev& C0 = tl.L[0].ch[chid];
-        tail_copy_in(lds + tv[0].ob, tl.L[0].b + C0.c0, C0.ncell);
+        add(tl.L[0].b + C0.c0, tv[0].ob, (int32_t)C0.ncell);
+        sstart[ns] = e;
+        nseg = ns;
     }
+    __syncthreads();
+    tail_copy_in(lds, seg, sstart, nseg);
     __syncthreads();
     // down: `sweeps` Jacobi sweeps (from zero) and the residual restriction per level
     for (int l = 0; l + 1 < nl; ++l) {

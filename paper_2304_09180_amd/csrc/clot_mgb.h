@@ -1,0 +1,183 @@
+// LDS-staged multi-sweep bricks for the coarse levels of the pressure multigrid
+// (gfx950, FP32 contexts).
+//
+// Above the fused tail, each coarse level's legs are six separate launches (first two
+// sweeps, the other sweeps, restriction; prolongation sweep, the other sweeps), each
+// bound by launch latency rather than by its few thousand to a hundred thousand cells.
+// A brick kernel does one whole leg of one level in one launch.  A 1024-thread block
+// owns a brick of 1024 cells and stages the brick with an H-cell halo in LDS: the
+// right-hand side, the level's diagonal and face coefficients and the leg's starting
+// iterate.  It then runs the leg's H stencil stages from LDS; each stage covers a region
+// one cell narrower than the one before, so the last covers exactly the own cells.  The
+// halo cells are computed redundantly by the neighbouring bricks, with the expressions
+// of the separate kernels, so every value is the same bit for bit.
+//
+//   DOWN: x1 = w D^-1 b (in the halo too), H-1 sweeps, then the residual b - A x_H of
+//         the own cells summed over each 2x2(x2) aggregate (in the pairwise order of the
+//         separate restriction) into the coarse right-hand side; x_H is stored for the
+//         up leg.  H = sweeps each way.
+//   UP:   x1 = x + P xc (injection), then H sweeps; the last is stored.
+//
+// A level is bricked only when every channel is coarsened along every axis there
+// (aggregates never straddle bricks, whose origins are even).  On the mesh the same
+// scheme loses: the staged arrays leave room for one block per CU and the three-cell
+// halo triples the work, against separate launches that are already wide.
+#pragma once
+#include "clot_mgm.h"
+
+namespace clot {
+
+enum { MGB_DOWN = 0, MGB_UP = 1 };
+constexpr int MGB_BS = 1024;
+
+template <int DIM, int H>
+struct PBrick {
+    static constexpr int BX = DIM == 3 ? 16 : 64, BY = DIM == 3 ? 8 : 16, BZ = DIM == 3 ? 8 : 1;
+    static constexpr int EX = BX + 2 * H, EY = BY + 2 * H, EZ = DIM == 3 ? BZ + 2 * H : 1;
+    static constexpr int NE = EX * EY * EZ;
+    static_assert(BX * BY * BZ == MGB_BS, "one own cell per thread");
+};
+inline void pbrick_dims(int dim, int& bx, int& by, int& bz) {
+    bx = dim == 3 ? 16 : 64;
+    by = dim == 3 ? 8 : 16;
+    bz = dim == 3 ? 8 : 1;
+}
+// LDS elements per array (the larger of the 2-D and 3-D bricks) and the bytes of the
+// seven arrays: b, the diagonal, two iterates, the three face-coefficient arrays.
+__host__ __device__ constexpr int mgb_ne(int h) {
+    return (16 + 2 * h) * (8 + 2 * h) * (8 + 2 * h) > (64 + 2 * h) * (16 + 2 * h)
+               ? (16 + 2 * h) * (8 + 2 * h) * (8 + 2 * h)
+               : (64 + 2 * h) * (16 + 2 * h);
+}
+__host__ __device__ constexpr size_t mgb_lds_bytes(int h, size_t tsize) { return 7 * (size_t)mgb_ne(h) * tsize; }
+
+template <class T, int MODE, int H, int DIM>
+__device__ inline void mgb_body(const ChanDev& C, const ChanDev& Cc, int bx, int by, int bz, const CoefOp<T>& op,
+                                const T* b, const T* xin, const T* xc, T* xout, T* bc, T w, T* sm) {
+    using D = PBrick<DIM, H>;
+    constexpr int NE = mgb_ne(H);
+    T* const sb = sm;
+    T* const sd = sm + NE;
+    T* s0 = sm + 2 * NE;
+    T* s1 = sm + 3 * NE;
+    T* const sa = sm + 4 * NE;     // cx
+    T* const sy = sm + 5 * NE;     // cy
+    T* const sz = sm + 6 * NE;     // cz
+    const int ox = bx * D::BX - H, oy = by * D::BY - H, oz = DIM == 3 ? bz * D::BZ - H : 0;
+    // 1. stage the brick and its halo; the leg's first iterate, pointwise
+    for (int e = threadIdx.x; e < D::NE; e += MGB_BS) {
+        const int ex = e % D::EX, ey = (e / D::EX) % D::EY, ez = DIM == 3 ? e / (D::EX * D::EY) : 0;
+        const int gi = ox + ex, gj = oy + ey, gk = oz + ez;
+        const bool in = gi >= 0 && gi < C.nx && gj >= 0 && gj < C.ny && gk >= 0 && gk < C.nz;
+        T vb = T(0), vd = T(1), va = T(0), vy = T(0), vz = T(0), vx = T(0);
+        if (in) {
+            const int64_t g = C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk);
+            vb = b[g];
+            vd = op.dg[g];
+            va = op.cx[fx_id(C, gi, gj, gk)];
+            vy = op.cy[fy_id(C, gi, gj, gk)];
+            if (DIM == 3) vz = op.cz[fz_id(C, gi, gj, gk)];
+            if (MODE == MGB_DOWN)
+                vx = w * vb / vd;
+            else
+                vx = xin[g] + xc[Cc.c0 + (gi >> 1) + (int64_t)Cc.nx * ((gj >> 1) + (int64_t)Cc.ny * (gk >> 1))];
+        }
+        sb[e] = vb;
+        sd[e] = vd;
+        sa[e] = va;
+        sy[e] = vy;
+        if (DIM == 3) sz[e] = vz;
+        s0[e] = vx;
+    }
+    __syncthreads();
+    // 2. the stencil stages, each on a region one cell narrower than the last
+    constexpr int SY = D::EX, SZ = D::EX * D::EY;
+#pragma unroll
+    for (int s = 1; s <= H; ++s) {
+        const int m = H - s;
+        const int RX = D::BX + 2 * m, RY = D::BY + 2 * m, RZ = DIM == 3 ? D::BZ + 2 * m : 1;
+        const int NR = RX * RY * RZ;
+        const bool last = s == H;
+        for (int q = threadIdx.x; q < NR; q += MGB_BS) {
+            const int ex = q % RX + s, ey = (q / RX) % RY + s, ez = DIM == 3 ? q / (RX * RY) + s : 0;
+            const int gi = ox + ex, gj = oy + ey, gk = oz + ez;
+            if (gi < 0 || gi >= C.nx || gj < 0 || gj >= C.ny || gk < 0 || gk >= C.nz) continue;
+            const int e = ex + SY * (ey + D::EY * ez);
+            // CoefOp's stencil, in its order: x-, x+, y-, y+, z-, z+
+            const T* x = s0;
+            T sacc = T(0);
+            if (gi > 0) sacc += sa[e] * x[e - 1];
+            if (gi < C.nx - 1) sacc += sa[e + 1] * x[e + 1];
+            if (gj > 0) sacc += sy[e] * x[e - SY];
+            if (gj < C.ny - 1) sacc += sy[e + SY] * x[e + SY];
+            if (DIM == 3) {
+                if (gk > 0) sacc += sz[e] * x[e - SZ];
+                if (gk < C.nz - 1) sacc += sz[e + SZ] * x[e + SZ];
+            }
+            const T ax = sd[e] * x[e] - sacc;
+            if (MODE == MGB_DOWN && last) {
+                s1[e] = sb[e] - ax;     // residual of the own cell
+            } else {
+                const T z = x[e] + w * (sb[e] - ax) / sd[e];
+                s1[e] = z;
+                if (last) xout[C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk)] = z;
+            }
+        }
+        __syncthreads();
+        if (!(MODE == MGB_DOWN && last)) {
+            T* t = s0;
+            s0 = s1;
+            s1 = t;
+        }
+    }
+    if (MODE == MGB_DOWN) {
+        // s0: x_H, s1: the own cells' residuals.  The iterate for the up leg, then the
+        // aggregate sums ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111)).
+        {
+            const int q = threadIdx.x;
+            const int lx = q % D::BX, ly = (q / D::BX) % D::BY, lz = DIM == 3 ? q / (D::BX * D::BY) : 0;
+            const int gi = ox + H + lx, gj = oy + H + ly, gk = oz + (DIM == 3 ? H : 0) + lz;
+            if (gi < C.nx && gj < C.ny && gk < C.nz)
+                xout[C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk)] =
+                    s0[(lx + H) + SY * ((ly + H) + D::EY * (DIM == 3 ? lz + H : 0))];
+        }
+        constexpr int AX = D::BX / 2, AY = D::BY / 2, AZ = DIM == 3 ? D::BZ / 2 : 1;
+        for (int a = threadIdx.x; a < AX * AY * AZ; a += MGB_BS) {
+            const int ax = a % AX, ay = (a / AX) % AY, az = a / (AX * AY);
+            T r[8];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                const int di = f & 1, dj = (f >> 1) & 1, dk = f >> 2;
+                const int lx = 2 * ax + di, ly = 2 * ay + dj, lz = DIM == 3 ? 2 * az + dk : 0;
+                const int gi = ox + H + lx, gj = oy + H + ly, gk = oz + (DIM == 3 ? H : 0) + lz;
+                const bool in = (DIM == 3 || dk == 0) && gi < C.nx && gj < C.ny && gk < C.nz;
+                r[f] = in ? s1[(lx + H) + SY * ((ly + H) + D::EY * (DIM == 3 ? lz + H : 0))] : T(0);
+            }
+            const T s01 = r[0] + r[1], s23 = r[2] + r[3], s45 = r[4] + r[5], s67 = r[6] + r[7];
+            const int ci = (ox + H) / 2 + ax, cj = (oy + H) / 2 + ay, ck = DIM == 3 ? (oz + H) / 2 + az : 0;
+            if (ci < Cc.nx && cj < Cc.ny && ck < Cc.nz)
+                bc[Cc.c0 + ci + (int64_t)Cc.nx * (cj + (int64_t)Cc.ny * ck)] = (s01 + s23) + (s45 + s67);
+        }
+    }
+}
+
+template <class T, int MODE, int H>
+__global__ __launch_bounds__(MGB_BS) void k_mg_brick(BrickGrid BG, MGPair L, CoefOp<T> op, const T* b, const T* xin,
+                                                     const T* xc, T* xout, T* bc, T w, const int32_t* chact) {
+    const int32_t bk = xcd_tile((int32_t)blockIdx.x, BG.nb);
+    const int32_t chid = BG.b2c[bk];
+    if (!chact[chid]) return;
+    const ChanDev C = L.fine.ch[chid];
+    const ChanDev Cc = L.coarse.ch[chid];
+    const BrickChan B = BG.bc[chid];
+    const int lb = bk - B.b0;
+    const int bx = lb % B.nbx, by = (lb / B.nbx) % B.nby, bz = lb / (B.nbx * B.nby);
+    extern __shared__ __align__(16) unsigned char mgb_lds[];
+    T* const sm = reinterpret_cast<T*>(mgb_lds);
+    if (C.dim == 3)
+        mgb_body<T, MODE, H, 3>(C, Cc, bx, by, bz, op, b, xin, xc, xout, bc, w, sm);
+    else
+        mgb_body<T, MODE, H, 2>(C, Cc, bx, by, bz, op, b, xin, xc, xout, bc, w, sm);
+}
+
+}  // namespace clot

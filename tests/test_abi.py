@@ -50,7 +50,7 @@ def test_params_default_and_argument_checks_without_gpu():
     p = clot.Params()
     assert lib.clot_params_default(ctypes.byref(p)) == 0
     assert p.nu == 2.62507 and p.M_rxn == 2 and p.P_max == 6.67e7
-    assert p.rtol_s == 1e-13 and p.rtol_tr == 1e-13 and p.I_0 == 3.4e-3 and p.mom_mg == 1   # the last fields
+    assert p.rtol_s == 1e-13 and p.rtol_tr == 1e-13 and p.I_0 == 3.4e-3 and p.mom_mg == 1 and p.mg_brick == 1   # the last fields
     assert lib.clot_params_default(None) == -1
     # workspace query is host-only arithmetic
     import clot_inputs as ci
@@ -117,10 +117,10 @@ def test_multigrid_sweep_count_is_checked_without_gpu():
     import clot_inputs as ci
     lib = clot.load()
     arr = (clot.Channel * 1)(clot.channel_struct(ci.workload("channel2d_64x16")))
-    for bad in (5, -1):
+    for field, bad in (("mg_sweeps", 5), ("mg_sweeps", -1), ("mg_brick", 2), ("mg_brick", -1)):
         q = clot.Params()
         lib.clot_params_default(ctypes.byref(q))
-        q.mg_sweeps = bad
+        setattr(q, field, bad)
         ctx = ctypes.c_void_p()
         assert lib.clot_create(arr, 1, ctypes.byref(q), clot.FP64, ctypes.c_void_p(256), 1 << 30, None,
                                ctypes.byref(ctx)) == -1
