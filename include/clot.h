@@ -114,7 +114,7 @@ typedef struct {
     double rtol_inner;    /* FP32 inner pressure solve of each refinement pass             */
     int32_t mg_tail;      /* pressure multigrid: the levels whose channels all have at most
                              this many cells run as one launch (one block per channel);
-                             0 = every level its own launches.  Default 4096.            */
+                             0 = every level its own launches.  Default 1024.            */
     int32_t mg_sweeps;    /* pressure multigrid: weighted-Jacobi sweeps before and after each
                              restriction, 1 to 4, or 0 (default): 3 when every channel is
                              3-D, else 2.  Each sweep costs one stencil pass per level;
@@ -144,11 +144,13 @@ typedef struct {
                              aggregation levels of the pressure solver carrying the mass
                              and viscous parts of the momentum matrix); 0 = BiCGStab with
                              the Jacobi preconditioner.  Both stop at rtol_s.             */
-    int32_t mg_brick;     /* pressure multigrid, FP32 contexts with 2 or 3 sweeps: 1 (default)
-                             = each leg of every coarse level above the fused tail as one
-                             launch over LDS-staged 1024-cell bricks with a halo of one
-                             cell per sweep, where every channel is coarsened along every
-                             axis; 0 = the separate launches.  Bit for bit the same.     */
+    int32_t mg_brick;     /* pressure multigrid, where every channel is coarsened along every
+                             axis: 1 (default) = the mesh's restriction over 1024-cell
+                             bricks and its prolongation by index halving, and (FP32, 2 or
+                             3 sweeps) each leg of every coarse level above the fused tail
+                             as one launch over LDS-staged 1024-cell bricks with a halo of
+                             one cell per sweep; 0 = the general separate launches.  Bit
+                             for bit the same.                                            */
 } clot_params;
 
 /* Per-channel statistics of the last step. */

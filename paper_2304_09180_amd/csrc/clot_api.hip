@@ -234,6 +234,15 @@ struct Ctx : clot_ctx {
     BrickChan* d_pbr[MG_MAXLEV] = {};
     int32_t* d_pb2c[MG_MAXLEV] = {};
     bool mgb_use = false;
+    // The mesh's restriction in bricks of shape 0 (k_mg_restrict_mesh) and its
+    // prolongation by halving (k_mg_post1_mesh): when every channel is coarsened along
+    // every axis from the mesh to lev[0] (the table) and mg_brick is set
+    std::vector<BrickChan> h_rbr;
+    std::vector<int32_t> h_rb2c;
+    BrickChan* d_rbr = nullptr;
+    int32_t* d_rb2c = nullptr;
+    bool mesh_on = false;
+    bool mesh_halves() const { return mesh_on && !h_rb2c.empty(); }
     BrickGrid pbricks(int j) const { return BrickGrid{d_pbr[j], d_pb2c[j], (int32_t)h_pb2c[j].size()}; }
     bool pbricked(int j) const { return mgb_use && !h_pb2c[j].empty(); }
     // reaction surrogate
@@ -454,6 +463,8 @@ struct Ctx : clot_ctx {
             d_pbr[j] = cv.take<BrickChan>(std::max<size_t>(h_pbr[j].size(), 1));
             d_pb2c[j] = cv.take<int32_t>(std::max<size_t>(h_pb2c[j].size(), 1));
         }
+        d_rbr = cv.take<BrickChan>(std::max<size_t>(h_rbr.size(), 1));
+        d_rb2c = cv.take<int32_t>(std::max<size_t>(h_rb2c.size(), 1));
         for (int q = 0; q < MGM_NSHAPE; ++q) {
             d_brick[q] = cv.take<BrickChan>(std::max<size_t>(h_brick[q].size(), 1));
             d_b2c[q] = cv.take<int32_t>(std::max<size_t>(h_b2c[q].size(), 1));
@@ -696,6 +707,22 @@ struct Ctx : clot_ctx {
                 }
             }
             mgb_use = p->mg_brick != 0 && sizeof(T) == 4 && (prm.mg_sweeps == 2 || prm.mg_sweeps == 3);
+            mesh_on = p->mg_brick != 0;
+            h_rbr.clear();
+            h_rb2c.clear();
+            bool ok = nl > 0;
+            for (int i = 0; ok && i < nch; ++i) {
+                const ChanDev& c = lev[0].ch[i];
+                ok = c.nx != ch[i].d.nx && c.ny != ch[i].d.ny && (c.dim == 2 || c.nz != ch[i].d.nz);
+            }
+            for (int i = 0; ok && i < nch; ++i) {
+                const clot_channel& d = ch[i].d;
+                int bx, by, bz;
+                brick_dims(d.dim, 0, bx, by, bz);
+                BrickChan b{(int32_t)h_rb2c.size(), (d.nx + bx - 1) / bx, (d.ny + by - 1) / by, (d.nz + bz - 1) / bz};
+                for (int t = 0; t < b.nbx * b.nby * b.nbz; ++t) h_rb2c.push_back(i);
+                h_rbr.push_back(b);
+            }
         }
         const clot_params& q = *p;
         M = ModelDev{q.nu, q.C_CK, q.D_P, q.D_ADP, q.D_chem, q.P_diam, q.P_max, q.P_0, q.k_adh, q.kcoh_Pmax,
@@ -845,6 +872,10 @@ struct Ctx : clot_ctx {
         }
         HIPCHK(hipMemcpyAsync(d_t2c, t2c.data(), t2c.size() * 4, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(d_mgm_last, h_mgm_last.data(), nch * 4, hipMemcpyHostToDevice, st));
+        if (!h_rb2c.empty()) {
+            HIPCHK(hipMemcpyAsync(d_rbr, h_rbr.data(), h_rbr.size() * sizeof(BrickChan), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(d_rb2c, h_rb2c.data(), h_rb2c.size() * 4, hipMemcpyHostToDevice, st));
+        }
         for (int j = 0; j < MG_MAXLEV; ++j)
             if (!h_pb2c[j].empty()) {
                 HIPCHK(hipMemcpyAsync(d_pbr[j], h_pbr[j].data(), h_pbr[j].size() * sizeof(BrickChan),
@@ -1459,8 +1490,13 @@ struct Ctx : clot_ctx {
         };
         // down (a bricked level leaves its smoothed iterate in Y for its up leg)
         T* s0 = down(p0, r, mg_z0, mg_y0, grid(), (int)ntiles);
-        hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>, false>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT), 0,
-                           st, MGPair{grid(), lev[0].grid()}, p0, r, (const T*)s0, lev[0].b, act, mg_w);
+        if (mesh_halves())
+            hipLaunchKernelGGL(k_mg_restrict_mesh<T>, dim3((unsigned)h_rb2c.size()), dim3(NT), 0, st,
+                               BrickGrid{d_rbr, d_rb2c, (int32_t)h_rb2c.size()}, MGPair{grid(), lev[0].grid()}, p0, r,
+                               (const T*)s0, lev[0].b, act);
+        else
+            hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>, false>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT),
+                               0, st, MGPair{grid(), lev[0].grid()}, p0, r, (const T*)s0, lev[0].b, act, mg_w);
         T* pre_end[MG_MAXLEV];
         for (int l = 0; l < t0; ++l) {
             Level& L = lev[l];
@@ -1492,8 +1528,12 @@ struct Ctx : clot_ctx {
             up_rest(op, (const T*)L.b, L.x, L.y, o1, L.grid(), (int)L.ntiles, false);
         }
         T* o1 = s0 == mg_z0 ? mg_y0 : mg_z0;
-        hipLaunchKernelGGL((k_mg_post1<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, MGPair{grid(), lev[0].grid()}, p0,
-                           r, (const T*)s0, lev[0].x, o1, mg_w, act);
+        if (mesh_halves())
+            hipLaunchKernelGGL(k_mg_post1_mesh<T>, dim3(ntiles), dim3(NT), 0, st, MGPair{grid(), lev[0].grid()}, p0, r,
+                               (const T*)s0, lev[0].x, o1, mg_w, act);
+        else
+            hipLaunchKernelGGL((k_mg_post1<T, PresOp<T, T>>), dim3(ntiles), dim3(NT), 0, st, MGPair{grid(), lev[0].grid()},
+                               p0, r, (const T*)s0, lev[0].x, o1, mg_w, act);
         up_rest(p0, r, mg_z0, mg_y0, o1, grid(), (int)ntiles, true);
         finish<1>(EpiMgDot{});
     }
@@ -2432,7 +2472,7 @@ clot_status clot_params_default(clot_params* p) {
     p->rtol_p = 1e-13;
     p->rtol_s = 1e-13;
     p->rtol_inner = 1e-4;
-    p->mg_tail = 4096;
+    p->mg_tail = 1024;
     p->mg_sweeps = 0;
     p->ddt_psi = 0.0;
     p->max_co = 0.0;

@@ -181,3 +181,113 @@ __global__ __launch_bounds__(MGB_BS) void k_mg_brick(BrickGrid BG, MGPair L, Coe
 }
 
 }  // namespace clot
+
+// ---- The mesh's leg ends, for a mesh that every channel coarsens along every axis -----
+namespace clot {
+
+// Residual restriction of the mesh: r = b - A x at every mesh cell, summed over each
+// 2x2(x2) aggregate into the coarse right-hand side.  The block walks a brick in the
+// momentum bricks' shape 0 (3-D 32x8x4, 2-D 64x16), so its loads run along x rows: a
+// thread's four cells are two aggregate pairs along the slow axis, the x partner is
+// lane l^1 and, in 3-D, the y partner lane l^32.  The sums are those of k_mg_restrict in
+// its order ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111)), the
+// missing z half of a 2-D aggregate adding (0 + 0) + (0 + 0) as there.
+template <class T, int DIM>
+__device__ inline void mg_restrict_mesh_body(const ChanDev& C, const ChanDev& Cc, int bx, int by, int bz,
+                                             const PresOp<T, T>& op, const T* b, const T* x, T* bc) {
+    using D = Brick<DIM, 0>;
+    const int x0 = bx * D::BX, y0 = by * D::BY, z0 = bz * D::BZ;
+    const int t = threadIdx.x;
+    T r[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        int lx, ly, lz;
+        D::cell(t, m, lx, ly, lz);
+        Cell P;
+        P.i = x0 + lx;
+        P.j = y0 + ly;
+        P.k = z0 + lz;
+        r[m] = T(0);
+        if (P.i < C.nx && P.j < C.ny && P.k < C.nz) {
+            P.g = C.c0 + P.i + (int64_t)C.nx * (P.j + (int64_t)C.ny * P.k);
+            r[m] = b[P.g] - op.apply(0, C, P, [&](int64_t g) { return x[g]; });
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        T s;
+        if (DIM == 3) {
+            T a0 = r[2 * h], a1 = r[2 * h + 1];     // dk = 0, 1
+            a0 += __shfl_xor(a0, 1, 64);
+            a1 += __shfl_xor(a1, 1, 64);
+            a0 += __shfl_xor(a0, 32, 64);
+            a1 += __shfl_xor(a1, 32, 64);
+            s = a0 + a1;
+        } else {
+            T a0 = r[2 * h], a1 = r[2 * h + 1];     // dj = 0, 1
+            a0 += __shfl_xor(a0, 1, 64);
+            a1 += __shfl_xor(a1, 1, 64);
+            s = (a0 + a1) + (T(0) + T(0));
+        }
+        int lx, ly, lz;
+        D::cell(t, 2 * h, lx, ly, lz);
+        const int gi = x0 + lx, gj = y0 + ly, gk = z0 + lz;
+        const bool lead = (lx & 1) == 0 && (DIM == 2 || (ly & 1) == 0);
+        if (lead && gi < C.nx && gj < C.ny && gk < C.nz)
+            bc[Cc.c0 + (gi >> 1) + (int64_t)Cc.nx * ((gj >> 1) + (int64_t)Cc.ny * (gk >> 1))] = s;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_mg_restrict_mesh(BrickGrid BG, MGPair L, PresOp<T, T> op, const T* b,
+                                                         const T* x, T* bc, const int32_t* chact) {
+    const int32_t bk = xcd_tile((int32_t)blockIdx.x, BG.nb);
+    const int32_t chid = BG.b2c[bk];
+    if (!chact[chid]) return;
+    const ChanDev C = L.fine.ch[chid];
+    const ChanDev Cc = L.coarse.ch[chid];
+    const BrickChan B = BG.bc[chid];
+    const int lb = bk - B.b0;
+    const int bx = lb % B.nbx, by = (lb / B.nbx) % B.nby, bz = lb / (B.nbx * B.nby);
+    if (C.dim == 3)
+        mg_restrict_mesh_body<T, 3>(C, Cc, bx, by, bz, op, b, x, bc);
+    else
+        mg_restrict_mesh_body<T, 2>(C, Cc, bx, by, bz, op, b, x, bc);
+}
+
+// Prolongation and the first up sweep on the mesh: x1 = x + P xc, y = x1 + w D^-1 (b -
+// A x1).  k_mg_post1's expressions (PresOp's stencil in its order), with each
+// neighbour's coarse cell taken from its indices by halving instead of by division.
+template <class T>
+__global__ __launch_bounds__(NT) void k_mg_post1_mesh(MGPair L, PresOp<T, T> op, const T* b, const T* x, const T* xc,
+                                                      T* y, T w, const int32_t* chact) {
+    CLOT_TILE_PROLOGUE(L.fine)
+    if (!chact[chid]) return;
+    const ChanDev Cc = L.coarse.ch[chid];
+    CLOT_FOR_CELLS(local)
+        const Cell P = cell_at(C, local);
+        auto x1 = [&](int64_t g, int i, int j, int k) {
+            return x[g] + xc[Cc.c0 + (i >> 1) + (int64_t)Cc.nx * ((j >> 1) + (int64_t)Cc.ny * (k >> 1))];
+        };
+        const T* rAU = op.rAU;
+        const T rP = rAU[P.g];
+        T s = T(0);
+        T gf = T(0.5 * C.gx);
+        if (P.i > 0) s += gf * (rP + rAU[P.g - 1]) * x1(P.g - 1, P.i - 1, P.j, P.k);
+        if (P.i < C.nx - 1) s += gf * (rP + rAU[P.g + 1]) * x1(P.g + 1, P.i + 1, P.j, P.k);
+        gf = T(0.5 * C.gy);
+        if (P.j > 0) s += gf * (rP + rAU[P.g - C.nx]) * x1(P.g - C.nx, P.i, P.j - 1, P.k);
+        if (P.j < C.ny - 1) s += gf * (rP + rAU[P.g + C.nx]) * x1(P.g + C.nx, P.i, P.j + 1, P.k);
+        if (C.dim == 3) {
+            const int64_t sz = (int64_t)C.nx * C.ny;
+            gf = T(0.5 * C.gz);
+            if (P.k > 0) s += gf * (rP + rAU[P.g - sz]) * x1(P.g - sz, P.i, P.j, P.k - 1);
+            if (P.k < C.nz - 1) s += gf * (rP + rAU[P.g + sz]) * x1(P.g + sz, P.i, P.j, P.k + 1);
+        }
+        const T xp = x1(P.g, P.i, P.j, P.k);
+        const T ax = op.dP[P.g] * xp - s;
+        y[P.g] = xp + w * (b[P.g] - ax) / op.dP[P.g];
+    CLOT_END_CELLS
+}
+
+}  // namespace clot

@@ -150,21 +150,24 @@ def test_fused_multigrid_tail_is_bitwise_equal_to_separate_launches(prec_name, d
             assert np.array_equal(fused[c][name], sep[c][name]), (c, name)
 
 
-@pytest.mark.parametrize("descs,over", [
-    ([ci.channel(3, 96, 32, 32, shear=800.0, dt=5e-5, seed=6)], {}),
-    ([ci.channel(3, 48, 16, 16, shear=800.0, dt=5e-5, seed=6)], {"mg_tail": 0}),
-    ([ci.channel(3, 37, 13, 11, shear=900.0, dt=5e-5, seed=9)], {"mg_sweeps": 2, "mg_tail": 0}),
-    ([ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5), ci.channel(2, 130, 34, shear=400.0, seed=8)],
+@pytest.mark.parametrize("prec_name,descs,over", [
+    ("FP32_MIXED", [ci.channel(3, 96, 32, 32, shear=800.0, dt=5e-5, seed=6)], {}),
+    ("FP32_MIXED", [ci.channel(3, 48, 16, 16, shear=800.0, dt=5e-5, seed=6)], {"mg_tail": 0}),
+    ("FP32_MIXED", [ci.channel(3, 37, 13, 11, shear=900.0, dt=5e-5, seed=9)], {"mg_sweeps": 2, "mg_tail": 0}),
+    ("FP32_MIXED", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5), ci.channel(2, 130, 34, shear=400.0, seed=8)],
      {"mg_tail": 0}),
-    ([ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5)], {"mg_sweeps": 3, "mg_tail": 0}),
+    ("FP32_MIXED", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5)], {"mg_sweeps": 3, "mg_tail": 0}),
+    ("FP64", [ci.channel(3, 37, 13, 11, shear=900.0, dt=5e-5, seed=9)], {}),
+    ("FP64", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5), ci.channel(2, 130, 34, shear=400.0, seed=8)], {}),
 ])
-def test_fp32_pressure_bricks_are_bitwise_equal_to_separate_launches(descs, over):
-    """The LDS-staged legs of the pressure V-cycle's coarse levels (default, mg_brick =
-    1) against the separate launches (mg_brick = 0): every cell value of a leg is formed
-    by the same expression, halo cells included, so the steps agree bit for bit.  Also
-    checks that the bricked legs ran (the down-leg probe counts launches)."""
+def test_pressure_bricks_are_bitwise_equal_to_separate_launches(prec_name, descs, over):
+    """The brick-ordered legs of the pressure V-cycle (default, mg_brick = 1: the mesh's
+    restriction and prolongation, and in FP32 the LDS-staged legs of the coarse levels)
+    against the general separate launches (mg_brick = 0): every cell value is formed by
+    the same expression, halo cells included, so the steps agree bit for bit.  In FP32
+    also checks that the staged legs ran (the down-leg probe counts launches)."""
     from paper_2304_09180_amd import clot
-    prec = clot.FP32_MIXED
+    prec = getattr(clot, prec_name)
     runs = []
     for brick in (1, 0):
         s = clot.Solver(descs, prec, clot.default_params(prec, mg_brick=brick, **over))
@@ -175,7 +178,7 @@ def test_fp32_pressure_bricks_are_bitwise_equal_to_separate_launches(descs, over
         s.step(6)
         _, n = s.probe_read()
         s.probe(None)
-        assert (n > 0) == (brick == 1), (brick, n)
+        assert (n > 0) == (brick == 1 and prec == clot.FP32_MIXED), (brick, n)
         runs.append([s.fields(i) for i in range(len(descs))])
         s.close()
     for c in range(len(descs)):
