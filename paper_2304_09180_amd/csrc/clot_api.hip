@@ -1861,7 +1861,7 @@ struct Ctx : clot_ctx {
         top.Wc = F.Wc;
         top.Pmax = T(M.P_max);
         top.n = N;
-        CLOT_LAUNCH(CLOT_PROBE_TR_ASM, k_tr_assemble<T>, gb, tb, 0, st, G, F, top, M);
+        CLOT_LAUNCH(CLOT_PROBE_TR_ASM, k_tr_assemble<T>, dim3(gb.x, NTR), tb, 0, st, G, F, top, M);
         if (eta_side) {
             const clot_status r = eta_side_join();
             if (r < 0) return r;

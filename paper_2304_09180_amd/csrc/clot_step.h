@@ -372,7 +372,8 @@ __global__ __launch_bounds__(64) void k_sigma_sched(const ChanDev* chans, SigSta
 // time derivative is that of the momentum assembly (k, w and the stored derivative
 // of each species' transport sub-step).  With a variable step, each tile also stores
 // the largest sum_f |phi_f| of its cells (the new flux) for the next step's Courant
-// limit.
+// limit.  Launch: blockIdx.y is the transported species, so a thread makes one pass of
+// loads instead of one per species.
 template <class T>
 __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T> op, ModelDev M) {
     CLOT_TILE_PROLOGUE(G)
@@ -387,7 +388,8 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
         const int64_t fi = C.inj0 + (P.i - C.inj_i0) + (int64_t)C.inj_ni * (P.k - C.inj_k0);
         const T fin = F.phin[0][fx_id(C, 0, P.j, P.k)];
         const T fout = F.phin[0][fx_id(C, C.nx, P.j, P.k)];
-        for (int k = 0; k < NTR; ++k) {
+        {
+            const int k = (int)blockIdx.y;
             const int sp = tr_species(k);
             const bool plt = k < 2;
             const T* c = op.Cn[k];
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(NT) void k_tr_assemble(Grid G, Fields<T> F, TrOp<T>
             F.trb[k][g] = b;
         }
     CLOT_END_CELLS
-    if (M.max_co > 0.0) {   // a pass of its own: inside the loop above it doubles the register use
+    if (M.max_co > 0.0 && blockIdx.y == 0) {   // a pass of its own: inside the loop above it doubles the register use
         double co_mx = 0.0;
         CLOT_FOR_CELLS(local)
             const Cell P = cell_at(C, local);
