@@ -1364,7 +1364,7 @@ struct Ctx : clot_ctx {
     template <class Op, int K>
     int run_bicg(const Op& op, KVec<T, K> V, double rtol, const int32_t* mask, int slot, int p1) {
         set_active(mask);
-        hipLaunchKernelGGL((k_bicg_init<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
+        hipLaunchKernelGGL((k_bicg_init<T, K, Op, true>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
         finish<3 * K>(EpiBicgInit<K>{rtol});
         return iterate<K>(slot, 1, 2, budget[slot], [&](int par) {
             CLOT_LAUNCH(p1, (k_bicg_1<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);

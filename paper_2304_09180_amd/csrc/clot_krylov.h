@@ -413,7 +413,17 @@ __global__ __launch_bounds__(NT) void k_cg_b(Grid G, Op op, KVec<T, K> V, KState
 }
 
 // ---- BiCGStab ----------------------------------------------------------------------
-template <class T, int K, class Op>
+// With the Jacobi preconditioner D (k_bicg_1/2/3) the solve keeps the preconditioned
+// vectors instead of dividing at every stencil point: V.r holds z = D^-1 r, V.p the
+// preconditioned direction D^-1 p and V.v the scaled product D^-1 v, with
+//   D^-1 p' = z + beta (D^-1 p - omega D^-1 v),  v' = A (D^-1 p'),
+//   D^-1 s  = z - alpha D^-1 v',                   s = D (D^-1 s),  t = A (D^-1 s),
+//   x += alpha D^-1 p' + omega D^-1 s,             r = s - omega t,  z = D^-1 r:
+// right-preconditioned BiCGStab with one division per cell and phase.  V.rh holds the
+// unscaled shadow residual, and every reduction takes the unscaled vectors.  SCALED
+// selects that form of the start (z in V.r); without it V.r holds r (the multigrid-
+// preconditioned momentum solve).
+template <class T, int K, class Op, bool SCALED = false>
 __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, KState S) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
@@ -438,7 +448,7 @@ __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, K
                 bd = (double)b;
                 r = b - ax;
             }
-            V.r[k][P.g] = r;
+            V.r[k][P.g] = SCALED ? r / op.diag(k, P.g) : r;
             V.rh[k][P.g] = r;
             V.p[0][k][P.g] = T(0);
             V.v[0][k][P.g] = T(0);
@@ -457,7 +467,8 @@ __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, K
     store_partials<3 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
-// p_new = r + beta (p_old - omega v_old); v_new = A (p_new/diag); rhat.v_new
+// D^-1 p_new = z + beta (D^-1 p_old - omega D^-1 v_old); v_new = A D^-1 p_new;
+// stores D^-1 p_new and D^-1 v_new; rhat.v_new
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_1(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
@@ -479,21 +490,21 @@ __global__ __launch_bounds__(NT) void k_bicg_1(Grid G, Op op, KVec<T, K> V, KSta
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (!act[k]) continue;
-            const T* r = V.r[k];
+            const T* z = V.r[k];
             const T* po = V.p[par][k];
-            const T* vo = V.v[par][k];
+            const T* wo = V.v[par][k];
             const T bk = (T)beta[k], om = (T)omega[k];
-            const T vn = op.apply(k, C, P, [&](int64_t g) { return (r[g] + bk * (po[g] - om * vo[g])) / op.diag(k, g); });
-            const T pn = r[P.g] + bk * (po[P.g] - om * vo[P.g]);
-            V.p[par ^ 1][k][P.g] = pn;
-            V.v[par ^ 1][k][P.g] = vn;
+            auto pn = [&](int64_t g) { return z[g] + bk * (po[g] - om * wo[g]); };
+            const T vn = op.apply(k, C, P, pn);
+            V.p[par ^ 1][k][P.g] = pn(P.g);
+            V.v[par ^ 1][k][P.g] = vn / op.diag(k, P.g);
             acc[k] += (double)V.rh[k][P.g] * (double)vn;
         }
     CLOT_END_CELLS
     store_partials<K>(acc, S.part, S.pstride, tile, lds);
 }
 
-// s = r - alpha v; t = A (s/diag); t.s, t.t
+// D^-1 s = z - alpha D^-1 v; t = A D^-1 s; t.s, t.t with s = D (D^-1 s)
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_2(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
@@ -514,11 +525,12 @@ __global__ __launch_bounds__(NT) void k_bicg_2(Grid G, Op op, KVec<T, K> V, KSta
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (!act[k]) continue;
-            const T* r = V.r[k];
-            const T* vn = V.v[par ^ 1][k];
+            const T* z = V.r[k];
+            const T* wn = V.v[par ^ 1][k];
             const T a = (T)alpha[k];
-            const T t = op.apply(k, C, P, [&](int64_t g) { return (r[g] - a * vn[g]) / op.diag(k, g); });
-            const T sv = r[P.g] - a * vn[P.g];
+            auto sh = [&](int64_t g) { return z[g] - a * wn[g]; };
+            const T t = op.apply(k, C, P, sh);
+            const T sv = op.diag(k, P.g) * sh(P.g);
             V.t[k][P.g] = t;
             acc[2 * k] += (double)t * (double)sv;
             acc[2 * k + 1] += (double)t * (double)t;
@@ -527,7 +539,7 @@ __global__ __launch_bounds__(NT) void k_bicg_2(Grid G, Op op, KVec<T, K> V, KSta
     store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
 }
 
-// x += alpha p/diag + omega s/diag; r = s - omega t; rhat.r, r.r
+// x += alpha D^-1 p + omega D^-1 s; r = s - omega t; z = D^-1 r; rhat.r, r.r
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_3(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
@@ -551,10 +563,10 @@ __global__ __launch_bounds__(NT) void k_bicg_3(Grid G, Op op, KVec<T, K> V, KSta
             if (!act[k]) continue;
             const T a = (T)alpha[k], om = (T)omega[k];
             const T d = op.diag(k, g);
-            const T sv = V.r[k][g] - a * V.v[par ^ 1][k][g];
-            V.x[k][g] += (a * V.p[par ^ 1][k][g] + om * sv) / d;
-            const T r = sv - om * V.t[k][g];
-            V.r[k][g] = r;
+            const T sh = V.r[k][g] - a * V.v[par ^ 1][k][g];
+            V.x[k][g] += a * V.p[par ^ 1][k][g] + om * sh;
+            const T r = d * sh - om * V.t[k][g];
+            V.r[k][g] = r / d;
             acc[2 * k] += (double)V.rh[k][g] * (double)r;
             acc[2 * k + 1] += (double)r * (double)r;
         }
