@@ -1364,14 +1364,14 @@ struct Ctx : clot_ctx {
     template <class Op, int K>
     int run_bicg(const Op& op, KVec<T, K> V, double rtol, const int32_t* mask, int slot, int p1) {
         set_active(mask);
-        hipLaunchKernelGGL((k_bicg_init<T, K, Op, true>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S);
+        hipLaunchKernelGGL((k_bicg_init<T, K, Op, true>), dim3(ntiles, K), dim3(NT), 0, st, grid(), op, V, S);
         finish<3 * K>(EpiBicgInit<K>{rtol});
         return iterate<K>(slot, 1, 2, budget[slot], [&](int par) {
-            CLOT_LAUNCH(p1, (k_bicg_1<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+            CLOT_LAUNCH(p1, (k_bicg_1<T, K, Op>), dim3(ntiles, K), dim3(NT), 0, st, grid(), op, V, S, par);
             finish<K>(EpiBicg1<K>{});
-            CLOT_LAUNCH(p1 + 1, (k_bicg_2<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+            CLOT_LAUNCH(p1 + 1, (k_bicg_2<T, K, Op>), dim3(ntiles, K), dim3(NT), 0, st, grid(), op, V, S, par);
             finish<2 * K>(EpiBicg2<K>{});
-            CLOT_LAUNCH(p1 + 2, (k_bicg_3<T, K, Op>), dim3(ntiles), dim3(NT), 0, st, grid(), op, V, S, par);
+            CLOT_LAUNCH(p1 + 2, (k_bicg_3<T, K, Op>), dim3(ntiles, K), dim3(NT), 0, st, grid(), op, V, S, par);
             finish<2 * K>(EpiBicg3<K>{});
         });
     }
@@ -1688,7 +1688,7 @@ struct Ctx : clot_ctx {
     // Jacobi-preconditioned solve.
     int run_mom_mg(const MomOp<T>& mop, KVec<T, 3> V, double rtol) {
         set_active(allmask);
-        hipLaunchKernelGGL((k_bicg_init<T, 3, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, V, S);
+        hipLaunchKernelGGL((k_bicg_init<T, 3, MomOp<T>>), dim3(ntiles, 3), dim3(NT), 0, st, grid(), mop, V, S);
         finish<9>(EpiBicgInit<3>{rtol});
         T* const (&Y)[MGM_K] = mgm_vec(0);
         T* const (&Z)[MGM_K] = mgm_vec(1);

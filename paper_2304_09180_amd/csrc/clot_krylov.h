@@ -423,48 +423,59 @@ __global__ __launch_bounds__(NT) void k_cg_b(Grid G, Op op, KVec<T, K> V, KState
 // unscaled shadow residual, and every reduction takes the unscaled vectors.  SCALED
 // selects that form of the start (z in V.r); without it V.r holds r (the multigrid-
 // preconditioned momentum solve).
+// One system per grid row: blockIdx.y is the system k, so a thread's loads are those
+// of one system and a converged system's blocks only zero their partials.  The
+// partials of system k are components NV k .. NV k + NV - 1 of the phase's sums.
+template <int NV>
+__device__ inline void store_partials_at(double (&v)[NV], const KState& S, int32_t tile, int q0, double* lds) {
+    block_sum<NV>(v, lds);
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        if (threadIdx.x == q) S.part[(int64_t)(q0 + q) * S.pstride + tile] = v[q];
+}
+template <int NV>
+__device__ inline void zero_partials_at(const KState& S, int32_t tile, int q0) {
+    if (threadIdx.x < NV) S.part[(int64_t)(q0 + threadIdx.x) * S.pstride + tile] = 0.0;
+}
+
 template <class T, int K, class Op, bool SCALED = false>
 __global__ __launch_bounds__(NT) void k_bicg_init(Grid G, Op op, KVec<T, K> V, KState S) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
-    __shared__ double lds[5 * 3 * K];
-    double acc[3 * K];
-#pragma unroll
-    for (int q = 0; q < 3 * K; ++q) acc[q] = 0.0;
+    const int k = (int)blockIdx.y;
+    __shared__ double lds[5 * 3];
+    double acc[3] = {0.0, 0.0, 0.0};
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const T* x = V.x[k];
-            double bd;
-            T r;
-            if constexpr (op_exact_residual<Op>::value) {
-                // delta form: the unknown is the change, starting at zero
-                r = T(op.residual64(k, C, P, bd));
-                V.x[k][P.g] = T(0);
-            } else {
-                const T ax = op.apply(k, C, P, [&](int64_t g) { return x[g]; });
-                const T b = V.b[k][P.g];
-                bd = (double)b;
-                r = b - ax;
-            }
-            V.r[k][P.g] = SCALED ? r / op.diag(k, P.g) : r;
-            V.rh[k][P.g] = r;
-            V.p[0][k][P.g] = T(0);
-            V.v[0][k][P.g] = T(0);
-            acc[3 * k] += bd * bd;
-            acc[3 * k + 1] += (double)r * (double)r;
-            // FP32: 1e-30 of the scale, and no residual below 1e-34 (the normal range
-            // ends at 1.2e-38); FP64: no floor
-            double f = 0.0;
-            if (sizeof(T) == 4) {
-                f = 1e-30 * (double)op.floor_scale(k) * (double)op.diag(k, P.g);
-                f = f > 1e-34 ? f : 1e-34;
-            }
-            acc[3 * k + 2] += f * f;
+        const T* x = V.x[k];
+        double bd;
+        T r;
+        if constexpr (op_exact_residual<Op>::value) {
+            // delta form: the unknown is the change, starting at zero
+            r = T(op.residual64(k, C, P, bd));
+            V.x[k][P.g] = T(0);
+        } else {
+            const T ax = op.apply(k, C, P, [&](int64_t g) { return x[g]; });
+            const T b = V.b[k][P.g];
+            bd = (double)b;
+            r = b - ax;
         }
+        V.r[k][P.g] = SCALED ? r / op.diag(k, P.g) : r;
+        V.rh[k][P.g] = r;
+        V.p[0][k][P.g] = T(0);
+        V.v[0][k][P.g] = T(0);
+        acc[0] += bd * bd;
+        acc[1] += (double)r * (double)r;
+        // FP32: 1e-30 of the scale, and no residual below 1e-34 (the normal range
+        // ends at 1.2e-38); FP64: no floor
+        double f = 0.0;
+        if (sizeof(T) == 4) {
+            f = 1e-30 * (double)op.floor_scale(k) * (double)op.diag(k, P.g);
+            f = f > 1e-34 ? f : 1e-34;
+        }
+        acc[2] += f * f;
     CLOT_END_CELLS
-    store_partials<3 * K>(acc, S.part, S.pstride, tile, lds);
+    store_partials_at<3>(acc, S, tile, 3 * k, lds);
 }
 
 // D^-1 p_new = z + beta (D^-1 p_old - omega D^-1 v_old); v_new = A D^-1 p_new;
@@ -473,35 +484,27 @@ template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_1(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
-    __shared__ double lds[5 * K];
-    double acc[K];
-    double beta[K], omega[K];
-    bool act[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        acc[k] = 0.0;
-        const double* s = scp(S, chid, k);
-        beta[k] = s[SC_BETA];
-        omega[k] = s[SC_OMEGA];
-        act[k] = s[SC_ACT] != 0.0;
+    const int k = (int)blockIdx.y;
+    const double* sk = scp(S, chid, k);
+    if (sk[SC_ACT] == 0.0) {
+        zero_partials_at<1>(S, tile, k);
+        return;
     }
+    __shared__ double lds[5];
+    double acc[1] = {0.0};
+    const T bk = (T)sk[SC_BETA], om = (T)sk[SC_OMEGA];
+    const T* z = V.r[k];
+    const T* po = V.p[par][k];
+    const T* wo = V.v[par][k];
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!act[k]) continue;
-            const T* z = V.r[k];
-            const T* po = V.p[par][k];
-            const T* wo = V.v[par][k];
-            const T bk = (T)beta[k], om = (T)omega[k];
-            auto pn = [&](int64_t g) { return z[g] + bk * (po[g] - om * wo[g]); };
-            const T vn = op.apply(k, C, P, pn);
-            V.p[par ^ 1][k][P.g] = pn(P.g);
-            V.v[par ^ 1][k][P.g] = vn / op.diag(k, P.g);
-            acc[k] += (double)V.rh[k][P.g] * (double)vn;
-        }
+        auto pn = [&](int64_t g) { return z[g] + bk * (po[g] - om * wo[g]); };
+        const T vn = op.apply(k, C, P, pn);
+        V.p[par ^ 1][k][P.g] = pn(P.g);
+        V.v[par ^ 1][k][P.g] = vn / op.diag(k, P.g);
+        acc[0] += (double)V.rh[k][P.g] * (double)vn;
     CLOT_END_CELLS
-    store_partials<K>(acc, S.part, S.pstride, tile, lds);
+    store_partials_at<1>(acc, S, tile, k, lds);
 }
 
 // D^-1 s = z - alpha D^-1 v; t = A D^-1 s; t.s, t.t with s = D (D^-1 s)
@@ -509,34 +512,27 @@ template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_2(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
-    __shared__ double lds[5 * 2 * K];
-    double acc[2 * K];
-    double alpha[K];
-    bool act[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        acc[2 * k] = acc[2 * k + 1] = 0.0;
-        const double* s = scp(S, chid, k);
-        alpha[k] = s[SC_ALPHA];
-        act[k] = s[SC_ACT] != 0.0;
+    const int k = (int)blockIdx.y;
+    const double* sk = scp(S, chid, k);
+    if (sk[SC_ACT] == 0.0) {
+        zero_partials_at<2>(S, tile, 2 * k);
+        return;
     }
+    __shared__ double lds[5 * 2];
+    double acc[2] = {0.0, 0.0};
+    const T a = (T)sk[SC_ALPHA];
+    const T* z = V.r[k];
+    const T* wn = V.v[par ^ 1][k];
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!act[k]) continue;
-            const T* z = V.r[k];
-            const T* wn = V.v[par ^ 1][k];
-            const T a = (T)alpha[k];
-            auto sh = [&](int64_t g) { return z[g] - a * wn[g]; };
-            const T t = op.apply(k, C, P, sh);
-            const T sv = op.diag(k, P.g) * sh(P.g);
-            V.t[k][P.g] = t;
-            acc[2 * k] += (double)t * (double)sv;
-            acc[2 * k + 1] += (double)t * (double)t;
-        }
+        auto sh = [&](int64_t g) { return z[g] - a * wn[g]; };
+        const T t = op.apply(k, C, P, sh);
+        const T sv = op.diag(k, P.g) * sh(P.g);
+        V.t[k][P.g] = t;
+        acc[0] += (double)t * (double)sv;
+        acc[1] += (double)t * (double)t;
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
+    store_partials_at<2>(acc, S, tile, 2 * k, lds);
 }
 
 // x += alpha D^-1 p + omega D^-1 s; r = s - omega t; z = D^-1 r; rhat.r, r.r
@@ -544,34 +540,26 @@ template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_bicg_3(Grid G, Op op, KVec<T, K> V, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
-    __shared__ double lds[5 * 2 * K];
-    double acc[2 * K];
-    double alpha[K], omega[K];
-    bool act[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        acc[2 * k] = acc[2 * k + 1] = 0.0;
-        const double* s = scp(S, chid, k);
-        alpha[k] = s[SC_ALPHA];
-        omega[k] = s[SC_OMEGA];
-        act[k] = s[SC_ACT] != 0.0;
+    const int k = (int)blockIdx.y;
+    const double* sk = scp(S, chid, k);
+    if (sk[SC_ACT] == 0.0) {
+        zero_partials_at<2>(S, tile, 2 * k);
+        return;
     }
+    __shared__ double lds[5 * 2];
+    double acc[2] = {0.0, 0.0};
+    const T a = (T)sk[SC_ALPHA], om = (T)sk[SC_OMEGA];
     CLOT_FOR_CELLS(local)
         const int64_t g = C.c0 + local;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!act[k]) continue;
-            const T a = (T)alpha[k], om = (T)omega[k];
-            const T d = op.diag(k, g);
-            const T sh = V.r[k][g] - a * V.v[par ^ 1][k][g];
-            V.x[k][g] += a * V.p[par ^ 1][k][g] + om * sh;
-            const T r = d * sh - om * V.t[k][g];
-            V.r[k][g] = r / d;
-            acc[2 * k] += (double)V.rh[k][g] * (double)r;
-            acc[2 * k + 1] += (double)r * (double)r;
-        }
+        const T d = op.diag(k, g);
+        const T sh = V.r[k][g] - a * V.v[par ^ 1][k][g];
+        V.x[k][g] += a * V.p[par ^ 1][k][g] + om * sh;
+        const T r = d * sh - om * V.t[k][g];
+        V.r[k][g] = r / d;
+        acc[0] += (double)V.rh[k][g] * (double)r;
+        acc[1] += (double)r * (double)r;
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
+    store_partials_at<2>(acc, S, tile, 2 * k, lds);
 }
 
 }  // namespace clot
