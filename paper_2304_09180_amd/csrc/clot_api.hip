@@ -422,6 +422,7 @@ struct Ctx : clot_ctx {
         S.part = cv.take<double>((size_t)ntiles * NPART);
         S.pstride = ntiles;
         S.tick = cv.take<uint32_t>(nch);
+        S.fin = cv.take<double>((size_t)nch * FIN_MAXNV);
         refmask = cv.take<int32_t>(nch);
         sigw = cv.take<double>((size_t)nch * NHIST);
         push = cv.take<int32_t>((size_t)nch * 2);
@@ -436,6 +437,8 @@ struct Ctx : clot_ctx {
         Se.part = cv.take<double>((size_t)ntiles * NPART);
         Se.pstride = ntiles;
         Se.nanflag = nanflag;
+        Se.tick = cv.take<uint32_t>(nch);
+        Se.fin = cv.take<double>((size_t)nch * FIN_MAXNV);
         for (int q = 0; q < 5; ++q) eta_v[q] = cv.take<T>(N);
         eta_info = cv.take<int32_t>(2);
         mg_y0 = cv.take<T>(N);
@@ -901,6 +904,7 @@ struct Ctx : clot_ctx {
         if (r) return r;
         std::vector<uint32_t> z(nch, 0);
         HIPCHK(hipMemcpy(S.tick, z.data(), nch * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(Se.tick, z.data(), nch * 4, hipMemcpyHostToDevice));
         std::vector<double> zs((size_t)nch * NSTAT, 0.0);
         HIPCHK(hipMemcpy(dstats, zs.data(), zs.size() * 8, hipMemcpyHostToDevice));
         return CLOT_OK;
@@ -1378,7 +1382,7 @@ struct Ctx : clot_ctx {
 
     template <int NV, class E>
     void finish(const E& e) {
-        hipLaunchKernelGGL((k_finish<NV, E>), dim3((int)ch.size()), dim3(FIN_BS), 0, st, d_ch, S, e);
+        hipLaunchKernelGGL((k_finish<NV, E>), dim3((int)ch.size(), FinSplit<NV>::G), dim3(FIN_BS), 0, st, d_ch, S, e);
     }
 
     // Pressure preconditioner setup: coarse operators from the current rAU.

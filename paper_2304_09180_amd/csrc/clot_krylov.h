@@ -32,7 +32,8 @@ struct KState {
     int32_t* chact;      // [nch] 1 while any system of the channel iterates
     int32_t* nact;       // global count of active channels
     double* part;        // [ntiles][NV]
-    uint32_t* tick;      // unused (kept for layout stability)
+    uint32_t* tick;      // [nch] arrival tickets of a split finishing launch (0 between launches)
+    double* fin;         // [nch][FIN_MAXNV] its per-component totals
     int32_t* nanflag;    // set to 1 when a NaN or infinity reaches any reduction
     int32_t maxit;
     int32_t sc_ch0;      // channel whose slots sc starts at (0: the whole table)
@@ -86,62 +87,121 @@ template <class E>
 struct epi_has_refmask<E, std::void_t<decltype(std::declval<E>().refmask)>> : std::true_type {};
 
 // Sums the tile partials of each active channel (fixed order) and runs the phase
-// epilogue in thread 0.  One 1024-thread block per channel.
+// epilogue in thread 0.  1024-thread blocks, blockIdx.x the channel.  A reduction of
+// more than three values is spread over several blocks per channel (blockIdx.y, two
+// components each: one CU's read rate bounds a block, 14 values took 13.9 us in one):
+// each block writes its totals, and the last to arrive (a ticket per channel; the
+// fence costs little here, the kernel writing only those totals) runs the epilogue on
+// all of them.  Each component is summed in the same order either way (a thread's
+// tiles in increasing order, then the block's waves), so the totals are the same.
 constexpr int FIN_BS = 1024;
+constexpr int FIN_MAXNV = 32;
+template <int NV>
+struct FinSplit {
+    static constexpr int CPG = NV <= 3 ? NV : 2;            // components per block
+    static constexpr int G = (NV + CPG - 1) / CPG;          // blocks per channel
+};
+
+// The epilogue of one channel in thread 0, on its scalar slots staged in LDS (scl), or,
+// when a NaN or infinity reached the sums, the channel's failure.
+template <int NV, class Epi>
+__device__ inline void finish_epilogue(const KState& S, const Epi& epi, int chid, const double (&acc)[NV],
+                                       double* scl) {
+    KState SL = S;
+    SL.sc = scl;
+    SL.sc_ch0 = chid;
+    bool finite = true;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) finite = finite && isfinite(acc[q]);
+    if (finite) {
+        epi(acc, SL, chid);
+    } else {
+        // a NaN or infinity reached the reductions: the channel's systems stop,
+        // marked failed (2), and the channel leaves the solve (and the active
+        // count, unless this phase would have admitted it) and any further
+        // refinement pass
+        for (int k = 0; k < MAXK; ++k) {
+            double* s = scp(SL, chid, k);
+            s[SC_FAIL] = 2.0;
+            s[SC_ACT] = 0.0;
+        }
+        S.chact[chid] = 0;
+        if (!epi_is_init<Epi>::value) atomicSub(S.nact, 1);
+        if constexpr (epi_has_refmask<Epi>::value) epi.refmask[chid] = 0;
+        if (S.nanflag) S.nanflag[0] = 1;
+    }
+}
+
 template <int NV, class Epi>
 __global__ __launch_bounds__(FIN_BS) void k_finish(const ChanDev* chans, KState S, Epi epi) {
+    using FS = FinSplit<NV>;
+    constexpr int CPG = FS::CPG;
     const int chid = blockIdx.x;
     if (!S.chact[chid]) return;
     const int32_t t0 = chans[chid].t0, nt = chans[chid].nt;
-    __shared__ double lds[NV * (FIN_BS / 64 + 1)];
+    const int q0 = FS::G > 1 ? (int)blockIdx.y * CPG : 0;
+    __shared__ double lds[CPG * (FIN_BS / 64 + 1)];
     // the channel's scalar slots, staged in LDS by all threads so that the epilogue
     // (one thread, system after system) does not wait on memory for each of them
     __shared__ double scl[MAXK * NSC];
     double* scg = S.sc + (int64_t)chid * MAXK * NSC;
-    for (int q = threadIdx.x; q < MAXK * NSC; q += FIN_BS) scl[q] = scg[q];
-    double acc[NV];
+    if (FS::G == 1)
+        for (int q = threadIdx.x; q < MAXK * NSC; q += FIN_BS) scl[q] = scg[q];
+    double acc[CPG];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    // U tiles per thread in flight at once (fewer for wide reductions, to bound registers)
-    constexpr int U = NV <= 8 ? 4 : NV <= 16 ? 2 : 1;
+    for (int q = 0; q < CPG; ++q) acc[q] = 0.0;
+    // U tiles per thread in flight at once
+    constexpr int U = 4;
     for (int tb = threadIdx.x; tb < nt; tb += U * FIN_BS) {
-        double v[U][NV];
+        double v[U][CPG];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = tb + u * FIN_BS;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) v[u][q] = t < nt ? S.part[(int64_t)q * S.pstride + t0 + t] : 0.0;
+            for (int q = 0; q < CPG; ++q)
+                v[u][q] = (t < nt && q0 + q < NV) ? S.part[(int64_t)(q0 + q) * S.pstride + t0 + t] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int q = 0; q < NV; ++q) acc[q] += v[u][q];
+            for (int q = 0; q < CPG; ++q) acc[q] += v[u][q];
     }
-    block_sum<NV, FIN_BS>(acc, lds);   // its barriers also publish scl
-    if (threadIdx.x == 0) {
-        KState SL = S;
-        SL.sc = scl;
-        SL.sc_ch0 = chid;
-        bool finite = true;
+    block_sum<CPG, FIN_BS>(acc, lds);   // its barriers also publish scl
+    if (FS::G == 1) {
+        if (threadIdx.x == 0) {
+            double all[NV];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) finite = finite && isfinite(acc[q]);
-        if (finite) {
-            epi(acc, SL, chid);
-        } else {
-            // a NaN or infinity reached the reductions: the channel's systems stop,
-            // marked failed (2), and the channel leaves the solve (and the active
-            // count, unless this phase would have admitted it) and any further
-            // refinement pass
-            for (int k = 0; k < MAXK; ++k) {
-                double* s = scp(SL, chid, k);
-                s[SC_FAIL] = 2.0;
-                s[SC_ACT] = 0.0;
-            }
-            S.chact[chid] = 0;
-            if (!epi_is_init<Epi>::value) atomicSub(S.nact, 1);
-            if constexpr (epi_has_refmask<Epi>::value) epi.refmask[chid] = 0;
-            if (S.nanflag) S.nanflag[0] = 1;
+            for (int q = 0; q < NV; ++q) all[q] = acc[q];
+            finish_epilogue<NV>(S, epi, chid, all, scl);
         }
+        __syncthreads();
+        for (int q = threadIdx.x; q < MAXK * NSC; q += FIN_BS) scg[q] = scl[q];
+        return;
+    }
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        double* tot = S.fin + (int64_t)chid * FIN_MAXNV;
+#pragma unroll
+        for (int q = 0; q < CPG; ++q)
+            if (q0 + q < NV) tot[q0 + q] = acc[q];
+        __threadfence();
+        const unsigned tk = atomicAdd(&S.tick[chid], 1u);
+        last = tk == (unsigned)(FS::G - 1);
+        if (last) {
+            S.tick[chid] = 0u;
+            __threadfence();
+        }
+    }
+    __syncthreads();
+    if (!last) return;
+    for (int q = threadIdx.x; q < MAXK * NSC; q += FIN_BS) scl[q] = scg[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double* tot = S.fin + (int64_t)chid * FIN_MAXNV;
+        double all[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) all[q] = __hip_atomic_load(tot + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        finish_epilogue<NV>(S, epi, chid, all, scl);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < MAXK * NSC; q += FIN_BS) scg[q] = scl[q];
