@@ -1706,7 +1706,7 @@ struct Ctx : clot_ctx {
             }
             T* pn[MGM_K] = {V.p[par ^ 1][0], V.p[par ^ 1][1], V.p[par ^ 1][2]};
             vcycle_mom<1>(mop, s1, pn, Y);
-            CLOT_LAUNCH(CLOT_PROBE_MOM_B1, (k_pbicg_1<T, 3, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, V,
+            CLOT_LAUNCH(CLOT_PROBE_MOM_B1, (k_pbicg_1<T, 3, MomOp<T>>), dim3(ntiles, 3), dim3(NT), 0, st, grid(), mop, V,
                         cv3(Y), S, par);
             finish<3>(EpiBicg1<3>{});
             MGSrc<T> s2{};
@@ -1715,10 +1715,10 @@ struct Ctx : clot_ctx {
                 s2.v[k] = V.v[par ^ 1][k];
             }
             vcycle_mom<2>(mop, s2, Sv, Z);
-            CLOT_LAUNCH(CLOT_PROBE_MOM_B2, (k_pbicg_2<T, 3, MomOp<T>>), dim3(ntiles), dim3(NT), 0, st, grid(), mop, V,
+            CLOT_LAUNCH(CLOT_PROBE_MOM_B2, (k_pbicg_2<T, 3, MomOp<T>>), dim3(ntiles, 3), dim3(NT), 0, st, grid(), mop, V,
                         cv3(Z), cv3(Sv), S);
             finish<6>(EpiBicg2<3>{});
-            CLOT_LAUNCH(CLOT_PROBE_MOM_B3, (k_pbicg_3<T, 3>), dim3(ntiles), dim3(NT), 0, st, grid(), V, cv3(Y), cv3(Z),
+            CLOT_LAUNCH(CLOT_PROBE_MOM_B3, (k_pbicg_3<T, 3>), dim3(ntiles, 3), dim3(NT), 0, st, grid(), V, cv3(Y), cv3(Z),
                         cv3(Sv), S);
             finish<6>(EpiBicg3<3>{});
         });

@@ -509,30 +509,26 @@ __global__ __launch_bounds__(NT) void k_mgm_brick(BrickGrid BG, MGPair L, MomOp<
 // y = M^-1 p and z = M^-1 s come from the V-cycles; the phases apply A to them.
 
 // v = A y; rhat . v
+// One component per grid row (blockIdx.y), as the Jacobi BiCGStab's phases.
 template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_pbicg_1(Grid G, Op op, KVec<T, K> V, MGCVec<T> y, KState S, int par) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
-    __shared__ double lds[5 * K];
-    double acc[K];
-    bool act[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        acc[k] = 0.0;
-        act[k] = scp(S, chid, k)[SC_ACT] != 0.0;
+    const int k = (int)blockIdx.y;
+    if (scp(S, chid, k)[SC_ACT] == 0.0) {
+        zero_partials_at<1>(S, tile, k);
+        return;
     }
+    __shared__ double lds[5];
+    double acc[1] = {0.0};
+    const T* yk = y.v[k];
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!act[k]) continue;
-            const T* yk = y.v[k];
-            const T vn = op.apply(k, C, P, [&](int64_t g) { return yk[g]; });
-            V.v[par ^ 1][k][P.g] = vn;
-            acc[k] += (double)V.rh[k][P.g] * (double)vn;
-        }
+        const T vn = op.apply(k, C, P, [&](int64_t g) { return yk[g]; });
+        V.v[par ^ 1][k][P.g] = vn;
+        acc[0] += (double)V.rh[k][P.g] * (double)vn;
     CLOT_END_CELLS
-    store_partials<K>(acc, S.part, S.pstride, tile, lds);
+    store_partials_at<1>(acc, S, tile, k, lds);
 }
 
 // t = A z; t.s, t.t
@@ -540,28 +536,23 @@ template <class T, int K, class Op>
 __global__ __launch_bounds__(NT) void k_pbicg_2(Grid G, Op op, KVec<T, K> V, MGCVec<T> z, MGCVec<T> s, KState S) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
-    __shared__ double lds[5 * 2 * K];
-    double acc[2 * K];
-    bool act[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        acc[2 * k] = acc[2 * k + 1] = 0.0;
-        act[k] = scp(S, chid, k)[SC_ACT] != 0.0;
+    const int k = (int)blockIdx.y;
+    if (scp(S, chid, k)[SC_ACT] == 0.0) {
+        zero_partials_at<2>(S, tile, 2 * k);
+        return;
     }
+    __shared__ double lds[5 * 2];
+    double acc[2] = {0.0, 0.0};
+    const T* zk = z.v[k];
     CLOT_FOR_CELLS(local)
         const Cell P = cell_at(C, local);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!act[k]) continue;
-            const T* zk = z.v[k];
-            const T t = op.apply(k, C, P, [&](int64_t g) { return zk[g]; });
-            V.t[k][P.g] = t;
-            const T sv = s.v[k][P.g];
-            acc[2 * k] += (double)t * (double)sv;
-            acc[2 * k + 1] += (double)t * (double)t;
-        }
+        const T t = op.apply(k, C, P, [&](int64_t g) { return zk[g]; });
+        V.t[k][P.g] = t;
+        const T sv = s.v[k][P.g];
+        acc[0] += (double)t * (double)sv;
+        acc[1] += (double)t * (double)t;
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
+    store_partials_at<2>(acc, S, tile, 2 * k, lds);
 }
 
 // x += alpha y + omega z; r = s - omega t; rhat.r, r.r
@@ -570,33 +561,25 @@ __global__ __launch_bounds__(NT) void k_pbicg_3(Grid G, KVec<T, K> V, MGCVec<T> 
                                                 KState S) {
     CLOT_TILE_PROLOGUE(G)
     if (!S.chact[chid]) return;
-    __shared__ double lds[5 * 2 * K];
-    double acc[2 * K];
-    double alpha[K], omega[K];
-    bool act[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        acc[2 * k] = acc[2 * k + 1] = 0.0;
-        const double* sc = scp(S, chid, k);
-        alpha[k] = sc[SC_ALPHA];
-        omega[k] = sc[SC_OMEGA];
-        act[k] = sc[SC_ACT] != 0.0;
+    const int k = (int)blockIdx.y;
+    const double* sc = scp(S, chid, k);
+    if (sc[SC_ACT] == 0.0) {
+        zero_partials_at<2>(S, tile, 2 * k);
+        return;
     }
+    __shared__ double lds[5 * 2];
+    double acc[2] = {0.0, 0.0};
+    const T a = (T)sc[SC_ALPHA], om = (T)sc[SC_OMEGA];
     CLOT_FOR_CELLS(local)
         const int64_t g = C.c0 + local;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!act[k]) continue;
-            const T a = (T)alpha[k], om = (T)omega[k];
-            const T sv = s.v[k][g];
-            V.x[k][g] += a * y.v[k][g] + om * z.v[k][g];
-            const T r = sv - om * V.t[k][g];
-            V.r[k][g] = r;
-            acc[2 * k] += (double)V.rh[k][g] * (double)r;
-            acc[2 * k + 1] += (double)r * (double)r;
-        }
+        const T sv = s.v[k][g];
+        V.x[k][g] += a * y.v[k][g] + om * z.v[k][g];
+        const T r = sv - om * V.t[k][g];
+        V.r[k][g] = r;
+        acc[0] += (double)V.rh[k][g] * (double)r;
+        acc[1] += (double)r * (double)r;
     CLOT_END_CELLS
-    store_partials<2 * K>(acc, S.part, S.pstride, tile, lds);
+    store_partials_at<2>(acc, S, tile, 2 * k, lds);
 }
 
 }  // namespace clot
