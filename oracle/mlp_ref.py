@@ -51,3 +51,32 @@ def bf16_round(a):
 def bf16_bits(a):
     u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
     return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def forward_stored(w, x, q=bf16_round):
+    """The forward with the values a bf16 implementation stores rounded by q: each hidden
+    activation is rounded after its tanh before it feeds the next layer (the weights and
+    inputs are the caller's, already rounded as the implementation holds them); all
+    arithmetic in FP64.  With q the identity this is `forward`."""
+    p = unpack(w)
+    x = np.asarray(x, dtype=np.float64)
+    h1 = q(np.tanh(x @ p["W1"].T + p["b1"]))
+    h2 = q(np.tanh(h1 @ p["W2"].T + p["b2"]))
+    y = h2 @ p["W3"].T + p["b3"]
+    return y, (x, h1, h2)
+
+
+def backward_stored(w, cache, dy, q=bf16_round):
+    """`backward` with the values a bf16 implementation stores rounded by q: the incoming
+    dy and each layer's delta are rounded before they enter a product or a bias sum (the
+    activations come rounded in the cache of `forward_stored`).  With q the identity this
+    is `backward`."""
+    p = unpack(w)
+    x, h1, h2 = cache
+    d3 = q(np.asarray(dy, dtype=np.float64))
+    g = {"W3": d3.T @ h2, "b3": d3.sum(0)}
+    d2 = q((d3 @ p["W3"]) * (1 - h2 ** 2))
+    g["W2"], g["b2"] = d2.T @ h1, d2.sum(0)
+    d1 = q((d2 @ p["W2"]) * (1 - h1 ** 2))
+    g["W1"], g["b1"] = d1.T @ x, d1.sum(0)
+    return np.concatenate([g[name].ravel() for name, _ in SHAPES])

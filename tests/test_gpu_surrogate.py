@@ -64,15 +64,25 @@ def test_mlp_forward_and_backward_match_fp64_reference():
     clot.check(lib.clot_mlp_backward(clot.ptr(wf), clot.ptr(wb), clot.ptr(xt), clot.ptr(cache), clot.ptr(dyt), n,
                                      clot.ptr(part), clot.ptr(dw), st), "bwd")
     torch.cuda.synchronize()
+    # the plain FP64 network (bf16 weights and inputs as given), and the same network with
+    # the values the kernels store in bf16 rounded there (activations, dy, layer deltas)
     y_ref, c_ref = mlp_ref.forward(wq, x)
-    g_ref = mlp_ref.backward(wq, c_ref, mlp_ref.bf16_round(dy))
+    g_ref = mlp_ref.backward(wq, c_ref, dy)
+    y_st, c_st = mlp_ref.forward_stored(wq, x)
+    g_st = mlp_ref.backward_stored(wq, c_st, dy)
     yg = y.cpu().numpy().astype(np.float64)
-    assert np.linalg.norm(yg - y_ref) / np.linalg.norm(y_ref) < 1e-2
+    e_plain = np.linalg.norm(yg - y_ref) / np.linalg.norm(y_ref)
+    e_st = np.linalg.norm(yg - y_st) / np.linalg.norm(y_st)
+    print(f"forward rel l2: plain {e_plain:.2e} stored-precision {e_st:.2e}", flush=True)
+    assert e_plain < 1e-2 and e_st < 2e-4
     gg = dw.cpu().numpy().astype(np.float64)
     for name, lo, hi in (("W1", 0, 2048), ("W2", 2112, 6208), ("W3", 6272, 7296), ("b1", 2048, 2112),
                          ("b2", 6208, 6272), ("b3", 7296, 7312)):
         err = np.linalg.norm(gg[lo:hi] - g_ref[lo:hi]) / np.linalg.norm(g_ref[lo:hi])
-        assert err < 2e-2, (name, err)
+        err_st = np.linalg.norm(gg[lo:hi] - g_st[lo:hi]) / np.linalg.norm(g_st[lo:hi])
+        print(f"{name} gradient rel l2: plain {err:.2e} stored-precision {err_st:.2e}", flush=True)
+        assert err < 1e-2, (name, err)
+        assert err_st < 5e-4, (name, err_st)
 
 
 @pytest.fixture(scope="module")
