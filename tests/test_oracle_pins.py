@@ -706,3 +706,40 @@ def test_limiter_linear_profile_is_central_on_reversed_flow():
     for i in range(0, 6):       # faces i|i+1 with a far-upwind cell i+2
         assert M[i, i + 1] == pytest.approx(-1e-6 * 0.5 - D * A / d, rel=1e-12)
         assert M[i + 1, i] == pytest.approx(1e-6 * 0.5 - D * A / d, rel=1e-12)
+
+
+@pytest.mark.parametrize("dims", [(2, 8, 4, 1), (3, 4, 4, 4)])
+def test_every_assembled_system_is_solved_to_the_dense_direct_solution(monkeypatch, dims):
+    """Linear algebra (pin S9): on 8x4 and 4x4x4 channels every system two oracle steps
+    assemble (momentum per component, pressure per corrector, eta, the seven transport
+    systems) is solved by the Krylov route the oracle takes on large grids (forced here:
+    Jacobi CG or BiCGStab to 1e-13) and by a dense direct solve of the same matrix; the
+    two agree to 1e-11, and the step goes on with the dense solution."""
+    import oracle.clot_oracle as oc
+    real = oc.linear_solver
+    seen = []
+
+    def both(M, spd, direct_max=oc.DIRECT_MAX):
+        krylov = real(M, spd, direct_max=0)
+        dense = M.toarray()
+
+        def run(b, x0=None):
+            xk = krylov(b, x0)
+            xd = np.linalg.solve(dense, b)
+            scale = max(float(np.linalg.norm(xd)), 1e-300)
+            seen.append((spd, M.shape[0], float(np.linalg.norm(xk - xd)) / scale))
+            return xd
+        return run
+
+    monkeypatch.setattr(oc, "linear_solver", both)
+    dim, nx, ny, nz = dims
+    d = ci.channel(dim, nx, ny, nz, shear=1000.0, dt=1e-4, seed=17)
+    o = oc.Oracle(d, *ci.noise(d))
+    for _ in range(2):
+        o.step()
+    ncorr = o.n_correctors()
+    per_step = dim + ncorr + 1 + 7          # momentum components, correctors, eta, transport
+    assert len(seen) == 2 * per_step, (len(seen), per_step)
+    assert sum(1 for spd, _, _ in seen if spd) == 2 * (ncorr + 1)
+    worst = max(e for _, _, e in seen)
+    assert worst <= 1e-11, worst
