@@ -15,7 +15,10 @@ differences between meshes are spatial errors only.
 
     python -m paper_2304_09180_amd.meshconv --h 3 1.5 0.75 0.375 --dt 4e-6 --seconds 0.25
 
-Progress goes to stderr; the result is one JSON line on stdout.
+Progress goes to stderr; the result is one JSON line on stdout.  A long study can span
+several processes: --max-steps stops after that many steps of this call and --save writes
+the context's state (a checkpoint), which --load resumes; the result is printed by the
+call that reaches the horizon.
 """
 from __future__ import annotations
 
@@ -88,6 +91,9 @@ def main(argv=None):
     ap.add_argument("--seconds", type=float, default=0.25)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--chunk", type=int, default=2500, help="steps per library call")
+    ap.add_argument("--max-steps", type=int, default=0, help="stop after this many steps of this call (0: none)")
+    ap.add_argument("--load", default=None, help="resume from this saved state (.npy)")
+    ap.add_argument("--save", default=None, help="save the state here (.npy) when this call stops")
     args = ap.parse_args(argv)
 
     import torch  # noqa: F401  (the library shares torch's HIP runtime)
@@ -101,15 +107,25 @@ def main(argv=None):
         n = d["nx"] * d["ny"]
         s.init_state(i, np.zeros((15, n)), np.zeros((2, s.count(i, "E0"))))
     nsteps = int(round(args.seconds / args.dt))
-    wall0 = time.perf_counter()
     done = 0
-    while done < nsteps:
-        k = min(args.chunk, nsteps - done)
+    if args.load:
+        s.load_state(np.load(args.load))
+        done = int(s.stats(len(descs) - 1)["steps"])
+    stop = nsteps if args.max_steps <= 0 else min(nsteps, done + args.max_steps)
+    wall0 = time.perf_counter()
+    while done < stop:
+        k = min(args.chunk, stop - done)
         s.step(k)
         done += k
         st = s.stats(len(descs) - 1)
         print(json.dumps({"steps": done, "t": st["t"], "status": st["status"], "it_p": st["it_p"][:2],
                           "wall_s": round(time.perf_counter() - wall0, 1)}), file=sys.stderr, flush=True)
+    if args.save:
+        np.save(args.save, s.save_state())
+    if done < nsteps:
+        print(json.dumps({"stopped_at": done, "of": nsteps, "saved": args.save}), flush=True)
+        s.close()
+        return 0
     sols = []
     for i, d in enumerate(descs):
         sols.append({n: s.get(i, n).reshape(d["ny"], d["nx"]) for n in ("S1", "E1", "PMU", "E2", "E2B")})

@@ -20,3 +20,20 @@ def test_mesh_convergence_driver_runs_and_reports_finite_errors(capsys):
         e = res["quantities"][q]["errors"]
         assert len(e) == 2 and all(np.isfinite(x) and x >= 0.0 for x in e), (q, e)
         assert np.isfinite(res["quantities"][q]["rate"])
+
+
+def test_mesh_convergence_study_resumes_from_a_checkpoint(tmp_path, capsys):
+    """A study split over two calls (stop after 50 steps, save; load, finish) reports the
+    same errors, bit for bit, as one call of 100 steps."""
+    from paper_2304_09180_amd import meshconv
+    base = ["--h", "3", "1.5", "0.75", "--dt", "4e-6", "--seconds", "4e-4", "--chunk", "25"]
+    assert meshconv.main(base) == 0
+    whole = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    ck = str(tmp_path / "state.npy")
+    assert meshconv.main(base + ["--max-steps", "50", "--save", ck]) == 0
+    first = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert first["stopped_at"] == 50 and first["of"] == 100
+    assert meshconv.main(base + ["--load", ck]) == 0
+    rest = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert rest["steps"] == 100 and rest["status"] == ["OK", "OK", "OK"]
+    assert rest["quantities"] == whole["quantities"]
