@@ -1231,10 +1231,11 @@ struct Ctx : clot_ctx {
     void fill(int32_t* p, int32_t v, int64_t n) {
         hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
     }
-    void set_active(const int32_t* mask) {
-        const int nch = (int)ch.size();
-        hipLaunchKernelGGL(k_copy<int32_t>, dim3((nch + 255) / 256), dim3(256), 0, st, S.chact, mask, (int64_t)nch);
-        fill(S.nact, 0, 1);
+    // chact = mask with the active count zero (count = false: the solve's start admits its
+    // channels) or the mask's count (count = true).
+    void set_active(const int32_t* mask, bool count = false) {
+        hipLaunchKernelGGL(k_set_active, dim3(1), dim3(256), 0, st, S.chact, mask, S.nact, (int)ch.size(),
+                           count ? 1 : 0);
     }
 
     // The iterations of one solve.  Eagerly: chunks of iterations, polling the count of
@@ -1804,9 +1805,7 @@ struct Ctx : clot_ctx {
             CLOT_LAUNCH(CLOT_PROBE_PRHS, k_prhs<T>, gb, tb, 0, st, G, F, M, cm);
             if (k == 0 && eta_side) HIPCHK(hipStreamWaitEvent(st, ev_mg, 0));
             // FP64 iterative refinement around a T-precision MG-PCG
-            set_active(cm);
-            // count of active channels for the residual kernel
-            hipLaunchKernelGGL(k_count_active, dim3(1), dim3(64), 0, st, S.chact, S.nact, nch);
+            set_active(cm, true);    // with the count of active channels for the residual kernel
             T* e = pool[5];
             T* rin = pool[0];
             PresOp<T, T> pop{F.rAU, F.dP};
@@ -1822,8 +1821,7 @@ struct Ctx : clot_ctx {
                 run_mgcg(V, 0.0, 1, refmask, 1 + std::min(k, 2), pass);
                 record(ST_P + std::min(k, MAXCORR - 1), ST_RESP, 1, pass > 0, refmask);
                 hipLaunchKernelGGL(k_pres_add<T>, gb, tb, 0, st, G, F, e, refmask);
-                set_active(refmask);
-                hipLaunchKernelGGL(k_count_active, dim3(1), dim3(64), 0, st, S.chact, S.nact, nch);
+                set_active(refmask, true);
             }
             if (capturing) {   // a channel still needing refinement after the last pass
                 CLOT_LAUNCH(CLOT_PROBE_P_RESID, k_pres_resid<T>, gb, tb, 0, st, G, F, rin, e, S);

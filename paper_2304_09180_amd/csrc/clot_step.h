@@ -792,10 +792,15 @@ __global__ __launch_bounds__(NT) void k_nonfinite_scan(Grid G, Fields<T> F, int6
 }
 
 // Driver bookkeeping kernels (graph-safe replacements for memset and host reads).
-__global__ void k_count_active(const int32_t* chact, int32_t* nact, int nch) {
+// chact = mask, and the active count: zero (a solve's start admits its channels) or, with
+// count, the number of channels the mask admits.  One block.
+__global__ __launch_bounds__(256) void k_set_active(int32_t* chact, const int32_t* mask, int32_t* nact, int nch,
+                                                    int count) {
+    for (int c = threadIdx.x; c < nch; c += 256) chact[c] = mask[c];
     if (threadIdx.x == 0) {
         int s = 0;
-        for (int c = 0; c < nch; ++c) s += chact[c] != 0;
+        if (count)
+            for (int c = 0; c < nch; ++c) s += mask[c] != 0;
         *nact = s;
     }
 }
