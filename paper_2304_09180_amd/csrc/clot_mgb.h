@@ -1,5 +1,7 @@
-// LDS-staged multi-sweep bricks for the coarse levels of the pressure multigrid
-// (gfx950, FP32 contexts).
+// Pressure multigrid legs in bricks (gfx950): the LDS-staged multi-sweep legs of the
+// coarse levels (FP32 contexts), and, at the end of the file, the mesh's restriction and
+// prolongation sweep for meshes that every channel coarsens along every axis (both
+// precisions).
 //
 // Above the fused tail, each coarse level's legs are six separate launches (first two
 // sweeps, the other sweeps, restriction; prolongation sweep, the other sweeps), each
