@@ -109,7 +109,7 @@ def parse():
     ap.add_argument("--no-brick-tune", action="store_true",
                     help="keep the default brick shape of the LDS-staged momentum kernels")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-reaction comparison")
-    ap.add_argument("--train-samples", type=int, default=400_000)
+    ap.add_argument("--train-samples", type=int, default=1_000_000)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-inhibitor", action="store_true",
                     help="skip the leg of the model with the inhibitor (section 3.4)")

@@ -206,12 +206,12 @@ class Trainer:
 
 
 def default_training_states(log=print):
-    """States from the 64x16 workload (100 steps at 1e-4 s) and a 1024x256 channel
-    (300 steps at 1e-5 s)."""
+    """States from the two 2-D workloads over their whole horizons: the 64x16 channel
+    (100 steps at 1e-4 s) and the 1024x256 channel (1000 steps at 1e-5 s)."""
     import clot_inputs as ci
     d1 = ci.workload("channel2d_64x16")
     d2 = ci.workload("channel2d_1024x256")
-    return collect_states([(d1, d1["steps"]), (d2, 300)], log=log)
+    return collect_states([(d1, d1["steps"]), (d2, d2["steps"])], log=log)
 
 
 def train_default(n_samples=1_000_000, epochs=12, log=print):
