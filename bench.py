@@ -329,7 +329,7 @@ def ensemble_leg(args):
     if tuned:
         out["autotune"] = {"ms_per_step": tuned["ms_per_step"], "kernel_us": tuned["kernel_us"]}
     if bricks:
-        out.setdefault("autotune", {})["bricks"] = {k: bricks[k] for k in ("restrict", "prolong", "sweep", "us")}
+        out.setdefault("autotune", {})["bricks"] = {k: bricks[k] for k in (*autotune.BRICK_PROBES, "us")}
     for mode in ("eager", "graph"):
         s = clot.Solver(descs, clot.FP32_MIXED, tile=tile)
         if bricks:
@@ -422,7 +422,7 @@ def main():
     if tuned:
         out["autotune"] = {"ms_per_step": tuned["ms_per_step"], "kernel_us": tuned["kernel_us"]}
     if bricks:
-        out.setdefault("autotune", {})["bricks"] = {k: bricks[k] for k in ("restrict", "prolong", "sweep", "us")}
+        out.setdefault("autotune", {})["bricks"] = {k: bricks[k] for k in (*autotune.BRICK_PROBES, "us")}
     s.close()
     if not args.no_time_scheme:
         out["time_scheme"] = time_scheme_leg(desc, prec, args, xc, xf, tile)

@@ -290,24 +290,33 @@ clot_status clot_set_graph_mode(clot_ctx* c, int32_t on, double budget_scale, in
  * of graphs of about 1500 nodes each).  info: 20 entries. */
 clot_status clot_graph_info(clot_ctx* c, int64_t* info);
 
-/* Tile shapes of the LDS-staged finest-level kernels of the momentum preconditioner
- * (a block owns a brick of 1024 cells and stages it with a one-cell halo in LDS).  The
- * tile autotuner times each kernel in each shape and sets its choice; shape 0 is the
- * default of every kernel.  Shapes (BX x BY x BZ cells): 3-D 32x8x4, 16x16x4, 32x4x8,
- * 16x8x8; 2-D 64x16, 128x8, 32x32, 256x4 (one shape index names one of each).
- * Contexts with a channel that has fewer than three cells on an axis do not use the
- * bricked kernels; the call still records the choice. */
+/* Tile shapes of the LDS-staged kernels: the finest-level kernels of the momentum
+ * preconditioner (a block owns a brick of 1024 cells and stages it with a one-cell halo
+ * in LDS) and the legs of the pressure hierarchy's coarse levels (a brick of 1024 cells
+ * with a halo of one cell per sweep; FP32 contexts, see mg_brick).  The tile autotuner
+ * times each kernel in each shape and sets its choice; shape 0 is the default of every
+ * kernel, and every shape gives the same step bit for bit.  Shapes (BX x BY x BZ cells),
+ * one shape index naming a 3-D and a 2-D shape: momentum 3-D 32x8x4, 16x16x4, 32x4x8,
+ * 16x8x8, 2-D 64x16, 128x8, 32x32, 256x4; pressure legs 3-D 16x8x8, 32x8x4, 8x8x16,
+ * 16x16x4, 2-D 64x16, 128x8, 32x32, 256x4.  Contexts that do not run a bricked kernel
+ * still record the choice. */
 typedef enum {
-    CLOT_BRICK_RESTRICT = 0,   /* residual restriction with the formed right-hand side */
-    CLOT_BRICK_PROLONG = 1,    /* prolongation + smoothing sweep                        */
-    CLOT_BRICK_SWEEP = 2,      /* the last smoothing sweep                              */
-    CLOT_NBRICK_KERNELS = 3
+    CLOT_BRICK_RESTRICT = 0,   /* momentum: residual restriction with the formed right-hand side */
+    CLOT_BRICK_PROLONG = 1,    /* momentum: prolongation + smoothing sweep                        */
+    CLOT_BRICK_SWEEP = 2,      /* momentum: the last smoothing sweep                              */
+    CLOT_BRICK_P_DOWN = 3,     /* pressure: a coarse level's sweeps and restriction               */
+    CLOT_BRICK_P_UP = 4,       /* pressure: a coarse level's prolongation and sweeps              */
+    CLOT_NBRICK_KERNELS = 5
 } clot_brick_kernel;
 /* kernel in [0, CLOT_NBRICK_KERNELS), shape in [0, 4), else CLOT_EINVAL.  Recorded
  * graphs are dropped (re-recorded at the next step in graph mode). */
 clot_status clot_set_brick_shape(clot_ctx* c, int32_t kernel, int32_t shape);
-/* dims[0..2] = BX, BY, BZ of shape for channels of dimension dim (2 or 3). */
+/* dims[0..2] = BX, BY, BZ of a momentum kernel's shape for channels of dimension dim
+ * (2 or 3). */
 clot_status clot_brick_dims(int32_t dim, int32_t shape, int32_t* dims);
+/* dims[0..2] = BX, BY, BZ of the shape of the given bricked kernel (clot_brick_kernel)
+ * for channels of dimension dim; CLOT_EINVAL for an invalid kernel, dim or shape. */
+clot_status clot_brick_kernel_dims(int32_t kernel, int32_t dim, int32_t shape, int32_t* dims);
 
 /* Kernel-phase timing probe.  While a phase is selected, every launch of it is
  * bracketed by HIP events on the context stream; clot_probe_read synchronises,
@@ -338,6 +347,7 @@ typedef enum {
     CLOT_PROBE_MOM_MG_P1 = 21,  /* momentum V-cycle: prolongation + finest-level sweep     */
     CLOT_PROBE_MOM_MG_P2 = 22,  /* momentum V-cycle: last finest-level sweep               */
     CLOT_PROBE_P_MG_DOWN = 23,  /* pressure multigrid, bricked: a coarse level's down leg   */
+    CLOT_PROBE_P_MG_UP = 24,    /* pressure multigrid, bricked: a coarse level's up leg     */
     CLOT_PROBE_NKERNELS
 } clot_probe_kernel;
 clot_status clot_probe(clot_ctx* c, int32_t kernel);

@@ -141,12 +141,16 @@ def tune(descs, precision, candidates=clot.TILES, steps=5, warmup=3, repeats=3, 
     return entry
 
 
-BRICK_PROBES = {"restrict": "mom_mg_r", "prolong": "mom_mg_p1", "sweep": "mom_mg_p2"}
+# each bricked kernel and the probe that times it: the momentum preconditioner's finest
+# level, and the pressure hierarchy's LDS-staged coarse-level legs (FP32 contexts)
+BRICK_PROBES = {"restrict": "mom_mg_r", "prolong": "mom_mg_p1", "sweep": "mom_mg_p2", "p_down": "p_mg_down",
+                "p_up": "p_mg_up"}
 
 
 def tune_bricks(descs, precision, tile=clot.TILES[0], steps=4, warmup=3, cache=None, force=False, log=None):
-    """Brick shape of each LDS-staged momentum kernel for this workload: from the cache,
-    or measured (average launch time of the kernel in each shape) and stored."""
+    """Brick shape of each LDS-staged kernel for this workload: from the cache, or
+    measured (average launch time of the kernel in each shape) and stored.  A kernel the
+    workload does not run keeps shape 0."""
     path = cache or default_cache_path()
     key = cache_key(descs, precision, arch_name()) + f"|tile{tile}|bricks"
     if not force:
@@ -171,8 +175,12 @@ def tune_bricks(descs, precision, tile=clot.TILES[0], steps=4, warmup=3, cache=N
                 s.probe(None)
                 us[kernel][shape] = 1e3 * ms / nl if nl else float("inf")
                 if log:
-                    log(f"# autotune {key} {kernel} shape {shape} {clot.brick_dims(descs[0]['dim'], shape)}: "
+                    log(f"# autotune {key} {kernel} shape {shape} {clot.brick_dims(descs[0]['dim'], shape, kernel)}: "
                         f"{us[kernel][shape]:.2f} us over {nl} launches")
+                if not nl:      # not run by this workload
+                    for q in range(shape + 1, clot.N_BRICK_SHAPES):
+                        us[kernel][q] = float("inf")
+                    break
             s.set_brick_shape(kernel, 0)
     finally:
         s.close()

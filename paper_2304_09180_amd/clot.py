@@ -121,6 +121,7 @@ def load(tile: int = 256, inhibitor: bool = False):
         "clot_graph_info": ([P, C.POINTER(C.c_int64)], C.c_int),
         "clot_set_brick_shape": ([P, C.c_int32, C.c_int32], C.c_int),
         "clot_brick_dims": ([C.c_int32, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+        "clot_brick_kernel_dims": ([C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "clot_mlp_nparam": ([], C.c_int64),
         "clot_mlp_backward_workspace": ([C.c_int64], C.c_size_t),
         "clot_mlp_forward": ([P, P, P, C.c_int64, P, P, P], C.c_int),
@@ -157,26 +158,27 @@ def exported_symbols():
             "clot_mlp_adam", "clot_mlp_mse", "clot_rxn_rk4_batch", "clot_surr_dataset", "clot_mfma_selftest",
             "clot_cell_species", "clot_tile_cells", "clot_set_graph_mode", "clot_graph_info", "clot_state_size",
             "clot_save_state", "clot_load_state", "clot_mlp_backward_noalloc", "clot_set_brick_shape",
-            "clot_brick_dims"]
+            "clot_brick_dims", "clot_brick_kernel_dims"]
 
 
-BRICK_KERNELS = {"restrict": 0, "prolong": 1, "sweep": 2}
+BRICK_KERNELS = {"restrict": 0, "prolong": 1, "sweep": 2, "p_down": 3, "p_up": 4}
 N_BRICK_SHAPES = 4
 
 
-def brick_dims(dim, shape):
-    """(BX, BY, BZ) of a brick shape for channels of dimension dim."""
+def brick_dims(dim, shape, kernel="restrict"):
+    """(BX, BY, BZ) of a bricked kernel's shape for channels of dimension dim."""
+    k = BRICK_KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     v = (C.c_int32 * 3)()
-    st = load().clot_brick_dims(int(dim), int(shape), v)
+    st = load().clot_brick_kernel_dims(k, int(dim), int(shape), v)
     if st != 0:
-        raise ClotError(f"brick_dims({dim}, {shape}): status {st}")
+        raise ClotError(f"brick_dims({dim}, {shape}, {kernel}): status {st}")
     return tuple(v)
 
 
 PROBES = {"p_cg_a": 1, "p_cg_b": 2, "tr_b1": 3, "tr_b2": 4, "tr_b3": 5, "mom_b1": 6, "mom_b2": 7, "mom_b3": 8,
           "rxn": 9, "tr_asm": 10, "eta_cg_a": 11, "eta_cg_b": 12, "p_resid": 13, "correct": 14, "hbya": 15,
           "prhs": 16, "mom_asm": 17, "p_mg_post": 18, "rxn_fallback": 19, "mom_mg_r": 20, "mom_mg_p1": 21,
-          "mom_mg_p2": 22, "p_mg_down": 23}
+          "mom_mg_p2": 22, "p_mg_down": 23, "p_mg_up": 24}
 
 
 def default_params(precision=FP64, **over) -> Params:

@@ -221,7 +221,7 @@ struct Ctx : clot_ctx {
     std::vector<int32_t> h_b2c[MGM_NSHAPE];
     BrickChan* d_brick[MGM_NSHAPE] = {};
     int32_t* d_b2c[MGM_NSHAPE] = {};
-    int brick_shape[CLOT_NBRICK_KERNELS] = {};   // per bricked kernel: restriction, prolongation sweep, sweep
+    int brick_shape[CLOT_NBRICK_KERNELS] = {};   // per bricked kernel (clot_brick_kernel)
     BrickGrid bricks(int s) const { return BrickGrid{d_brick[s], d_b2c[s], (int32_t)h_b2c[s].size()}; }
     bool bricked() const { return !h_b2c[0].empty(); }
     // LDS-staged legs of the pressure V-cycle's coarse levels (clot_mgb.h).  Table j >= 1:
@@ -229,10 +229,11 @@ struct Ctx : clot_ctx {
     // coarsened along every axis there (table 0, the mesh, stays empty).  The tables
     // depend on the geometry only; mgb_use (mg_brick, FP32, 2 or 3 sweeps) decides
     // whether they are used.
-    std::vector<BrickChan> h_pbr[MG_MAXLEV];
-    std::vector<int32_t> h_pb2c[MG_MAXLEV];
-    BrickChan* d_pbr[MG_MAXLEV] = {};
-    int32_t* d_pb2c[MG_MAXLEV] = {};
+    // One set of tables per brick shape.
+    std::vector<BrickChan> h_pbr[MGB_NSHAPE][MG_MAXLEV];
+    std::vector<int32_t> h_pb2c[MGB_NSHAPE][MG_MAXLEV];
+    BrickChan* d_pbr[MGB_NSHAPE][MG_MAXLEV] = {};
+    int32_t* d_pb2c[MGB_NSHAPE][MG_MAXLEV] = {};
     bool mgb_use = false;
     // The mesh's restriction in bricks of shape 0 (k_mg_restrict_mesh) and its
     // prolongation by halving (k_mg_post1_mesh): when every channel is coarsened along
@@ -243,8 +244,8 @@ struct Ctx : clot_ctx {
     int32_t* d_rb2c = nullptr;
     bool mesh_on = false;
     bool mesh_halves() const { return mesh_on && !h_rb2c.empty(); }
-    BrickGrid pbricks(int j) const { return BrickGrid{d_pbr[j], d_pb2c[j], (int32_t)h_pb2c[j].size()}; }
-    bool pbricked(int j) const { return mgb_use && !h_pb2c[j].empty(); }
+    BrickGrid pbricks(int q, int j) const { return BrickGrid{d_pbr[q][j], d_pb2c[q][j], (int32_t)h_pb2c[q][j].size()}; }
+    bool pbricked(int j) const { return mgb_use && !h_pb2c[0][j].empty(); }
     // reaction surrogate
     clot_rxn_mode rxn_mode = CLOT_RXN_PLAIN;
     float surr_tol = 1e-3f;
@@ -462,10 +463,11 @@ struct Ctx : clot_ctx {
             L.cz = cv.take<T>(L.NFZ);
         }
         d_mgm_last = cv.take<int32_t>(nch);
-        for (int j = 0; j < MG_MAXLEV; ++j) {
-            d_pbr[j] = cv.take<BrickChan>(std::max<size_t>(h_pbr[j].size(), 1));
-            d_pb2c[j] = cv.take<int32_t>(std::max<size_t>(h_pb2c[j].size(), 1));
-        }
+        for (int q = 0; q < MGB_NSHAPE; ++q)
+            for (int j = 0; j < MG_MAXLEV; ++j) {
+                d_pbr[q][j] = cv.take<BrickChan>(std::max<size_t>(h_pbr[q][j].size(), 1));
+                d_pb2c[q][j] = cv.take<int32_t>(std::max<size_t>(h_pb2c[q][j].size(), 1));
+            }
         d_rbr = cv.take<BrickChan>(std::max<size_t>(h_rbr.size(), 1));
         d_rb2c = cv.take<int32_t>(std::max<size_t>(h_rb2c.size(), 1));
         for (int q = 0; q < MGM_NSHAPE; ++q) {
@@ -687,10 +689,11 @@ struct Ctx : clot_ctx {
         // coarsens along every axis
         {
             const int nl = (int)lev.size();
-            for (int j = 0; j < MG_MAXLEV; ++j) {
-                h_pbr[j].clear();
-                h_pb2c[j].clear();
-            }
+            for (int q = 0; q < MGB_NSHAPE; ++q)
+                for (int j = 0; j < MG_MAXLEV; ++j) {
+                    h_pbr[q][j].clear();
+                    h_pb2c[q][j].clear();
+                }
             for (int j = 1; j < nl && j < MG_MAXLEV; ++j) {
                 bool ok = true;
                 for (int i = 0; ok && i < nch; ++i) {
@@ -699,15 +702,17 @@ struct Ctx : clot_ctx {
                     ok = c.nx != f.nx && c.ny != f.ny && (c.dim == 2 || c.nz != f.nz);
                 }
                 if (!ok) continue;
-                for (int i = 0; i < nch; ++i) {
-                    const int dim = lev[j].ch[i].dim;
-                    const int fx = lev[j - 1].ch[i].nx, fy = lev[j - 1].ch[i].ny, fz = lev[j - 1].ch[i].nz;
-                    int bx, by, bz;
-                    pbrick_dims(dim, bx, by, bz);
-                    BrickChan b{(int32_t)h_pb2c[j].size(), (fx + bx - 1) / bx, (fy + by - 1) / by, (fz + bz - 1) / bz};
-                    for (int t = 0; t < b.nbx * b.nby * b.nbz; ++t) h_pb2c[j].push_back(i);
-                    h_pbr[j].push_back(b);
-                }
+                for (int q = 0; q < MGB_NSHAPE; ++q)
+                    for (int i = 0; i < nch; ++i) {
+                        const int dim = lev[j].ch[i].dim;
+                        const int fx = lev[j - 1].ch[i].nx, fy = lev[j - 1].ch[i].ny, fz = lev[j - 1].ch[i].nz;
+                        int bx, by, bz;
+                        pbrick_dims(dim, q, bx, by, bz);
+                        BrickChan b{(int32_t)h_pb2c[q][j].size(), (fx + bx - 1) / bx, (fy + by - 1) / by,
+                                    (fz + bz - 1) / bz};
+                        for (int t = 0; t < b.nbx * b.nby * b.nbz; ++t) h_pb2c[q][j].push_back(i);
+                        h_pbr[q][j].push_back(b);
+                    }
             }
             mgb_use = p->mg_brick != 0 && sizeof(T) == 4 && (prm.mg_sweeps == 2 || prm.mg_sweeps == 3);
             mesh_on = p->mg_brick != 0;
@@ -755,14 +760,26 @@ struct Ctx : clot_ctx {
         };
         if (mg_t0 >= 0) attr(reinterpret_cast<const void*>(&k_mg_tail<T>), mg_tail_lds);
         if (mgb_use) {
-            const size_t by = mgb_lds_bytes(prm.mg_sweeps, sizeof(T));
-            if (prm.mg_sweeps == 3) {
-                attr(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_DOWN, 3>), by);
-                attr(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_UP, 3>), by);
+            const int h = prm.mg_sweeps;
+            auto both = [&](const void* down, const void* up, int q) {
+                attr(down, mgb_lds_bytes(h, q, sizeof(T)));
+                attr(up, mgb_lds_bytes(h, q, sizeof(T)));
+            };
+#define CLOT_MGB_ATTR(H, Q)                                                          \
+    both(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_DOWN, H, Q>),              \
+         reinterpret_cast<const void*>(&k_mg_brick<T, MGB_UP, H, Q>), Q)
+            if (h == 3) {
+                CLOT_MGB_ATTR(3, 0);
+                CLOT_MGB_ATTR(3, 1);
+                CLOT_MGB_ATTR(3, 2);
+                CLOT_MGB_ATTR(3, 3);
             } else {
-                attr(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_DOWN, 2>), by);
-                attr(reinterpret_cast<const void*>(&k_mg_brick<T, MGB_UP, 2>), by);
+                CLOT_MGB_ATTR(2, 0);
+                CLOT_MGB_ATTR(2, 1);
+                CLOT_MGB_ATTR(2, 2);
+                CLOT_MGB_ATTR(2, 3);
             }
+#undef CLOT_MGB_ATTR
         }
         if (!set) {
             err = "cannot raise the dynamic LDS limit of the multigrid kernels";
@@ -879,12 +896,14 @@ struct Ctx : clot_ctx {
             HIPCHK(hipMemcpyAsync(d_rbr, h_rbr.data(), h_rbr.size() * sizeof(BrickChan), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(d_rb2c, h_rb2c.data(), h_rb2c.size() * 4, hipMemcpyHostToDevice, st));
         }
-        for (int j = 0; j < MG_MAXLEV; ++j)
-            if (!h_pb2c[j].empty()) {
-                HIPCHK(hipMemcpyAsync(d_pbr[j], h_pbr[j].data(), h_pbr[j].size() * sizeof(BrickChan),
-                                      hipMemcpyHostToDevice, st));
-                HIPCHK(hipMemcpyAsync(d_pb2c[j], h_pb2c[j].data(), h_pb2c[j].size() * 4, hipMemcpyHostToDevice, st));
-            }
+        for (int q = 0; q < MGB_NSHAPE; ++q)
+            for (int j = 0; j < MG_MAXLEV; ++j)
+                if (!h_pb2c[q][j].empty()) {
+                    HIPCHK(hipMemcpyAsync(d_pbr[q][j], h_pbr[q][j].data(), h_pbr[q][j].size() * sizeof(BrickChan),
+                                          hipMemcpyHostToDevice, st));
+                    HIPCHK(hipMemcpyAsync(d_pb2c[q][j], h_pb2c[q][j].data(), h_pb2c[q][j].size() * 4,
+                                          hipMemcpyHostToDevice, st));
+                }
         for (int q = 0; q < MGM_NSHAPE; ++q)
             if (!h_b2c[q].empty()) {
                 HIPCHK(hipMemcpyAsync(d_brick[q], h_brick[q].data(), h_brick[q].size() * sizeof(BrickChan),
@@ -1523,7 +1542,7 @@ struct Ctx : clot_ctx {
             Level& L = lev[l];
             CoefOp<T> op{L.dg, L.cx, L.cy, L.cz};
             if (pbricked(l + 1)) {
-                mgb_launch<MGB_UP>(l + 1, CLOT_PROBE_OFF, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, pre_end[l],
+                mgb_launch<MGB_UP>(l + 1, CLOT_PROBE_P_MG_UP, MGPair{L.grid(), lev[l + 1].grid()}, op, L.b, pre_end[l],
                                    lev[l + 1].x, L.x, nullptr);
                 continue;
             }
@@ -1543,18 +1562,31 @@ struct Ctx : clot_ctx {
         finish<1>(EpiMgDot{});
     }
 
-    // One LDS-staged leg of the pressure V-cycle on the coarse level of brick table j.
+    // One LDS-staged leg of the pressure V-cycle on the coarse level of brick table j, in
+    // the brick shape chosen for that leg.
     template <int MODE>
     void mgb_launch(int j, int probe, const MGPair& pr, const CoefOp<T>& op, const T* b, const T* xin, const T* xc,
                     T* xout, T* bc) {
-        const dim3 gd((unsigned)h_pb2c[j].size());
-        const size_t lds = mgb_lds_bytes(prm.mg_sweeps, sizeof(T));
-        if (prm.mg_sweeps == 3)
-            CLOT_LAUNCH(probe, (k_mg_brick<T, MODE, 3>), gd, dim3(MGB_BS), lds, st, pbricks(j), pr, op, b, xin, xc, xout,
-                        bc, mg_w, (const int32_t*)S.chact);
-        else
-            CLOT_LAUNCH(probe, (k_mg_brick<T, MODE, 2>), gd, dim3(MGB_BS), lds, st, pbricks(j), pr, op, b, xin, xc, xout,
-                        bc, mg_w, (const int32_t*)S.chact);
+        const int q = brick_shape[MODE == MGB_DOWN ? CLOT_BRICK_P_DOWN : CLOT_BRICK_P_UP];
+        const dim3 gd((unsigned)h_pb2c[q][j].size());
+        const int h = prm.mg_sweeps;
+        const size_t lds = mgb_lds_bytes(h, q, sizeof(T));
+        const BrickGrid bg = pbricks(q, j);
+        const int32_t* act = S.chact;
+#define CLOT_MGB(H, Q)                                                                                              \
+    CLOT_LAUNCH(probe, (k_mg_brick<T, MODE, H, Q>), gd, dim3(MGB_BS), lds, st, bg, pr, op, b, xin, xc, xout, bc, mg_w, \
+                act)
+        switch (h * 4 + q) {
+            case 8: CLOT_MGB(2, 0); break;
+            case 9: CLOT_MGB(2, 1); break;
+            case 10: CLOT_MGB(2, 2); break;
+            case 11: CLOT_MGB(2, 3); break;
+            case 12: CLOT_MGB(3, 0); break;
+            case 13: CLOT_MGB(3, 1); break;
+            case 14: CLOT_MGB(3, 2); break;
+            default: CLOT_MGB(3, 3); break;
+        }
+#undef CLOT_MGB
     }
 
     // Multigrid-preconditioned CG on the pressure correction.
@@ -2113,8 +2145,9 @@ struct Ctx : clot_ctx {
     }
 
     clot_status set_brick(int kernel, int shape) override {
+        static_assert(MGM_NSHAPE == 4 && MGB_NSHAPE == 4, "four shapes per bricked kernel");
         if (kernel < 0 || kernel >= CLOT_NBRICK_KERNELS || shape < 0 || shape >= MGM_NSHAPE) {
-            err = "set_brick_shape: kernel in [0, 3), shape in [0, 4)";
+            err = "set_brick_shape: kernel in [0, 5), shape in [0, 4)";
             return CLOT_EINVAL;
         }
         HIPCHK(hipStreamSynchronize(st));
@@ -2729,14 +2762,22 @@ clot_status clot_set_brick_shape(clot_ctx* c, int32_t kernel, int32_t shape) {
     if (!c) return CLOT_EINVAL;
     return c->set_brick(kernel, shape);
 }
-clot_status clot_brick_dims(int32_t dim, int32_t shape, int32_t* dims) {
-    if (!dims || (dim != 2 && dim != 3) || shape < 0 || shape >= MGM_NSHAPE) return CLOT_EINVAL;
+clot_status clot_brick_kernel_dims(int32_t kernel, int32_t dim, int32_t shape, int32_t* dims) {
+    if (!dims || (dim != 2 && dim != 3) || shape < 0 || shape >= MGM_NSHAPE || kernel < 0 ||
+        kernel >= CLOT_NBRICK_KERNELS)
+        return CLOT_EINVAL;
     int bx, by, bz;
-    brick_dims(dim, shape, bx, by, bz);
+    if (kernel == CLOT_BRICK_P_DOWN || kernel == CLOT_BRICK_P_UP)
+        pbrick_dims(dim, shape, bx, by, bz);
+    else
+        brick_dims(dim, shape, bx, by, bz);
     dims[0] = bx;
     dims[1] = by;
     dims[2] = bz;
     return CLOT_OK;
+}
+clot_status clot_brick_dims(int32_t dim, int32_t shape, int32_t* dims) {
+    return clot_brick_kernel_dims(CLOT_BRICK_RESTRICT, dim, shape, dims);
 }
 void clot_destroy(clot_ctx* c) { delete c; }
 const char* clot_last_error(const clot_ctx* c) {

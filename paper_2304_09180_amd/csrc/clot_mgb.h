@@ -32,32 +32,51 @@ namespace clot {
 enum { MGB_DOWN = 0, MGB_UP = 1 };
 constexpr int MGB_BS = 1024;
 
-template <int DIM, int H>
+// Brick shapes, chosen per leg by the tile autotuner (one shape index covers a 3-D and a
+// 2-D shape; every dimension even, so aggregates never straddle bricks): 3-D 16x8x8,
+// 32x8x4, 8x8x16, 16x16x4; 2-D 64x16, 128x8, 32x32, 256x4.
+constexpr int MGB_NSHAPE = 4;
+__host__ __device__ constexpr int pb_dim(int dim, int shape, int axis) {
+    return dim == 3 ? (shape == 0 ? (axis == 0 ? 16 : 8)
+                       : shape == 1 ? (axis == 0 ? 32 : axis == 1 ? 8 : 4)
+                       : shape == 2 ? (axis == 2 ? 16 : 8)
+                                    : (axis == 2 ? 4 : 16))
+                    : (axis == 2 ? 1
+                       : shape == 0 ? (axis == 0 ? 64 : 16)
+                       : shape == 1 ? (axis == 0 ? 128 : 8)
+                       : shape == 2 ? 32
+                                    : (axis == 0 ? 256 : 4));
+}
+template <int DIM, int H, int SHAPE>
 struct PBrick {
-    static constexpr int BX = DIM == 3 ? 16 : 64, BY = DIM == 3 ? 8 : 16, BZ = DIM == 3 ? 8 : 1;
+    static constexpr int BX = pb_dim(DIM, SHAPE, 0), BY = pb_dim(DIM, SHAPE, 1), BZ = pb_dim(DIM, SHAPE, 2);
     static constexpr int EX = BX + 2 * H, EY = BY + 2 * H, EZ = DIM == 3 ? BZ + 2 * H : 1;
     static constexpr int NE = EX * EY * EZ;
     static_assert(BX * BY * BZ == MGB_BS, "one own cell per thread");
+    static_assert(BX % 2 == 0 && BY % 2 == 0 && (DIM == 2 || BZ % 2 == 0), "whole aggregates");
 };
-inline void pbrick_dims(int dim, int& bx, int& by, int& bz) {
-    bx = dim == 3 ? 16 : 64;
-    by = dim == 3 ? 8 : 16;
-    bz = dim == 3 ? 8 : 1;
+inline void pbrick_dims(int dim, int shape, int& bx, int& by, int& bz) {
+    bx = pb_dim(dim, shape, 0);
+    by = pb_dim(dim, shape, 1);
+    bz = pb_dim(dim, shape, 2);
 }
-// LDS elements per array (the larger of the 2-D and 3-D bricks) and the bytes of the
-// seven arrays: b, the diagonal, two iterates, the three face-coefficient arrays.
-__host__ __device__ constexpr int mgb_ne(int h) {
-    return (16 + 2 * h) * (8 + 2 * h) * (8 + 2 * h) > (64 + 2 * h) * (16 + 2 * h)
-               ? (16 + 2 * h) * (8 + 2 * h) * (8 + 2 * h)
-               : (64 + 2 * h) * (16 + 2 * h);
+// LDS elements per array (the larger of the shape's 2-D and 3-D bricks) and the bytes
+// of the seven arrays: b, the diagonal, two iterates, the three face-coefficient arrays.
+__host__ __device__ constexpr int mgb_ne(int h, int shape) {
+    return (pb_dim(3, shape, 0) + 2 * h) * (pb_dim(3, shape, 1) + 2 * h) * (pb_dim(3, shape, 2) + 2 * h) >
+                   (pb_dim(2, shape, 0) + 2 * h) * (pb_dim(2, shape, 1) + 2 * h)
+               ? (pb_dim(3, shape, 0) + 2 * h) * (pb_dim(3, shape, 1) + 2 * h) * (pb_dim(3, shape, 2) + 2 * h)
+               : (pb_dim(2, shape, 0) + 2 * h) * (pb_dim(2, shape, 1) + 2 * h);
 }
-__host__ __device__ constexpr size_t mgb_lds_bytes(int h, size_t tsize) { return 7 * (size_t)mgb_ne(h) * tsize; }
+__host__ __device__ constexpr size_t mgb_lds_bytes(int h, int shape, size_t tsize) {
+    return 7 * (size_t)mgb_ne(h, shape) * tsize;
+}
 
-template <class T, int MODE, int H, int DIM>
+template <class T, int MODE, int H, int SHAPE, int DIM>
 __device__ inline void mgb_body(const ChanDev& C, const ChanDev& Cc, int bx, int by, int bz, const CoefOp<T>& op,
                                 const T* b, const T* xin, const T* xc, T* xout, T* bc, T w, T* sm) {
-    using D = PBrick<DIM, H>;
-    constexpr int NE = mgb_ne(H);
+    using D = PBrick<DIM, H, SHAPE>;
+    constexpr int NE = mgb_ne(H, SHAPE);
     T* const sb = sm;
     T* const sd = sm + NE;
     T* s0 = sm + 2 * NE;
@@ -163,7 +182,7 @@ __device__ inline void mgb_body(const ChanDev& C, const ChanDev& Cc, int bx, int
     }
 }
 
-template <class T, int MODE, int H>
+template <class T, int MODE, int H, int SHAPE>
 __global__ __launch_bounds__(MGB_BS) void k_mg_brick(BrickGrid BG, MGPair L, CoefOp<T> op, const T* b, const T* xin,
                                                      const T* xc, T* xout, T* bc, T w, const int32_t* chact) {
     const int32_t bk = xcd_tile((int32_t)blockIdx.x, BG.nb);
@@ -177,9 +196,9 @@ __global__ __launch_bounds__(MGB_BS) void k_mg_brick(BrickGrid BG, MGPair L, Coe
     extern __shared__ __align__(16) unsigned char mgb_lds[];
     T* const sm = reinterpret_cast<T*>(mgb_lds);
     if (C.dim == 3)
-        mgb_body<T, MODE, H, 3>(C, Cc, bx, by, bz, op, b, xin, xc, xout, bc, w, sm);
+        mgb_body<T, MODE, H, SHAPE, 3>(C, Cc, bx, by, bz, op, b, xin, xc, xout, bc, w, sm);
     else
-        mgb_body<T, MODE, H, 2>(C, Cc, bx, by, bz, op, b, xin, xc, xout, bc, w, sm);
+        mgb_body<T, MODE, H, SHAPE, 2>(C, Cc, bx, by, bz, op, b, xin, xc, xout, bc, w, sm);
 }
 
 }  // namespace clot

@@ -129,11 +129,15 @@ def test_multigrid_sweep_count_is_checked_without_gpu():
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libclot.so not built")
 def test_brick_shapes_without_gpu():
     from paper_2304_09180_amd import clot
-    for dim in (2, 3):
-        for q in range(clot.N_BRICK_SHAPES):
-            bx, by, bz = clot.brick_dims(dim, q)
-            assert bx * by * bz == 1024 and (dim == 3 or bz == 1)
+    for kernel in clot.BRICK_KERNELS:
+        for dim in (2, 3):
+            for q in range(clot.N_BRICK_SHAPES):
+                bx, by, bz = clot.brick_dims(dim, q, kernel)
+                assert bx * by * bz == 1024 and (dim == 3 or bz == 1)
+                assert bx % 2 == 0 and by % 2 == 0 and (dim == 2 or bz % 2 == 0)   # whole aggregates
+    assert clot.brick_dims(3, 0, "p_down") == (16, 8, 8) and clot.brick_dims(3, 0) == (32, 8, 4)
     lib = clot.load()
     v = (ctypes.c_int32 * 3)()
     assert lib.clot_brick_dims(3, 4, v) == -1 and lib.clot_brick_dims(1, 0, v) == -1
+    assert lib.clot_brick_kernel_dims(5, 3, 0, v) == -1 and lib.clot_brick_kernel_dims(-1, 3, 0, v) == -1
     assert lib.clot_set_brick_shape(None, 0, 0) == -1

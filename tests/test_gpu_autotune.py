@@ -54,10 +54,12 @@ def test_autotune_stores_and_reuses_its_choice(tmp_path):
 
 @pytest.mark.parametrize("precision", ["FP32_MIXED", "FP64"])
 def test_brick_shapes_give_bit_identical_steps(precision):
-    """Every brick shape of the LDS-staged momentum kernels computes each cell with the
-    same expression and adds each aggregate in the same order, so a step is the same
-    bit for bit in every shape.  Odd extents: partial bricks on every axis and
-    single-cell aggregates at the far faces."""
+    """Every brick shape of the LDS-staged kernels (the momentum preconditioner's finest
+    level; in FP32 also the pressure hierarchy's coarse-level legs, here two sweeps each
+    way on both channels' first coarse level) computes each cell with the same
+    expression and adds each aggregate in the same order, so a step is the same bit for
+    bit in every shape.  Odd extents: partial bricks on every axis and single-cell
+    aggregates at the far faces."""
     from paper_2304_09180_amd import clot
     prec = getattr(clot, precision)
     descs = [ci.channel(2, 201, 73, shear=400.0, seed=7), ci.channel(3, 41, 21, 19, shear=900.0, seed=8)]
