@@ -244,6 +244,13 @@ struct Ctx : clot_ctx {
     int32_t* d_rb2c = nullptr;
     bool mesh_on = false;
     bool mesh_halves() const { return mesh_on && !h_rb2c.empty(); }
+    // The mesh's three down sweeps in one launch (k_mg_pre3_mesh), bricks of the pressure
+    // shape 0: FP32 contexts with three sweeps each way and mg_brick set.
+    std::vector<BrickChan> h_p3br;
+    std::vector<int32_t> h_p3b2c;
+    BrickChan* d_p3br = nullptr;
+    int32_t* d_p3b2c = nullptr;
+    bool mesh_pre3() const { return !h_p3b2c.empty(); }
     BrickGrid pbricks(int q, int j) const { return BrickGrid{d_pbr[q][j], d_pb2c[q][j], (int32_t)h_pb2c[q][j].size()}; }
     bool pbricked(int j) const { return mgb_use && !h_pb2c[0][j].empty(); }
     // reaction surrogate
@@ -470,6 +477,8 @@ struct Ctx : clot_ctx {
             }
         d_rbr = cv.take<BrickChan>(std::max<size_t>(h_rbr.size(), 1));
         d_rb2c = cv.take<int32_t>(std::max<size_t>(h_rb2c.size(), 1));
+        d_p3br = cv.take<BrickChan>(std::max<size_t>(h_p3br.size(), 1));
+        d_p3b2c = cv.take<int32_t>(std::max<size_t>(h_p3b2c.size(), 1));
         for (int q = 0; q < MGM_NSHAPE; ++q) {
             d_brick[q] = cv.take<BrickChan>(std::max<size_t>(h_brick[q].size(), 1));
             d_b2c[q] = cv.take<int32_t>(std::max<size_t>(h_b2c[q].size(), 1));
@@ -731,6 +740,18 @@ struct Ctx : clot_ctx {
                 for (int t = 0; t < b.nbx * b.nby * b.nbz; ++t) h_rb2c.push_back(i);
                 h_rbr.push_back(b);
             }
+            h_p3br.clear();
+            h_p3b2c.clear();
+            if (p->mg_brick != 0 && sizeof(T) == 4 && prm.mg_sweeps == 3 && nl > 0)
+                for (int i = 0; i < nch; ++i) {
+                    const clot_channel& d = ch[i].d;
+                    int bx, by, bz;
+                    pbrick_dims(d.dim, 0, bx, by, bz);
+                    BrickChan b{(int32_t)h_p3b2c.size(), (d.nx + bx - 1) / bx, (d.ny + by - 1) / by,
+                                (d.nz + bz - 1) / bz};
+                    for (int t = 0; t < b.nbx * b.nby * b.nbz; ++t) h_p3b2c.push_back(i);
+                    h_p3br.push_back(b);
+                }
         }
         const clot_params& q = *p;
         M = ModelDev{q.nu, q.C_CK, q.D_P, q.D_ADP, q.D_chem, q.P_diam, q.P_max, q.P_0, q.k_adh, q.kcoh_Pmax,
@@ -759,6 +780,7 @@ struct Ctx : clot_ctx {
                 set = set && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
         };
         if (mg_t0 >= 0) attr(reinterpret_cast<const void*>(&k_mg_tail<T>), mg_tail_lds);
+        if (mesh_pre3()) attr(reinterpret_cast<const void*>(&k_mg_pre3_mesh<T>), mesh_pre3_lds_bytes(sizeof(T)));
         if (mgb_use) {
             const int h = prm.mg_sweeps;
             auto both = [&](const void* down, const void* up, int q) {
@@ -895,6 +917,10 @@ struct Ctx : clot_ctx {
         if (!h_rb2c.empty()) {
             HIPCHK(hipMemcpyAsync(d_rbr, h_rbr.data(), h_rbr.size() * sizeof(BrickChan), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(d_rb2c, h_rb2c.data(), h_rb2c.size() * 4, hipMemcpyHostToDevice, st));
+        }
+        if (mesh_pre3()) {
+            HIPCHK(hipMemcpyAsync(d_p3br, h_p3br.data(), h_p3br.size() * sizeof(BrickChan), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(d_p3b2c, h_p3b2c.data(), h_p3b2c.size() * 4, hipMemcpyHostToDevice, st));
         }
         for (int q = 0; q < MGB_NSHAPE; ++q)
             for (int j = 0; j < MG_MAXLEV; ++j)
@@ -1512,8 +1538,15 @@ struct Ctx : clot_ctx {
                 cur = nxt;
             }
         };
-        // down (a bricked level leaves its smoothed iterate in Y for its up leg)
-        T* s0 = down(p0, r, mg_z0, mg_y0, grid(), (int)ntiles);
+        // down (a bricked level leaves its smoothed iterate in Y for its up leg; so does the
+        // mesh's fused three sweeps, where the separate launches end too)
+        T* s0 = mg_y0;
+        if (mesh_pre3())
+            CLOT_LAUNCH(CLOT_PROBE_P_MG_PRE3, k_mg_pre3_mesh<T>, dim3((unsigned)h_p3b2c.size()), dim3(MGB_BS),
+                        mesh_pre3_lds_bytes(sizeof(T)), st, BrickGrid{d_p3br, d_p3b2c, (int32_t)h_p3b2c.size()},
+                        grid(), p0, r, mg_y0, mg_w, act);
+        else
+            s0 = down(p0, r, mg_z0, mg_y0, grid(), (int)ntiles);
         if (mesh_halves())
             hipLaunchKernelGGL(k_mg_restrict_mesh<T>, dim3((unsigned)h_rb2c.size()), dim3(NT), 0, st,
                                BrickGrid{d_rbr, d_rb2c, (int32_t)h_rb2c.size()}, MGPair{grid(), lev[0].grid()}, p0, r,

@@ -1,7 +1,7 @@
 // Pressure multigrid legs in bricks (gfx950): the LDS-staged multi-sweep legs of the
 // coarse levels (FP32 contexts), and, at the end of the file, the mesh's restriction and
 // prolongation sweep for meshes that every channel coarsens along every axis (both
-// precisions).
+// precisions) and the mesh's three down sweeps in one launch (FP32 contexts).
 //
 // Above the fused tail, each coarse level's legs are six separate launches (first two
 // sweeps, the other sweeps, restriction; prolongation sweep, the other sweeps), each
@@ -21,9 +21,10 @@
 //   UP:   x1 = x + P xc (injection), then H sweeps; the last is stored.
 //
 // A level is bricked only when every channel is coarsened along every axis there
-// (aggregates never straddle bricks, whose origins are even).  On the mesh the same
-// scheme loses: the staged arrays leave room for one block per CU and the three-cell
-// halo triples the work, against separate launches that are already wide.
+// (aggregates never straddle bricks, whose origins are even).  On the mesh the whole
+// leg loses: the staged arrays leave room for one block per CU and the three-cell halo
+// triples the work, against separate launches that are already wide.  Only the mesh's
+// three down sweeps are staged there (k_mg_pre3_mesh, a two-cell halo, five arrays).
 #pragma once
 #include "clot_mgm.h"
 
@@ -275,6 +276,95 @@ __global__ __launch_bounds__(NT) void k_mg_restrict_mesh(BrickGrid BG, MGPair L,
     else
         mg_restrict_mesh_body<T, 2>(C, Cc, bx, by, bz, op, b, x, bc);
 }
+
+// The mesh's three down sweeps from zero (k_mg_pre's two and one k_mg_post2) as one
+// launch: a 1024-thread block stages a brick of shape 0 with a two-cell halo in LDS
+// (rAU, the diagonal, b and two iterates, 58 KB in FP32): x1 = w D^-1 b in the whole
+// halo, x2 on the brick and a one-cell ring, x3 on the brick, written out.  PresOp's
+// stencil in its order, each value the separate kernels' expression.
+template <class T, int DIM>
+__device__ inline void mesh_pre3_body(const ChanDev& C, int bx, int by, int bz, const PresOp<T, T>& op, const T* b,
+                                      T* xout, T w, T* sm) {
+    constexpr int H = 2;
+    using D = PBrick<DIM, H, 0>;
+    constexpr int NE = mgb_ne(H, 0);
+    T* const sb = sm;
+    T* const sd = sm + NE;
+    T* const sa = sm + 2 * NE;     // rAU
+    T* s0 = sm + 3 * NE;
+    T* s1 = sm + 4 * NE;
+    const int ox = bx * D::BX - H, oy = by * D::BY - H, oz = DIM == 3 ? bz * D::BZ - H : 0;
+    for (int e = threadIdx.x; e < D::NE; e += MGB_BS) {
+        const int ex = e % D::EX, ey = (e / D::EX) % D::EY, ez = DIM == 3 ? e / (D::EX * D::EY) : 0;
+        const int gi = ox + ex, gj = oy + ey, gk = oz + ez;
+        const bool in = gi >= 0 && gi < C.nx && gj >= 0 && gj < C.ny && gk >= 0 && gk < C.nz;
+        T vb = T(0), vd = T(1), va = T(0), vx = T(0);
+        if (in) {
+            const int64_t g = C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk);
+            vb = b[g];
+            vd = op.dP[g];
+            va = op.rAU[g];
+            vx = w * vb / vd;
+        }
+        sb[e] = vb;
+        sd[e] = vd;
+        sa[e] = va;
+        s0[e] = vx;
+    }
+    __syncthreads();
+    constexpr int SY = D::EX, SZ = D::EX * D::EY;
+    const T gxh = T(0.5 * C.gx), gyh = T(0.5 * C.gy), gzh = T(0.5 * C.gz);
+#pragma unroll
+    for (int s = 1; s <= H; ++s) {
+        const int m = H - s;
+        const int RX = D::BX + 2 * m, RY = D::BY + 2 * m, RZ = DIM == 3 ? D::BZ + 2 * m : 1;
+        const int NR = RX * RY * RZ;
+        for (int q = threadIdx.x; q < NR; q += MGB_BS) {
+            const int ex = q % RX + s, ey = (q / RX) % RY + s, ez = DIM == 3 ? q / (RX * RY) + s : 0;
+            const int gi = ox + ex, gj = oy + ey, gk = oz + ez;
+            if (gi < 0 || gi >= C.nx || gj < 0 || gj >= C.ny || gk < 0 || gk >= C.nz) continue;
+            const int e = ex + SY * (ey + D::EY * ez);
+            const T* x = s0;
+            const T rP = sa[e];
+            T sacc = T(0);
+            if (gi > 0) sacc += gxh * (rP + sa[e - 1]) * x[e - 1];
+            if (gi < C.nx - 1) sacc += gxh * (rP + sa[e + 1]) * x[e + 1];
+            if (gj > 0) sacc += gyh * (rP + sa[e - SY]) * x[e - SY];
+            if (gj < C.ny - 1) sacc += gyh * (rP + sa[e + SY]) * x[e + SY];
+            if (DIM == 3) {
+                if (gk > 0) sacc += gzh * (rP + sa[e - SZ]) * x[e - SZ];
+                if (gk < C.nz - 1) sacc += gzh * (rP + sa[e + SZ]) * x[e + SZ];
+            }
+            const T ax = sd[e] * x[e] - sacc;
+            const T z = x[e] + w * (sb[e] - ax) / sd[e];
+            s1[e] = z;
+            if (s == H) xout[C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk)] = z;
+        }
+        __syncthreads();
+        T* t = s0;
+        s0 = s1;
+        s1 = t;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(MGB_BS) void k_mg_pre3_mesh(BrickGrid BG, Grid G, PresOp<T, T> op, const T* b, T* xout,
+                                                         T w, const int32_t* chact) {
+    const int32_t bk = xcd_tile((int32_t)blockIdx.x, BG.nb);
+    const int32_t chid = BG.b2c[bk];
+    if (!chact[chid]) return;
+    const ChanDev C = G.ch[chid];
+    const BrickChan B = BG.bc[chid];
+    const int lb = bk - B.b0;
+    const int bx = lb % B.nbx, by = (lb / B.nbx) % B.nby, bz = lb / (B.nbx * B.nby);
+    extern __shared__ __align__(16) unsigned char mgb_lds[];
+    T* const sm = reinterpret_cast<T*>(mgb_lds);
+    if (C.dim == 3)
+        mesh_pre3_body<T, 3>(C, bx, by, bz, op, b, xout, w, sm);
+    else
+        mesh_pre3_body<T, 2>(C, bx, by, bz, op, b, xout, w, sm);
+}
+constexpr size_t mesh_pre3_lds_bytes(size_t tsize) { return 5 * (size_t)mgb_ne(2, 0) * tsize; }
 
 // Prolongation and the first up sweep on the mesh: x1 = x + P xc, y = x1 + w D^-1 (b -
 // A x1).  k_mg_post1's expressions (PresOp's stencil in its order), with each

@@ -157,17 +157,21 @@ def test_fused_multigrid_tail_is_bitwise_equal_to_separate_launches(prec_name, d
     ("FP32_MIXED", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5), ci.channel(2, 130, 34, shear=400.0, seed=8)],
      {"mg_tail": 0}),
     ("FP32_MIXED", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5)], {"mg_sweeps": 3, "mg_tail": 0}),
+    ("FP32_MIXED", [ci.channel(3, 37, 13, 11, shear=900.0, dt=5e-5, seed=9), ci.channel(2, 130, 34, shear=400.0, seed=8)],
+     {"mg_sweeps": 3}),
     ("FP64", [ci.channel(3, 37, 13, 11, shear=900.0, dt=5e-5, seed=9)], {}),
     ("FP64", [ci.channel(2, 72, 20, shear=1000.0, dt=1e-4, seed=5), ci.channel(2, 130, 34, shear=400.0, seed=8)], {}),
 ])
 def test_pressure_bricks_are_bitwise_equal_to_separate_launches(prec_name, descs, over):
     """The brick-ordered legs of the pressure V-cycle (default, mg_brick = 1: the mesh's
-    restriction and prolongation, and in FP32 the LDS-staged legs of the coarse levels)
-    against the general separate launches (mg_brick = 0): every cell value is formed by
-    the same expression, halo cells included, so the steps agree bit for bit.  In FP32
-    also checks that the staged legs ran (the down-leg probe counts launches)."""
+    restriction and prolongation, and in FP32 the LDS-staged legs of the coarse levels
+    and, with three sweeps each way, the mesh's three down sweeps in one launch) against
+    the general separate launches (mg_brick = 0): every cell value is formed by the same
+    expression, halo cells included, so the steps agree bit for bit.  In FP32 also checks
+    that the staged legs ran (the probes count launches)."""
     from paper_2304_09180_amd import clot
     prec = getattr(clot, prec_name)
+    sweeps = over.get("mg_sweeps", 3 if all(d["dim"] == 3 for d in descs) else 2)
     runs = []
     for brick in (1, 0):
         s = clot.Solver(descs, prec, clot.default_params(prec, mg_brick=brick, **over))
@@ -175,10 +179,15 @@ def test_pressure_bricks_are_bitwise_equal_to_separate_launches(prec_name, descs
             xc, xf = ci.noise(d)
             s.init_state(i, xc, xf)
         s.probe("p_mg_down")
-        s.step(6)
+        s.step(3)
         _, n = s.probe_read()
+        s.probe("p_mg_pre3")
+        s.step(3)
+        _, n3 = s.probe_read()
         s.probe(None)
-        assert (n > 0) == (brick == 1 and prec == clot.FP32_MIXED), (brick, n)
+        staged = brick == 1 and prec == clot.FP32_MIXED
+        assert (n > 0) == staged, (brick, n)
+        assert (n3 > 0) == (staged and sweeps == 3), (brick, n3)
         runs.append([s.fields(i) for i in range(len(descs))])
         s.close()
     for c in range(len(descs)):
