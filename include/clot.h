@@ -362,7 +362,10 @@ clot_status clot_probe_read(clot_ctx* c, double* total_ms, int64_t* launches);
  * clot_mlp_nparam() entries) is W1[64][32] b1[64] W2[64][64] b2[64] W3[16][64]
  * b3[16]; the mode blob appends sf[14] and sc[14], the RMS over the training set of
  * the scaled explicit increments f/s and of the relative corrections (RK4 - f)/|f|.  The plain RK4 step (section 3.2) is the arbiter: a cell whose
- * relative midpoint defect exceeds resid_tol is recomputed by it.
+ * midpoint defect relative to the increment, max over species of
+ * |Delta_i - Dt R_i(y + Delta/2)| / (|Delta_i| + 1e-5 |y_i| + 1e-6 s_i) with s_i the
+ * species scale (P_max for the platelets, S1_0 or S2_0 for the chemicals), exceeds
+ * resid_tol is recomputed by it.
  * State rows for the batch calls: 18 float64 each = 14 species (Pmu Pma Pba Pbse S1
  * S2 E1 E2 S1b S2b E1b E2b C1 C2), ADP, eta, H_adh, Dt. */
 int64_t clot_mlp_nparam(void);

@@ -2248,7 +2248,7 @@ struct Ctx : clot_ctx {
         if (st2) HIPCHK(hipStreamSynchronize(st2));
         StateHead h{};
         h.magic = STATE_MAGIC;
-        h.version = 2;
+        h.version = 3;
         h.prec = (int32_t)prec;
         h.nch = (int32_t)ch.size();
         h.parity = parity;
@@ -2292,7 +2292,7 @@ struct Ctx : clot_ctx {
         const char* p = static_cast<const char*>(host);
         std::memcpy(&h, p, sizeof(h));
         p += sizeof(h);
-        if (h.magic != STATE_MAGIC || h.version != 2 || h.prec != (int32_t)prec || h.nch != (int32_t)ch.size() ||
+        if (h.magic != STATE_MAGIC || h.version != 3 || h.prec != (int32_t)prec || h.nch != (int32_t)ch.size() ||
             h.N != N || h.NFX != NFX || h.NFY != NFY || h.NFZ != NFZ || h.NINJ != NINJ || h.ntiles != ntiles ||
             h.ws != (int64_t)ws_bytes || (h.parity != 0 && h.parity != 1)) {
             err = "load_state: the blob was saved from a context of another layout";

@@ -11,9 +11,17 @@
 // species, slog(f_i/(s_i sf_i)) with sf_i the RMS of f/s, ADP/ADP*, g(eta), H_adh,
 // log10(Dt)+5.  The same device function builds the
 // features for training and inference.  A cell is accepted when its midpoint defect
-// in species scales,  max_i |Delta_i - Dt R_i(y + Delta/2)| / s_i,  is below the
-// residual tolerance; otherwise it is queued for the plain RK4 step (so a zero
-// tolerance sends every cell to the plain integrator).
+// relative to the increment,
+//     max_i |Delta_i - Dt R_i(y + Delta/2)| / (|Delta_i| + 1e-5 |y_i| + 1e-6 s_i),
+// is below the residual tolerance; otherwise it is queued for the plain RK4 step (so a
+// zero tolerance sends every cell to the plain integrator).  The exact increment's
+// defect is O(Dt^3), so the test bounds the error of each increment by a fraction of
+// the increment: summed over steps, the error of a field stays that fraction of its
+// change.  Measured against the species' size or scale instead, a slowly changing
+// species (|Delta| << |y|, or thrombin three decades under S2_0) would pass with its
+// increment wrong by tens of percent.  The floor terms, about a hundred units in the
+// last place of the stored value and a millionth of the scale, keep cells where a
+// species barely changes from failing on rounding.
 #pragma once
 #include "clot_mlp.h"
 #include "clot_step.h"
@@ -26,6 +34,7 @@ struct SurrTables {
     float sc[MLP_NSP];     // RMS of the relative corrections over the training set
     float inv_s[MLP_NSP];  // 1/s
     float inv_f[MLP_NSP];  // 1/(s sf)
+    float fl[MLP_NSP];     // floor of the defect's denominator, 1e-6 s
 };
 
 __host__ __device__ inline void species_scales(const ModelDev& M, float (&s)[MLP_NSP]) {
@@ -41,6 +50,7 @@ inline void surr_tables_finish(const ModelDev& M, SurrTables& tb) {
     for (int i = 0; i < MLP_NSP; ++i) {
         tb.inv_s[i] = 1.f / tb.s[i];
         tb.inv_f[i] = 1.f / (tb.s[i] * tb.sf[i]);
+        tb.fl[i] = 1e-6f * tb.s[i];
     }
 }
 
@@ -74,7 +84,7 @@ __device__ inline void surr_features(const T (&y)[NRX], T adp, T gam, T hadh, T 
     x[31] = fmaf(__log2f((float)dt), 0.30102999566f, 5.f);   // log10(Dt) + 5
 }
 
-// Midpoint defect of an increment in species scales (one right-hand-side evaluation).
+// Midpoint defect of an increment relative to the increment (one right-hand-side evaluation).
 template <class T>
 __device__ inline float surr_defect(const T (&y)[NRX], const T (&inc)[NRX], T adp, T gam, T hadh, T dt,
                                     const RxnK<T>& K, const SurrTables& tb) {
@@ -85,7 +95,8 @@ __device__ inline float surr_defect(const T (&y)[NRX], const T (&inc)[NRX], T ad
     float worst = 0.f;
 #pragma unroll
     for (int i = 0; i < NRX; ++i) {
-        const float r = (float)fabs(inc[i] - dt * fm[i]) * tb.inv_s[i];
+        const float den = fabsf((float)inc[i]) + 1e-5f * fabsf((float)y[i]) + tb.fl[i];
+        const float r = (float)fabs(inc[i] - dt * fm[i]) / den;
         worst = (r > worst || r != r) ? r : worst;
     }
     return worst;

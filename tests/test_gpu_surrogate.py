@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import clot_inputs as ci
+from parity_util import rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -112,6 +113,13 @@ def test_training_on_gpu_reduces_the_loss_and_beats_the_midpoint_step(trained):
     assert held_net < 0.75 * held_zero
 
 
+# velocity, the 15 transported species and the two bound-enzyme fields, each measured
+# with the parity helper's floor (a field that stays at round-off, such as thrombin and
+# its complexes in the first steps, at 1e-26 of its scale, is compared on its scale)
+PARITY_FIELDS = ["UX", "UY", "PMU", "PMA", "PBA", "PBSE", "ADP", "S1", "S2", "E1", "E2", "S1B", "S2B", "E1B", "E2B",
+                 "C1", "C2", "E0", "C0"]
+
+
 def _run(d, steps, mode, blob=None, tol=1e-3):
     from paper_2304_09180_amd import clot
     s = clot.Solver([d], clot.FP32_MIXED)
@@ -143,9 +151,11 @@ def test_surrogate_step_parity_gain_and_fallback(trained):
     print("fallback fraction", st_s["fallback_frac"], st_f["fallback_frac"])
 
     def err(a, name):
-        return np.linalg.norm(a[name] - ref[name]) / max(np.linalg.norm(ref[name]), 1e-300)
+        return rel_l2(a[name], ref[name], name)
 
-    names = ["UX", "PMU", "PBSE", "S1", "S2", "E1", "S1B", "S2B"]
+    names = PARITY_FIELDS
+    for n in names:
+        print(n, "surrogate", f"{err(surr, n):.3e}", flush=True)
     for n in names:
         assert err(surr, n) <= 1e-3, (n, err(surr, n))
     # what the network gains over the explicit increment alone, on the bound platelets
@@ -154,8 +164,36 @@ def test_surrogate_step_parity_gain_and_fallback(trained):
     for n in ("PBSE", "S1B", "S2B"):
         print(n, "surrogate", err(surr, n), "midpoint alone", err(euler, n))
     # with a zero tolerance every changed cell is recomputed by the plain RK4 step
-    for n in names + ["PMA", "PBA", "E2", "C1", "C2"]:
+    for n in names:
         assert np.array_equal(allfb[n], plain[n]), n
+
+
+def test_a_wrong_network_is_caught_by_the_defect_check(trained):
+    """A network whose output bias is forced high pushes every correction to its clamp,
+    +50% of the explicit increment.  The defect check, relative to the increment,
+    rejects the cells that react (the increment is then far off the midpoint
+    equation), so they take the plain RK4 step and the run still matches the oracle on
+    every field; without the check (tolerance 1e9) some field drifts off by over 1%."""
+    from oracle import clot_oracle as oc
+    tr = trained[0]
+    d = ci.channel(2, 64, 16, shear=1000.0, dt=1e-4, steps=60, seed=5)
+    steps = d["steps"]
+    xc, xf = ci.noise(d)
+    o = oc.Oracle(d, xc, xf)
+    for _ in range(steps):
+        o.step()
+    ref = o.fields()
+    bad = tr.blob().copy()
+    bad[tr.npar - 16:tr.npar] = 1e4          # b3, the output layer's bias
+    caught, st = _run(d, steps, "surrogate", bad, 1e-3)
+    loose, st_l = _run(d, steps, "surrogate", bad, 1e9)
+    print("fallback fraction", st["fallback_frac"], st_l["fallback_frac"], flush=True)
+    assert st["fallback_frac"] > 0.0 and st_l["fallback_frac"] == 0.0
+    for n in PARITY_FIELDS:
+        e = rel_l2(caught[n], ref[n], n)
+        print(n, "caught", f"{e:.3e}", "unchecked", f"{rel_l2(loose[n], ref[n], n):.3e}", flush=True)
+        assert e <= 1e-3, (n, e)
+    assert max(rel_l2(loose[n], ref[n], n) for n in PARITY_FIELDS) > 1e-2
 
 
 def test_surrogate_under_crank_nicolson_and_variable_step(trained):
@@ -190,8 +228,10 @@ def test_surrogate_under_crank_nicolson_and_variable_step(trained):
     assert st_s["dt"] == pytest.approx(o.dt, rel=1e-4)
 
     def err(a, name):
-        return np.linalg.norm(a[name] - ref[name]) / max(np.linalg.norm(ref[name]), 1e-300)
-    for n in ["UX", "PMU", "PBSE", "S1", "S2", "E1", "S1B", "S2B"]:
+        return rel_l2(a[name], ref[name], name)
+    for n in PARITY_FIELDS:
+        print(n, "surrogate", f"{err(surr, n):.3e}", flush=True)
+    for n in PARITY_FIELDS:
         assert err(surr, n) <= 1e-3, (n, err(surr, n))
-    for n in ["UX", "PMU", "PMA", "PBA", "PBSE", "S1", "S2", "E1", "E2", "S1B", "S2B", "C1", "C2"]:
+    for n in PARITY_FIELDS:
         assert np.array_equal(allfb[n], plain[n]), n
