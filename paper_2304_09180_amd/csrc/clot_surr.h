@@ -84,22 +84,22 @@ __device__ inline void surr_features(const T (&y)[NRX], T adp, T gam, T hadh, T 
     x[31] = fmaf(__log2f((float)dt), 0.30102999566f, 5.f);   // log10(Dt) + 5
 }
 
-// Midpoint defect of an increment relative to the increment (one right-hand-side evaluation).
+// Whether every species' midpoint defect, relative to the increment, is below tol (one
+// right-hand-side evaluation; compared as |defect| < tol * den, so a NaN fails).
 template <class T>
-__device__ inline float surr_defect(const T (&y)[NRX], const T (&inc)[NRX], T adp, T gam, T hadh, T dt,
-                                    const RxnK<T>& K, const SurrTables& tb) {
+__device__ inline bool surr_accept(const T (&y)[NRX], const T (&inc)[NRX], T adp, T gam, T hadh, T dt,
+                                   const RxnK<T>& K, const SurrTables& tb, float tol) {
     T ym[NRX], fm[NRX];
 #pragma unroll
     for (int i = 0; i < NRX; ++i) ym[i] = y[i] + T(0.5) * inc[i];
     rxn_rhs(ym, adp, gam, hadh, K, fm);
-    float worst = 0.f;
+    bool ok = true;
 #pragma unroll
     for (int i = 0; i < NRX; ++i) {
         const float den = fabsf((float)inc[i]) + 1e-5f * fabsf((float)y[i]) + tb.fl[i];
-        const float r = (float)fabs(inc[i] - dt * fm[i]) / den;
-        worst = (r > worst || r != r) ? r : worst;
+        ok = ok && (float)fabs(inc[i] - dt * fm[i]) < tol * den;
     }
-    return worst;
+    return ok;
 }
 
 // The learned step works on the stored values (FP32 in the mixed path) and leaves no low parts.
@@ -194,8 +194,7 @@ __global__ __launch_bounds__(256) void k_rxn_surr(Grid G, Fields<T> F, RxnK<T> K
                 r = r > 0.5f ? 0.5f : (r < -0.5f ? -0.5f : r);
                 inc[i] = f[i] * (T(1) + T(r));
             }
-            const float d = surr_defect(y, inc, adp, gam, hadh, dt, K, tb);
-            if (d < tol) {
+            if (surr_accept(y, inc, adp, gam, hadh, dt, K, tb, tol)) {
 #pragma unroll
                 for (int i = 0; i < NRX; ++i) y[i] += inc[i];
                 store_rxn_state(F, g, y);
