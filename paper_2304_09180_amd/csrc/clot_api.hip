@@ -208,6 +208,8 @@ struct Ctx : clot_ctx {
     T mg_w = T(0.8);         // weighted-Jacobi smoothing weight (set with the channels)
     int mg_t0 = -1;          // first level run by the fused tail launch (-1: none)
     size_t mg_tail_lds = 0;  // its dynamic LDS bytes
+    TailPlan* d_tplan = nullptr;   // per channel: the fused tail's set-up (clot_mg.h)
+    std::vector<TailPlan> h_tplan;  // its host copy (kept until the upload completes)
     T* mg_y0 = nullptr;      // level-0 smoother scratch
     T* mg_z0 = nullptr;      // preconditioned residual z = M r
     double* mg_inv = nullptr;  // per-channel inverse of the coarsest-level matrix
@@ -470,6 +472,7 @@ struct Ctx : clot_ctx {
             L.cz = cv.take<T>(L.NFZ);
         }
         d_mgm_last = cv.take<int32_t>(nch);
+        d_tplan = cv.take<TailPlan>(nch);
         for (int q = 0; q < MGB_NSHAPE; ++q)
             for (int j = 0; j < MG_MAXLEV; ++j) {
                 d_pbr[q][j] = cv.take<BrickChan>(std::max<size_t>(h_pbr[q][j].size(), 1));
@@ -668,7 +671,8 @@ struct Ctx : clot_ctx {
             if (hipGetDevice(&dev) == hipSuccess)
                 (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
             // less the kernel's static LDS (level table, coarse right-hand side) and a margin
-            const int64_t limit = (int64_t)lds_max - (int64_t)(MG_MAXLEV * sizeof(TailLds)) - 1024;
+            const int64_t limit =
+                (int64_t)lds_max - (int64_t)(sizeof(TailPlan) + MG_TAIL_SEGS * sizeof(TailSeg<T>)) - 1024;
             const int nl = (int)lev.size();
             auto bytes_from = [&](int t) {
                 int64_t worst = 0;
@@ -914,6 +918,16 @@ struct Ctx : clot_ctx {
         }
         HIPCHK(hipMemcpyAsync(d_t2c, t2c.data(), t2c.size() * 4, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(d_mgm_last, h_mgm_last.data(), nch * 4, hipMemcpyHostToDevice, st));
+        if (mg_t0 >= 0) {
+            const int nl = (int)lev.size();
+            h_tplan.assign(nch, TailPlan{});
+            std::vector<ChanDev> lc(nl - mg_t0);
+            for (int i = 0; i < nch; ++i) {
+                for (int l = mg_t0; l < nl; ++l) lc[l - mg_t0] = lev[l].ch[i];
+                tail_plan_build(h_tplan[i], nl - mg_t0, lc.data(), (int)sizeof(T));
+            }
+            HIPCHK(hipMemcpyAsync(d_tplan, h_tplan.data(), nch * sizeof(TailPlan), hipMemcpyHostToDevice, st));
+        }
         if (!h_rb2c.empty()) {
             HIPCHK(hipMemcpyAsync(d_rbr, h_rbr.data(), h_rbr.size() * sizeof(BrickChan), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(d_rb2c, h_rb2c.data(), h_rb2c.size() * 4, hipMemcpyHostToDevice, st));
@@ -1475,9 +1489,10 @@ struct Ctx : clot_ctx {
                 tl.n = nl - t0;
                 for (int l = t0; l < nl; ++l) {
                     Level& L = lev[l];
-                    tl.L[l - t0] = MGTailLevel<T>{L.d_ch, L.x, L.y, L.b, L.dg, L.cx, L.cy, L.cz, L.cout};
+                    tl.L[l - t0] = MGTailLevel<T>{L.x, L.y, L.b, L.dg, L.cx, L.cy, L.cz, L.cout};
                 }
-                hipLaunchKernelGGL(k_mg_tail<T>, dim3((int)ch.size()), dim3(MG_TAIL_BS), mg_tail_lds, st, tl, mg_w, mg_inv,
+                hipLaunchKernelGGL(k_mg_tail<T>, dim3((int)ch.size()), dim3(MG_TAIL_BS), mg_tail_lds, st, tl,
+                                   (const TailPlan*)d_tplan, mg_w, mg_inv,
                                    act, (int)prm.mg_sweeps);
             } else {
                 Level& Lc = lev[nl - 1];

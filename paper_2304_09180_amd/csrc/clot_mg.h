@@ -337,7 +337,8 @@ __global__ __launch_bounds__(MG_COARSE) void k_mg_coarse(Grid G, const double* i
 // The small end of the hierarchy in one launch: for the levels whose every channel
 // has at most a few thousand cells (the separate launches of those levels cost more
 // than their work), one 1024-thread block per channel runs the rest of the V-cycle
-// in LDS: it loads the levels' coefficients and the restricted residual once, does
+// in LDS: it reads its channel's plan (the levels' geometry and LDS layout, built on
+// the host at set-up), loads the levels' coefficients and the restricted residual once, does
 // the pre-smoothing and restriction down to the coarsest level, the dense solve, the
 // prolongation and post-smoothing back up, with block barriers between the passes,
 // and writes back the correction of the first tail level.  Every cell update is the
@@ -347,8 +348,7 @@ __global__ __launch_bounds__(MG_COARSE) void k_mg_coarse(Grid G, const double* i
 constexpr int MG_TAIL_BS = 1024;
 
 template <class T>
-struct MGTailLevel {
-    const ChanDev* ch;
+struct MGTailLevel {   // a tail level's arrays (the channels' geometry comes from TailPlan)
     T *x, *y, *b, *dg, *cx, *cy, *cz, *cout;
 };
 template <class T>
@@ -387,6 +387,81 @@ struct TailSeg {
 };
 constexpr int MG_TAIL_SEGS = 4 * MG_MAXLEV + 1;
 
+// The tail's set-up for one channel, built on the host when the context is created
+// (geometry only, no addresses, so a saved workspace carries it unchanged): each
+// level's table with zero offsets and the LDS offsets of its arrays, and the arrays to
+// copy in as (level, array, first element, LDS offset, count).  The block reads it in
+// one round of loads instead of walking the levels' channel tables from one thread.
+enum { TAIL_DG = 0, TAIL_CX = 1, TAIL_CY = 2, TAIL_CZ = 3, TAIL_B = 4 };
+struct TailSegRef {
+    int64_t off;
+    int32_t lvl, kind, dst, n;
+};
+struct TailPlan {
+    TailLds lv[MG_MAXLEV];
+    TailSegRef seg[MG_TAIL_SEGS];
+    int32_t start[MG_TAIL_SEGS + 1];
+    int32_t nseg, nl;
+    int64_t out0;   // the channel's first cell on the first tail level (the write-back)
+};
+static_assert(sizeof(TailPlan) % 4 == 0, "copied as 32-bit words");
+
+// lc[l]: this channel's table on tail level l (l < nl, the last the coarsest).
+inline void tail_plan_build(TailPlan& P, int nl, const ChanDev* lc, int bytes) {
+    P = TailPlan{};
+    P.nl = nl;
+    int64_t o = 0;
+    for (int l = 0; l < nl; ++l) {
+        TailLds& v = P.lv[l];
+        v.C = lc[l];
+        v.C.c0 = 0;
+        v.C.fx0 = 0;
+        v.C.fy0 = 0;
+        v.C.fz0 = 0;
+        const int64_t n = v.C.ncell;
+        v.ob = (int32_t)o;
+        o += tail_align(n, bytes);
+        v.ox = (int32_t)o;
+        o += tail_align(n, bytes);
+        v.oy = v.odg = v.ocx = v.ocy = v.ocz = 0;
+        v.nfx = (v.C.nx + 1) * v.C.ny * v.C.nz;
+        v.nfy = v.C.nx * (v.C.ny + 1) * v.C.nz;
+        v.nfz = v.C.dim == 3 ? v.C.nx * v.C.ny * (v.C.nz + 1) : 0;
+        if (l + 1 == nl) break;
+        v.oy = (int32_t)o;
+        o += tail_align(n, bytes);
+        v.odg = (int32_t)o;
+        o += tail_align(n, bytes);
+        v.ocx = (int32_t)o;
+        o += tail_align(v.nfx, bytes);
+        v.ocy = (int32_t)o;
+        o += tail_align(v.nfy, bytes);
+        v.ocz = (int32_t)o;
+        o += tail_align(v.nfz, bytes);
+    }
+    int ns = 0;
+    int32_t e = 0;
+    auto add = [&](int lvl, int kind, int64_t off, int32_t dst, int32_t n) {
+        if (n <= 0) return;
+        P.seg[ns] = TailSegRef{off, lvl, kind, dst, n};
+        P.start[ns] = e;
+        e += n;
+        ++ns;
+    };
+    for (int l = 0; l + 1 < nl; ++l) {
+        const ChanDev& C = lc[l];
+        const TailLds& v = P.lv[l];
+        add(l, TAIL_DG, C.c0, v.odg, (int32_t)C.ncell);
+        add(l, TAIL_CX, C.fx0, v.ocx, v.nfx);
+        add(l, TAIL_CY, C.fy0, v.ocy, v.nfy);
+        add(l, TAIL_CZ, C.fz0, v.ocz, v.nfz);
+    }
+    add(0, TAIL_B, lc[0].c0, P.lv[0].ob, (int32_t)lc[0].ncell);
+    P.start[ns] = e;
+    P.nseg = ns;
+    P.out0 = lc[0].c0;
+}
+
 // All the segments in one pass over their concatenation: each thread issues the loads
 // of up to U elements, whatever arrays they fall in, before it stores any of them, so
 // that the latencies of the arrays overlap instead of adding up array by array.
@@ -417,76 +492,32 @@ __device__ inline void tail_copy_in(T* lds, const TailSeg<T>* seg, const int32_t
 }
 
 template <class T>
-__global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const double* inv, const int32_t* chact,
-                                                        int sweeps) {
+__global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, const TailPlan* plans, T w, const double* inv,
+                                                        const int32_t* chact, int sweeps) {
     const int chid = blockIdx.x;
     if (!chact[chid]) return;
     extern __shared__ __align__(16) unsigned char tail_lds[];
     T* const lds = reinterpret_cast<T*>(tail_lds);
-    __shared__ TailLds tv[MG_MAXLEV];
-    const int nl = tl.n;
-    // carve the LDS arrays (thread 0), then copy the coefficients and the top level's b in
-    if (threadIdx.x == 0) {
-        const int bytes = (int)sizeof(T);
-        int64_t o = 0;
-        for (int l = 0; l < nl; ++l) {
-            TailLds& v = tv[l];
-            v.C = tl.L[l].ch[chid];
-            v.C.c0 = 0;
-            v.C.fx0 = 0;
-            v.C.fy0 = 0;
-            v.C.fz0 = 0;
-            const int64_t n = v.C.ncell;
-            v.ob = (int32_t)o;
-            o += tail_align(n, bytes);
-            v.ox = (int32_t)o;
-            o += tail_align(n, bytes);
-            v.oy = v.odg = v.ocx = v.ocy = v.ocz = 0;
-            v.nfx = (v.C.nx + 1) * v.C.ny * v.C.nz;
-            v.nfy = v.C.nx * (v.C.ny + 1) * v.C.nz;
-            v.nfz = v.C.dim == 3 ? v.C.nx * v.C.ny * (v.C.nz + 1) : 0;
-            if (l + 1 == nl) break;
-            v.oy = (int32_t)o;
-            o += tail_align(n, bytes);
-            v.odg = (int32_t)o;
-            o += tail_align(n, bytes);
-            v.ocx = (int32_t)o;
-            o += tail_align(v.nfx, bytes);
-            v.ocy = (int32_t)o;
-            o += tail_align(v.nfy, bytes);
-            v.ocz = (int32_t)o;
-            o += tail_align(v.nfz, bytes);
-        }
-    }
+    // the channel's plan, copied in by the whole block, then each segment's address
+    __shared__ TailPlan pl;
     __shared__ TailSeg<T> seg[MG_TAIL_SEGS];
-    __shared__ int32_t sstart[MG_TAIL_SEGS + 1];
-    __shared__ int nseg;
-    if (threadIdx.x == 0) {
-        int ns = 0;
-        int32_t e = 0;
-        auto add = [&](const T* src, int32_t dst, int32_t n) {
-            if (n <= 0) return;
-            seg[ns] = TailSeg<T>{src, dst, n};
-            sstart[ns] = e;
-            e += n;
-            ++ns;
-        };
-        for (int l = 0; l + 1 < nl; ++l) {
-            const MGTailLevel<T>& Lv = tl.L[l];
-            const ChanDev& C = Lv.ch[chid];
-            const TailLds& v = tv[l];
-            add(Lv.dg + C.c0, v.odg, (int32_t)C.ncell);
-            add(Lv.cx + C.fx0, v.ocx, v.nfx);
-            add(Lv.cy + C.fy0, v.ocy, v.nfy);
-            add(Lv.cz + C.fz0, v.ocz, v.nfz);
-        }
-        const ChanDev& C0 = tl.L[0].ch[chid];
-        add(tl.L[0].b + C0.c0, tv[0].ob, (int32_t)C0.ncell);
-        sstart[ns] = e;
-        nseg = ns;
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(plans + chid);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&pl);
+        for (int q = threadIdx.x; q < (int)(sizeof(TailPlan) / 4); q += MG_TAIL_BS) dst[q] = src[q];
     }
     __syncthreads();
-    tail_copy_in(lds, seg, sstart, nseg);
+    if ((int)threadIdx.x < pl.nseg) {
+        const TailSegRef& r = pl.seg[threadIdx.x];
+        const MGTailLevel<T>& L = tl.L[r.lvl];
+        const T* base = r.kind == TAIL_DG ? L.dg : r.kind == TAIL_CX ? L.cx : r.kind == TAIL_CY ? L.cy
+                      : r.kind == TAIL_CZ ? L.cz : L.b;
+        seg[threadIdx.x] = TailSeg<T>{base + r.off, r.dst, r.n};
+    }
+    __syncthreads();
+    const TailLds* const tv = pl.lv;
+    const int nl = tl.n;
+    tail_copy_in(lds, seg, pl.start, pl.nseg);
     __syncthreads();
     // down: `sweeps` Jacobi sweeps (from zero) and the residual restriction per level
     for (int l = 0; l + 1 < nl; ++l) {
@@ -585,9 +616,8 @@ __global__ __launch_bounds__(MG_TAIL_BS) void k_mg_tail(MGTail<T> tl, T w, const
         }
     }
     // the first tail level's correction, for the prolongation of the level above
-    const ChanDev& C0 = tl.L[0].ch[chid];
     const int32_t o0 = (nl == 1 || sweeps % 2 == 0) ? tv[0].ox : tv[0].oy;
-    for (int64_t q = threadIdx.x; q < C0.ncell; q += MG_TAIL_BS) tl.L[0].x[C0.c0 + q] = lds[o0 + q];
+    for (int64_t q = threadIdx.x; q < tv[0].C.ncell; q += MG_TAIL_BS) tl.L[0].x[pl.out0 + q] = lds[o0 + q];
 }
 
 // ------------------------------------------------------------------------------------
