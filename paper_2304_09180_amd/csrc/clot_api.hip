@@ -246,13 +246,17 @@ struct Ctx : clot_ctx {
     int32_t* d_rb2c = nullptr;
     bool mesh_on = false;
     bool mesh_halves() const { return mesh_on && !h_rb2c.empty(); }
-    // The mesh's three down sweeps in one launch (k_mg_pre3_mesh), bricks of the pressure
-    // shape 0: FP32 contexts with three sweeps each way and mg_brick set.
+    // The mesh's down leg in one launch (k_mg_down_mesh), bricks of the pressure shape 0,
+    // in FP32 contexts with mg_brick set: three sweeps (mesh_down_n = 3), or two sweeps
+    // and the restriction where every channel is coarsened along every axis (2).
     std::vector<BrickChan> h_p3br;
     std::vector<int32_t> h_p3b2c;
     BrickChan* d_p3br = nullptr;
     int32_t* d_p3b2c = nullptr;
-    bool mesh_pre3() const { return !h_p3b2c.empty(); }
+    int mesh_down_n = 0;
+    bool mesh_down_3d = false;   // some channel is 3-D (the larger LDS brick)
+    bool mesh_down() const { return !h_p3b2c.empty(); }
+    size_t mesh_down_lds() const { return mesh_down_lds_bytes(mesh_down_3d, sizeof(T)); }
     BrickGrid pbricks(int q, int j) const { return BrickGrid{d_pbr[q][j], d_pb2c[q][j], (int32_t)h_pb2c[q][j].size()}; }
     bool pbricked(int j) const { return mgb_use && !h_pb2c[0][j].empty(); }
     // reaction surrogate
@@ -746,8 +750,13 @@ struct Ctx : clot_ctx {
             }
             h_p3br.clear();
             h_p3b2c.clear();
-            if (p->mg_brick != 0 && sizeof(T) == 4 && prm.mg_sweeps == 3 && nl > 0)
+            mesh_down_n = 0;
+            if (p->mg_brick != 0 && sizeof(T) == 4 && nl > 0)
+                mesh_down_n = prm.mg_sweeps == 3 ? 3 : (prm.mg_sweeps == 2 && !h_rb2c.empty() ? 2 : 0);
+            mesh_down_3d = false;
+            if (mesh_down_n > 0)
                 for (int i = 0; i < nch; ++i) {
+                    mesh_down_3d = mesh_down_3d || ch[i].d.dim == 3;
                     const clot_channel& d = ch[i].d;
                     int bx, by, bz;
                     pbrick_dims(d.dim, 0, bx, by, bz);
@@ -784,7 +793,10 @@ struct Ctx : clot_ctx {
                 set = set && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
         };
         if (mg_t0 >= 0) attr(reinterpret_cast<const void*>(&k_mg_tail<T>), mg_tail_lds);
-        if (mesh_pre3()) attr(reinterpret_cast<const void*>(&k_mg_pre3_mesh<T>), mesh_pre3_lds_bytes(sizeof(T)));
+        if (mesh_down()) {
+            attr(reinterpret_cast<const void*>(&k_mg_down_mesh<T, false>), mesh_down_lds());
+            attr(reinterpret_cast<const void*>(&k_mg_down_mesh<T, true>), mesh_down_lds());
+        }
         if (mgb_use) {
             const int h = prm.mg_sweeps;
             auto both = [&](const void* down, const void* up, int q) {
@@ -932,7 +944,7 @@ struct Ctx : clot_ctx {
             HIPCHK(hipMemcpyAsync(d_rbr, h_rbr.data(), h_rbr.size() * sizeof(BrickChan), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(d_rb2c, h_rb2c.data(), h_rb2c.size() * 4, hipMemcpyHostToDevice, st));
         }
-        if (mesh_pre3()) {
+        if (mesh_down()) {
             HIPCHK(hipMemcpyAsync(d_p3br, h_p3br.data(), h_p3br.size() * sizeof(BrickChan), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(d_p3b2c, h_p3b2c.data(), h_p3b2c.size() * 4, hipMemcpyHostToDevice, st));
         }
@@ -1553,22 +1565,33 @@ struct Ctx : clot_ctx {
                 cur = nxt;
             }
         };
-        // down (a bricked level leaves its smoothed iterate in Y for its up leg; so does the
-        // mesh's fused three sweeps, where the separate launches end too)
-        T* s0 = mg_y0;
-        if (mesh_pre3())
-            CLOT_LAUNCH(CLOT_PROBE_P_MG_PRE3, k_mg_pre3_mesh<T>, dim3((unsigned)h_p3b2c.size()), dim3(MGB_BS),
-                        mesh_pre3_lds_bytes(sizeof(T)), st, BrickGrid{d_p3br, d_p3b2c, (int32_t)h_p3b2c.size()},
-                        grid(), p0, r, mg_y0, mg_w, act);
-        else
+        // down (a bricked level leaves its smoothed iterate in Y for its up leg; the mesh's
+        // fused leg ends where the separate launches do: three sweeps in Y, two in X)
+        T* s0 = nullptr;
+        const BrickGrid mdg{d_p3br, d_p3b2c, (int32_t)h_p3b2c.size()};
+        if (mesh_down_n == 3) {
+            s0 = mg_y0;
+            CLOT_LAUNCH(CLOT_PROBE_P_MG_MESH_DOWN, (k_mg_down_mesh<T, false>), dim3((unsigned)h_p3b2c.size()),
+                        dim3(MGB_BS), mesh_down_lds(), st, mdg, MGPair{grid(), lev[0].grid()}, p0, r, s0, (T*)nullptr,
+                        mg_w, act);
+        } else if (mesh_down_n == 2) {
+            s0 = mg_z0;
+            CLOT_LAUNCH(CLOT_PROBE_P_MG_MESH_DOWN, (k_mg_down_mesh<T, true>), dim3((unsigned)h_p3b2c.size()),
+                        dim3(MGB_BS), mesh_down_lds(), st, mdg, MGPair{grid(), lev[0].grid()}, p0, r, s0, lev[0].b,
+                        mg_w, act);
+        } else {
             s0 = down(p0, r, mg_z0, mg_y0, grid(), (int)ntiles);
-        if (mesh_halves())
-            hipLaunchKernelGGL(k_mg_restrict_mesh<T>, dim3((unsigned)h_rb2c.size()), dim3(NT), 0, st,
-                               BrickGrid{d_rbr, d_rb2c, (int32_t)h_rb2c.size()}, MGPair{grid(), lev[0].grid()}, p0, r,
-                               (const T*)s0, lev[0].b, act);
-        else
-            hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>, false>), dim3(lev[0].ntiles * (TILE / (NT / 8))), dim3(NT),
-                               0, st, MGPair{grid(), lev[0].grid()}, p0, r, (const T*)s0, lev[0].b, act, mg_w);
+        }
+        if (mesh_down_n != 2) {   // (the two-sweep fused leg restricts too)
+            if (mesh_halves())
+                hipLaunchKernelGGL(k_mg_restrict_mesh<T>, dim3((unsigned)h_rb2c.size()), dim3(NT), 0, st,
+                                   BrickGrid{d_rbr, d_rb2c, (int32_t)h_rb2c.size()}, MGPair{grid(), lev[0].grid()}, p0,
+                                   r, (const T*)s0, lev[0].b, act);
+            else
+                hipLaunchKernelGGL((k_mg_restrict<T, PresOp<T, T>, false>), dim3(lev[0].ntiles * (TILE / (NT / 8))),
+                                   dim3(NT), 0, st, MGPair{grid(), lev[0].grid()}, p0, r, (const T*)s0, lev[0].b, act,
+                                   mg_w);
+        }
         T* pre_end[MG_MAXLEV];
         for (int l = 0; l < t0; ++l) {
             Level& L = lev[l];

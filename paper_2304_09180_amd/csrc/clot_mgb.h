@@ -1,7 +1,7 @@
 // Pressure multigrid legs in bricks (gfx950): the LDS-staged multi-sweep legs of the
 // coarse levels (FP32 contexts), and, at the end of the file, the mesh's restriction and
 // prolongation sweep for meshes that every channel coarsens along every axis (both
-// precisions) and the mesh's three down sweeps in one launch (FP32 contexts).
+// precisions) and the mesh's down leg in one launch (FP32 contexts).
 //
 // Above the fused tail, each coarse level's legs are six separate launches (first two
 // sweeps, the other sweeps, restriction; prolongation sweep, the other sweeps), each
@@ -24,7 +24,8 @@
 // (aggregates never straddle bricks, whose origins are even).  On the mesh the whole
 // leg loses: the staged arrays leave room for one block per CU and the three-cell halo
 // triples the work, against separate launches that are already wide.  Only the mesh's
-// three down sweeps are staged there (k_mg_pre3_mesh, a two-cell halo, five arrays).
+// down leg is staged there, with a two-cell halo and five arrays (k_mg_down_mesh: three
+// sweeps, or two sweeps and the restriction).
 #pragma once
 #include "clot_mgm.h"
 
@@ -277,17 +278,22 @@ __global__ __launch_bounds__(NT) void k_mg_restrict_mesh(BrickGrid BG, MGPair L,
         mg_restrict_mesh_body<T, 2>(C, Cc, bx, by, bz, op, b, x, bc);
 }
 
-// The mesh's three down sweeps from zero (k_mg_pre's two and one k_mg_post2) as one
-// launch: a 1024-thread block stages a brick of shape 0 with a two-cell halo in LDS
-// (rAU, the diagonal, b and two iterates, 58 KB in FP32): x1 = w D^-1 b in the whole
-// halo, x2 on the brick and a one-cell ring, x3 on the brick, written out.  PresOp's
-// stencil in its order, each value the separate kernels' expression.
-template <class T, int DIM>
-__device__ inline void mesh_pre3_body(const ChanDev& C, int bx, int by, int bz, const PresOp<T, T>& op, const T* b,
-                                      T* xout, T w, T* sm) {
+// The mesh's down leg from zero in one launch, in two forms:
+//   three sweeps (k_mg_pre's two and one k_mg_post2; the residual restriction stays a
+//     launch of its own, since a third halo cell would cost more than it saves);
+//   two sweeps and the residual summed over each aggregate (k_mg_pre and
+//     k_mg_restrict_mesh), for meshes that every channel coarsens along every axis.
+// A 1024-thread block stages a brick of shape 0 with a two-cell halo in LDS (rAU, the
+// diagonal, b and two iterates; 58 KB in FP32 in 3-D, 27 KB in 2-D): x1 = w D^-1 b in
+// the whole halo, x2 on the brick and a one-cell ring, then x3 (or the residual b - A x2)
+// on the brick.  PresOp's stencil in its order, each value the separate kernels'
+// expression, the aggregate sums in the separate restriction's pairwise order.
+template <class T, int DIM, bool RESTRICT>
+__device__ inline void mesh_down_body(const ChanDev& C, const ChanDev& Cc, int bx, int by, int bz,
+                                      const PresOp<T, T>& op, const T* b, T* xout, T* bc, T w, T* sm) {
     constexpr int H = 2;
     using D = PBrick<DIM, H, 0>;
-    constexpr int NE = mgb_ne(H, 0);
+    constexpr int NE = D::NE;
     T* const sb = sm;
     T* const sd = sm + NE;
     T* const sa = sm + 2 * NE;     // rAU
@@ -317,6 +323,7 @@ __device__ inline void mesh_pre3_body(const ChanDev& C, int bx, int by, int bz, 
 #pragma unroll
     for (int s = 1; s <= H; ++s) {
         const int m = H - s;
+        const bool resid = RESTRICT && s == H;
         const int RX = D::BX + 2 * m, RY = D::BY + 2 * m, RZ = DIM == 3 ? D::BZ + 2 * m : 1;
         const int NR = RX * RY * RZ;
         for (int q = threadIdx.x; q < NR; q += MGB_BS) {
@@ -336,35 +343,74 @@ __device__ inline void mesh_pre3_body(const ChanDev& C, int bx, int by, int bz, 
                 if (gk < C.nz - 1) sacc += gzh * (rP + sa[e + SZ]) * x[e + SZ];
             }
             const T ax = sd[e] * x[e] - sacc;
-            const T z = x[e] + w * (sb[e] - ax) / sd[e];
-            s1[e] = z;
-            if (s == H) xout[C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk)] = z;
+            if (resid) {
+                s1[e] = sb[e] - ax;
+            } else {
+                const T z = x[e] + w * (sb[e] - ax) / sd[e];
+                s1[e] = z;
+                if (s == H) xout[C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk)] = z;
+            }
         }
         __syncthreads();
-        T* t = s0;
-        s0 = s1;
-        s1 = t;
+        if (!resid) {
+            T* t = s0;
+            s0 = s1;
+            s1 = t;
+        }
+    }
+    if (RESTRICT) {
+        // s0: x2, s1: the own cells' residuals.  x2 for the up leg, then the aggregate
+        // sums ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111)).
+        {
+            const int q = threadIdx.x;
+            const int lx = q % D::BX, ly = (q / D::BX) % D::BY, lz = DIM == 3 ? q / (D::BX * D::BY) : 0;
+            const int gi = ox + H + lx, gj = oy + H + ly, gk = oz + (DIM == 3 ? H : 0) + lz;
+            if (gi < C.nx && gj < C.ny && gk < C.nz)
+                xout[C.c0 + gi + (int64_t)C.nx * (gj + (int64_t)C.ny * gk)] =
+                    s0[(lx + H) + SY * ((ly + H) + D::EY * (DIM == 3 ? lz + H : 0))];
+        }
+        constexpr int AX = D::BX / 2, AY = D::BY / 2, AZ = DIM == 3 ? D::BZ / 2 : 1;
+        for (int a = threadIdx.x; a < AX * AY * AZ; a += MGB_BS) {
+            const int ax = a % AX, ay = (a / AX) % AY, az = a / (AX * AY);
+            T r[8];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                const int di = f & 1, dj = (f >> 1) & 1, dk = f >> 2;
+                const int lx = 2 * ax + di, ly = 2 * ay + dj, lz = DIM == 3 ? 2 * az + dk : 0;
+                const int gi = ox + H + lx, gj = oy + H + ly, gk = oz + (DIM == 3 ? H : 0) + lz;
+                const bool in = (DIM == 3 || dk == 0) && gi < C.nx && gj < C.ny && gk < C.nz;
+                r[f] = in ? s1[(lx + H) + SY * ((ly + H) + D::EY * (DIM == 3 ? lz + H : 0))] : T(0);
+            }
+            const T s01 = r[0] + r[1], s23 = r[2] + r[3], s45 = r[4] + r[5], s67 = r[6] + r[7];
+            const int ci = (ox + H) / 2 + ax, cj = (oy + H) / 2 + ay, ck = DIM == 3 ? (oz + H) / 2 + az : 0;
+            if (ci < Cc.nx && cj < Cc.ny && ck < Cc.nz)
+                bc[Cc.c0 + ci + (int64_t)Cc.nx * (cj + (int64_t)Cc.ny * ck)] = (s01 + s23) + (s45 + s67);
+        }
     }
 }
 
-template <class T>
-__global__ __launch_bounds__(MGB_BS) void k_mg_pre3_mesh(BrickGrid BG, Grid G, PresOp<T, T> op, const T* b, T* xout,
-                                                         T w, const int32_t* chact) {
+template <class T, bool RESTRICT>
+__global__ __launch_bounds__(MGB_BS) void k_mg_down_mesh(BrickGrid BG, MGPair L, PresOp<T, T> op, const T* b, T* xout,
+                                                         T* bc, T w, const int32_t* chact) {
     const int32_t bk = xcd_tile((int32_t)blockIdx.x, BG.nb);
     const int32_t chid = BG.b2c[bk];
     if (!chact[chid]) return;
-    const ChanDev C = G.ch[chid];
+    const ChanDev C = L.fine.ch[chid];
+    const ChanDev Cc = RESTRICT ? L.coarse.ch[chid] : C;
     const BrickChan B = BG.bc[chid];
     const int lb = bk - B.b0;
     const int bx = lb % B.nbx, by = (lb / B.nbx) % B.nby, bz = lb / (B.nbx * B.nby);
     extern __shared__ __align__(16) unsigned char mgb_lds[];
     T* const sm = reinterpret_cast<T*>(mgb_lds);
     if (C.dim == 3)
-        mesh_pre3_body<T, 3>(C, bx, by, bz, op, b, xout, w, sm);
+        mesh_down_body<T, 3, RESTRICT>(C, Cc, bx, by, bz, op, b, xout, bc, w, sm);
     else
-        mesh_pre3_body<T, 2>(C, bx, by, bz, op, b, xout, w, sm);
+        mesh_down_body<T, 2, RESTRICT>(C, Cc, bx, by, bz, op, b, xout, bc, w, sm);
 }
-constexpr size_t mesh_pre3_lds_bytes(size_t tsize) { return 5 * (size_t)mgb_ne(2, 0) * tsize; }
+// dynamic LDS of k_mg_down_mesh: five arrays of the larger brick among the dimensions present
+constexpr size_t mesh_down_lds_bytes(bool any3d, size_t tsize) {
+    return 5 * (size_t)(any3d ? PBrick<3, 2, 0>::NE : PBrick<2, 2, 0>::NE) * tsize;
+}
 
 // Prolongation and the first up sweep on the mesh: x1 = x + P xc, y = x1 + w D^-1 (b -
 // A x1).  k_mg_post1's expressions (PresOp's stencil in its order), with each
