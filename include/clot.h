@@ -349,6 +349,7 @@ typedef enum {
     CLOT_PROBE_P_MG_DOWN = 23,  /* pressure multigrid, bricked: a coarse level's down leg   */
     CLOT_PROBE_P_MG_UP = 24,    /* pressure multigrid, bricked: a coarse level's up leg     */
     CLOT_PROBE_P_MG_MESH_DOWN = 25, /* pressure multigrid: the mesh's down leg in one launch */
+    CLOT_PROBE_P_MG_MESH_UP = 26,   /* pressure multigrid: the mesh's prolongation and next sweep */
     CLOT_PROBE_NKERNELS
 } clot_probe_kernel;
 clot_status clot_probe(clot_ctx* c, int32_t kernel);

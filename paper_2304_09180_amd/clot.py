@@ -179,7 +179,7 @@ PROBES = {"p_cg_a": 1, "p_cg_b": 2, "tr_b1": 3, "tr_b2": 4, "tr_b3": 5, "mom_b1"
           "rxn": 9, "tr_asm": 10, "eta_cg_a": 11, "eta_cg_b": 12, "p_resid": 13, "correct": 14, "hbya": 15,
           "prhs": 16, "mom_asm": 17, "p_mg_post": 18, "rxn_fallback": 19, "mom_mg_r": 20, "mom_mg_p1": 21,
           "mom_mg_p2": 22, "p_mg_down": 23, "p_mg_up": 24,
-          "p_mg_mesh_down": 25}
+          "p_mg_mesh_down": 25, "p_mg_mesh_up": 26}
 
 
 def default_params(precision=FP64, **over) -> Params:

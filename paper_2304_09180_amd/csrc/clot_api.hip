@@ -246,17 +246,20 @@ struct Ctx : clot_ctx {
     int32_t* d_rb2c = nullptr;
     bool mesh_on = false;
     bool mesh_halves() const { return mesh_on && !h_rb2c.empty(); }
-    // The mesh's down leg in one launch (k_mg_down_mesh), bricks of the pressure shape 0,
-    // in FP32 contexts with mg_brick set: three sweeps (mesh_down_n = 3), or two sweeps
-    // and the restriction where every channel is coarsened along every axis (2).
+    // The mesh's legs in LDS-staged launches (k_mg_mesh_leg), bricks of the pressure shape
+    // 0, in FP32 contexts with mg_brick set: the down leg's three sweeps (mesh_down_n = 3),
+    // or two sweeps and the restriction where every channel is coarsened along every axis
+    // (2); with three sweeps on such a mesh also the up leg's prolongation and the sweep
+    // after it (mesh_up2).
     std::vector<BrickChan> h_p3br;
     std::vector<int32_t> h_p3b2c;
     BrickChan* d_p3br = nullptr;
     int32_t* d_p3b2c = nullptr;
     int mesh_down_n = 0;
+    bool mesh_up2 = false;
     bool mesh_down_3d = false;   // some channel is 3-D (the larger LDS brick)
     bool mesh_down() const { return !h_p3b2c.empty(); }
-    size_t mesh_down_lds() const { return mesh_down_lds_bytes(mesh_down_3d, sizeof(T)); }
+    size_t mesh_down_lds() const { return mesh_leg_lds_bytes(mesh_down_3d, sizeof(T)); }
     BrickGrid pbricks(int q, int j) const { return BrickGrid{d_pbr[q][j], d_pb2c[q][j], (int32_t)h_pb2c[q][j].size()}; }
     bool pbricked(int j) const { return mgb_use && !h_pb2c[0][j].empty(); }
     // reaction surrogate
@@ -753,6 +756,7 @@ struct Ctx : clot_ctx {
             mesh_down_n = 0;
             if (p->mg_brick != 0 && sizeof(T) == 4 && nl > 0)
                 mesh_down_n = prm.mg_sweeps == 3 ? 3 : (prm.mg_sweeps == 2 && !h_rb2c.empty() ? 2 : 0);
+            mesh_up2 = mesh_down_n == 3 && !h_rb2c.empty();
             mesh_down_3d = false;
             if (mesh_down_n > 0)
                 for (int i = 0; i < nch; ++i) {
@@ -794,8 +798,9 @@ struct Ctx : clot_ctx {
         };
         if (mg_t0 >= 0) attr(reinterpret_cast<const void*>(&k_mg_tail<T>), mg_tail_lds);
         if (mesh_down()) {
-            attr(reinterpret_cast<const void*>(&k_mg_down_mesh<T, false>), mesh_down_lds());
-            attr(reinterpret_cast<const void*>(&k_mg_down_mesh<T, true>), mesh_down_lds());
+            attr(reinterpret_cast<const void*>(&k_mg_mesh_leg<T, MESH_DOWN3>), mesh_down_lds());
+            attr(reinterpret_cast<const void*>(&k_mg_mesh_leg<T, MESH_DOWN2R>), mesh_down_lds());
+            attr(reinterpret_cast<const void*>(&k_mg_mesh_leg<T, MESH_UP2>), mesh_down_lds());
         }
         if (mgb_use) {
             const int h = prm.mg_sweeps;
@@ -1566,19 +1571,21 @@ struct Ctx : clot_ctx {
             }
         };
         // down (a bricked level leaves its smoothed iterate in Y for its up leg; the mesh's
-        // fused leg ends where the separate launches do: three sweeps in Y, two in X)
+        // fused leg ends where the separate launches do, three sweeps in Y and two in X,
+        // except before a fused up leg, which needs its input apart from its output: X)
         T* s0 = nullptr;
         const BrickGrid mdg{d_p3br, d_p3b2c, (int32_t)h_p3b2c.size()};
+        const MGPair m0{grid(), lev[0].grid()};
         if (mesh_down_n == 3) {
-            s0 = mg_y0;
-            CLOT_LAUNCH(CLOT_PROBE_P_MG_MESH_DOWN, (k_mg_down_mesh<T, false>), dim3((unsigned)h_p3b2c.size()),
-                        dim3(MGB_BS), mesh_down_lds(), st, mdg, MGPair{grid(), lev[0].grid()}, p0, r, s0, (T*)nullptr,
-                        mg_w, act);
+            s0 = mesh_up2 ? mg_z0 : mg_y0;
+            CLOT_LAUNCH(CLOT_PROBE_P_MG_MESH_DOWN, (k_mg_mesh_leg<T, MESH_DOWN3>), dim3((unsigned)h_p3b2c.size()),
+                        dim3(MGB_BS), mesh_down_lds(), st, mdg, m0, p0, r, (const T*)nullptr, (const T*)nullptr, s0,
+                        (T*)nullptr, mg_w, act);
         } else if (mesh_down_n == 2) {
             s0 = mg_z0;
-            CLOT_LAUNCH(CLOT_PROBE_P_MG_MESH_DOWN, (k_mg_down_mesh<T, true>), dim3((unsigned)h_p3b2c.size()),
-                        dim3(MGB_BS), mesh_down_lds(), st, mdg, MGPair{grid(), lev[0].grid()}, p0, r, s0, lev[0].b,
-                        mg_w, act);
+            CLOT_LAUNCH(CLOT_PROBE_P_MG_MESH_DOWN, (k_mg_mesh_leg<T, MESH_DOWN2R>), dim3((unsigned)h_p3b2c.size()),
+                        dim3(MGB_BS), mesh_down_lds(), st, mdg, m0, p0, r, (const T*)nullptr, (const T*)nullptr, s0,
+                        lev[0].b, mg_w, act);
         } else {
             s0 = down(p0, r, mg_z0, mg_y0, grid(), (int)ntiles);
         }
@@ -1621,6 +1628,18 @@ struct Ctx : clot_ctx {
             hipLaunchKernelGGL((k_mg_post1<T, CoefOp<T>>), dim3(L.ntiles), dim3(NT), 0, st, MGPair{L.grid(), lev[l + 1].grid()},
                                op, L.b, (const T*)pre_end[l], lev[l + 1].x, o1, mg_w, act);
             up_rest(op, (const T*)L.b, L.x, L.y, o1, L.grid(), (int)L.ntiles, false);
+        }
+        if (mesh_up2) {
+            // prolongation and the first two up sweeps in one launch (X -> Y), then the last
+            // sweep with r.z (Y -> X)
+            CLOT_LAUNCH(CLOT_PROBE_P_MG_MESH_UP, (k_mg_mesh_leg<T, MESH_UP2>), dim3((unsigned)h_p3b2c.size()),
+                        dim3(MGB_BS), mesh_down_lds(), st, BrickGrid{d_p3br, d_p3b2c, (int32_t)h_p3b2c.size()},
+                        MGPair{grid(), lev[0].grid()}, p0, r, (const T*)s0, (const T*)lev[0].x, mg_y0, (T*)nullptr,
+                        mg_w, act);
+            CLOT_LAUNCH(CLOT_PROBE_P_MG_POST, (k_mg_post2<T, PresOp<T, T>, true>), dim3(ntiles), dim3(NT), 0, st, grid(),
+                        p0, r, (const T*)mg_y0, mg_z0, mg_w, S);
+            finish<1>(EpiMgDot{});
+            return;
         }
         T* o1 = s0 == mg_z0 ? mg_y0 : mg_z0;
         if (mesh_halves())

@@ -1,7 +1,7 @@
 // Pressure multigrid legs in bricks (gfx950): the LDS-staged multi-sweep legs of the
 // coarse levels (FP32 contexts), and, at the end of the file, the mesh's restriction and
 // prolongation sweep for meshes that every channel coarsens along every axis (both
-// precisions) and the mesh's down leg in one launch (FP32 contexts).
+// precisions) and the mesh's legs in LDS-staged launches (FP32 contexts).
 //
 // Above the fused tail, each coarse level's legs are six separate launches (first two
 // sweeps, the other sweeps, restriction; prolongation sweep, the other sweeps), each
@@ -24,8 +24,9 @@
 // (aggregates never straddle bricks, whose origins are even).  On the mesh the whole
 // leg loses: the staged arrays leave room for one block per CU and the three-cell halo
 // triples the work, against separate launches that are already wide.  Only the mesh's
-// down leg is staged there, with a two-cell halo and five arrays (k_mg_down_mesh: three
-// sweeps, or two sweeps and the restriction).
+// legs are staged there with a two-cell halo and five arrays (k_mg_mesh_leg: the down
+// leg's sweeps, with the restriction when there are two; the up leg's prolongation and
+// the sweep after it).
 #pragma once
 #include "clot_mgm.h"
 
@@ -278,19 +279,28 @@ __global__ __launch_bounds__(NT) void k_mg_restrict_mesh(BrickGrid BG, MGPair L,
         mg_restrict_mesh_body<T, 2>(C, Cc, bx, by, bz, op, b, x, bc);
 }
 
-// The mesh's down leg from zero in one launch, in two forms:
-//   three sweeps (k_mg_pre's two and one k_mg_post2; the residual restriction stays a
-//     launch of its own, since a third halo cell would cost more than it saves);
-//   two sweeps and the residual summed over each aggregate (k_mg_pre and
-//     k_mg_restrict_mesh), for meshes that every channel coarsens along every axis.
-// A 1024-thread block stages a brick of shape 0 with a two-cell halo in LDS (rAU, the
-// diagonal, b and two iterates; 58 KB in FP32 in 3-D, 27 KB in 2-D): x1 = w D^-1 b in
-// the whole halo, x2 on the brick and a one-cell ring, then x3 (or the residual b - A x2)
-// on the brick.  PresOp's stencil in its order, each value the separate kernels'
-// expression, the aggregate sums in the separate restriction's pairwise order.
-template <class T, int DIM, bool RESTRICT>
-__device__ inline void mesh_down_body(const ChanDev& C, const ChanDev& Cc, int bx, int by, int bz,
-                                      const PresOp<T, T>& op, const T* b, T* xout, T* bc, T w, T* sm) {
+// Legs of the mesh's V-cycle in one launch each, in three forms:
+//   MESH_DOWN3: three sweeps from zero (k_mg_pre's two and one k_mg_post2; the residual
+//     restriction stays a launch of its own, since a third halo cell would cost more
+//     than it saves);
+//   MESH_DOWN2R: two sweeps from zero and the residual summed over each aggregate
+//     (k_mg_pre and k_mg_restrict_mesh);
+//   MESH_UP2: the prolonged iterate x + P xc and two sweeps (k_mg_post1_mesh and one
+//     k_mg_post2; the last sweep, which also forms r.z, stays a launch of its own, so
+//     that r.z is summed in the same order).
+// The last two need a mesh that every channel coarsens along every axis.  A
+// 1024-thread block stages a brick of shape 0 with a two-cell halo in LDS (rAU, the
+// diagonal, b and two iterates; 58 KB in FP32 in 3-D, 27 KB in 2-D): the first iterate
+// in the whole halo, pointwise (w D^-1 b, or x + P xc with the coarse cell by halving),
+// the next on the brick and a one-cell ring, then the last (or the residual) on the
+// brick.  PresOp's stencil in its order, each value the separate kernels' expression,
+// the aggregate sums in the separate restriction's pairwise order.
+enum { MESH_DOWN3 = 0, MESH_DOWN2R = 1, MESH_UP2 = 2 };
+template <class T, int DIM, int MODE>
+__device__ inline void mesh_leg_body(const ChanDev& C, const ChanDev& Cc, int bx, int by, int bz,
+                                     const PresOp<T, T>& op, const T* b, const T* xin, const T* xc, T* xout, T* bc,
+                                     T w, T* sm) {
+    constexpr bool RESTRICT = MODE == MESH_DOWN2R;
     constexpr int H = 2;
     using D = PBrick<DIM, H, 0>;
     constexpr int NE = D::NE;
@@ -310,7 +320,10 @@ __device__ inline void mesh_down_body(const ChanDev& C, const ChanDev& Cc, int b
             vb = b[g];
             vd = op.dP[g];
             va = op.rAU[g];
-            vx = w * vb / vd;
+            if (MODE == MESH_UP2)
+                vx = xin[g] + xc[Cc.c0 + (gi >> 1) + (int64_t)Cc.nx * ((gj >> 1) + (int64_t)Cc.ny * (gk >> 1))];
+            else
+                vx = w * vb / vd;
         }
         sb[e] = vb;
         sd[e] = vd;
@@ -389,26 +402,27 @@ __device__ inline void mesh_down_body(const ChanDev& C, const ChanDev& Cc, int b
     }
 }
 
-template <class T, bool RESTRICT>
-__global__ __launch_bounds__(MGB_BS) void k_mg_down_mesh(BrickGrid BG, MGPair L, PresOp<T, T> op, const T* b, T* xout,
-                                                         T* bc, T w, const int32_t* chact) {
+template <class T, int MODE>
+__global__ __launch_bounds__(MGB_BS) void k_mg_mesh_leg(BrickGrid BG, MGPair L, PresOp<T, T> op, const T* b,
+                                                        const T* xin, const T* xc, T* xout, T* bc, T w,
+                                                        const int32_t* chact) {
     const int32_t bk = xcd_tile((int32_t)blockIdx.x, BG.nb);
     const int32_t chid = BG.b2c[bk];
     if (!chact[chid]) return;
     const ChanDev C = L.fine.ch[chid];
-    const ChanDev Cc = RESTRICT ? L.coarse.ch[chid] : C;
+    const ChanDev Cc = MODE == MESH_DOWN3 ? C : L.coarse.ch[chid];
     const BrickChan B = BG.bc[chid];
     const int lb = bk - B.b0;
     const int bx = lb % B.nbx, by = (lb / B.nbx) % B.nby, bz = lb / (B.nbx * B.nby);
     extern __shared__ __align__(16) unsigned char mgb_lds[];
     T* const sm = reinterpret_cast<T*>(mgb_lds);
     if (C.dim == 3)
-        mesh_down_body<T, 3, RESTRICT>(C, Cc, bx, by, bz, op, b, xout, bc, w, sm);
+        mesh_leg_body<T, 3, MODE>(C, Cc, bx, by, bz, op, b, xin, xc, xout, bc, w, sm);
     else
-        mesh_down_body<T, 2, RESTRICT>(C, Cc, bx, by, bz, op, b, xout, bc, w, sm);
+        mesh_leg_body<T, 2, MODE>(C, Cc, bx, by, bz, op, b, xin, xc, xout, bc, w, sm);
 }
-// dynamic LDS of k_mg_down_mesh: five arrays of the larger brick among the dimensions present
-constexpr size_t mesh_down_lds_bytes(bool any3d, size_t tsize) {
+// dynamic LDS of k_mg_mesh_leg: five arrays of the larger brick among the dimensions present
+constexpr size_t mesh_leg_lds_bytes(bool any3d, size_t tsize) {
     return 5 * (size_t)(any3d ? PBrick<3, 2, 0>::NE : PBrick<2, 2, 0>::NE) * tsize;
 }
 

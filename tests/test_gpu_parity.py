@@ -165,8 +165,8 @@ def test_fused_multigrid_tail_is_bitwise_equal_to_separate_launches(prec_name, d
 def test_pressure_bricks_are_bitwise_equal_to_separate_launches(prec_name, descs, over):
     """The brick-ordered legs of the pressure V-cycle (default, mg_brick = 1: the mesh's
     restriction and prolongation, and in FP32 the LDS-staged legs of the coarse levels
-    and the mesh's down leg in one launch: three sweeps, or two sweeps and the
-    restriction) against
+    and the mesh's legs in one launch each: the down leg's three sweeps, or two sweeps
+    and the restriction; with three, the up leg's prolongation and next sweep) against
     the general separate launches (mg_brick = 0): every cell value is formed by the same
     expression, halo cells included, so the steps agree bit for bit.  In FP32 also checks
     that the staged legs ran (the probes count launches)."""
@@ -180,15 +180,19 @@ def test_pressure_bricks_are_bitwise_equal_to_separate_launches(prec_name, descs
             xc, xf = ci.noise(d)
             s.init_state(i, xc, xf)
         s.probe("p_mg_down")
-        s.step(3)
+        s.step(2)
         _, n = s.probe_read()
         s.probe("p_mg_mesh_down")
-        s.step(3)
+        s.step(2)
         _, n3 = s.probe_read()
+        s.probe("p_mg_mesh_up")
+        s.step(2)
+        _, nu = s.probe_read()
         s.probe(None)
         staged = brick == 1 and prec == clot.FP32_MIXED
         assert (n > 0) == staged, (brick, n)
         assert (n3 > 0) == (staged and sweeps in (2, 3)), (brick, n3)
+        assert (nu > 0) == (staged and sweeps == 3), (brick, nu)
         runs.append([s.fields(i) for i in range(len(descs))])
         s.close()
     for c in range(len(descs)):
