@@ -21,7 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    # the kernel sources and the build script (its compiler flags shape the code too)
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))) + [os.path.join(HERE, "build.py")]:
         h.update(os.path.basename(p).encode())
         with open(p, "rb") as f:
             h.update(f.read())
