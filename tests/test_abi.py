@@ -141,3 +141,17 @@ def test_brick_shapes_without_gpu():
     assert lib.clot_brick_dims(3, 4, v) == -1 and lib.clot_brick_dims(1, 0, v) == -1
     assert lib.clot_brick_kernel_dims(5, 3, 0, v) == -1 and lib.clot_brick_kernel_dims(-1, 3, 0, v) == -1
     assert lib.clot_set_brick_shape(None, 0, 0) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on exactly one GPU: with --gpus 2 it prints one JSON line naming
+    the reason and exits with status 2, before touching a device."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2, (r.returncode, r.stderr[-500:])
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
