@@ -1447,7 +1447,9 @@ struct Ctx : clot_ctx {
         set_active(mask);
         hipLaunchKernelGGL((k_bicg_init<T, K, Op, true>), dim3(ntiles, K), dim3(NT), 0, st, grid(), op, V, S);
         finish<3 * K>(EpiBicgInit<K>{rtol});
-        return iterate<K>(slot, 1, 2, budget[slot], [&](int par) {
+        // past the first chunk, one iteration per poll: an iteration run after every
+        // channel has converged costs more launches than the poll it saves
+        return iterate<K>(slot, 1, 1, budget[slot], [&](int par) {
             CLOT_LAUNCH(p1, (k_bicg_1<T, K, Op>), dim3(ntiles, K), dim3(NT), 0, st, grid(), op, V, S, par);
             finish<K>(EpiBicg1<K>{});
             CLOT_LAUNCH(p1 + 1, (k_bicg_2<T, K, Op>), dim3(ntiles, K), dim3(NT), 0, st, grid(), op, V, S, par);
@@ -1820,7 +1822,8 @@ struct Ctx : clot_ctx {
         T* const (&Y)[MGM_K] = mgm_vec(0);
         T* const (&Z)[MGM_K] = mgm_vec(1);
         T* const (&Sv)[MGM_K] = mgm_vec(2);
-        return iterate<3>(0, 1, 2, budget[0], [&](int par) {
+        // one iteration per poll past the first chunk, as in run_bicg
+        return iterate<3>(0, 1, 1, budget[0], [&](int par) {
             MGSrc<T> s1{};
             for (int k = 0; k < MGM_K; ++k) {
                 s1.r[k] = V.r[k];
